@@ -1,0 +1,231 @@
+"""CPU oracle for the physical-optics Stratton-Chu mirror integrals.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product library.  It wraps the plain
+C implementation in ``sc_oracle.c`` (FP64, long-double phase) with numpy
+arrays.  Every function follows the paper directly:
+
+* ``gauss_legendre``          -- quadrature rule of Sec. III-C (Gauss-Legendre in r)
+* ``mirror``                  -- paraboloid z = r^2/4f - f, cylindrical nodes (Sec. III-A/C)
+* ``incident``/``incident_tables`` -- collimated beam along -z on the mirror (Sec. III-A)
+* ``reflected_field``         -- Stokes-converted POA integrals (Sec. II, eq. stratton-chu-poa-og)
+* ``reflected_field_dgrad``   -- double-gradient POA form (Sec. II, eq. stratton-chu-poa), cross-check
+* ``time_transform``          -- semi-discrete Fourier sum (Sec. III-B, eq. impl.semiDiscreteFFT)
+
+Parity pins for all of these live in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sc_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+_lib = None
+
+PLANE, GAUSSIAN, GAUSSIAN_CONSISTENT = 0, 1, 2
+PARABOLOID, FLAT = 0, 1
+
+
+def compile_source(src: str, out: str) -> str:
+    """Compile an oracle C source with gcc (OpenMP, -O2, no fast-math) into a shared library."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
+                           "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = False) -> str:
+    """Build oracle/_build/liboracle.so (rebuilt when the source is newer)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        compile_source(_SRC, _LIB_PATH)
+    return _LIB_PATH
+
+
+def open_library(path: str):
+    """Load an oracle build (the default one, or a test's deliberately broken copy)."""
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER(ctypes.c_double)
+    I, D = ctypes.c_int, ctypes.c_double
+    lib.orc_gauss_legendre.argtypes = [I, P, P]
+    lib.orc_mirror.argtypes = [I, D, D, I, I, P, P, P, P]
+    lib.orc_incident.argtypes = [I, I, P, D, D, D, D, D, P, P]
+    lib.orc_reflected_field.argtypes = [I, I, P, P, P, P, I, P, P, P, I, P, P, P, I, I]
+    lib.orc_reflected_field_dgrad.argtypes = [I, P, P, P, I, I, P, P, I, P, P, I]
+    lib.orc_time_transform.argtypes = [I, P, D, I, P, ctypes.c_long, P, P, I]
+    lib.orc_max_threads.restype = I
+    return lib
+
+
+_override = None
+
+
+class use_library:
+    """Context manager: route every oracle call through another build (mutation tests)."""
+
+    def __init__(self, path: str):
+        self.lib = open_library(path)
+
+    def __enter__(self):
+        global _override
+        self._prev = _override
+        _override = self.lib
+        return self
+
+    def __exit__(self, *exc):
+        global _override
+        _override = self._prev
+        return False
+
+
+def _load():
+    global _lib
+    if _override is not None:
+        return _override
+    if _lib is None:
+        _lib = open_library(build())
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    if a.dtype == np.complex128:
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert a.dtype == np.float64, a.dtype
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+def gauss_legendre(n: int):
+    """Gauss-Legendre nodes (ascending) and weights on [-1, 1]."""
+    x = np.empty(n)
+    w = np.empty(n)
+    if _load().orc_gauss_legendre(int(n), _p(x), _p(w)) != 0:
+        raise ValueError("n must be >= 1")
+    return x, w
+
+
+@dataclass
+class Mirror:
+    f: float
+    a: float
+    n_r: int
+    n_phi: int
+    kind: int
+    pos: np.ndarray   # [n_tot, 3]
+    nrm: np.ndarray   # [n_tot, 3] unnormalised normal n~ (n dS = n~ r dr dphi)
+    wgt: np.ndarray   # [n_tot] surface weights, then the trapezoid step for rim nodes
+    tan: np.ndarray   # [n_phi, 3] rim tangent dr_s/dphi
+
+    @property
+    def n_surf(self) -> int:
+        return self.n_r * self.n_phi
+
+    @property
+    def n_rim(self) -> int:
+        return self.n_phi
+
+    @property
+    def n_tot(self) -> int:
+        return self.n_surf + self.n_rim
+
+
+def mirror(f: float, a: float, n_r: int, n_phi: int, kind: int = PARABOLOID) -> Mirror:
+    n_tot = (n_r + 1) * n_phi
+    pos = np.empty((n_tot, 3))
+    nrm = np.empty((n_tot, 3))
+    wgt = np.empty(n_tot)
+    tan = np.empty((n_phi, 3))
+    rc = _load().orc_mirror(int(kind), float(f), float(a), int(n_r), int(n_phi),
+                            _p(pos), _p(nrm), _p(wgt), _p(tan))
+    if rc != 0:
+        raise ValueError("invalid mirror parameters")
+    return Mirror(f, a, n_r, n_phi, kind, pos, nrm, wgt, tan)
+
+
+def incident(kind: int, pts, k: float, w0: float = np.inf, pol: float = 0.0, amp: complex = 1.0):
+    """Incident E, B (complex [n, 3]) of a collimated beam travelling along -z."""
+    pts = _f64(pts).reshape(-1, 3)
+    n = pts.shape[0]
+    E = np.empty((n, 3), np.complex128)
+    B = np.empty((n, 3), np.complex128)
+    _load().orc_incident(int(kind), n, _p(pts), float(k), float(w0), float(pol),
+                         float(np.real(amp)), float(np.imag(amp)), _p(E), _p(B))
+    return E, B
+
+
+def incident_tables(m: Mirror, k, kind: int, w0: float = np.inf, pol: float = 0.0, spectrum=None):
+    """E_inc, B_inc tables [n_k, n_tot, 3] on the mirror nodes (rim row included)."""
+    k = _f64(k).ravel()
+    spectrum = np.ones(k.shape[0], np.complex128) if spectrum is None else _c128(spectrum)
+    E = np.empty((k.shape[0], m.n_tot, 3), np.complex128)
+    B = np.empty_like(E)
+    for i, kk in enumerate(k):
+        E[i], B[i] = incident(kind, m.pos, kk, w0, pol, spectrum[i])
+    return E, B
+
+
+def reflected_field(m: Mirror, k, Einc, Binc, obs, line_term: bool = True, threads: int = 0):
+    """Reflected E, B [n_k, n_obs, 3] by the Stokes-converted POA integrals."""
+    k = _f64(k).ravel()
+    obs = _f64(obs).reshape(-1, 3)
+    Einc = _c128(Einc)
+    Binc = _c128(Binc)
+    assert Einc.shape == (k.shape[0], m.n_tot, 3) and Binc.shape == Einc.shape
+    E = np.empty((k.shape[0], obs.shape[0], 3), np.complex128)
+    B = np.empty_like(E)
+    _load().orc_reflected_field(m.n_surf, m.n_rim, _p(m.pos), _p(m.nrm), _p(m.wgt), _p(m.tan),
+                                k.shape[0], _p(k), _p(Einc), _p(Binc), obs.shape[0], _p(obs),
+                                _p(E), _p(B), int(bool(line_term)), int(threads))
+    return E, B
+
+
+def reflected_field_dgrad(m: Mirror, k, Binc, obs, threads: int = 0):
+    """Reflected E [n_k, n_obs, 3] by the double-gradient POA form (no line integral)."""
+    k = _f64(k).ravel()
+    obs = _f64(obs).reshape(-1, 3)
+    Binc = _c128(Binc)
+    E = np.empty((k.shape[0], obs.shape[0], 3), np.complex128)
+    _load().orc_reflected_field_dgrad(m.n_surf, _p(m.pos), _p(m.nrm), _p(m.wgt), m.n_tot,
+                                      k.shape[0], _p(k), _p(Binc), obs.shape[0], _p(obs), _p(E),
+                                      int(threads))
+    return E
+
+
+def time_transform(k, dk: float, t, F, threads: int = 0):
+    """F(t_m) = sum_n F_n e^{-i k_n t_m} dk for F of shape [n_k, ...] (complex)."""
+    k = _f64(k).ravel()
+    t = _f64(t).ravel()
+    F = _c128(F)
+    tail = F.shape[1:]
+    n_x = int(np.prod(tail)) if tail else 1
+    Ft = np.empty((t.shape[0],) + tail, np.complex128)
+    _load().orc_time_transform(k.shape[0], _p(k), float(dk), t.shape[0], _p(t), n_x,
+                               _p(F.reshape(k.shape[0], n_x)), _p(Ft), int(threads))
+    return Ft
+
+
+def solve(w, kind: int = GAUSSIAN, threads: int = 0, line_term: bool = True):
+    """Mirror + Gaussian incident tables + reflected field for a ``workloads.Workload``."""
+    kind = GAUSSIAN_CONSISTENT if (kind == GAUSSIAN and getattr(w, "consistent", 0)) else kind
+    m = mirror(w.f, w.a, w.n_r, w.n_phi)
+    Ei, Bi = incident_tables(m, w.k, kind, w.w0, w.pol, w.spectrum)
+    return reflected_field(m, w.k, Ei, Bi, w.obs, line_term=line_term, threads=threads)

@@ -1,0 +1,228 @@
+"""Seeded synthetic inputs for the parabolic-mirror Stratton-Chu solves.
+
+This module only *describes* workloads: mirror parameters, quadrature sizes,
+observation grids, frequency samples and spectral amplitudes, and seeded
+random draws.  It contains none of the diffraction arithmetic, so both the
+CPU oracle (``oracle/``) and the HIP library (``paper_1609_08146_amd``) can
+consume the same inputs without sharing any of the method's code.
+
+Units: lengths in metres (or in wavelengths for the unit-wavelength case),
+c = 1 so that the wavenumber k equals the angular frequency (Sec. II, the
+Lorentz-Heaviside convention, and Sec. III-B, the Fourier convention
+F(r,t) = int F(r,k) e^{-ikt} dk).  Times are c*t, in the length unit.
+
+The paper's own workloads are parameter sets (Table I); none of them is a
+public dataset.  The configurations below stand in for them:
+
+* ``mono``      -- monochromatic, lambda = 1, f = 20, aperture 40, 200x200 nodes,
+                   32x32 focal-plane grid over +-2 lambda (NA = 1).
+* ``broadband`` -- 800 nm carrier, Gaussian spectrum of 10 fs intensity FWHM,
+                   128 samples over +-3 sigma, f = 0.1 m, aperture radius 0.075 m,
+                   w0 = 0.05 m, 400x400 nodes, 64x64 focal plane +-4 lambda0 plus
+                   64 axial points, 256 time samples about the focal arrival 2f.
+* ``stress``    -- f = 5 cm, aperture radius 15 cm, w0 = 7 cm, 64 samples,
+                   800x800 nodes, 128x128 focal plane over +-2 lambda0.
+* ``sweep``     -- 256 seeded instances of uneven size (batched launch).
+* ``serving``   -- a seeded Poisson stream of requests drawn like ``sweep``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Optional
+
+import numpy as np
+
+C_LIGHT = 299_792_458.0          # m/s, only used to turn SI frequencies into wavenumbers
+LAMBDA0 = 800e-9                 # m, carrier wavelength of the broadband workloads
+TAU_FWHM = 10e-15                # s, intensity FWHM of the broadband pulse
+
+SWEEP_SEED = 160908146
+SERVING_SEED = 160908147
+
+
+@dataclass
+class Workload:
+    """One mirror + beam + observation set.
+
+    ``k``        wavenumbers (c = 1), shape [n_k]
+    ``spectrum`` complex spectral amplitude multiplying the beam at each k, [n_k]
+    ``obs``      observation points, shape [n_obs, 3]
+    ``w0``       Gaussian waist of the collimated incident beam (inf = plane wave)
+    ``pol``      polarisation angle about z (0 = x-polarised)
+    ``consistent`` 0: E_x = G e^{-ikz}, B = -y G e^{-ikz};  1: curl-consistent pair
+    ``t``        time samples (c*t) for the semi-discrete transform, or None
+    ``dk``       frequency spacing used as the transform weight
+    """
+
+    name: str
+    f: float
+    a: float
+    n_r: int
+    n_phi: int
+    k: np.ndarray
+    spectrum: np.ndarray
+    obs: np.ndarray
+    w0: float
+    pol: float = 0.0
+    consistent: int = 0
+    t: Optional[np.ndarray] = None
+    dk: float = 1.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_k(self) -> int:
+        return int(self.k.shape[0])
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.obs.shape[0])
+
+    @property
+    def n_nodes(self) -> int:
+        """Surface quadrature nodes (the rim nodes of the line integral excluded)."""
+        return self.n_r * self.n_phi
+
+    @property
+    def evals(self) -> int:
+        """Integrand evaluations: observation points x frequencies x surface nodes."""
+        return self.n_obs * self.n_k * self.n_nodes
+
+    def subset(self, obs_idx=None, k_idx=None, name=None) -> "Workload":
+        """Same mirror and quadrature, a subset of observation points and/or frequencies."""
+        obs = self.obs if obs_idx is None else self.obs[np.asarray(obs_idx)]
+        k = self.k if k_idx is None else self.k[np.asarray(k_idx)]
+        sp = self.spectrum if k_idx is None else self.spectrum[np.asarray(k_idx)]
+        return replace(self, name=name or self.name + "-subset", obs=np.ascontiguousarray(obs),
+                       k=np.ascontiguousarray(k), spectrum=np.ascontiguousarray(sp))
+
+    def with_nodes(self, n_r: int, n_phi: int) -> "Workload":
+        return replace(self, n_r=int(n_r), n_phi=int(n_phi))
+
+
+# --------------------------------------------------------------------------- grids
+
+def focal_plane(half_width: float, n: int, z: float = 0.0) -> np.ndarray:
+    """n x n points, linspace(-h, h, n)^2 in the plane z (x fastest varying)."""
+    s = np.linspace(-half_width, half_width, n)
+    yy, xx = np.meshgrid(s, s, indexing="ij")
+    pts = np.stack([xx.ravel(), yy.ravel(), np.full(n * n, z)], axis=-1)
+    return np.ascontiguousarray(pts)
+
+
+def axial_line(half_len: float, n: int) -> np.ndarray:
+    """n points on the optical axis, z = linspace(-L, L, n)."""
+    z = np.linspace(-half_len, half_len, n)
+    return np.ascontiguousarray(np.stack([np.zeros(n), np.zeros(n), z], axis=-1))
+
+
+# --------------------------------------------------------------------------- spectra
+
+def gaussian_spectrum(n_k: int, lam0: float = LAMBDA0, tau: float = TAU_FWHM, n_sigma: float = 3.0):
+    """Uniform wavenumber samples of a Gaussian pulse spectrum.
+
+    tau is the intensity FWHM, so the spectral field amplitude is
+    A(w) = exp(-(w - w0)^2 / (2 sigma_w^2)) with sigma_w = 2 sqrt(ln 2) / tau.
+    Samples are uniform on w0 +- n_sigma sigma_w, end points included; n_k = 1
+    gives the carrier alone.  Returns (k, amplitude, dk) with k = w / c.
+    """
+    k0 = 2.0 * math.pi / lam0
+    sigma_k = 2.0 * math.sqrt(math.log(2.0)) / tau / C_LIGHT
+    if n_k == 1:
+        return np.array([k0]), np.array([1.0 + 0j]), 2.0 * n_sigma * sigma_k
+    k = np.linspace(k0 - n_sigma * sigma_k, k0 + n_sigma * sigma_k, n_k)
+    amp = np.exp(-((k - k0) ** 2) / (2.0 * sigma_k ** 2)).astype(np.complex128)
+    return k, amp, float(k[1] - k[0])
+
+
+def time_window(dk: float, n_t: int, t_center: float) -> np.ndarray:
+    """n_t samples t_m = t_c + (m - n_t/2) dt with dt = 2 pi / (n_t dk) (one period of the sum)."""
+    dt = 2.0 * math.pi / (n_t * dk)
+    return t_center + (np.arange(n_t) - n_t // 2) * dt
+
+
+# --------------------------------------------------------------------------- named configs
+
+def mono() -> Workload:
+    """Monochromatic unit-wavelength case: lambda = 1, f = 20, aperture 40 (NA = 1)."""
+    k = np.array([2.0 * math.pi])
+    return Workload(name="mono", f=20.0, a=40.0, n_r=200, n_phi=200, k=k,
+                    spectrum=np.array([1.0 + 0j]), obs=focal_plane(2.0, 32), w0=20.0,
+                    t=None, dk=1.0)
+
+
+def broadband(n_k: int = 128, n_nodes: int = 400) -> Workload:
+    """800 nm / 10 fs pulse, f = 0.1 m, aperture radius 0.075 m, w0 = 0.05 m."""
+    k, amp, dk = gaussian_spectrum(n_k)
+    obs = np.concatenate([focal_plane(4 * LAMBDA0, 64), axial_line(4 * LAMBDA0, 64)])
+    f = 0.1
+    return Workload(name="broadband", f=f, a=0.075, n_r=n_nodes, n_phi=n_nodes, k=k, spectrum=amp,
+                    obs=obs, w0=0.05, t=time_window(dk, 256, 2.0 * f), dk=dk)
+
+
+def stress(n_k: int = 64, n_nodes: int = 800) -> Workload:
+    """Precision stress: f = 5 cm, aperture radius 15 cm (rim above the focal plane), kR ~ 1.6e6 rad."""
+    k, amp, dk = gaussian_spectrum(n_k)
+    f = 0.05
+    return Workload(name="stress", f=f, a=0.15, n_r=n_nodes, n_phi=n_nodes, k=k, spectrum=amp,
+                    obs=focal_plane(2 * LAMBDA0, 128), w0=0.07, t=time_window(dk, 256, 2.0 * f), dk=dk)
+
+
+def sweep_instance(rng: np.random.Generator, index: int = 0) -> Workload:
+    """One instance of the batched sweep, drawn in a fixed order from ``rng``."""
+    f = rng.uniform(0.02, 0.2)
+    a = rng.uniform(1.0, 3.0) * f
+    w0 = rng.uniform(0.3, 0.7) * a
+    n_k = int(min(256, max(1, round(math.exp(rng.uniform(0.0, math.log(256.0)))))))
+    n_g = int(rng.integers(16, 129))
+    n_ax = int(rng.integers(16, 129))
+    n = int(rng.integers(100, 601))
+    k, amp, dk = gaussian_spectrum(n_k)
+    obs = np.concatenate([focal_plane(4 * LAMBDA0, n_g), axial_line(4 * LAMBDA0, n_ax)])
+    return Workload(name=f"sweep{index}", f=f, a=a, n_r=n, n_phi=n, k=k, spectrum=amp, obs=obs, w0=w0,
+                    t=time_window(dk, 256, 2.0 * f), dk=dk)
+
+
+def sweep(n_instances: int = 256, seed: int = SWEEP_SEED) -> List[Workload]:
+    rng = np.random.default_rng(seed)
+    return [sweep_instance(rng, i) for i in range(n_instances)]
+
+
+def serving_arrivals(rate_hz: float, duration_s: float, seed: int = SERVING_SEED):
+    """Poisson arrival times (s) and a generator of requests drawn like ``sweep``.
+
+    Two independent streams are spawned from the seed: one for the inter-arrival
+    gaps and one for the request parameters.
+    """
+    ss = np.random.SeedSequence(seed)
+    s_time, s_req = ss.spawn(2)
+    rt = np.random.default_rng(s_time)
+    times = []
+    t = 0.0
+    while True:
+        t += rt.exponential(1.0 / rate_hz)
+        if t >= duration_s:
+            break
+        times.append(t)
+    rq = np.random.default_rng(s_req)
+    return np.array(times), (lambda i: sweep_instance(rq, i))
+
+
+# --------------------------------------------------------------------------- random tables
+
+def random_incident_tables(n_k: int, n_nodes_total: int, seed: int):
+    """Seeded complex tables E_inc, B_inc of shape [n_k, n_nodes_total, 3] (complex128).
+
+    Used to exercise the quadrature as a plain linear map of arbitrary tables;
+    each entry is uniform in the unit complex disc's bounding square.
+    """
+    rng = np.random.default_rng(seed)
+    shape = (n_k, n_nodes_total, 3)
+    E = rng.uniform(-1, 1, shape) + 1j * rng.uniform(-1, 1, shape)
+    B = rng.uniform(-1, 1, shape) + 1j * rng.uniform(-1, 1, shape)
+    return np.ascontiguousarray(E), np.ascontiguousarray(B)
+
+
+def random_points(n: int, half_width: float, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(rng.uniform(-half_width, half_width, (n, 3)))
