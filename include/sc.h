@@ -1,0 +1,260 @@
+/*
+ * sc.h -- C ABI of the MI355X (gfx950) Stratton-Chu mirror-focusing library.
+ *
+ * The library evaluates the physical-optics (POA) Stratton-Chu diffraction
+ * integrals of a field reflected off a parabolic mirror, in the
+ * Stokes-converted form of Dumont et al. (arXiv:1609.08146, Sec. II,
+ * eq. stratton-chu-poa-og):
+ *
+ *   E'(r',k) = 2 SS { ik (n x B_inc) g + (n . E_inc) grad g } dS
+ *              - (2/ik) O grad g [ n x (n x B_inc) ] . dl
+ *   B'(r',k) = 2 SS (n x B_inc) x grad g dS,      g = e^{ik|r-r'|} / (4 pi |r-r'|),
+ *
+ * with the gradient taken on the mirror variable r, by plain tensor-product
+ * quadrature over the mirror (Gauss-Legendre in r, trapezoid rule in phi;
+ * Sec. III-C), for every observation point and every frequency, and then
+ * transforms the spectral field to the time domain with the semi-discrete
+ * Fourier sum F(t) = sum_n F_n e^{-i k_n t} dk (Sec. III-B,
+ * eq. impl.semiDiscreteFFT).
+ *
+ * Units and conventions: c = 1 (Lorentz-Heaviside), k = omega, time factor
+ * e^{-ikt}; any consistent length unit; t is c*t.  The mirror is the
+ * paraboloid z = r^2/(4f) - f with its focus at the origin (Sec. III-C-1);
+ * the incident beam travels along -z (Sec. III-A).  The unnormalised normal
+ * n~ = (-x/2f, -y/2f, 1) points from the mirror toward the focus and the
+ * incoming beam, so that n dS = n~ r dr dphi.  Results are the REFLECTED
+ * field only.  Observation points on the mirror surface are outside the
+ * method's domain (g is singular there); they are not checked.
+ *
+ * Complex arrays are interleaved (re, im) pairs: complex128 = 2 doubles,
+ * complex64 = 2 floats.
+ *
+ * Memory and streams: every entry point enqueues its GPU work on the
+ * context's HIP stream.  Pointers flagged on_device = 1 are device pointers
+ * on the context's device; they must stay valid until the stream work that
+ * reads or writes them has completed (sc_ctx_synchronize).  Host pointers
+ * (on_device = 0) are read before the call returns; host outputs are complete
+ * when the call returns.  The library never retains or frees caller memory.
+ *
+ * Errors: every entry point returns an sc_status; nothing throws across the
+ * ABI.  On a non-OK status, sc_last_error() returns a thread-local message.
+ * A failed call leaves the object in its previous valid state unless stated.
+ *
+ * Threads: a context and its problems must not be used from two threads at
+ * once; the serving API below is the thread-safe front end.
+ */
+#ifndef SC_H
+#define SC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sc_ctx sc_ctx;
+typedef struct sc_prob sc_prob;
+typedef struct sc_server sc_server;
+
+typedef enum {
+    SC_OK = 0,
+    SC_E_INVAL = -1,        /* bad argument (size, value, null pointer)            */
+    SC_E_NOMEM = -2,        /* device or host allocation failed / over HBM budget   */
+    SC_E_DEVICE = -3,       /* HIP runtime error                                    */
+    SC_E_STATE = -4,        /* call out of order (e.g. evaluate before inputs)      */
+    SC_E_UNSUPPORTED = -5,  /* option not available                                 */
+    SC_E_TIMEOUT = -6,      /* serving: wait timed out (request still queued)       */
+    SC_E_CANCELLED = -7,    /* serving: request was cancelled                       */
+    SC_E_REJECTED = -8      /* serving: request can never fit the HBM budget        */
+} sc_status;
+
+/* Arithmetic of the quadrature.
+ *  SC_FP64       all per-pair arithmetic in FP64; node phase k|r_s| in double-double.
+ *                Output complex128.
+ *  SC_FP32_SPLIT the large phase k|r_s| (up to ~1e6 rad) is folded into the
+ *                per-(k,node) tables in double-double/FP64 and reduced mod 2pi;
+ *                the per-pair remainder k(|r_s - r'| - |r_s|) is formed without
+ *                cancellation and evaluated in FP32, with blocked compensated
+ *                (Kahan) node sums.  Output complex64.
+ *  SC_FP32       naive FP32: per-pair phase k|r_s - r'| in FP32 (an ablation;
+ *                loses accuracy once k|r_s| >> 1e3).  Output complex64.
+ */
+typedef enum { SC_FP64 = 0, SC_FP32_SPLIT = 1, SC_FP32 = 2 } sc_precision;
+
+const char *sc_last_error(void);
+const char *sc_version(void);
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t to use,
+ * or NULL for a library-owned stream (default priority).  */
+sc_status sc_ctx_create(int device, void *stream, sc_ctx **out);
+/* Destroy a context.  All problems created on it must be destroyed first.   */
+sc_status sc_ctx_destroy(sc_ctx *ctx);
+/* Wait for all work enqueued on the context's stream.                       */
+sc_status sc_ctx_synchronize(sc_ctx *ctx);
+/* Record HIP events around each kernel phase (see sc_get_timing).           */
+sc_status sc_ctx_set_profiling(sc_ctx *ctx, int enable);
+
+/* Per-phase device times of the most recent evaluate / to_time on a problem,
+ * in milliseconds, measured with HIP events on the context's stream
+ * (valid once the stream has completed; needs profiling enabled). */
+typedef struct {
+    double prep_ms;      /* incident/node table preparation (last set_incident*) */
+    double quad_ms;      /* the quadrature kernel (all tiles)                     */
+    double reduce_ms;    /* split-K reduction into the output                     */
+    double time_ms;      /* the semi-discrete time transform                      */
+    int64_t evals;       /* obs x freq x surface nodes of the last evaluate       */
+    int64_t tiles;       /* quadrature tiles of the last evaluate                 */
+} sc_timing;
+sc_status sc_get_timing(const sc_prob *p, sc_timing *out);
+
+/* Quadrature launch shape.  Only `chunk` changes the floating-point
+ * summation order (and therefore the last bits of FP32 results); the other
+ * fields change speed only.  Zero fields mean "library default".            */
+typedef struct {
+    int obs_per_lane;    /* 1 or 2 observation points per lane                    */
+    int waves_per_block; /* 1, 2, 4 or 8 waves of 64 lanes per workgroup          */
+    int chunk;           /* mirror nodes per split-K chunk (multiple of 64)        */
+    int blocks_per_cu;   /* persistent workgroups per compute unit                 */
+} sc_launch;
+/* Fix the launch shape for a problem (overrides the context's tuned value). */
+sc_status sc_set_launch(sc_prob *p, const sc_launch *launch);
+/* Time candidate launch shapes on problem `p` and store the fastest in the
+ * context's cache, keyed by (precision, size bucket of n_obs, n_k, nodes).
+ * `budget_ms` bounds the total time spent (0 = default).                    */
+sc_status sc_autotune(sc_prob *p, sc_precision prec, double budget_ms, sc_launch *best);
+/* Load / save the context's tuning cache (plain text).                     */
+sc_status sc_autotune_load(sc_ctx *ctx, const char *path);
+sc_status sc_autotune_save(sc_ctx *ctx, const char *path);
+
+/* ------------------------------------------------------------------ problem */
+
+sc_status sc_prob_create(sc_ctx *ctx, sc_prob **out);
+/* Frees every device buffer the problem owns; never caller memory.          */
+sc_status sc_prob_destroy(sc_prob *p);
+
+/* Mirror z = r^2/(4f) - f, r in [0, r_max] (Sec. III-C-1): n_r Gauss-Legendre
+ * nodes in r on [0, r_max] and n_phi trapezoid nodes phi_j = 2 pi j / n_phi,
+ * plus n_phi rim nodes at r = r_max for the line integral.  Node order:
+ * surface node (i, j) at index i*n_phi + j, then the rim nodes.
+ * f > 0, r_max > 0, 1 <= n_r, 1 <= n_phi, (n_r+1)*n_phi < 2^31 (SC_E_INVAL).
+ * Invalidates the incident tables and results.                             */
+sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, int n_phi);
+/* Number of surface nodes (n_r*n_phi) and rim nodes (n_phi).                */
+sc_status sc_get_num_nodes(const sc_prob *p, int *n_surface, int *n_rim);
+/* Copy node data to host arrays (any may be NULL):
+ *   xyz    [(n_r+1)*n_phi][3] positions (surface nodes, then rim),
+ *   normal [(n_r+1)*n_phi][3] unnormalised normals n~,
+ *   weight [(n_r+1)*n_phi]    surface weights w_r(i) r_i 2pi/n_phi, then 2pi/n_phi. */
+sc_status sc_get_nodes(const sc_prob *p, double *xyz, double *normal, double *weight);
+
+/* Wavenumbers k_n > 0 (c = 1), n_k >= 1.  Invalidates incident tables.     */
+sc_status sc_set_frequencies(sc_prob *p, const double *k, int n_k);
+
+/* Incident field on the mirror nodes (Sec. III-A): E and B are complex128
+ * [n_k][(n_r+1)*n_phi][3] in sc_get_nodes order, rim row included, and hold the
+ * full spectral field at each node (propagation phase such as e^{-ikz},
+ * spectral amplitude and any spectral phase, Sec. III-B).  The physical-
+ * optics current J = 2 n x B_inc (Sec. II, eq. poa) and the charge term
+ * n . E_inc are formed on the device.  Needs mirror and frequencies
+ * (SC_E_STATE).  Device tables of ~64 B per (k, node) are kept resident.    */
+sc_status sc_set_incident(sc_prob *p, const double *E, const double *B, int on_device);
+/* Built-in collimated Gaussian beam travelling along -z, evaluated on the
+ * device at every node and frequency:
+ *   consistent = 0: E = p G e^{-ikz}, B = (-z) x E, G = exp(-(x^2+y^2)/w0^2)
+ *   consistent = 1: B = psi (0, -1, -2iy/(k w0^2)), E = (i/k) curl B, psi = G e^{-ikz}
+ *                   (written in the frame where the polarisation is along x)
+ * w0 = +inf gives a plane wave.  pol_angle rotates the beam about z.
+ * spectrum: complex128 [n_k] amplitudes (NULL = all 1).                     */
+sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_angle,
+                                   const double *spectrum, int consistent);
+
+/* Observation points, [n_obs][3] doubles, n_obs >= 1.                       */
+sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs, int on_device);
+
+/* Evaluate the reflected spectral field at every (observation point, k).
+ * E, B: [n_k][n_obs][3] complex128 (SC_FP64) or complex64 (FP32 forms),
+ * host or device per on_device; either may be NULL to keep the result only
+ * on the device (for sc_to_time / sc_get_result).  Needs mirror, frequencies,
+ * incident field and observation points (SC_E_STATE).                      */
+sc_status sc_evaluate(sc_prob *p, sc_precision prec, void *E, void *B, int on_device);
+/* Copy the last result (same layout and type as sc_evaluate).              */
+sc_status sc_get_result(const sc_prob *p, void *E, void *B, int on_device);
+
+/* Semi-discrete transform of the last result to n_t times t[] (host array):
+ *   F(t_m) = dk * sum_n F_n e^{-i k_n t_m}    (complex; the physical field is
+ * 2 Re F(t) when the samples cover positive frequencies only).
+ * Et, Bt: [n_t][n_obs][3], same complex type as the result.                 */
+sc_status sc_to_time(sc_prob *p, double dk, const double *t, int n_t, void *Et, void *Bt, int on_device);
+
+/* Evaluate several problems in ONE persistent launch (tiles of all problems
+ * share the device), then reduce each; results are kept per problem (read
+ * with sc_get_result).  Each problem's result is bitwise identical to what
+ * sc_evaluate gives it alone with the same launch chunk.                    */
+sc_status sc_evaluate_batch(sc_ctx *ctx, sc_prob *const *probs, int n, sc_precision prec);
+
+/* Device bytes held by the problem (tables, observation data, results).    */
+sc_status sc_prob_device_bytes(const sc_prob *p, size_t *bytes);
+
+/* ------------------------------------------------------------------ serving */
+
+/* A field-solve request (all arrays are host memory, copied at submit). */
+typedef struct {
+    double f, r_max;          /* mirror                                       */
+    int n_r, n_phi;           /* quadrature                                   */
+    int n_k;                  /* frequencies                                  */
+    const double *k;          /* [n_k]                                        */
+    const double *spectrum;   /* complex128 [n_k] or NULL                     */
+    double w0, pol_angle;     /* Gaussian beam (w0 = inf: plane wave)         */
+    int consistent;           /* beam variant, see sc_set_incident_gaussian   */
+    int n_obs;                /* observation points                           */
+    const double *obs;        /* [n_obs][3]                                   */
+    sc_precision prec;        /* arithmetic                                   */
+    int n_t;                  /* 0, or number of time samples                 */
+    const double *t;          /* [n_t] time samples                           */
+    double dk;                /* transform weight                             */
+} sc_request;
+
+typedef struct {
+    double queue_ms;          /* submit -> admitted                           */
+    double run_ms;            /* admitted -> result ready on host             */
+    double total_ms;          /* submit -> result ready                       */
+    int64_t evals;            /* obs x freq x surface nodes                   */
+    size_t device_bytes;      /* HBM footprint charged at admission           */
+} sc_request_stats;
+
+typedef struct {
+    int64_t submitted, admitted, completed, rejected, cancelled, queued, running;
+    size_t hbm_in_use, hbm_budget;
+    int64_t launches;         /* scheduling quanta launched                    */
+    int64_t evals_done;
+} sc_server_stats;
+
+/* Start a serving loop on `ctx`: requests are admitted while their HBM
+ * footprint fits `hbm_budget` bytes and at most `max_running` are in flight;
+ * the tiles of all admitted requests are scheduled together in persistent
+ * launches of about `quantum_ms` of work, so requests that arrive while
+ * others run join the next launch (continuous batching).  The server owns a
+ * host thread and uses `ctx` exclusively until destroyed.                  */
+sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_running, double quantum_ms,
+                           sc_server **out);
+/* Queue a request; returns a ticket.  SC_E_REJECTED if it can never fit.   */
+sc_status sc_server_submit(sc_server *s, const sc_request *req, uint64_t *ticket);
+/* Wait up to timeout_ms (< 0: forever) for a result.  E, B: host arrays
+ * [n_k][n_obs][3] (complex128 for SC_FP64, complex64 otherwise); Et, Bt:
+ * [n_t][n_obs][3] or NULL.  The ticket is released on SC_OK/SC_E_CANCELLED. */
+sc_status sc_server_wait(sc_server *s, uint64_t ticket, double timeout_ms, void *E, void *B,
+                         void *Et, void *Bt, sc_request_stats *stats);
+/* Cancel a queued request (running requests finish normally).              */
+sc_status sc_server_cancel(sc_server *s, uint64_t ticket);
+sc_status sc_server_get_stats(sc_server *s, sc_server_stats *out);
+/* Stop the loop after in-flight work completes and free everything.        */
+sc_status sc_server_destroy(sc_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SC_H */

@@ -1,0 +1,227 @@
+"""Thin Python binding of the C ABI (include/sc.h).
+
+Arguments are marshalled to the library; all computation runs in the gfx950
+kernels of libsc.so.  Host arrays are numpy; device arrays are torch tensors
+on the context's device (torch provides device memory and the stream only).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _abi
+from ._abi import SC_FP32, SC_FP32_SPLIT, SC_FP64, ScError, call, call_status
+
+PRECISIONS = {"fp64": SC_FP64, "fp32_split": SC_FP32_SPLIT, "fp32": SC_FP32}
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return PRECISIONS[p]
+    return int(p)
+
+
+def _host_f64(a, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _host_c128(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def _ptr(a) -> int:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    # torch tensor
+    assert a.is_contiguous(), "device tensors must be contiguous"
+    return a.data_ptr()
+
+
+def _is_device(a) -> bool:
+    return a is not None and not isinstance(a, np.ndarray)
+
+
+class Context:
+    """sc_ctx: one HIP device + stream.  stream=None uses torch's current stream on `device`."""
+
+    def __init__(self, device: int = 0, stream=None, use_torch_stream: bool = True):
+        self.device = device
+        handle = None
+        if stream is not None:
+            handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        elif use_torch_stream:
+            import torch
+            handle = torch.cuda.current_stream(device).cuda_stream
+        out = ctypes.c_void_p()
+        call("sc_ctx_create", int(device), handle, ctypes.byref(out))
+        self.h = out
+
+    def close(self):
+        if self.h:
+            call("sc_ctx_destroy", self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def synchronize(self):
+        call("sc_ctx_synchronize", self.h)
+
+    def set_profiling(self, on: bool = True):
+        call("sc_ctx_set_profiling", self.h, int(bool(on)))
+
+    def evaluate_batch(self, probs: Sequence["Problem"], precision="fp32_split"):
+        arr = (ctypes.c_void_p * len(probs))(*[p.h for p in probs])
+        call("sc_evaluate_batch", self.h, arr, len(probs), _prec(precision))
+        for p in probs:
+            p._res_prec = _prec(precision)
+
+    def autotune_save(self, path: str):
+        call("sc_autotune_save", self.h, path.encode())
+
+    def autotune_load(self, path: str):
+        call("sc_autotune_load", self.h, path.encode())
+
+
+class Problem:
+    """sc_prob: one mirror, spectrum, incident field and observation set."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        out = ctypes.c_void_p()
+        call("sc_prob_create", ctx.h, ctypes.byref(out))
+        self.h = out
+        self.n_k = 0
+        self.n_obs = 0
+        self._res_prec = None
+
+    def close(self):
+        if self.h:
+            call("sc_prob_destroy", self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- inputs
+    def set_mirror(self, f: float, r_max: float, n_r: int, n_phi: int):
+        call("sc_set_mirror", self.h, float(f), float(r_max), int(n_r), int(n_phi))
+        self.n_r, self.n_phi = int(n_r), int(n_phi)
+
+    def num_nodes(self):
+        ns, nr = ctypes.c_int(), ctypes.c_int()
+        call("sc_get_num_nodes", self.h, ctypes.byref(ns), ctypes.byref(nr))
+        return ns.value, nr.value
+
+    def get_nodes(self):
+        ns, nr = self.num_nodes()
+        n = ns + nr
+        xyz, nrm, w = np.empty((n, 3)), np.empty((n, 3)), np.empty(n)
+        call("sc_get_nodes", self.h, _ptr(xyz), _ptr(nrm), _ptr(w))
+        return xyz, nrm, w
+
+    def set_frequencies(self, k):
+        k = _host_f64(k).ravel()
+        call("sc_set_frequencies", self.h, _ptr(k), int(k.shape[0]))
+        self.n_k = int(k.shape[0])
+
+    def set_incident(self, E, B):
+        """E, B: complex128 [n_k][n_nodes_total][3] (numpy, or complex128 torch tensors on the device)."""
+        dev = _is_device(E)
+        if not dev:
+            E, B = _host_c128(E), _host_c128(B)
+        call("sc_set_incident", self.h, _ptr(E), _ptr(B), int(dev))
+
+    def set_incident_gaussian(self, w0: float, pol: float = 0.0, spectrum=None, consistent: bool = False):
+        sp = None if spectrum is None else _host_c128(spectrum).ravel()
+        call("sc_set_incident_gaussian", self.h, float(w0), float(pol), _ptr(sp), int(bool(consistent)))
+
+    def set_observation(self, xyz):
+        dev = _is_device(xyz)
+        if not dev:
+            xyz = _host_f64(xyz, (-1, 3))
+        n = int(xyz.shape[0])
+        call("sc_set_observation", self.h, _ptr(xyz), n, int(dev))
+        self.n_obs = n
+
+    def set_launch(self, obs_per_lane=0, waves_per_block=0, chunk=0, blocks_per_cu=0, reset=False):
+        if reset:
+            call("sc_set_launch", self.h, None)
+            return
+        l = _abi.sc_launch(obs_per_lane, waves_per_block, chunk, blocks_per_cu)
+        call("sc_set_launch", self.h, ctypes.byref(l))
+
+    def autotune(self, precision="fp32_split", budget_ms: float = 0.0):
+        l = _abi.sc_launch()
+        call("sc_autotune", self.h, _prec(precision), float(budget_ms), ctypes.byref(l))
+        return dict(obs_per_lane=l.obs_per_lane, waves_per_block=l.waves_per_block, chunk=l.chunk,
+                    blocks_per_cu=l.blocks_per_cu)
+
+    # ---- evaluation
+    def _out_host(self, prec, n_first):
+        dt = np.complex128 if prec == SC_FP64 else np.complex64
+        return np.empty((n_first, self.n_obs, 3), dt)
+
+    def evaluate(self, precision="fp32_split", out=None, keep_on_device: bool = False):
+        """Evaluate; returns host (E, B) arrays [n_k][n_obs][3], or fills `out`=(E, B) device tensors."""
+        prec = _prec(precision)
+        self._res_prec = prec
+        if keep_on_device:
+            call("sc_evaluate", self.h, prec, None, None, 1)
+            return None
+        if out is not None:
+            E, B = out
+            call("sc_evaluate", self.h, prec, _ptr(E), _ptr(B), 1)
+            return out
+        E, B = self._out_host(prec, self.n_k), self._out_host(prec, self.n_k)
+        call("sc_evaluate", self.h, prec, _ptr(E), _ptr(B), 0)
+        return E, B
+
+    def result(self):
+        E, B = self._out_host(self._res_prec, self.n_k), self._out_host(self._res_prec, self.n_k)
+        call("sc_get_result", self.h, _ptr(E), _ptr(B), 0)
+        return E, B
+
+    def to_time(self, dk: float, t, out=None):
+        t = _host_f64(t).ravel()
+        if out is not None:
+            Et, Bt = out
+            call("sc_to_time", self.h, float(dk), _ptr(t), int(t.shape[0]), _ptr(Et), _ptr(Bt), 1)
+            return out
+        Et, Bt = self._out_host(self._res_prec, t.shape[0]), self._out_host(self._res_prec, t.shape[0])
+        call("sc_to_time", self.h, float(dk), _ptr(t), int(t.shape[0]), _ptr(Et), _ptr(Bt), 0)
+        return Et, Bt
+
+    def timing(self) -> dict:
+        tm = _abi.sc_timing()
+        call("sc_get_timing", self.h, ctypes.byref(tm))
+        return {f: getattr(tm, f) for f, _ in tm._fields_}
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        call("sc_prob_device_bytes", self.h, ctypes.byref(b))
+        return b.value
+
+
+def problem_from_workload(ctx: Context, w, consistent: Optional[bool] = None) -> Problem:
+    """A Problem set up with a ``workloads.Workload``'s mirror, spectrum, Gaussian beam and points."""
+    p = Problem(ctx)
+    p.set_mirror(w.f, w.a, w.n_r, w.n_phi)
+    p.set_frequencies(w.k)
+    p.set_incident_gaussian(w.w0, w.pol, w.spectrum, bool(w.consistent if consistent is None else consistent))
+    p.set_observation(w.obs)
+    return p

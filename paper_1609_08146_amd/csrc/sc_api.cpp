@@ -1,0 +1,826 @@
+// sc_api.cpp -- host runtime behind the C ABI declared in include/sc.h:
+// contexts, problems, argument validation, device memory, launch shapes,
+// the batched persistent launch, timing and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <new>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "sc_host.h"
+
+using namespace sc;
+
+// ===================================================================== errors
+
+static thread_local std::string g_err;
+
+sc_status sc::fail(sc_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+extern "C" const char *sc_last_error(void) { return g_err.c_str(); }
+extern "C" const char *sc_version(void) { return "sc-mi355x 0.1 (gfx950)"; }
+
+bool sc::debug_fail_this_alloc()
+{
+    static std::mutex mu;
+    static long count = 0;
+    static long fail_at = -2;
+    std::lock_guard<std::mutex> lk(mu);
+    if (fail_at == -2) {
+        const char *s = getenv("SC_DEBUG_FAIL_ALLOC");
+        fail_at = s ? atol(s) : -1;
+    }
+    ++count;
+    return fail_at > 0 && count == fail_at;
+}
+
+extern "C" sc_status sc_ctx_create(int device, void *stream, sc_ctx **out)
+{
+    if (!out) return fail(SC_E_INVAL, "sc_ctx_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(SC_E_INVAL, "sc_ctx_create: device %d not in [0, %d)", device, n);
+    DeviceGuard g(device);
+    sc_ctx *c = new (std::nothrow) sc_ctx();
+    if (!c) return fail(SC_E_NOMEM, "sc_ctx_create: out of host memory");
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->n_cu = prop.multiProcessorCount;
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(SC_E_DEVICE, "sc_ctx_create: hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    sc_status st = c->counter.reserve(256);
+    if (st == SC_OK && hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess)
+        st = fail(SC_E_DEVICE, "sc_ctx_create: hipEventCreate failed");
+    if (st != SC_OK) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_ctx_destroy(sc_ctx *c)
+{
+    if (!c) return SC_OK;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+    c->counter.release();
+    c->jobs.release();
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_ctx_synchronize(sc_ctx *c)
+{
+    if (!c) return fail(SC_E_INVAL, "sc_ctx_synchronize: ctx is NULL");
+    DeviceGuard g(c->device);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SC_OK;
+}
+
+extern "C" sc_status sc_ctx_set_profiling(sc_ctx *c, int enable)
+{
+    if (!c) return fail(SC_E_INVAL, "sc_ctx_set_profiling: ctx is NULL");
+    c->profiling = enable ? 1 : 0;
+    return SC_OK;
+}
+
+// ================================================================== problem
+
+static size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
+
+static int log2_bucket(int64_t v)
+{
+    int b = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+extern "C" sc_status sc_prob_create(sc_ctx *ctx, sc_prob **out)
+{
+    if (!ctx || !out) return fail(SC_E_INVAL, "sc_prob_create: NULL argument");
+    *out = nullptr;
+    DeviceGuard g(ctx->device);
+    sc_prob *p = new (std::nothrow) sc_prob();
+    if (!p) return fail(SC_E_NOMEM, "sc_prob_create: out of host memory");
+    p->ctx = ctx;
+    for (int i = 0; i < EV_N; ++i) {
+        if (hipEventCreate(&p->ev[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(p->ev[j]);
+            delete p;
+            return fail(SC_E_DEVICE, "sc_prob_create: hipEventCreate failed");
+        }
+    }
+    *out = p;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_prob_destroy(sc_prob *p)
+{
+    if (!p) return SC_OK;
+    DeviceGuard g(p->ctx->device);
+    (void)hipStreamSynchronize(p->ctx->stream);
+    for (int i = 0; i < EV_N; ++i)
+        if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
+    delete p;   // DevBufs free themselves
+    return SC_OK;
+}
+
+// Gauss-Legendre rule on [-1, 1] (ascending).  Roots of P_n from Tricomi's
+// asymptotic initial guess, refined by Newton's method in long double with
+// P_n and P_n' from their three-term recurrences; the rule is symmetric, so
+// only the positive half is computed.  Weights 2 / ((1 - x^2) P_n'(x)^2).
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double nn = (long double)n;
+    for (int i = 1; i <= (n + 1) / 2; ++i) {
+        long double th = pi * (4.0L * i - 1.0L) / (4.0L * nn + 2.0L);
+        long double z = (1.0L - (nn - 1.0L) / (8.0L * nn * nn * nn)) * cosl(th);
+        long double dp = 1.0L;
+        int polish = 0;
+        for (int it = 0; it < 64; ++it) {
+            long double p0 = 1.0L, p1 = z, d0 = 0.0L, d1 = 1.0L;
+            for (int m = 1; m < n; ++m) {
+                long double p2 = ((2.0L * m + 1.0L) * z * p1 - m * p0) / (m + 1.0L);
+                long double d2 = d0 + (2.0L * m + 1.0L) * p1;   // P'_{m+1} = P'_{m-1} + (2m+1) P_m
+                p0 = p1;
+                p1 = p2;
+                d0 = d1;
+                d1 = d2;
+            }
+            if (n == 1) {
+                p1 = z;
+                d1 = 1.0L;
+            }
+            dp = d1;
+            long double step = p1 / d1;
+            z -= step;
+            if (fabsl(step) < 1e-11L) {
+                // quadratic convergence: one more step reaches long-double precision
+                if (++polish == 2) break;
+            }
+        }
+        // final derivative at the converged root
+        {
+            long double p0 = 1.0L, p1 = z, d0 = 0.0L, d1 = 1.0L;
+            for (int m = 1; m < n; ++m) {
+                long double p2 = ((2.0L * m + 1.0L) * z * p1 - m * p0) / (m + 1.0L);
+                long double d2 = d0 + (2.0L * m + 1.0L) * p1;
+                p0 = p1;
+                p1 = p2;
+                d0 = d1;
+                d1 = d2;
+            }
+            dp = (n == 1) ? 1.0L : d1;
+        }
+        long double wi = 2.0L / ((1.0L - z * z) * dp * dp);
+        if (2 * i - 1 == n) z = 0.0L;   // middle node of an odd rule
+        x[n - i] = (double)z;
+        x[i - 1] = -(double)z;
+        w[n - i] = (double)wi;
+        w[i - 1] = (double)wi;
+    }
+}
+
+static void invalidate_tables(sc_prob *p)
+{
+    p->has_tab = p->tab32_ok = p->tab32n_ok = false;
+    p->res_prec = -1;
+}
+
+extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, int n_phi)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_set_mirror: prob is NULL");
+    if (!(f > 0.0) || !std::isfinite(f)) return fail(SC_E_INVAL, "sc_set_mirror: f must be > 0 (got %g)", f);
+    if (!(r_max > 0.0) || !std::isfinite(r_max)) return fail(SC_E_INVAL, "sc_set_mirror: r_max must be > 0");
+    if (n_r < 1 || n_phi < 1) return fail(SC_E_INVAL, "sc_set_mirror: n_r, n_phi must be >= 1");
+    if ((int64_t)(n_r + 1) * n_phi >= (1LL << 31))
+        return fail(SC_E_INVAL, "sc_set_mirror: (n_r+1)*n_phi must be < 2^31");
+    DeviceGuard g(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    std::vector<double> x, w;
+    gauss_legendre(n_r, x, w);
+    std::vector<double> r(n_r + 1), wr(n_r), c(n_phi), s(n_phi);
+    for (int i = 0; i < n_r; ++i) {
+        r[i] = r_max * (1.0 + x[i]) / 2.0;
+        wr[i] = r_max * w[i] / 2.0;
+    }
+    r[n_r] = r_max;
+    for (int j = 0; j < n_phi; ++j) {
+        double phi = 2.0 * M_PI * (double)j / (double)n_phi;
+        c[j] = cos(phi);
+        s[j] = sin(phi);
+    }
+    const int n_tot = (n_r + 1) * n_phi;
+    invalidate_tables(p);
+    p->has_mirror = false;
+    SC_TRY(p->d_r.reserve(sizeof(double) * (n_r + 1), p->alloc_stream));
+    SC_TRY(p->d_wr.reserve(sizeof(double) * n_r, p->alloc_stream));
+    SC_TRY(p->d_c.reserve(sizeof(double) * n_phi, p->alloc_stream));
+    SC_TRY(p->d_s.reserve(sizeof(double) * n_phi, p->alloc_stream));
+    SC_TRY(p->pos64.reserve(sizeof(double) * 4 * n_tot, p->alloc_stream));
+    SC_TRY(p->pos32.reserve(sizeof(float) * 4 * n_tot, p->alloc_stream));
+    SC_TRY(p->nrm.reserve(sizeof(double) * 3 * n_tot, p->alloc_stream));
+    SC_TRY(p->wgt.reserve(sizeof(double) * n_tot, p->alloc_stream));
+    SC_TRY(p->tan.reserve(sizeof(double) * 3 * n_phi, p->alloc_stream));
+    HIP_TRY(hipMemcpyAsync(p->d_r.p, r.data(), sizeof(double) * (n_r + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->d_wr.p, wr.data(), sizeof(double) * n_r, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->d_c.p, c.data(), sizeof(double) * n_phi, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->d_s.p, s.data(), sizeof(double) * n_phi, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_node_tables(st, n_r, n_phi, f, p->d_r.as<double>(), p->d_wr.as<double>(), p->d_c.as<double>(),
+                               p->d_s.as<double>(), 2.0 * M_PI / (double)n_phi, p->pos64.as<double>(),
+                               p->pos32.as<float>(), p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>()));
+    // the host vectors above are pageable: make the copies complete before they go out of scope
+    HIP_TRY(hipStreamSynchronize(st));
+    p->f = f;
+    p->a = r_max;
+    p->n_r = n_r;
+    p->n_phi = n_phi;
+    p->n_surf = n_r * n_phi;
+    p->n_rim = n_phi;
+    p->n_tot = n_tot;
+    p->has_mirror = true;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_get_num_nodes(const sc_prob *p, int *n_surface, int *n_rim)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_get_num_nodes: prob is NULL");
+    if (!p->has_mirror) return fail(SC_E_STATE, "sc_get_num_nodes: no mirror set");
+    if (n_surface) *n_surface = p->n_surf;
+    if (n_rim) *n_rim = p->n_rim;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_get_nodes(const sc_prob *p, double *xyz, double *normal, double *weight)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_get_nodes: prob is NULL");
+    if (!p->has_mirror) return fail(SC_E_STATE, "sc_get_nodes: no mirror set");
+    DeviceGuard g(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    HIP_TRY(hipStreamSynchronize(st));
+    if (xyz) {
+        std::vector<double> tmp((size_t)4 * p->n_tot);
+        HIP_TRY(hipMemcpy(tmp.data(), p->pos64.p, sizeof(double) * 4 * p->n_tot, hipMemcpyDeviceToHost));
+        for (int q = 0; q < p->n_tot; ++q)
+            for (int c = 0; c < 3; ++c) xyz[3 * (size_t)q + c] = tmp[4 * (size_t)q + c];
+    }
+    if (normal) HIP_TRY(hipMemcpy(normal, p->nrm.p, sizeof(double) * 3 * p->n_tot, hipMemcpyDeviceToHost));
+    if (weight) HIP_TRY(hipMemcpy(weight, p->wgt.p, sizeof(double) * p->n_tot, hipMemcpyDeviceToHost));
+    return SC_OK;
+}
+
+extern "C" sc_status sc_set_frequencies(sc_prob *p, const double *k, int n_k)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_set_frequencies: prob is NULL");
+    if (!k || n_k < 1) return fail(SC_E_INVAL, "sc_set_frequencies: need n_k >= 1 wavenumbers");
+    for (int i = 0; i < n_k; ++i)
+        if (!(k[i] > 0.0) || !std::isfinite(k[i]))
+            return fail(SC_E_INVAL, "sc_set_frequencies: k[%d] = %g is not a positive wavenumber", i, k[i]);
+    DeviceGuard g(p->ctx->device);
+    invalidate_tables(p);
+    p->k.assign(k, k + n_k);
+    SC_TRY(p->d_k.reserve(sizeof(double) * n_k, p->alloc_stream));
+    HIP_TRY(hipMemcpyAsync(p->d_k.p, p->k.data(), sizeof(double) * n_k, hipMemcpyHostToDevice, p->ctx->stream));
+    return SC_OK;
+}
+
+static void ev_record(sc_prob *p, int which)
+{
+    if (p->ctx->profiling) (void)hipEventRecord(p->ev[which], p->ctx->stream);
+}
+
+extern "C" sc_status sc_set_incident(sc_prob *p, const double *E, const double *B, int on_device)
+{
+    if (!p || !E || !B) return fail(SC_E_INVAL, "sc_set_incident: NULL argument");
+    if (!p->has_mirror || p->k.empty()) return fail(SC_E_STATE, "sc_set_incident: set mirror and frequencies first");
+    DeviceGuard g(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    const int n_k = (int)p->k.size();
+    const size_t nrec = (size_t)n_k * p->n_tot;
+    invalidate_tables(p);
+    SC_TRY(p->tab64.reserve(sizeof(double) * 8 * nrec, p->alloc_stream));
+    DevBuf stageE, stageB;
+    const double *dE = E, *dB = B;
+    if (!on_device) {
+        SC_TRY(stageE.reserve(sizeof(double) * 6 * nrec, p->alloc_stream));
+        SC_TRY(stageB.reserve(sizeof(double) * 6 * nrec, p->alloc_stream));
+        HIP_TRY(hipMemcpyAsync(stageE.p, E, sizeof(double) * 6 * nrec, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(stageB.p, B, sizeof(double) * 6 * nrec, hipMemcpyHostToDevice, st));
+        dE = stageE.as<double>();
+        dB = stageB.as<double>();
+    }
+    ev_record(p, EV_PREP0);
+    HIP_TRY(launch_tables_from_fields(st, n_k, p->n_surf, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
+                                      p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>(), dE, dB,
+                                      p->tab64.as<double>()));
+    ev_record(p, EV_PREP1);
+    p->ev_prep = p->ctx->profiling;
+    if (!on_device) HIP_TRY(hipStreamSynchronize(st));   // staging buffers are freed on return
+    p->has_tab = true;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_angle, const double *spectrum,
+                                              int consistent)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_set_incident_gaussian: prob is NULL");
+    if (!(w0 > 0.0)) return fail(SC_E_INVAL, "sc_set_incident_gaussian: w0 must be > 0 (inf = plane wave)");
+    if (!std::isfinite(pol_angle)) return fail(SC_E_INVAL, "sc_set_incident_gaussian: bad polarisation angle");
+    if (!p->has_mirror || p->k.empty())
+        return fail(SC_E_STATE, "sc_set_incident_gaussian: set mirror and frequencies first");
+    DeviceGuard g(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    const int n_k = (int)p->k.size();
+    invalidate_tables(p);
+    SC_TRY(p->tab64.reserve(sizeof(double) * 8 * (size_t)n_k * p->n_tot, p->alloc_stream));
+    DevBuf dspec;
+    if (spectrum) {
+        SC_TRY(dspec.reserve(sizeof(double) * 2 * n_k, p->alloc_stream));
+        HIP_TRY(hipMemcpyAsync(dspec.p, spectrum, sizeof(double) * 2 * n_k, hipMemcpyHostToDevice, st));
+    }
+    ev_record(p, EV_PREP0);
+    HIP_TRY(launch_tables_gaussian(st, n_k, p->n_surf, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
+                                   p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>(), w0, pol_angle,
+                                   spectrum ? dspec.as<double>() : nullptr, consistent ? 1 : 0,
+                                   p->tab64.as<double>()));
+    ev_record(p, EV_PREP1);
+    p->ev_prep = p->ctx->profiling;
+    HIP_TRY(hipStreamSynchronize(st));   // dspec is freed on return
+    p->has_tab = true;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs, int on_device)
+{
+    if (!p || !xyz) return fail(SC_E_INVAL, "sc_set_observation: NULL argument");
+    if (n_obs < 1) return fail(SC_E_INVAL, "sc_set_observation: n_obs must be >= 1");
+    if (!on_device) {
+        for (int o = 0; o < n_obs; ++o)
+            for (int c = 0; c < 3; ++c)
+                if (!std::isfinite(xyz[3 * (size_t)o + c]))
+                    return fail(SC_E_INVAL, "sc_set_observation: point %d is not finite", o);
+    }
+    DeviceGuard g(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    const int pad = (int)round_up((size_t)n_obs, OBS_PAD);
+    p->res_prec = -1;
+    SC_TRY(p->obs64.reserve(sizeof(double) * 4 * pad, p->alloc_stream));
+    SC_TRY(p->obs32.reserve(sizeof(float) * 4 * pad, p->alloc_stream));
+    DevBuf stage;
+    const double *d = xyz;
+    if (!on_device) {
+        SC_TRY(stage.reserve(sizeof(double) * 3 * n_obs, p->alloc_stream));
+        HIP_TRY(hipMemcpyAsync(stage.p, xyz, sizeof(double) * 3 * n_obs, hipMemcpyHostToDevice, st));
+        d = stage.as<double>();
+    }
+    HIP_TRY(launch_obs_prep(st, d, n_obs, pad, p->obs64.as<double>(), p->obs32.as<float>()));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(st));
+    p->n_obs = n_obs;
+    p->n_obs_pad = pad;
+    return SC_OK;
+}
+
+// ============================================================ launch shapes
+
+static sc_launch default_launch(sc_precision prec)
+{
+    sc_launch l{};
+    l.obs_per_lane = (prec == SC_FP64) ? 1 : 2;
+    l.waves_per_block = 4;
+    l.chunk = 4096;
+    l.blocks_per_cu = 0;   // 0 = occupancy limit
+    return l;
+}
+
+static TuneKey tune_key(const sc_prob *p, sc_precision prec)
+{
+    return {(int)prec, log2_bucket(p->n_obs), log2_bucket((int64_t)p->k.size()), log2_bucket(p->n_tot)};
+}
+
+sc_status sc::check_launch(const sc_launch &l)
+{
+    if (l.obs_per_lane != 1 && l.obs_per_lane != 2) return fail(SC_E_INVAL, "launch: obs_per_lane must be 1 or 2");
+    if (l.waves_per_block != 1 && l.waves_per_block != 2 && l.waves_per_block != 4)
+        return fail(SC_E_INVAL, "launch: waves_per_block must be 1, 2 or 4");
+    if (l.chunk < 64 || l.chunk % 64 != 0) return fail(SC_E_INVAL, "launch: chunk must be a positive multiple of 64");
+    if (l.blocks_per_cu < 0 || l.blocks_per_cu > 64) return fail(SC_E_INVAL, "launch: blocks_per_cu out of range");
+    return SC_OK;
+}
+
+sc_launch sc::resolve_launch(const sc_prob *p, sc_precision prec)
+{
+    sc_launch l = default_launch(prec);
+    auto it = p->ctx->tune.find(tune_key(p, prec));
+    if (it != p->ctx->tune.end()) l = it->second;
+    if (p->has_launch) {
+        if (p->launch.obs_per_lane) l.obs_per_lane = p->launch.obs_per_lane;
+        if (p->launch.waves_per_block) l.waves_per_block = p->launch.waves_per_block;
+        if (p->launch.chunk) l.chunk = p->launch.chunk;
+        if (p->launch.blocks_per_cu) l.blocks_per_cu = p->launch.blocks_per_cu;
+    }
+    return l;
+}
+
+extern "C" sc_status sc_set_launch(sc_prob *p, const sc_launch *l)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_set_launch: prob is NULL");
+    if (!l) {
+        p->has_launch = false;
+        return SC_OK;
+    }
+    sc_launch full = default_launch(SC_FP32_SPLIT);
+    if (l->obs_per_lane) full.obs_per_lane = l->obs_per_lane;
+    if (l->waves_per_block) full.waves_per_block = l->waves_per_block;
+    if (l->chunk) full.chunk = l->chunk;
+    full.blocks_per_cu = l->blocks_per_cu;
+    SC_TRY(check_launch(full));
+    p->launch = *l;
+    p->has_launch = true;
+    return SC_OK;
+}
+
+// ====================================================================== evaluate
+
+int sc::mode_of(sc_precision prec)
+{
+    return prec == SC_FP64 ? MODE_FP64 : (prec == SC_FP32_SPLIT ? MODE_SPLIT : MODE_NAIVE);
+}
+
+size_t sc::real_size(sc_precision prec) { return prec == SC_FP64 ? sizeof(double) : sizeof(float); }
+
+// Make sure the tables of precision `prec` exist; size the partial and result buffers.
+sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob &job)
+{
+    if (prec != SC_FP64 && prec != SC_FP32_SPLIT && prec != SC_FP32)
+        return fail(SC_E_INVAL, "evaluate: unknown precision %d", (int)prec);
+    if (!p->has_mirror || p->k.empty() || !p->has_tab || p->n_obs < 1)
+        return fail(SC_E_STATE, "evaluate: mirror, frequencies, incident field and observation points are required");
+    hipStream_t st = p->ctx->stream;
+    const int n_k = (int)p->k.size();
+    const size_t nrec = (size_t)n_k * p->n_tot;
+    const void *tab = p->tab64.p;
+    if (prec == SC_FP32_SPLIT) {
+        if (!p->tab32_ok) {
+            SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
+            HIP_TRY(launch_tables_cast(st, n_k, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
+                                       p->tab64.as<double>(), p->tab32.as<float>(), 0));
+            p->tab32_ok = true;
+        }
+        tab = p->tab32.p;
+    } else if (prec == SC_FP32) {
+        if (!p->tab32n_ok) {
+            SC_TRY(p->tab32n.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
+            HIP_TRY(launch_tables_cast(st, n_k, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
+                                       p->tab64.as<double>(), p->tab32n.as<float>(), 1));
+            p->tab32n_ok = true;
+        }
+        tab = p->tab32n.p;
+    }
+    const int n_chunks = (p->n_tot + l.chunk - 1) / l.chunk;
+    const size_t rs = real_size(prec);
+    SC_TRY(p->partial.reserve(rs * 12 * (size_t)n_chunks * n_k * p->n_obs_pad, p->alloc_stream));
+    SC_TRY(p->resE.reserve(rs * 6 * (size_t)n_k * p->n_obs, p->alloc_stream));
+    SC_TRY(p->resB.reserve(rs * 6 * (size_t)n_k * p->n_obs, p->alloc_stream));
+    job.tab = tab;
+    job.pos = prec == SC_FP64 ? p->pos64.p : p->pos32.p;
+    job.obs = prec == SC_FP64 ? p->obs64.p : p->obs32.p;
+    job.k = p->d_k.as<double>();
+    job.partial = p->partial.p;
+    job.n_tot = p->n_tot;
+    job.n_obs_pad = p->n_obs_pad;
+    job.n_k = n_k;
+    job.chunk = l.chunk;
+    job.n_chunks = n_chunks;
+    job.obs_blocks = p->n_obs_pad / (64 * l.obs_per_lane);
+    job.tile0 = 0;
+    job.tile_offset = 0;
+    job.n_tiles = (int64_t)job.obs_blocks * n_chunks * n_k;
+    return SC_OK;
+}
+
+size_t sc::footprint_bytes(int n_r, int n_phi, int n_k, int n_obs, int n_t, sc_precision prec, int chunk)
+{
+    const size_t n_tot = (size_t)(n_r + 1) * n_phi;
+    const size_t pad = round_up((size_t)n_obs, OBS_PAD);
+    const size_t rs = real_size(prec);
+    const size_t n_chunks = (n_tot + chunk - 1) / chunk;
+    size_t b = 0;
+    b += sizeof(double) * (2 * (size_t)n_r + 1 + 2 * (size_t)n_phi + 3 * (size_t)n_phi);   // 1-D rule, rim tangents
+    b += n_tot * (sizeof(double) * (4 + 3 + 1) + sizeof(float) * 4);                        // node records
+    b += sizeof(double) * n_k;
+    b += (size_t)n_k * n_tot * sizeof(double) * 8;                                          // FP64 tables
+    if (prec != SC_FP64) b += (size_t)n_k * n_tot * sizeof(float) * 8;                      // FP32 tables
+    b += pad * (sizeof(double) + sizeof(float)) * 4;                                        // observation records
+    b += rs * 12 * (size_t)n_k * n_obs;                                                      // results E, B
+    b += rs * 12 * n_chunks * (size_t)n_k * pad;                                             // split-K partials
+    if (n_t > 0) b += sizeof(double) * ((size_t)n_t + 2 * (size_t)n_t * n_k) + rs * 12 * (size_t)n_t * n_obs;
+    return b;
+}
+
+// Upload jobs and run one persistent quadrature launch over all their tiles.
+sc_status sc::run_quad(sc_ctx *c, std::vector<QuadJob> &jobs, sc_precision prec, const sc_launch &l,
+                          sc_prob *timed)
+{
+    hipStream_t st = c->stream;
+    int64_t n_tiles = 0;
+    for (auto &j : jobs) {
+        j.tile0 = n_tiles;
+        n_tiles += j.n_tiles;
+    }
+    if (n_tiles >= (1LL << 31) - (1LL << 24)) return fail(SC_E_UNSUPPORTED, "evaluate: too many tiles (%lld)",
+                                                           (long long)n_tiles);
+    SC_TRY(c->jobs.reserve(sizeof(QuadJob) * jobs.size()));
+    // the previous upload from host_jobs must have completed before it is overwritten
+    HIP_TRY(hipEventSynchronize(c->upload_done));
+    c->host_jobs = jobs;
+    HIP_TRY(hipMemcpyAsync(c->jobs.p, c->host_jobs.data(), sizeof(QuadJob) * jobs.size(), hipMemcpyHostToDevice,
+                           st));
+    HIP_TRY(hipEventRecord(c->upload_done, st));
+    HIP_TRY(launch_fill_u32(st, c->counter.as<unsigned int>(), 0u, 1));
+    const int mode = mode_of(prec);
+    int bpc = l.blocks_per_cu;
+    const int occ = quad_max_blocks_per_cu(mode, l.obs_per_lane, l.waves_per_block);
+    if (bpc <= 0 || bpc > occ) bpc = occ;
+    int64_t grid = (int64_t)bpc * c->n_cu;
+    const int64_t waves_needed = (n_tiles + 0);
+    const int64_t blocks_needed = (waves_needed + l.waves_per_block - 1) / l.waves_per_block;
+    if (grid > blocks_needed) grid = blocks_needed;
+    if (grid < 1) grid = 1;
+    if (timed) ev_record(timed, EV_Q0);
+    HIP_TRY(launch_quad(st, mode, l.obs_per_lane, l.waves_per_block, (int)grid, c->jobs.as<QuadJob>(),
+                        (int)jobs.size(), n_tiles, c->counter.as<unsigned int>()));
+    if (timed) ev_record(timed, EV_Q1);
+    return SC_OK;
+}
+
+static sc_status copy_out(sc_prob *p, void *E, void *B, int on_device, size_t bytes)
+{
+    hipStream_t st = p->ctx->stream;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (E) HIP_TRY(hipMemcpyAsync(E, p->resE.p, bytes, kind, st));
+    if (B) HIP_TRY(hipMemcpyAsync(B, p->resB.p, bytes, kind, st));
+    if (!on_device && (E || B)) HIP_TRY(hipStreamSynchronize(st));
+    return SC_OK;
+}
+
+extern "C" sc_status sc_evaluate(sc_prob *p, sc_precision prec, void *E, void *B, int on_device)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_evaluate: prob is NULL");
+    DeviceGuard g(p->ctx->device);
+    const sc_launch l = resolve_launch(p, prec);
+    SC_TRY(check_launch(l));
+    QuadJob job{};
+    SC_TRY(prepare(p, prec, l, job));
+    std::vector<QuadJob> jobs{job};
+    p->res_prec = -1;
+    SC_TRY(run_quad(p->ctx, jobs, prec, l, p));
+    HIP_TRY(launch_reduce(p->ctx->stream, mode_of(prec), p->partial.p, job.n_chunks, job.n_k, p->n_obs,
+                          p->n_obs_pad, p->d_k.as<double>(), p->resE.p, p->resB.p));
+    ev_record(p, EV_R1);
+    p->ev_quad = p->ctx->profiling;
+    p->res_prec = (int)prec;
+    p->last_evals = (int64_t)p->n_obs * job.n_k * p->n_surf;
+    p->last_tiles = job.n_tiles;
+    return copy_out(p, E, B, on_device, real_size(prec) * 6 * (size_t)job.n_k * p->n_obs);
+}
+
+extern "C" sc_status sc_get_result(const sc_prob *p, void *E, void *B, int on_device)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_get_result: prob is NULL");
+    if (p->res_prec < 0) return fail(SC_E_STATE, "sc_get_result: no result (evaluate first)");
+    DeviceGuard g(p->ctx->device);
+    return copy_out((sc_prob *)p, E, B, on_device,
+                    real_size((sc_precision)p->res_prec) * 6 * p->k.size() * (size_t)p->n_obs);
+}
+
+extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, sc_precision prec)
+{
+    if (!c || (!probs && n > 0) || n < 0) return fail(SC_E_INVAL, "sc_evaluate_batch: bad arguments");
+    if (n == 0) return SC_OK;
+    DeviceGuard g(c->device);
+    // one launch needs one obs-per-lane / waves shape: take it from the first problem
+    for (int i = 0; i < n; ++i)
+        if (!probs[i] || probs[i]->ctx != c) return fail(SC_E_INVAL, "sc_evaluate_batch: problem %d not on ctx", i);
+    sc_launch l0 = resolve_launch(probs[0], prec);
+    SC_TRY(check_launch(l0));
+    std::vector<QuadJob> jobs(n);
+    std::vector<sc_launch> ls(n);
+    for (int i = 0; i < n; ++i) {
+        ls[i] = resolve_launch(probs[i], prec);
+        ls[i].obs_per_lane = l0.obs_per_lane;   // chunk stays per problem (it fixes the summation order)
+        SC_TRY(check_launch(ls[i]));
+        SC_TRY(prepare(probs[i], prec, ls[i], jobs[i]));
+        probs[i]->res_prec = -1;
+    }
+    // the same partial buffer must not serve two jobs
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            if (probs[i] == probs[j]) return fail(SC_E_INVAL, "sc_evaluate_batch: problem %d repeated", j);
+    SC_TRY(run_quad(c, jobs, prec, l0, probs[0]));
+    for (int i = 0; i < n; ++i) {
+        sc_prob *p = probs[i];
+        HIP_TRY(launch_reduce(c->stream, mode_of(prec), p->partial.p, jobs[i].n_chunks, jobs[i].n_k, p->n_obs,
+                              p->n_obs_pad, p->d_k.as<double>(), p->resE.p, p->resB.p));
+        p->res_prec = (int)prec;
+        p->last_evals = (int64_t)p->n_obs * jobs[i].n_k * p->n_surf;
+        p->last_tiles = jobs[i].n_tiles;
+    }
+    ev_record(probs[0], EV_R1);
+    probs[0]->ev_quad = c->profiling;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_to_time(sc_prob *p, double dk, const double *t, int n_t, void *Et, void *Bt, int on_device)
+{
+    if (!p || !t) return fail(SC_E_INVAL, "sc_to_time: NULL argument");
+    if (n_t < 1) return fail(SC_E_INVAL, "sc_to_time: n_t must be >= 1");
+    if (!std::isfinite(dk)) return fail(SC_E_INVAL, "sc_to_time: dk must be finite");
+    if (p->res_prec < 0) return fail(SC_E_STATE, "sc_to_time: no spectral result (evaluate first)");
+    DeviceGuard g(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    const int n_k = (int)p->k.size();
+    const int f64 = p->res_prec == SC_FP64;
+    const size_t rs = f64 ? sizeof(double) : sizeof(float);
+    const int64_t n_x = (int64_t)p->n_obs * 3;
+    SC_TRY(p->d_t.reserve(sizeof(double) * n_t, p->alloc_stream));
+    SC_TRY(p->tw.reserve(sizeof(double) * 2 * (size_t)n_t * n_k, p->alloc_stream));
+    SC_TRY(p->timeE.reserve(rs * 2 * (size_t)n_t * n_x, p->alloc_stream));
+    SC_TRY(p->timeB.reserve(rs * 2 * (size_t)n_t * n_x, p->alloc_stream));
+    HIP_TRY(hipMemcpyAsync(p->d_t.p, t, sizeof(double) * n_t, hipMemcpyHostToDevice, st));
+    ev_record(p, EV_T0);
+    HIP_TRY(launch_twiddles(st, n_k, p->d_k.as<double>(), n_t, p->d_t.as<double>(), dk, p->tw.as<double>()));
+    HIP_TRY(launch_time(st, f64, n_k, n_t, n_x, p->tw.as<double>(), p->resE.p, p->timeE.p));
+    HIP_TRY(launch_time(st, f64, n_k, n_t, n_x, p->tw.as<double>(), p->resB.p, p->timeB.p));
+    ev_record(p, EV_T1);
+    p->ev_time = p->ctx->profiling;
+    const size_t bytes = rs * 2 * (size_t)n_t * n_x;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (Et) HIP_TRY(hipMemcpyAsync(Et, p->timeE.p, bytes, kind, st));
+    if (Bt) HIP_TRY(hipMemcpyAsync(Bt, p->timeB.p, bytes, kind, st));
+    // t was copied from pageable host memory; complete before returning
+    HIP_TRY(hipStreamSynchronize(st));
+    return SC_OK;
+}
+
+extern "C" sc_status sc_get_timing(const sc_prob *p, sc_timing *out)
+{
+    if (!p || !out) return fail(SC_E_INVAL, "sc_get_timing: NULL argument");
+    memset(out, 0, sizeof *out);
+    DeviceGuard g(p->ctx->device);
+    float ms = 0.f;
+    if (p->ev_prep && hipEventElapsedTime(&ms, p->ev[EV_PREP0], p->ev[EV_PREP1]) == hipSuccess) out->prep_ms = ms;
+    if (p->ev_quad) {
+        if (hipEventElapsedTime(&ms, p->ev[EV_Q0], p->ev[EV_Q1]) == hipSuccess) out->quad_ms = ms;
+        if (hipEventElapsedTime(&ms, p->ev[EV_Q1], p->ev[EV_R1]) == hipSuccess) out->reduce_ms = ms;
+    }
+    if (p->ev_time && hipEventElapsedTime(&ms, p->ev[EV_T0], p->ev[EV_T1]) == hipSuccess) out->time_ms = ms;
+    (void)hipGetLastError();
+    out->evals = p->last_evals;
+    out->tiles = p->last_tiles;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_prob_device_bytes(const sc_prob *p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SC_E_INVAL, "sc_prob_device_bytes: NULL argument");
+    const DevBuf *bufs[] = {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->nrm, &p->wgt,
+                            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->obs64, &p->obs32,
+                            &p->resE, &p->resB, &p->partial, &p->d_t, &p->tw, &p->timeE, &p->timeB};
+    size_t s = 0;
+    for (const DevBuf *b : bufs) s += b->bytes;
+    *bytes = s;
+    return SC_OK;
+}
+
+// ================================================================== autotuner
+
+extern "C" sc_status sc_autotune(sc_prob *p, sc_precision prec, double budget_ms, sc_launch *best)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_autotune: prob is NULL");
+    DeviceGuard g(p->ctx->device);
+    if (budget_ms <= 0) budget_ms = 20000.0;
+    sc_ctx *c = p->ctx;
+    const int saved_prof = c->profiling;
+    const bool saved_has = p->has_launch;
+    const sc_launch saved = p->launch;
+    c->profiling = 1;
+    std::vector<sc_launch> cands;
+    const int chunk0 = default_launch(prec).chunk;
+    for (int opl : {1, 2})
+        for (int wpb : {1, 2, 4})
+            for (int bpc : {0, 2, 1}) {
+                sc_launch l{};
+                l.obs_per_lane = opl;
+                l.waves_per_block = wpb;
+                l.chunk = chunk0;
+                l.blocks_per_cu = bpc;
+                cands.push_back(l);
+            }
+    auto t_start = std::chrono::steady_clock::now();
+    double best_ms = 1e300;
+    sc_launch best_l = default_launch(prec);
+    sc_status st = SC_OK;
+    for (const sc_launch &l : cands) {
+        p->launch = l;
+        p->has_launch = true;
+        double tmin = 1e300;
+        for (int rep = 0; rep < 2 && st == SC_OK; ++rep) {
+            st = sc_evaluate(p, prec, nullptr, nullptr, 1);
+            if (st != SC_OK) break;
+            if (hipStreamSynchronize(c->stream) != hipSuccess) {
+                st = fail(SC_E_DEVICE, "sc_autotune: stream failed");
+                break;
+            }
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p->ev[EV_Q0], p->ev[EV_Q1]) == hipSuccess) tmin = std::min(tmin, (double)ms);
+        }
+        if (st != SC_OK) break;
+        if (tmin < best_ms) {
+            best_ms = tmin;
+            best_l = l;
+        }
+        double spent = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        if (spent > budget_ms) break;
+    }
+    c->profiling = saved_prof;
+    p->launch = saved;
+    p->has_launch = saved_has;
+    if (st != SC_OK) return st;
+    c->tune[tune_key(p, prec)] = best_l;
+    if (best) *best = best_l;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_autotune_save(sc_ctx *c, const char *path)
+{
+    if (!c || !path) return fail(SC_E_INVAL, "sc_autotune_save: NULL argument");
+    std::ofstream f(path);
+    if (!f) return fail(SC_E_INVAL, "sc_autotune_save: cannot open %s", path);
+    f << "# prec log2_obs log2_k log2_nodes obs_per_lane waves_per_block chunk blocks_per_cu\n";
+    for (auto &kv : c->tune)
+        f << kv.first.prec << ' ' << kv.first.b_obs << ' ' << kv.first.b_k << ' ' << kv.first.b_nodes << ' '
+          << kv.second.obs_per_lane << ' ' << kv.second.waves_per_block << ' ' << kv.second.chunk << ' '
+          << kv.second.blocks_per_cu << '\n';
+    return f ? SC_OK : fail(SC_E_INVAL, "sc_autotune_save: write failed");
+}
+
+extern "C" sc_status sc_autotune_load(sc_ctx *c, const char *path)
+{
+    if (!c || !path) return fail(SC_E_INVAL, "sc_autotune_load: NULL argument");
+    std::ifstream f(path);
+    if (!f) return fail(SC_E_INVAL, "sc_autotune_load: cannot open %s", path);
+    std::string line;
+    std::map<TuneKey, sc_launch> m;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream is(line);
+        TuneKey k{};
+        sc_launch l{};
+        if (!(is >> k.prec >> k.b_obs >> k.b_k >> k.b_nodes >> l.obs_per_lane >> l.waves_per_block >> l.chunk >>
+              l.blocks_per_cu))
+            return fail(SC_E_INVAL, "sc_autotune_load: malformed line '%s'", line.c_str());
+        if (check_launch(l) != SC_OK) return fail(SC_E_INVAL, "sc_autotune_load: invalid launch in '%s'", line.c_str());
+        m[k] = l;
+    }
+    for (auto &kv : m) c->tune[kv.first] = kv.second;
+    return SC_OK;
+}

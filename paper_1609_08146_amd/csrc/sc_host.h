@@ -1,0 +1,168 @@
+// sc_host.h -- host-side objects shared by the C ABI (sc_api.cpp) and the
+// serving loop (sc_serve.cpp): device buffers, contexts, problems.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sc.h"
+#include "sc_internal.h"
+
+namespace sc {
+
+// Record a thread-local error message and return `st`.
+sc_status fail(sc_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define HIP_TRY(expr)                                                                                      \
+    do {                                                                                                   \
+        hipError_t e_ = (expr);                                                                            \
+        if (e_ != hipSuccess)                                                                              \
+            return ::sc::fail(SC_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+#define SC_TRY(expr)                \
+    do {                            \
+        sc_status s_ = (expr);      \
+        if (s_ != SC_OK) return s_; \
+    } while (0)
+
+// Allocation hook for tests: SC_DEBUG_FAIL_ALLOC=<n> makes the n-th device
+// allocation of the process report SC_E_NOMEM.
+bool debug_fail_this_alloc();
+
+// A device allocation that frees itself.  With a non-null `stream` it uses the
+// stream-ordered allocator (hipMallocAsync / hipFreeAsync on that stream), so
+// that freeing never waits for unrelated work on the device.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) {
+            if (stream) (void)hipFreeAsync(p, stream);
+            else (void)hipFree(p);
+        }
+        p = nullptr;
+        bytes = 0;
+    }
+    // capacity >= n bytes (contents are not preserved on growth)
+    sc_status reserve(size_t n, hipStream_t st = nullptr)
+    {
+        if (n <= bytes && p) return SC_OK;
+        release();
+        if (n == 0) n = 16;
+        if (debug_fail_this_alloc()) return fail(SC_E_NOMEM, "injected allocation failure (%zu bytes)", n);
+        hipError_t e = st ? hipMallocAsync(&p, n, st) : hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return fail(SC_E_NOMEM, "device allocation of %zu bytes failed: %s", n, hipGetErrorString(e));
+        }
+        bytes = n;
+        stream = st;
+        return SC_OK;
+    }
+    template <typename T>
+    T *as() const
+    {
+        return (T *)p;
+    }
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+struct TuneKey {
+    int prec, b_obs, b_k, b_nodes;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(prec, b_obs, b_k, b_nodes) < std::tie(o.prec, o.b_obs, o.b_k, o.b_nodes);
+    }
+};
+
+enum { EV_PREP0, EV_PREP1, EV_Q0, EV_Q1, EV_R1, EV_T0, EV_T1, EV_N };
+
+}  // namespace sc
+
+struct sc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int profiling = 0;
+    int n_cu = 256;
+    sc::DevBuf counter;   // persistent-launch work counter
+    sc::DevBuf jobs;      // QuadJob array for launches
+    std::vector<sc::QuadJob> host_jobs;
+    hipEvent_t upload_done = nullptr;
+    std::map<sc::TuneKey, sc_launch> tune;
+};
+
+struct sc_prob {
+    sc_ctx *ctx = nullptr;
+    hipStream_t alloc_stream = nullptr;   // stream-ordered allocations (serving loop)
+    // mirror
+    bool has_mirror = false;
+    double f = 0, a = 0;
+    int n_r = 0, n_phi = 0, n_surf = 0, n_rim = 0, n_tot = 0;
+    sc::DevBuf d_r, d_wr, d_c, d_s;          // 1-D rule (device copies)
+    sc::DevBuf pos64, pos32, nrm, wgt, tan;  // node records
+    // frequencies
+    std::vector<double> k;
+    sc::DevBuf d_k;
+    // tables
+    bool has_tab = false, tab32_ok = false, tab32n_ok = false;
+    sc::DevBuf tab64, tab32, tab32n;
+    // observation points
+    int n_obs = 0, n_obs_pad = 0;
+    sc::DevBuf obs64, obs32;
+    // result of the last evaluate
+    int res_prec = -1;
+    sc::DevBuf resE, resB;
+    sc::DevBuf partial;
+    // time transform
+    sc::DevBuf d_t, tw, timeE, timeB;
+    // launch override
+    bool has_launch = false;
+    sc_launch launch{};
+    // profiling
+    hipEvent_t ev[sc::EV_N] = {};
+    bool ev_prep = false, ev_quad = false, ev_time = false;
+    int64_t last_evals = 0, last_tiles = 0;
+};
+
+namespace sc {
+
+constexpr int OBS_PAD = 128;   // observation padding (64 lanes x up to 2 points per lane)
+
+// Launch shape for a problem and precision (override > tuned > default).
+sc_launch resolve_launch(const sc_prob *p, sc_precision prec);
+sc_status check_launch(const sc_launch &l);
+int mode_of(sc_precision prec);
+size_t real_size(sc_precision prec);
+// Tables of the precision, partial and result buffers; fills `job` (tile0 = 0, offset 0, all tiles).
+sc_status prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob &job);
+// Upload `jobs` (tile0 assigned here) and run one persistent quadrature launch on ctx's stream.
+sc_status run_quad(sc_ctx *c, std::vector<QuadJob> &jobs, sc_precision prec, const sc_launch &l, sc_prob *timed);
+// Device bytes a problem of this shape holds after an evaluate (+ time transform with n_t samples).
+size_t footprint_bytes(int n_r, int n_phi, int n_k, int n_obs, int n_t, sc_precision prec, int chunk);
+
+}  // namespace sc

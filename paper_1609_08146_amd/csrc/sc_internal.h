@@ -1,0 +1,61 @@
+// sc_internal.h -- host-side declarations shared by the C ABI (sc_api.cpp) and
+// the kernel translation unit (sc_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sc {
+
+// One problem instance as seen by the quadrature kernel.  All pointers are
+// device pointers.  Tiles of a job are numbered
+//   local = (k * n_chunks + chunk) * obs_blocks + obs_block
+// so that waves running side by side share (k, chunk) table data.
+struct QuadJob {
+    const void *tab;      // [n_k][n_tot][8] real (float or double)
+    const void *pos;      // [n_tot][4] real
+    const void *obs;      // [n_obs_pad][4] real
+    const double *k;      // [n_k]
+    void *partial;        // [n_chunks][n_k][12][n_obs_pad] real
+    int n_tot;            // surface + rim nodes
+    int n_obs_pad;        // observation points, padded to the obs block
+    int n_k;
+    int chunk;            // nodes per split-K chunk
+    int n_chunks;
+    int obs_blocks;       // n_obs_pad / (64 * obs_per_lane)
+    int64_t tile0;        // first global tile of this job in the launch
+    int64_t tile_offset;  // first job-local tile covered (a launch may cover a sub-range)
+    int64_t n_tiles;      // tiles covered by this launch
+};
+
+enum QuadMode { MODE_FP64 = 0, MODE_SPLIT = 1, MODE_NAIVE = 2 };
+
+// ---- launchers (all asynchronous on `stream`; return hipError_t)
+hipError_t launch_node_tables(hipStream_t st, int n_r, int n_phi, double f, const double *r,
+                              const double *wr, const double *cphi, const double *sphi, double dphi,
+                              double *pos64, float *pos32, double *nrm, double *wgt, double *tan);
+hipError_t launch_obs_prep(hipStream_t st, const double *xyz, int n_obs, int n_obs_pad, double *obs64,
+                           float *obs32);
+hipError_t launch_tables_from_fields(hipStream_t st, int n_k, int n_surf, int n_tot, const double *k,
+                                     const double *pos64, const double *nrm, const double *wgt,
+                                     const double *tan, const double *E, const double *B, double *tab64);
+hipError_t launch_tables_gaussian(hipStream_t st, int n_k, int n_surf, int n_tot, const double *k,
+                                  const double *pos64, const double *nrm, const double *wgt,
+                                  const double *tan, double w0, double pol, const double *spectrum,
+                                  int consistent, double *tab64);
+hipError_t launch_tables_cast(hipStream_t st, int n_k, int n_tot, const double *k, const double *pos64,
+                              const double *tab64, float *tab32, int naive);
+hipError_t launch_quad(hipStream_t st, int mode, int obs_per_lane, int waves_per_block, int grid,
+                       const QuadJob *jobs, int n_jobs, int64_t n_tiles, unsigned int *counter);
+hipError_t launch_reduce(hipStream_t st, int mode, const void *partial, int n_chunks, int n_k, int n_obs,
+                         int n_obs_pad, const double *k, void *E, void *B);
+hipError_t launch_twiddles(hipStream_t st, int n_k, const double *k, int n_t, const double *t, double dk,
+                           double *tw);
+hipError_t launch_time(hipStream_t st, int is_f64, int n_k, int n_t, int64_t n_x, const double *tw,
+                       const void *F, void *Ft);
+hipError_t launch_fill_u32(hipStream_t st, unsigned int *p, unsigned int v, int n);
+
+// Occupancy helper: max resident workgroups per CU for a quadrature variant.
+int quad_max_blocks_per_cu(int mode, int obs_per_lane, int waves_per_block);
+
+}  // namespace sc

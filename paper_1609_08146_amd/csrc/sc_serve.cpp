@@ -1,0 +1,556 @@
+// sc_serve.cpp -- continuous-batching serving loop for field solves.
+//
+// Requests (mirror + beam + spectrum + observation points) arrive from any
+// host thread.  A worker thread admits them in arrival order while their HBM
+// footprint fits the budget and the running count allows, builds their
+// mirror / incident tables on a preparation stream (tables stay resident for
+// the request's lifetime), and schedules the quadrature tiles of ALL running
+// requests together: each scheduling quantum is one persistent launch whose
+// tile list holds a share of every running request's remaining tiles, sized to
+// about `quantum_ms` of work.  A request that arrives while others are on the
+// GPU joins the next quantum.  Two quanta are kept in flight so the device
+// never idles while the next one is built.  When a request's last tile has
+// been scheduled, its split-K reduction (and time transform) and the copy of
+// its results to pinned host memory are queued behind that quantum.
+//
+// Every (chunk, k, observation block) partial of a request is computed by
+// exactly one tile with the same kernel and chunking as sc_evaluate uses, so
+// a request's result does not depend on what it was batched with.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "sc_host.h"
+
+using namespace sc;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+enum ReqState { R_QUEUED, R_RUNNING, R_FINISHING, R_DONE, R_FAILED, R_CANCELLED };
+
+struct Req {
+    uint64_t ticket = 0;
+    double f = 0, a = 0, w0 = 0, pol = 0, dk = 0;
+    int n_r = 0, n_phi = 0, consistent = 0, n_t = 0, n_obs = 0;
+    sc_precision prec = SC_FP32_SPLIT;
+    std::vector<double> k, spec, obs, t;
+    size_t bytes = 0;
+    ReqState state = R_QUEUED;
+    sc_status status = SC_OK;
+    std::string err;
+    sc_prob *prob = nullptr;
+    QuadJob job{};
+    int64_t cursor = 0;
+    hipEvent_t ready_ev = nullptr;
+    hipEvent_t done_ev = nullptr;
+    void *hE = nullptr, *hB = nullptr, *hEt = nullptr, *hBt = nullptr;
+    size_t res_bytes = 0, time_bytes = 0;
+    Clock::time_point t_submit, t_admit, t_done;
+    int64_t evals = 0;
+};
+
+struct Quantum {
+    int slot;
+    int64_t evals;
+    Clock::time_point t_launch;
+};
+
+double ms_between(Clock::time_point a, Clock::time_point b)
+{
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+}  // namespace
+
+struct sc_server {
+    sc_ctx *ctx = nullptr;
+    sc_ctx *prep = nullptr;
+    size_t budget = 0;
+    int max_running = 1;
+    double quantum_ms = 20.0;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    std::deque<Req *> queue;
+    std::vector<Req *> active;
+    std::map<uint64_t, Req *> all;
+    sc_server_stats stats{};
+    static constexpr int RING = 3;
+    DevBuf jobbuf[RING];
+    QuadJob *hjobs[RING] = {};
+    size_t hjobs_cap[RING] = {};
+    hipEvent_t slot_ev[RING] = {};
+    bool slot_busy[RING] = {};
+    std::deque<Quantum> inflight;
+    double evals_per_ms = 1.0e8;   // running throughput estimate used to size quanta
+    int next_slot = 0;
+    std::string worker_error;
+};
+
+static void free_req_host(Req *r)
+{
+    for (void **p : {&r->hE, &r->hB, &r->hEt, &r->hBt})
+        if (*p) {
+            (void)hipHostFree(*p);
+            *p = nullptr;
+        }
+    if (r->ready_ev) (void)hipEventDestroy(r->ready_ev);
+    if (r->done_ev) (void)hipEventDestroy(r->done_ev);
+    r->ready_ev = r->done_ev = nullptr;
+}
+
+static void release_prob(Req *r)
+{
+    if (r->prob) {
+        (void)sc_prob_destroy(r->prob);
+        r->prob = nullptr;
+    }
+}
+
+static int server_opl(sc_precision prec) { return prec == SC_FP64 ? 1 : 2; }
+
+// Build the request's device state on the preparation stream.
+static sc_status setup_request(sc_server *s, Req *r)
+{
+    SC_TRY(sc_prob_create(s->prep, &r->prob));
+    sc_prob *p = r->prob;
+    p->alloc_stream = s->prep->stream;
+    SC_TRY(sc_set_mirror(p, r->f, r->a, r->n_r, r->n_phi));
+    SC_TRY(sc_set_frequencies(p, r->k.data(), (int)r->k.size()));
+    SC_TRY(sc_set_incident_gaussian(p, r->w0, r->pol, r->spec.empty() ? nullptr : r->spec.data(), r->consistent));
+    SC_TRY(sc_set_observation(p, r->obs.data(), r->n_obs, 0));
+    sc_launch l = resolve_launch(p, r->prec);
+    l.obs_per_lane = server_opl(r->prec);
+    SC_TRY(prepare(p, r->prec, l, r->job));
+    const int n_k = (int)r->k.size();
+    const size_t rs = real_size(r->prec);
+    if (r->n_t > 0) {
+        SC_TRY(p->d_t.reserve(sizeof(double) * r->n_t, p->alloc_stream));
+        SC_TRY(p->tw.reserve(sizeof(double) * 2 * (size_t)r->n_t * n_k, p->alloc_stream));
+        SC_TRY(p->timeE.reserve(rs * 6 * (size_t)r->n_t * r->n_obs, p->alloc_stream));
+        SC_TRY(p->timeB.reserve(rs * 6 * (size_t)r->n_t * r->n_obs, p->alloc_stream));
+        HIP_TRY(hipMemcpyAsync(p->d_t.p, r->t.data(), sizeof(double) * r->n_t, hipMemcpyHostToDevice,
+                               s->prep->stream));
+    }
+    r->res_bytes = rs * 6 * (size_t)n_k * r->n_obs;
+    r->time_bytes = rs * 6 * (size_t)r->n_t * r->n_obs;
+    HIP_TRY(hipHostMalloc(&r->hE, r->res_bytes, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&r->hB, r->res_bytes, hipHostMallocDefault));
+    if (r->n_t > 0) {
+        HIP_TRY(hipHostMalloc(&r->hEt, r->time_bytes, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc(&r->hBt, r->time_bytes, hipHostMallocDefault));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&r->ready_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(r->ready_ev, s->prep->stream));
+    // the time samples were copied from pageable memory
+    HIP_TRY(hipStreamSynchronize(s->prep->stream));
+    r->evals = (int64_t)r->n_obs * n_k * p->n_surf;
+    return SC_OK;
+}
+
+// After the last tile of `r` is queued: reduction, time transform, copies to pinned host memory.
+static sc_status finish_request(sc_server *s, Req *r)
+{
+    hipStream_t st = s->ctx->stream;
+    sc_prob *p = r->prob;
+    const int n_k = (int)r->k.size();
+    HIP_TRY(launch_reduce(st, mode_of(r->prec), p->partial.p, r->job.n_chunks, n_k, r->n_obs, p->n_obs_pad,
+                          p->d_k.as<double>(), p->resE.p, p->resB.p));
+    HIP_TRY(hipMemcpyAsync(r->hE, p->resE.p, r->res_bytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(r->hB, p->resB.p, r->res_bytes, hipMemcpyDeviceToHost, st));
+    if (r->n_t > 0) {
+        const int f64 = r->prec == SC_FP64;
+        const int64_t n_x = (int64_t)r->n_obs * 3;
+        HIP_TRY(launch_twiddles(st, n_k, p->d_k.as<double>(), r->n_t, p->d_t.as<double>(), r->dk, p->tw.as<double>()));
+        HIP_TRY(launch_time(st, f64, n_k, r->n_t, n_x, p->tw.as<double>(), p->resE.p, p->timeE.p));
+        HIP_TRY(launch_time(st, f64, n_k, r->n_t, n_x, p->tw.as<double>(), p->resB.p, p->timeB.p));
+        HIP_TRY(hipMemcpyAsync(r->hEt, p->timeE.p, r->time_bytes, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(r->hBt, p->timeB.p, r->time_bytes, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipEventRecord(r->done_ev, st));
+    return SC_OK;
+}
+
+// Launch one scheduling quantum over the running requests of one precision.
+// Called with the server lock held.
+static sc_status launch_quantum(sc_server *s)
+{
+    // the oldest running request with tiles left decides the precision of this quantum
+    sc_precision prec = SC_FP32_SPLIT;
+    bool found = false;
+    for (Req *r : s->active)
+        if (r->state == R_RUNNING && r->cursor < r->job.n_tiles) {
+            prec = r->prec;
+            found = true;
+            break;
+        }
+    if (!found) return SC_OK;
+    std::vector<Req *> group;
+    for (Req *r : s->active)
+        if (r->state == R_RUNNING && r->cursor < r->job.n_tiles && r->prec == prec) group.push_back(r);
+    const int opl = server_opl(prec);
+    const double budget_evals = std::max(1.0, s->quantum_ms * s->evals_per_ms);
+    const double share = budget_evals / (double)group.size();
+    std::vector<QuadJob> jobs;
+    std::vector<Req *> finals;
+    int64_t total = 0, evals = 0;
+    for (Req *r : group) {
+        const double per_tile = 64.0 * opl * std::min<double>(r->job.chunk, r->job.n_tot);
+        int64_t n = (int64_t)std::ceil(share / per_tile);
+        n = std::max<int64_t>(1, std::min<int64_t>(n, r->job.n_tiles - r->cursor));
+        QuadJob j = r->job;
+        j.tile0 = total;
+        j.tile_offset = r->cursor;
+        j.n_tiles = n;
+        jobs.push_back(j);
+        total += n;
+        evals += (int64_t)(n * per_tile);
+        r->cursor += n;
+        if (r->cursor == r->job.n_tiles) finals.push_back(r);
+    }
+    // a free ring slot (at most two quanta are in flight, the ring has three)
+    int slot = -1;
+    for (int i = 0; i < sc_server::RING; ++i) {
+        int c = (s->next_slot + i) % sc_server::RING;
+        if (!s->slot_busy[c]) {
+            slot = c;
+            break;
+        }
+    }
+    if (slot < 0) return fail(SC_E_DEVICE, "serving: no free launch slot");
+    s->next_slot = (slot + 1) % sc_server::RING;
+    hipStream_t st = s->ctx->stream;
+    if (s->hjobs_cap[slot] < jobs.size()) {
+        if (s->hjobs[slot]) (void)hipHostFree(s->hjobs[slot]);
+        s->hjobs[slot] = nullptr;
+        s->hjobs_cap[slot] = 0;
+        size_t cap = std::max<size_t>(64, jobs.size() * 2);
+        HIP_TRY(hipHostMalloc((void **)&s->hjobs[slot], sizeof(QuadJob) * cap, hipHostMallocDefault));
+        s->hjobs_cap[slot] = cap;
+    }
+    SC_TRY(s->jobbuf[slot].reserve(sizeof(QuadJob) * s->hjobs_cap[slot]));
+    memcpy(s->hjobs[slot], jobs.data(), sizeof(QuadJob) * jobs.size());
+    for (Req *r : group) HIP_TRY(hipStreamWaitEvent(st, r->ready_ev, 0));
+    HIP_TRY(hipMemcpyAsync(s->jobbuf[slot].p, s->hjobs[slot], sizeof(QuadJob) * jobs.size(), hipMemcpyHostToDevice,
+                           st));
+    HIP_TRY(launch_fill_u32(st, s->ctx->counter.as<unsigned int>(), 0u, 1));
+    const int mode = mode_of(prec);
+    const int wpb = 4;
+    const int occ = quad_max_blocks_per_cu(mode, opl, wpb);
+    int64_t grid = std::min<int64_t>((int64_t)occ * s->ctx->n_cu, (total + wpb - 1) / wpb);
+    grid = std::max<int64_t>(grid, 1);
+    HIP_TRY(launch_quad(st, mode, opl, wpb, (int)grid, s->jobbuf[slot].as<QuadJob>(), (int)jobs.size(), total,
+                        s->ctx->counter.as<unsigned int>()));
+    HIP_TRY(hipEventRecord(s->slot_ev[slot], st));
+    s->slot_busy[slot] = true;
+    s->inflight.push_back({slot, evals, Clock::now()});
+    s->stats.launches++;
+    for (Req *r : finals) {
+        sc_status fs = finish_request(s, r);
+        if (fs != SC_OK) return fs;
+        r->state = R_FINISHING;
+    }
+    return SC_OK;
+}
+
+static void complete_request(sc_server *s, Req *r, ReqState state, sc_status st, const std::string &err)
+{
+    r->state = state;
+    r->status = st;
+    r->err = err;
+    r->t_done = Clock::now();
+    if (s->stats.running > 0) s->stats.running--;
+    if (state == R_DONE) {
+        s->stats.completed++;
+        s->stats.evals_done += r->evals;
+    }
+    s->stats.hbm_in_use -= std::min(s->stats.hbm_in_use, r->bytes);
+    release_prob(r);
+    s->cv_done.notify_all();
+}
+
+static void worker_main(sc_server *s)
+{
+    (void)hipSetDevice(s->ctx->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        // 1. admission, in arrival order, while memory and running slots allow
+        std::vector<Req *> admitted;
+        while (!s->queue.empty() && (int)(s->active.size() + admitted.size()) < s->max_running) {
+            Req *r = s->queue.front();
+            if (s->stats.hbm_in_use + r->bytes > s->budget) break;
+            s->queue.pop_front();
+            r->state = R_RUNNING;
+            r->t_admit = Clock::now();
+            s->stats.hbm_in_use += r->bytes;
+            s->stats.admitted++;
+            s->stats.queued--;
+            s->stats.running++;
+            admitted.push_back(r);
+        }
+        if (!admitted.empty()) {
+            lk.unlock();
+            std::vector<std::pair<sc_status, std::string>> res;
+            for (Req *r : admitted) {
+                sc_status st = setup_request(s, r);
+                res.push_back({st, st == SC_OK ? std::string() : std::string(sc_last_error())});
+            }
+            lk.lock();
+            for (size_t i = 0; i < admitted.size(); ++i) {
+                if (res[i].first == SC_OK) s->active.push_back(admitted[i]);
+                else complete_request(s, admitted[i], R_FAILED, res[i].first, res[i].second);
+            }
+        }
+        // 2. requests whose results reached the host
+        for (size_t i = 0; i < s->active.size();) {
+            Req *r = s->active[i];
+            if (r->state == R_FINISHING && hipEventQuery(r->done_ev) == hipSuccess) {
+                complete_request(s, r, R_DONE, SC_OK, "");
+                s->active.erase(s->active.begin() + i);
+            } else {
+                ++i;
+            }
+        }
+        // 3. finished quanta update the throughput estimate
+        while (!s->inflight.empty() && hipEventQuery(s->slot_ev[s->inflight.front().slot]) == hipSuccess) {
+            const Quantum &q = s->inflight.front();
+            const double ms = ms_between(q.t_launch, Clock::now());
+            if (ms > 0.5 && s->inflight.size() == 1) s->evals_per_ms = 0.7 * s->evals_per_ms + 0.3 * (q.evals / ms);
+            s->slot_busy[q.slot] = false;
+            s->inflight.pop_front();
+        }
+        // 4. keep two quanta in flight
+        bool more = false;
+        for (Req *r : s->active)
+            if (r->state == R_RUNNING && r->cursor < r->job.n_tiles) more = true;
+        if (more && s->inflight.size() < 2) {
+            sc_status st = launch_quantum(s);
+            if (st != SC_OK) {
+                // a device error poisons every running request
+                std::string err = sc_last_error();
+                for (Req *r : s->active) complete_request(s, r, R_FAILED, st, err);
+                s->active.clear();
+                s->worker_error = err;
+            }
+            continue;
+        }
+        if (s->stop && s->queue.empty() && s->active.empty() && s->inflight.empty()) break;
+        // 5. wait for a submission, or poll the device
+        if (s->active.empty() && s->inflight.empty() && (s->queue.empty() || !s->stop))
+            s->cv_work.wait_for(lk, std::chrono::milliseconds(s->queue.empty() ? 50 : 1));
+        else
+            s->cv_work.wait_for(lk, std::chrono::microseconds(200));
+    }
+}
+
+// ======================================================================= ABI
+
+extern "C" sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_running, double quantum_ms,
+                                      sc_server **out)
+{
+    if (!ctx || !out) return fail(SC_E_INVAL, "sc_server_create: NULL argument");
+    if (hbm_budget == 0 || max_running < 1 || !(quantum_ms > 0.0))
+        return fail(SC_E_INVAL, "sc_server_create: need hbm_budget > 0, max_running >= 1, quantum_ms > 0");
+    *out = nullptr;
+    DeviceGuard g(ctx->device);
+    sc_server *s = new (std::nothrow) sc_server();
+    if (!s) return fail(SC_E_NOMEM, "sc_server_create: out of host memory");
+    s->ctx = ctx;
+    s->budget = hbm_budget;
+    s->max_running = max_running;
+    s->quantum_ms = quantum_ms;
+    s->stats.hbm_budget = hbm_budget;
+    sc_status st = sc_ctx_create(ctx->device, nullptr, &s->prep);
+    if (st != SC_OK) {
+        delete s;
+        return st;
+    }
+    s->prep->tune = ctx->tune;
+    for (int i = 0; i < sc_server::RING; ++i)
+        if (hipEventCreateWithFlags(&s->slot_ev[i], hipEventDisableTiming) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(s->slot_ev[j]);
+            (void)sc_ctx_destroy(s->prep);
+            delete s;
+            return fail(SC_E_DEVICE, "sc_server_create: hipEventCreate failed");
+        }
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return SC_OK;
+}
+
+static sc_status validate_request(const sc_request *q)
+{
+    if (!q) return fail(SC_E_INVAL, "sc_server_submit: request is NULL");
+    if (!(q->f > 0.0) || !(q->r_max > 0.0)) return fail(SC_E_INVAL, "request: f and r_max must be > 0");
+    if (q->n_r < 1 || q->n_phi < 1 || (int64_t)(q->n_r + 1) * q->n_phi >= (1LL << 31))
+        return fail(SC_E_INVAL, "request: bad quadrature size");
+    if (q->n_k < 1 || !q->k) return fail(SC_E_INVAL, "request: need n_k >= 1 wavenumbers");
+    for (int i = 0; i < q->n_k; ++i)
+        if (!(q->k[i] > 0.0) || !std::isfinite(q->k[i])) return fail(SC_E_INVAL, "request: k[%d] invalid", i);
+    if (!(q->w0 > 0.0)) return fail(SC_E_INVAL, "request: w0 must be > 0");
+    if (q->n_obs < 1 || !q->obs) return fail(SC_E_INVAL, "request: need n_obs >= 1 points");
+    if (q->prec != SC_FP64 && q->prec != SC_FP32_SPLIT && q->prec != SC_FP32)
+        return fail(SC_E_INVAL, "request: unknown precision");
+    if (q->n_t < 0 || (q->n_t > 0 && !q->t)) return fail(SC_E_INVAL, "request: bad time samples");
+    return SC_OK;
+}
+
+extern "C" sc_status sc_server_submit(sc_server *s, const sc_request *q, uint64_t *ticket)
+{
+    if (!s || !ticket) return fail(SC_E_INVAL, "sc_server_submit: NULL argument");
+    SC_TRY(validate_request(q));
+    Req *r = new (std::nothrow) Req();
+    if (!r) return fail(SC_E_NOMEM, "sc_server_submit: out of host memory");
+    r->f = q->f;
+    r->a = q->r_max;
+    r->n_r = q->n_r;
+    r->n_phi = q->n_phi;
+    r->k.assign(q->k, q->k + q->n_k);
+    if (q->spectrum) r->spec.assign(q->spectrum, q->spectrum + 2 * q->n_k);
+    r->w0 = q->w0;
+    r->pol = q->pol_angle;
+    r->consistent = q->consistent;
+    r->n_obs = q->n_obs;
+    r->obs.assign(q->obs, q->obs + 3 * (size_t)q->n_obs);
+    r->prec = q->prec;
+    r->n_t = q->n_t;
+    if (q->n_t > 0) r->t.assign(q->t, q->t + q->n_t);
+    r->dk = q->dk;
+    {
+        // the chunk the request will be evaluated with (same rule as sc_evaluate)
+        sc_prob probe;
+        probe.ctx = s->ctx;
+        probe.n_obs = q->n_obs;
+        probe.k = r->k;
+        probe.n_tot = (q->n_r + 1) * q->n_phi;
+        const sc_launch l = resolve_launch(&probe, q->prec);
+        r->bytes = footprint_bytes(q->n_r, q->n_phi, q->n_k, q->n_obs, q->n_t, q->prec, l.chunk);
+    }
+    r->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+        delete r;
+        return fail(SC_E_STATE, "sc_server_submit: server is shutting down");
+    }
+    if (r->bytes > s->budget) {
+        s->stats.rejected++;
+        size_t b = r->bytes;
+        delete r;
+        return fail(SC_E_REJECTED, "request needs %zu device bytes, budget is %zu", b, s->budget);
+    }
+    r->ticket = s->next_ticket++;
+    s->all[r->ticket] = r;
+    s->queue.push_back(r);
+    s->stats.submitted++;
+    s->stats.queued++;
+    *ticket = r->ticket;
+    s->cv_work.notify_one();
+    return SC_OK;
+}
+
+extern "C" sc_status sc_server_wait(sc_server *s, uint64_t ticket, double timeout_ms, void *E, void *B, void *Et,
+                                    void *Bt, sc_request_stats *stats)
+{
+    if (!s) return fail(SC_E_INVAL, "sc_server_wait: server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(SC_E_INVAL, "sc_server_wait: unknown ticket %llu", (unsigned long long)ticket);
+    Req *r = it->second;
+    auto ready = [r] { return r->state == R_DONE || r->state == R_FAILED || r->state == R_CANCELLED; };
+    if (timeout_ms < 0) s->cv_done.wait(lk, ready);
+    else if (!s->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), ready))
+        return fail(SC_E_TIMEOUT, "sc_server_wait: ticket %llu not ready", (unsigned long long)ticket);
+    sc_status st = SC_OK;
+    if (r->state == R_DONE) {
+        if (E) memcpy(E, r->hE, r->res_bytes);
+        if (B) memcpy(B, r->hB, r->res_bytes);
+        if (Et && r->hEt) memcpy(Et, r->hEt, r->time_bytes);
+        if (Bt && r->hBt) memcpy(Bt, r->hBt, r->time_bytes);
+        if (stats) {
+            stats->queue_ms = ms_between(r->t_submit, r->t_admit);
+            stats->run_ms = ms_between(r->t_admit, r->t_done);
+            stats->total_ms = ms_between(r->t_submit, r->t_done);
+            stats->evals = r->evals;
+            stats->device_bytes = r->bytes;
+        }
+    } else if (r->state == R_CANCELLED) {
+        st = fail(SC_E_CANCELLED, "ticket %llu was cancelled", (unsigned long long)ticket);
+    } else {
+        st = fail(r->status, "request failed: %s", r->err.c_str());
+    }
+    s->all.erase(it);
+    free_req_host(r);
+    delete r;
+    return st;
+}
+
+extern "C" sc_status sc_server_cancel(sc_server *s, uint64_t ticket)
+{
+    if (!s) return fail(SC_E_INVAL, "sc_server_cancel: server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(SC_E_INVAL, "sc_server_cancel: unknown ticket");
+    Req *r = it->second;
+    if (r->state != R_QUEUED) return fail(SC_E_STATE, "sc_server_cancel: request already admitted");
+    s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), r), s->queue.end());
+    r->state = R_CANCELLED;
+    s->stats.queued--;
+    s->stats.cancelled++;
+    s->cv_done.notify_all();
+    return SC_OK;
+}
+
+extern "C" sc_status sc_server_get_stats(sc_server *s, sc_server_stats *out)
+{
+    if (!s || !out) return fail(SC_E_INVAL, "sc_server_get_stats: NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_server_destroy(sc_server *s)
+{
+    if (!s) return SC_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (Req *r : s->queue) {
+            r->state = R_CANCELLED;
+            s->stats.cancelled++;
+        }
+        s->queue.clear();
+        s->stats.queued = 0;
+        s->cv_done.notify_all();
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    DeviceGuard g(s->ctx->device);
+    (void)hipStreamSynchronize(s->ctx->stream);
+    for (auto &kv : s->all) {
+        release_prob(kv.second);
+        free_req_host(kv.second);
+        delete kv.second;
+    }
+    s->all.clear();
+    for (int i = 0; i < sc_server::RING; ++i) {
+        if (s->slot_ev[i]) (void)hipEventDestroy(s->slot_ev[i]);
+        if (s->hjobs[i]) (void)hipHostFree(s->hjobs[i]);
+        s->jobbuf[i].release();
+    }
+    (void)sc_ctx_destroy(s->prep);
+    delete s;
+    return SC_OK;
+}

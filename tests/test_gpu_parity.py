@@ -1,0 +1,220 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (relative L2 per field, over all observation points, frequencies
+and components, E and B separately):
+  * SC_FP64        <= 1e-12
+  * SC_FP32_SPLIT  <= 1e-5
+Sizes are chosen so the oracle finishes in seconds while the GPU path still
+spans several node chunks, several observation blocks and ragged tails.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+K = 2 * math.pi
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_08146_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def make_problem(ctx, f, a, n_r, n_phi, k, obs, launch=None):
+    from paper_1609_08146_amd import Problem
+    p = Problem(ctx)
+    p.set_mirror(f, a, n_r, n_phi)
+    p.set_frequencies(k)
+    p.set_observation(obs)
+    if launch:
+        p.set_launch(**launch)
+    return p
+
+
+def test_nodes_match_oracle_bitwise(ctx, orc):
+    for (f, a, nr, nphi) in [(20.0, 40.0, 200, 200), (0.1, 0.075, 37, 24), (0.05, 0.15, 801, 16)]:
+        p = make_problem(ctx, f, a, nr, nphi, [K], np.zeros((1, 3)))
+        xyz, nrm, w = p.get_nodes()
+        m = orc.mirror(f, a, nr, nphi)
+        assert np.array_equal(xyz, m.pos), np.abs(xyz - m.pos).max()
+        assert np.array_equal(nrm, m.nrm)
+        assert np.array_equal(w, m.wgt)
+        p.close()
+
+
+@pytest.mark.parametrize("launch", [dict(chunk=256), dict(chunk=4096)])
+def test_fp64_random_tables(ctx, orc, launch):
+    # arbitrary tables exercise the quadrature as a linear map of E_inc, B_inc
+    f, a, nr, nphi = 20.0, 40.0, 37, 24
+    ks = np.array([K, 1.3 * K, 0.7 * K])
+    obs = workloads.random_points(200, 2.5, seed=5)
+    m = orc.mirror(f, a, nr, nphi)
+    Ei, Bi = workloads.random_incident_tables(len(ks), m.n_tot, seed=9)
+    Eo, Bo = orc.reflected_field(m, ks, Ei, Bi, obs)
+    p = make_problem(ctx, f, a, nr, nphi, ks, obs, launch)
+    p.set_incident(Ei, Bi)
+    E, B = p.evaluate("fp64")
+    assert rel_l2(E, Eo) < 1e-12
+    assert rel_l2(B, Bo) < 1e-12
+    p.close()
+
+
+def test_fp64_gaussian_mono(ctx, orc):
+    w = workloads.mono()
+    sub = w.subset(obs_idx=np.arange(0, 1024, 5))   # 205 points: ragged vs the 128-point blocks
+    Eo, Bo = orc.solve(sub)
+    from paper_1609_08146_amd import problem_from_workload
+    p = problem_from_workload(ctx, sub)
+    p.set_launch(chunk=2048)                         # 40200 nodes -> 20 chunks, ragged last chunk
+    E, B = p.evaluate("fp64")
+    assert rel_l2(E, Eo) < 1e-12
+    assert rel_l2(B, Bo) < 1e-12
+    p.close()
+
+
+def test_fp64_and_split_broadband_subset(ctx, orc):
+    w = workloads.broadband(n_k=128, n_nodes=120)
+    sub = w.subset(obs_idx=np.arange(0, w.n_obs, 29), k_idx=np.arange(0, 128, 21))
+    Eo, Bo = orc.solve(sub)
+    from paper_1609_08146_amd import problem_from_workload
+    p = problem_from_workload(ctx, sub)
+    E, B = p.evaluate("fp64")
+    assert rel_l2(E, Eo) < 1e-12
+    assert rel_l2(B, Bo) < 1e-12
+    E, B = p.evaluate("fp32_split")
+    assert E.dtype == np.complex64
+    assert rel_l2(E, Eo) < 1e-5
+    assert rel_l2(B, Bo) < 1e-5
+    p.close()
+
+
+def test_fp32_split_stress_geometry(ctx, orc):
+    # deep dish, kR up to 1.6e6 rad: the split form keeps FP32 accuracy, the naive form does not
+    w = workloads.stress(n_k=64, n_nodes=200)
+    sub = w.subset(obs_idx=np.arange(0, w.n_obs, 1023), k_idx=[0, 31, 63])
+    Eo, Bo = orc.solve(sub)
+    from paper_1609_08146_amd import problem_from_workload
+    p = problem_from_workload(ctx, sub)
+    E, B = p.evaluate("fp32_split")
+    err_split = max(rel_l2(E, Eo), rel_l2(B, Bo))
+    E, B = p.evaluate("fp32")
+    err_naive = max(rel_l2(E, Eo), rel_l2(B, Bo))
+    E, B = p.evaluate("fp64")
+    err_64 = max(rel_l2(E, Eo), rel_l2(B, Bo))
+    print(f"stress: fp64 {err_64:.2e}  fp32_split {err_split:.2e}  fp32 naive {err_naive:.2e}")
+    assert err_64 < 1e-12
+    assert err_split < 1e-5
+    assert err_naive > 100 * err_split
+    p.close()
+
+
+def test_time_transform(ctx, orc):
+    w = workloads.broadband(n_k=32, n_nodes=60)
+    sub = w.subset(obs_idx=np.arange(0, w.n_obs, 97))
+    Eo, Bo = orc.solve(sub)
+    from paper_1609_08146_amd import problem_from_workload
+    p = problem_from_workload(ctx, sub)
+    t = w.t[::5]
+    for prec, tol in (("fp64", 1e-12), ("fp32_split", 1e-5)):
+        E, B = p.evaluate(prec)
+        Et, Bt = p.to_time(w.dk, t)
+        Eto = orc.time_transform(sub.k, w.dk, t, Eo)
+        Bto = orc.time_transform(sub.k, w.dk, t, Bo)
+        assert rel_l2(Et, Eto) < tol, prec
+        assert rel_l2(Bt, Bto) < tol, prec
+        # and the transform of the GPU's own spectrum is the transform to rounding
+        Etg = orc.time_transform(sub.k, w.dk, t, E.astype(np.complex128))
+        assert rel_l2(Et, Etg) < (1e-14 if prec == "fp64" else 1e-6)
+    p.close()
+
+
+def test_launch_shape_does_not_change_bits(ctx):
+    w = workloads.broadband(n_k=4, n_nodes=64)
+    from paper_1609_08146_amd import problem_from_workload
+    p = problem_from_workload(ctx, w)
+    ref = None
+    for opl in (1, 2):
+        for wpb in (1, 2, 4):
+            for bpc in (0, 1):
+                p.set_launch(obs_per_lane=opl, waves_per_block=wpb, chunk=1024, blocks_per_cu=bpc)
+                for prec in ("fp32_split", "fp64"):
+                    E, B = p.evaluate(prec)
+                    key = prec
+                    if ref is None:
+                        ref = {}
+                    if key not in ref:
+                        ref[key] = (E, B)
+                    else:
+                        assert np.array_equal(E, ref[key][0]) and np.array_equal(B, ref[key][1]), (opl, wpb, bpc)
+    p.close()
+
+
+def test_batch_equals_alone_bitwise(ctx):
+    from paper_1609_08146_amd import problem_from_workload
+    ws = workloads.sweep(5)
+    ws = [w.with_nodes(min(w.n_r, 80), min(w.n_phi, 48)).subset(k_idx=np.arange(min(w.n_k, 3))) for w in ws]
+    probs = [problem_from_workload(ctx, w) for w in ws]
+    alone = [p.evaluate("fp32_split") for p in probs]
+    ctx.evaluate_batch(probs, "fp32_split")
+    for p, (E, B) in zip(probs, alone):
+        Eb, Bb = p.result()
+        assert np.array_equal(E, Eb) and np.array_equal(B, Bb)
+    for p in probs:
+        p.close()
+
+
+def test_error_paths(ctx):
+    from paper_1609_08146_amd import Problem, ScError
+    from paper_1609_08146_amd._abi import SC_E_INVAL, SC_E_STATE
+    p = Problem(ctx)
+    with pytest.raises(ScError) as e:
+        p.evaluate("fp64")
+    assert e.value.status == SC_E_STATE
+    with pytest.raises(ScError) as e:
+        p.set_mirror(-1.0, 1.0, 10, 10)
+    assert e.value.status == SC_E_INVAL
+    with pytest.raises(ScError) as e:
+        p.set_frequencies([1.0, -2.0])
+    assert e.value.status == SC_E_INVAL
+    p.set_mirror(1.0, 1.0, 8, 8)
+    with pytest.raises(ScError) as e:
+        p.set_incident_gaussian(1.0)          # no frequencies yet
+    assert e.value.status == SC_E_STATE
+    with pytest.raises(ScError) as e:
+        p.set_launch(obs_per_lane=3)
+    assert e.value.status == SC_E_INVAL
+    p.close()
+
+
+def test_full_size_broadband_sampled(ctx, orc):
+    """Bench configuration (400x400 nodes, 4160 points) on two frequencies; sampled outputs vs the oracle."""
+    w = workloads.broadband()
+    kidx = [0, 77]
+    sub = w.subset(k_idx=kidx)
+    from paper_1609_08146_amd import problem_from_workload
+    p = problem_from_workload(ctx, sub)
+    E, B = p.evaluate("fp32_split")
+    rng = np.random.default_rng(1)
+    sample = np.sort(rng.choice(w.n_obs, 12, replace=False))
+    Eo, Bo = orc.solve(sub.subset(obs_idx=sample))
+    assert rel_l2(E[:, sample], Eo) < 1e-5
+    assert rel_l2(B[:, sample], Bo) < 1e-5
+    E64, B64 = p.evaluate("fp64")
+    assert rel_l2(E64[:, sample], Eo) < 1e-12
+    # full-grid consistency of the split form against the FP64 GPU form
+    assert rel_l2(E, E64) < 1e-5 and rel_l2(B, B64) < 1e-5
+    p.close()
