@@ -90,7 +90,8 @@ const char *sc_version(void);
 /* Create a context on HIP device `device`.  `stream` is a hipStream_t to use,
  * or NULL for a library-owned stream (default priority).  */
 sc_status sc_ctx_create(int device, void *stream, sc_ctx **out);
-/* Destroy a context.  All problems created on it must be destroyed first.   */
+/* Destroy a context.  SC_E_STATE (and nothing is freed) while problems
+ * created on it are still alive.                                           */
 sc_status sc_ctx_destroy(sc_ctx *ctx);
 /* Wait for all work enqueued on the context's stream.                       */
 sc_status sc_ctx_synchronize(sc_ctx *ctx);

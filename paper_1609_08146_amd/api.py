@@ -6,7 +6,9 @@ on the context's device (torch provides device memory and the stream only).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -15,6 +17,18 @@ from . import _abi
 from ._abi import SC_FP32, SC_FP32_SPLIT, SC_FP64, ScError, call, call_status
 
 PRECISIONS = {"fp64": SC_FP64, "fp32_split": SC_FP32_SPLIT, "fp32": SC_FP32}
+
+_LIVE_CONTEXTS = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # release device objects before the HIP runtime is torn down at process exit
+    for c in list(_LIVE_CONTEXTS):
+        try:
+            c.close()
+        except Exception:
+            pass
 
 
 def _prec(p) -> int:
@@ -63,9 +77,14 @@ class Context:
         out = ctypes.c_void_p()
         call("sc_ctx_create", int(device), handle, ctypes.byref(out))
         self.h = out
+        self._probs = weakref.WeakSet()
+        _LIVE_CONTEXTS.add(self)
 
     def close(self):
+        """Destroy the context, closing every problem still open on it first."""
         if self.h:
+            for p in list(self._probs):
+                p.close()
             call("sc_ctx_destroy", self.h)
             self.h = None
 
@@ -99,16 +118,20 @@ class Problem:
 
     def __init__(self, ctx: Context):
         self.ctx = ctx
+        if not ctx.h:
+            raise ValueError("context is closed")
         out = ctypes.c_void_p()
         call("sc_prob_create", ctx.h, ctypes.byref(out))
         self.h = out
+        ctx._probs.add(self)
         self.n_k = 0
         self.n_obs = 0
         self._res_prec = None
 
     def close(self):
         if self.h:
-            call("sc_prob_destroy", self.h)
+            if self.ctx.h:
+                call("sc_prob_destroy", self.h)
             self.h = None
 
     def __del__(self):

@@ -92,6 +92,8 @@ extern "C" sc_status sc_ctx_create(int device, void *stream, sc_ctx **out)
 extern "C" sc_status sc_ctx_destroy(sc_ctx *c)
 {
     if (!c) return SC_OK;
+    if (c->n_probs > 0)
+        return fail(SC_E_STATE, "sc_ctx_destroy: %d problem(s) still alive on this context", c->n_probs);
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
@@ -139,9 +141,11 @@ extern "C" sc_status sc_prob_create(sc_ctx *ctx, sc_prob **out)
     sc_prob *p = new (std::nothrow) sc_prob();
     if (!p) return fail(SC_E_NOMEM, "sc_prob_create: out of host memory");
     p->ctx = ctx;
+    ctx->n_probs++;
     for (int i = 0; i < EV_N; ++i) {
         if (hipEventCreate(&p->ev[i]) != hipSuccess) {
             for (int j = 0; j < i; ++j) (void)hipEventDestroy(p->ev[j]);
+            ctx->n_probs--;
             delete p;
             return fail(SC_E_DEVICE, "sc_prob_create: hipEventCreate failed");
         }
@@ -157,6 +161,7 @@ extern "C" sc_status sc_prob_destroy(sc_prob *p)
     (void)hipStreamSynchronize(p->ctx->stream);
     for (int i = 0; i < EV_N; ++i)
         if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
+    p->ctx->n_probs--;
     delete p;   // DevBufs free themselves
     return SC_OK;
 }

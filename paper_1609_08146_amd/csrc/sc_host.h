@@ -114,6 +114,7 @@ struct sc_ctx {
     std::vector<sc::QuadJob> host_jobs;
     hipEvent_t upload_done = nullptr;
     std::map<sc::TuneKey, sc_launch> tune;
+    int n_probs = 0;   // live problems (a context outlives its problems)
 };
 
 struct sc_prob {
