@@ -78,11 +78,14 @@ class Context:
         call("sc_ctx_create", int(device), handle, ctypes.byref(out))
         self.h = out
         self._probs = weakref.WeakSet()
+        self._servers = weakref.WeakSet()
         _LIVE_CONTEXTS.add(self)
 
     def close(self):
         """Destroy the context, closing every problem still open on it first."""
         if self.h:
+            for sv in list(self._servers):
+                sv.close()
             for p in list(self._probs):
                 p.close()
             call("sc_ctx_destroy", self.h)
@@ -248,3 +251,78 @@ def problem_from_workload(ctx: Context, w, consistent: Optional[bool] = None) ->
     p.set_incident_gaussian(w.w0, w.pol, w.spectrum, bool(w.consistent if consistent is None else consistent))
     p.set_observation(w.obs)
     return p
+
+
+class Server:
+    """sc_server: continuous-batching serving loop on a context (thread-safe submit / wait)."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_running: int = 8, quantum_ms: float = 20.0):
+        self.ctx = ctx
+        out = ctypes.c_void_p()
+        call("sc_server_create", ctx.h, ctypes.c_size_t(int(hbm_budget)), int(max_running), float(quantum_ms),
+             ctypes.byref(out))
+        self.h = out
+        self._meta = {}
+        ctx._servers.add(self)
+
+    def close(self):
+        if self.h:
+            if self.ctx.h:
+                call("sc_server_destroy", self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, w, precision="fp32_split", t=None, dk: float = 1.0, consistent: Optional[bool] = None) -> int:
+        """Queue a solve of a ``workloads.Workload``; returns its ticket."""
+        k = _host_f64(w.k).ravel()
+        spec = None if w.spectrum is None else _host_c128(w.spectrum).ravel()
+        obs = _host_f64(w.obs, (-1, 3))
+        tt = None if t is None else _host_f64(t).ravel()
+        req = _abi.sc_request(
+            f=float(w.f), r_max=float(w.a), n_r=int(w.n_r), n_phi=int(w.n_phi), n_k=int(k.shape[0]),
+            k=_ptr(k), spectrum=_ptr(spec), w0=float(w.w0), pol_angle=float(w.pol),
+            consistent=int(bool(w.consistent if consistent is None else consistent)), n_obs=int(obs.shape[0]),
+            obs=_ptr(obs), prec=_prec(precision), n_t=0 if tt is None else int(tt.shape[0]), t=_ptr(tt),
+            dk=float(dk))
+        ticket = ctypes.c_uint64()
+        call("sc_server_submit", self.h, ctypes.byref(req), ctypes.byref(ticket))
+        self._meta[ticket.value] = (_prec(precision), int(k.shape[0]), int(obs.shape[0]),
+                                    0 if tt is None else int(tt.shape[0]))
+        return ticket.value
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0):
+        """Block for a result: (E, B, Et, Bt, stats) on the host (Et, Bt None without time samples)."""
+        prec, n_k, n_obs, n_t = self._meta[ticket]
+        dt = np.complex128 if prec == SC_FP64 else np.complex64
+        E, B = np.empty((n_k, n_obs, 3), dt), np.empty((n_k, n_obs, 3), dt)
+        Et = Bt = None
+        if n_t:
+            Et, Bt = np.empty((n_t, n_obs, 3), dt), np.empty((n_t, n_obs, 3), dt)
+        st = _abi.sc_request_stats()
+        call("sc_server_wait", self.h, ctypes.c_uint64(ticket), float(timeout_ms), _ptr(E), _ptr(B), _ptr(Et),
+             _ptr(Bt), ctypes.byref(st))
+        self._meta.pop(ticket, None)
+        stats = {f: getattr(st, f) for f, _ in st._fields_}
+        return E, B, Et, Bt, stats
+
+    def wait_status(self, ticket: int, timeout_ms: float = -1.0) -> int:
+        """Wait and return only the status code (the result, if any, is discarded)."""
+        prec, n_k, n_obs, n_t = self._meta[ticket]
+        st = call_status("sc_server_wait", self.h, ctypes.c_uint64(ticket), float(timeout_ms), None, None, None,
+                         None, None)
+        if st not in (_abi.SC_E_TIMEOUT,):
+            self._meta.pop(ticket, None)
+        return st
+
+    def cancel(self, ticket: int):
+        call("sc_server_cancel", self.h, ctypes.c_uint64(ticket))
+
+    def stats(self) -> dict:
+        s = _abi.sc_server_stats()
+        call("sc_server_get_stats", self.h, ctypes.byref(s))
+        return {f: getattr(s, f) for f, _ in s._fields_}

@@ -386,6 +386,7 @@ extern "C" sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_ru
             delete s;
             return fail(SC_E_DEVICE, "sc_server_create: hipEventCreate failed");
         }
+    ctx->n_probs++;   // the context must outlive the server
     s->worker = std::thread(worker_main, s);
     *out = s;
     return SC_OK;
@@ -551,6 +552,7 @@ extern "C" sc_status sc_server_destroy(sc_server *s)
         s->jobbuf[i].release();
     }
     (void)sc_ctx_destroy(s->prep);
+    s->ctx->n_probs--;
     delete s;
     return SC_OK;
 }

@@ -1,0 +1,177 @@
+"""GPU tests of the serving loop (continuous batching with HBM admission).
+
+A request's result must be the same alone and in the mix: every partial sum
+of a request is produced by one tile with the same kernel and node chunking
+as a single sc_evaluate, so the comparison is bitwise.
+"""
+import math
+import os
+import subprocess
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_08146_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def small_requests(n, seed=3):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        w = workloads.sweep_instance(rng, i)
+        nn = int(rng.integers(40, 120))
+        w = w.with_nodes(nn, int(rng.integers(24, 80)))
+        w = w.subset(obs_idx=np.arange(0, w.n_obs, int(rng.integers(3, 40))), k_idx=np.arange(min(w.n_k, 3)))
+        out.append(w)
+    return out
+
+
+def alone(ctx, w, prec, t=None, dk=1.0):
+    from paper_1609_08146_amd import problem_from_workload
+    p = problem_from_workload(ctx, w)
+    E, B = p.evaluate(prec)
+    Et = Bt = None
+    if t is not None:
+        Et, Bt = p.to_time(dk, t)
+    p.close()
+    return E, B, Et, Bt
+
+
+def test_same_result_alone_and_in_the_mix(ctx):
+    from paper_1609_08146_amd import Server
+    ws = small_requests(8)
+    precs = ["fp32_split"] * 6 + ["fp64", "fp32_split"]
+    ref = [alone(ctx, w, pr, w.t[::32], w.dk) for w, pr in zip(ws, precs)]
+    # at most three running at once, so later arrivals queue and join running work
+    srv = Server(ctx, hbm_budget=int(3e9), max_running=3, quantum_ms=1.0)
+    tickets = []
+    for i, (w, pr) in enumerate(zip(ws, precs)):
+        tickets.append(srv.submit(w, pr, t=w.t[::32], dk=w.dk))
+        if i == 3:
+            time.sleep(0.01)   # later arrivals join running work
+    for tk, (E0, B0, Et0, Bt0) in zip(tickets, ref):
+        E, B, Et, Bt, st = srv.wait(tk)
+        assert np.array_equal(E, E0) and np.array_equal(B, B0)
+        assert np.array_equal(Et, Et0) and np.array_equal(Bt, Bt0)
+        assert st["total_ms"] >= st["run_ms"] >= 0 and st["evals"] > 0
+    s = srv.stats()
+    assert s["completed"] == len(ws) and s["rejected"] == 0
+    assert s["hbm_in_use"] == 0
+    assert s["launches"] >= 1
+    srv.close()
+
+
+def test_admission_respects_hbm_budget(ctx):
+    from paper_1609_08146_amd import Server
+    ws = small_requests(6, seed=11)
+    # budget fits only one of these requests at a time
+    from paper_1609_08146_amd import problem_from_workload
+    p = problem_from_workload(ctx, ws[0])
+    p.evaluate("fp32_split")
+    one = p.device_bytes()
+    p.close()
+    biggest = max(w.n_k * (w.n_r + 1) * w.n_phi for w in ws)
+    budget = int(max(one, 120 * biggest + 64 * max(w.n_obs for w in ws) * 200) * 1.6)
+    srv = Server(ctx, hbm_budget=budget, max_running=8, quantum_ms=0.5)
+    seen = []
+    stop = threading.Event()
+
+    def sample():
+        while not stop.is_set():
+            st = srv.stats()
+            seen.append((st["hbm_in_use"], st["queued"], st["running"]))
+            time.sleep(0.0005)
+
+    th = threading.Thread(target=sample)
+    th.start()
+    tickets = []
+    for w in ws:
+        try:
+            tickets.append(srv.submit(w, "fp32_split"))
+        except Exception as e:   # a request larger than the whole budget is rejected up front
+            assert "REJECTED" in str(e)
+    for tk in tickets:
+        srv.wait(tk)
+    stop.set()
+    th.join()
+    assert all(h <= budget for h, _, _ in seen)
+    assert srv.stats()["completed"] == len(tickets)
+    srv.close()
+
+
+def test_rejection_cancel_timeout_and_bad_request(ctx):
+    from paper_1609_08146_amd import ScError, Server
+    from paper_1609_08146_amd._abi import SC_E_CANCELLED, SC_E_INVAL, SC_E_REJECTED, SC_E_TIMEOUT
+    big = workloads.broadband(n_k=8, n_nodes=300)
+    srv = Server(ctx, hbm_budget=int(64e6), max_running=1, quantum_ms=5.0)
+    with pytest.raises(ScError) as e:
+        srv.submit(big, "fp32_split")
+    assert e.value.status == SC_E_REJECTED
+    bad = workloads.mono().subset(obs_idx=[0, 1])
+    bad.f = -1.0
+    with pytest.raises(ScError) as e:
+        srv.submit(bad, "fp32_split")
+    assert e.value.status == SC_E_INVAL
+    srv.close()
+    # one long request occupies the only running slot; the next one queues and can be cancelled
+    srv = Server(ctx, hbm_budget=int(8e9), max_running=1, quantum_ms=5.0)
+    long_req = workloads.broadband(n_k=8, n_nodes=400)
+    t1 = srv.submit(long_req, "fp32_split")
+    t2 = srv.submit(workloads.mono().with_nodes(40, 32), "fp32_split")
+    srv.cancel(t2)
+    assert srv.wait_status(t2) == SC_E_CANCELLED
+    st = srv.wait_status(t1, timeout_ms=0.0)
+    assert st in (SC_E_TIMEOUT, 0)
+    if st == SC_E_TIMEOUT:
+        E, B, _, _, stats = srv.wait(t1)
+        assert np.isfinite(E).all()
+    s = srv.stats()
+    assert s["cancelled"] == 1
+    srv.close()
+
+
+def test_injected_allocation_failure_is_isolated():
+    """With the n-th device allocation forced to fail, that request fails cleanly and the others complete."""
+    code = r'''
+import os, sys
+sys.path.insert(0, %r)
+import numpy as np, workloads
+from paper_1609_08146_amd import Context, Server, ScError
+ctx = Context(0)
+srv = Server(ctx, hbm_budget=int(8e9), max_running=1, quantum_ms=2.0)
+ws = [workloads.mono().with_nodes(40, 32).subset(obs_idx=np.arange(0, 1024, 7)) for _ in range(3)]
+tk = [srv.submit(w, "fp32_split") for w in ws]
+res = []
+for t in tk:
+    try:
+        srv.wait(t); res.append("ok")
+    except ScError as e:
+        res.append("fail:%%d" %% e.status)
+print("RESULTS", res, srv.stats()["hbm_in_use"])
+srv.close(); ctx.close()
+''' % ROOT
+    env = dict(os.environ, SC_DEBUG_FAIL_ALLOC="30")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    print(out.stdout[-2000:], out.stderr[-2000:])
+    assert out.returncode == 0
+    line = [l for l in out.stdout.splitlines() if l.startswith("RESULTS")][0]
+    assert "fail:-2" in line            # SC_E_NOMEM for the request that hit the failure
+    assert line.count("'ok'") == 2
+    assert line.rstrip().endswith(" 0")  # nothing left charged
