@@ -116,9 +116,11 @@ sc_status sc_get_timing(const sc_prob *p, sc_timing *out);
  * fields change speed only.  Zero fields mean "library default".            */
 typedef struct {
     int obs_per_lane;    /* 1 or 2 observation points per lane                    */
-    int waves_per_block; /* 1, 2, 4 or 8 waves of 64 lanes per workgroup          */
+    int waves_per_block; /* 1, 2 or 4 waves of 64 lanes per workgroup             */
     int chunk;           /* mirror nodes per split-K chunk (multiple of 64)        */
-    int blocks_per_cu;   /* persistent workgroups per compute unit                 */
+    int blocks_per_cu;   /* persistent workgroups per compute unit (0 = max)       */
+    int freq_per_lane;   /* 1, 2 or 4 frequencies per lane sharing one geometry
+                            (obs_per_lane x freq_per_lane <= 4, not 2 x 4)        */
 } sc_launch;
 /* Fix the launch shape for a problem (overrides the context's tuned value). */
 sc_status sc_set_launch(sc_prob *p, const sc_launch *launch);

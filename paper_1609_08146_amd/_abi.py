@@ -32,7 +32,7 @@ class sc_timing(ctypes.Structure):
 
 class sc_launch(ctypes.Structure):
     _fields_ = [("obs_per_lane", ctypes.c_int), ("waves_per_block", ctypes.c_int), ("chunk", ctypes.c_int),
-                ("blocks_per_cu", ctypes.c_int)]
+                ("blocks_per_cu", ctypes.c_int), ("freq_per_lane", ctypes.c_int)]
 
 
 class sc_request(ctypes.Structure):

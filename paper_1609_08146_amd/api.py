@@ -184,18 +184,19 @@ class Problem:
         call("sc_set_observation", self.h, _ptr(xyz), n, int(dev))
         self.n_obs = n
 
-    def set_launch(self, obs_per_lane=0, waves_per_block=0, chunk=0, blocks_per_cu=0, reset=False):
+    def set_launch(self, obs_per_lane=0, waves_per_block=0, chunk=0, blocks_per_cu=0, freq_per_lane=0,
+                   reset=False):
         if reset:
             call("sc_set_launch", self.h, None)
             return
-        l = _abi.sc_launch(obs_per_lane, waves_per_block, chunk, blocks_per_cu)
+        l = _abi.sc_launch(obs_per_lane, waves_per_block, chunk, blocks_per_cu, freq_per_lane)
         call("sc_set_launch", self.h, ctypes.byref(l))
 
     def autotune(self, precision="fp32_split", budget_ms: float = 0.0):
         l = _abi.sc_launch()
         call("sc_autotune", self.h, _prec(precision), float(budget_ms), ctypes.byref(l))
         return dict(obs_per_lane=l.obs_per_lane, waves_per_block=l.waves_per_block, chunk=l.chunk,
-                    blocks_per_cu=l.blocks_per_cu)
+                    blocks_per_cu=l.blocks_per_cu, freq_per_lane=l.freq_per_lane)
 
     # ---- evaluation
     def _out_host(self, prec, n_first):

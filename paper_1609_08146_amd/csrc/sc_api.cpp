@@ -430,6 +430,7 @@ static sc_launch default_launch(sc_precision prec)
 {
     sc_launch l{};
     l.obs_per_lane = (prec == SC_FP64) ? 1 : 2;
+    l.freq_per_lane = 1;
     l.waves_per_block = 4;
     l.chunk = 4096;
     l.blocks_per_cu = 0;   // 0 = occupancy limit
@@ -444,6 +445,10 @@ static TuneKey tune_key(const sc_prob *p, sc_precision prec)
 sc_status sc::check_launch(const sc_launch &l)
 {
     if (l.obs_per_lane != 1 && l.obs_per_lane != 2) return fail(SC_E_INVAL, "launch: obs_per_lane must be 1 or 2");
+    if (l.freq_per_lane != 1 && l.freq_per_lane != 2 && l.freq_per_lane != 4)
+        return fail(SC_E_INVAL, "launch: freq_per_lane must be 1, 2 or 4");
+    if (l.obs_per_lane * l.freq_per_lane > 4 || (l.obs_per_lane == 2 && l.freq_per_lane == 4))
+        return fail(SC_E_INVAL, "launch: obs_per_lane x freq_per_lane must be 1, 2 or 4 (not 2 x 4)");
     if (l.waves_per_block != 1 && l.waves_per_block != 2 && l.waves_per_block != 4)
         return fail(SC_E_INVAL, "launch: waves_per_block must be 1, 2 or 4");
     if (l.chunk < 64 || l.chunk % 64 != 0) return fail(SC_E_INVAL, "launch: chunk must be a positive multiple of 64");
@@ -461,6 +466,7 @@ sc_launch sc::resolve_launch(const sc_prob *p, sc_precision prec)
         if (p->launch.waves_per_block) l.waves_per_block = p->launch.waves_per_block;
         if (p->launch.chunk) l.chunk = p->launch.chunk;
         if (p->launch.blocks_per_cu) l.blocks_per_cu = p->launch.blocks_per_cu;
+        if (p->launch.freq_per_lane) l.freq_per_lane = p->launch.freq_per_lane;
     }
     return l;
 }
@@ -476,6 +482,7 @@ extern "C" sc_status sc_set_launch(sc_prob *p, const sc_launch *l)
     if (l->obs_per_lane) full.obs_per_lane = l->obs_per_lane;
     if (l->waves_per_block) full.waves_per_block = l->waves_per_block;
     if (l->chunk) full.chunk = l->chunk;
+    if (l->freq_per_lane) full.freq_per_lane = l->freq_per_lane;
     full.blocks_per_cu = l->blocks_per_cu;
     SC_TRY(check_launch(full));
     p->launch = *l;
@@ -538,7 +545,7 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
     job.obs_blocks = p->n_obs_pad / (64 * l.obs_per_lane);
     job.tile0 = 0;
     job.tile_offset = 0;
-    job.n_tiles = (int64_t)job.obs_blocks * n_chunks * n_k;
+    job.n_tiles = (int64_t)job.obs_blocks * n_chunks * ((n_k + l.freq_per_lane - 1) / l.freq_per_lane);
     return SC_OK;
 }
 
@@ -583,7 +590,7 @@ sc_status sc::run_quad(sc_ctx *c, std::vector<QuadJob> &jobs, sc_precision prec,
     HIP_TRY(launch_fill_u32(st, c->counter.as<unsigned int>(), 0u, 1));
     const int mode = mode_of(prec);
     int bpc = l.blocks_per_cu;
-    const int occ = quad_max_blocks_per_cu(mode, l.obs_per_lane, l.waves_per_block);
+    const int occ = quad_max_blocks_per_cu(mode, l.obs_per_lane, l.freq_per_lane, l.waves_per_block);
     if (bpc <= 0 || bpc > occ) bpc = occ;
     int64_t grid = (int64_t)bpc * c->n_cu;
     const int64_t waves_needed = (n_tiles + 0);
@@ -591,8 +598,8 @@ sc_status sc::run_quad(sc_ctx *c, std::vector<QuadJob> &jobs, sc_precision prec,
     if (grid > blocks_needed) grid = blocks_needed;
     if (grid < 1) grid = 1;
     if (timed) ev_record(timed, EV_Q0);
-    HIP_TRY(launch_quad(st, mode, l.obs_per_lane, l.waves_per_block, (int)grid, c->jobs.as<QuadJob>(),
-                        (int)jobs.size(), n_tiles, c->counter.as<unsigned int>()));
+    HIP_TRY(launch_quad(st, mode, l.obs_per_lane, l.freq_per_lane, l.waves_per_block, (int)grid,
+                        c->jobs.as<QuadJob>(), (int)jobs.size(), n_tiles, c->counter.as<unsigned int>()));
     if (timed) ev_record(timed, EV_Q1);
     return SC_OK;
 }
@@ -651,7 +658,8 @@ extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, 
     std::vector<sc_launch> ls(n);
     for (int i = 0; i < n; ++i) {
         ls[i] = resolve_launch(probs[i], prec);
-        ls[i].obs_per_lane = l0.obs_per_lane;   // chunk stays per problem (it fixes the summation order)
+        ls[i].obs_per_lane = l0.obs_per_lane;   // one kernel shape per launch; the chunk stays per problem
+        ls[i].freq_per_lane = l0.freq_per_lane; // (only the chunk fixes the summation order)
         SC_TRY(check_launch(ls[i]));
         SC_TRY(prepare(probs[i], prec, ls[i], jobs[i]));
         probs[i]->res_prec = -1;
@@ -750,11 +758,13 @@ extern "C" sc_status sc_autotune(sc_prob *p, sc_precision prec, double budget_ms
     c->profiling = 1;
     std::vector<sc_launch> cands;
     const int chunk0 = default_launch(prec).chunk;
-    for (int opl : {1, 2})
+    const int shapes[5][2] = {{1, 1}, {2, 1}, {1, 2}, {2, 2}, {1, 4}};
+    for (auto &sh : shapes)
         for (int wpb : {1, 2, 4})
             for (int bpc : {0, 2, 1}) {
                 sc_launch l{};
-                l.obs_per_lane = opl;
+                l.obs_per_lane = sh[0];
+                l.freq_per_lane = sh[1];
                 l.waves_per_block = wpb;
                 l.chunk = chunk0;
                 l.blocks_per_cu = bpc;
@@ -800,11 +810,11 @@ extern "C" sc_status sc_autotune_save(sc_ctx *c, const char *path)
     if (!c || !path) return fail(SC_E_INVAL, "sc_autotune_save: NULL argument");
     std::ofstream f(path);
     if (!f) return fail(SC_E_INVAL, "sc_autotune_save: cannot open %s", path);
-    f << "# prec log2_obs log2_k log2_nodes obs_per_lane waves_per_block chunk blocks_per_cu\n";
+    f << "# prec log2_obs log2_k log2_nodes obs_per_lane waves_per_block chunk blocks_per_cu freq_per_lane\n";
     for (auto &kv : c->tune)
         f << kv.first.prec << ' ' << kv.first.b_obs << ' ' << kv.first.b_k << ' ' << kv.first.b_nodes << ' '
           << kv.second.obs_per_lane << ' ' << kv.second.waves_per_block << ' ' << kv.second.chunk << ' '
-          << kv.second.blocks_per_cu << '\n';
+          << kv.second.blocks_per_cu << ' ' << kv.second.freq_per_lane << '\n';
     return f ? SC_OK : fail(SC_E_INVAL, "sc_autotune_save: write failed");
 }
 
@@ -821,7 +831,7 @@ extern "C" sc_status sc_autotune_load(sc_ctx *c, const char *path)
         TuneKey k{};
         sc_launch l{};
         if (!(is >> k.prec >> k.b_obs >> k.b_k >> k.b_nodes >> l.obs_per_lane >> l.waves_per_block >> l.chunk >>
-              l.blocks_per_cu))
+              l.blocks_per_cu >> l.freq_per_lane))
             return fail(SC_E_INVAL, "sc_autotune_load: malformed line '%s'", line.c_str());
         if (check_launch(l) != SC_OK) return fail(SC_E_INVAL, "sc_autotune_load: invalid launch in '%s'", line.c_str());
         m[k] = l;

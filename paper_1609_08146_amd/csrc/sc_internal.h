@@ -45,8 +45,8 @@ hipError_t launch_tables_gaussian(hipStream_t st, int n_k, int n_surf, int n_tot
                                   int consistent, double *tab64);
 hipError_t launch_tables_cast(hipStream_t st, int n_k, int n_tot, const double *k, const double *pos64,
                               const double *tab64, float *tab32, int naive);
-hipError_t launch_quad(hipStream_t st, int mode, int obs_per_lane, int waves_per_block, int grid,
-                       const QuadJob *jobs, int n_jobs, int64_t n_tiles, unsigned int *counter);
+hipError_t launch_quad(hipStream_t st, int mode, int obs_per_lane, int freq_per_lane, int waves_per_block,
+                       int grid, const QuadJob *jobs, int n_jobs, int64_t n_tiles, unsigned int *counter);
 hipError_t launch_reduce(hipStream_t st, int mode, const void *partial, int n_chunks, int n_k, int n_obs,
                          int n_obs_pad, const double *k, void *E, void *B);
 hipError_t launch_twiddles(hipStream_t st, int n_k, const double *k, int n_t, const double *t, double dk,
@@ -56,6 +56,6 @@ hipError_t launch_time(hipStream_t st, int is_f64, int n_k, int n_t, int64_t n_x
 hipError_t launch_fill_u32(hipStream_t st, unsigned int *p, unsigned int v, int n);
 
 // Occupancy helper: max resident workgroups per CU for a quadrature variant.
-int quad_max_blocks_per_cu(int mode, int obs_per_lane, int waves_per_block);
+int quad_max_blocks_per_cu(int mode, int obs_per_lane, int freq_per_lane, int waves_per_block);
 
 }  // namespace sc

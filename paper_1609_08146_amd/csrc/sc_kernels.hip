@@ -255,24 +255,42 @@ __device__ __forceinline__ void sincos_turns(float t, float &s, float &c)
     c = __builtin_amdgcn_cosf(r);
 }
 
-// One (node, observation) pair of the split form in FP32.
-//   p = (x, y, z, |r_s|), o = (x, y, z, |r'|^2), t0/t1 = table record,
-//   k and kt = k / 2pi.  acc[0..5] = E (re, im) x,y,z;  acc[6..11] = B sum before 1/ik.
-__device__ __forceinline__ void pair_split(const v4f p, const v4f t0, const v4f t1, const v4f o,
-                                           float k, float kt, float *acc)
+// The per-pair work is split into a geometry part (one per node and
+// observation point) and a per-frequency part, so that a lane holding several
+// frequencies reuses the geometry.  The arithmetic sequence of one (point,
+// frequency) pair is the same whatever the blocking.
+
+// Geometry of the split form in FP32:  R = r_s - r',  1/|R|,
+//   delta = |R| - |r_s| = (|r'|^2 - 2 r_s.r') / (|R| + |r_s|)  (no cancellation).
+//   p = (x, y, z, |r_s|), o = (x, y, z, |r'|^2).
+struct GeomF {
+    float dx, dy, dz, rinv, delta;
+};
+
+__device__ __forceinline__ GeomF geom_split(const v4f p, const v4f o)
 {
-    const float dx = p.x - o.x, dy = p.y - o.y, dz = p.z - o.z;
-    const float R2 = __fmaf_rn(dx, dx, __fmaf_rn(dy, dy, dz * dz));
-    const float rinv = __builtin_amdgcn_rsqf(R2);
-    const float R = R2 * rinv;
-    // delta = R - |r_s| = (|r'|^2 - 2 r_s.r') / (R + |r_s|): no cancellation
+    GeomF g;
+    g.dx = p.x - o.x;
+    g.dy = p.y - o.y;
+    g.dz = p.z - o.z;
+    const float R2 = __fmaf_rn(g.dx, g.dx, __fmaf_rn(g.dy, g.dy, g.dz * g.dz));
+    g.rinv = __builtin_amdgcn_rsqf(R2);
+    const float R = R2 * g.rinv;
     const float dot = __fmaf_rn(p.x, o.x, __fmaf_rn(p.y, o.y, p.z * o.z));
     const float num = __fmaf_rn(-2.0f, dot, o.w);
-    const float delta = num * __builtin_amdgcn_rcpf(R + p.w);
-    float s, c;
-    sincos_turns(kt * delta, s, c);
-    const float gr = c * rinv, gi = s * rinv;         // gt = e^{ik delta} / R
-    const float a = -(rinv * rinv), b = k * rinv;      // (ik - 1/R) / R
+    g.delta = num * __builtin_amdgcn_rcpf(R + p.w);
+    return g;
+}
+
+// Accumulate one (node, point, frequency) term given e^{i theta} = (c, s):
+//   gt = e^{i theta} / R,  ht = (ik - 1/R) gt / R,
+//   acc[0..5] += Jt gt + rho_t ht R   (E),   acc[6..11] += (Jt ht) x R   (B before 1/ik).
+//   t0 = (Jt.x, Jt.y), t1 = (Jt.z, rho_t), each complex as (re, im).
+__device__ __forceinline__ void accumulate_f32(float dx, float dy, float dz, float rinv, float c, float s,
+                                               const v4f t0, const v4f t1, float k, float *acc)
+{
+    const float gr = c * rinv, gi = s * rinv;
+    const float a = -(rinv * rinv), b = k * rinv;
     const float hr = __fmaf_rn(gr, a, -(gi * b));
     const float hi = __fmaf_rn(gr, b, gi * a);
     // E += Jt gt
@@ -303,57 +321,58 @@ __device__ __forceinline__ void pair_split(const v4f p, const v4f t0, const v4f 
     acc[11] = __fmaf_rn(qxi, dy, __fmaf_rn(-qyi, dx, acc[11]));
 }
 
-// Naive FP32 pair: the whole phase k R in FP32 (the table carries no node phase).
-__device__ __forceinline__ void pair_naive(const v4f p, const v4f t0, const v4f t1, const v4f o,
-                                           float k, float *acc)
+// Split form, one frequency: phase k delta (kt = k / 2 pi, in turns).
+__device__ __forceinline__ void freq_split(const GeomF &g, const v4f t0, const v4f t1, float k, float kt, float *acc)
 {
-    const float dx = p.x - o.x, dy = p.y - o.y, dz = p.z - o.z;
-    const float R2 = __fmaf_rn(dx, dx, __fmaf_rn(dy, dy, dz * dz));
-    const float rinv = __builtin_amdgcn_rsqf(R2);
-    const float R = R2 * rinv;
     float s, c;
-    sincosf(k * R, &s, &c);
-    const float gr = c * rinv, gi = s * rinv;
-    const float a = -(rinv * rinv), b = k * rinv;
-    const float hr = __fmaf_rn(gr, a, -(gi * b));
-    const float hi = __fmaf_rn(gr, b, gi * a);
-    acc[0] = __fmaf_rn(t0.x, gr, __fmaf_rn(-t0.y, gi, acc[0]));
-    acc[1] = __fmaf_rn(t0.x, gi, __fmaf_rn(t0.y, gr, acc[1]));
-    acc[2] = __fmaf_rn(t0.z, gr, __fmaf_rn(-t0.w, gi, acc[2]));
-    acc[3] = __fmaf_rn(t0.z, gi, __fmaf_rn(t0.w, gr, acc[3]));
-    acc[4] = __fmaf_rn(t1.x, gr, __fmaf_rn(-t1.y, gi, acc[4]));
-    acc[5] = __fmaf_rn(t1.x, gi, __fmaf_rn(t1.y, gr, acc[5]));
-    const float tr = __fmaf_rn(t1.z, hr, -(t1.w * hi));
-    const float ti = __fmaf_rn(t1.z, hi, t1.w * hr);
-    acc[0] = __fmaf_rn(tr, dx, acc[0]);
-    acc[1] = __fmaf_rn(ti, dx, acc[1]);
-    acc[2] = __fmaf_rn(tr, dy, acc[2]);
-    acc[3] = __fmaf_rn(ti, dy, acc[3]);
-    acc[4] = __fmaf_rn(tr, dz, acc[4]);
-    acc[5] = __fmaf_rn(ti, dz, acc[5]);
-    const float qxr = __fmaf_rn(t0.x, hr, -(t0.y * hi)), qxi = __fmaf_rn(t0.x, hi, t0.y * hr);
-    const float qyr = __fmaf_rn(t0.z, hr, -(t0.w * hi)), qyi = __fmaf_rn(t0.z, hi, t0.w * hr);
-    const float qzr = __fmaf_rn(t1.x, hr, -(t1.y * hi)), qzi = __fmaf_rn(t1.x, hi, t1.y * hr);
-    acc[6] = __fmaf_rn(qyr, dz, __fmaf_rn(-qzr, dy, acc[6]));
-    acc[7] = __fmaf_rn(qyi, dz, __fmaf_rn(-qzi, dy, acc[7]));
-    acc[8] = __fmaf_rn(qzr, dx, __fmaf_rn(-qxr, dz, acc[8]));
-    acc[9] = __fmaf_rn(qzi, dx, __fmaf_rn(-qxi, dz, acc[9]));
-    acc[10] = __fmaf_rn(qxr, dy, __fmaf_rn(-qyr, dx, acc[10]));
-    acc[11] = __fmaf_rn(qxi, dy, __fmaf_rn(-qyi, dx, acc[11]));
+    sincos_turns(kt * g.delta, s, c);
+    accumulate_f32(g.dx, g.dy, g.dz, g.rinv, c, s, t0, t1, k, acc);
 }
 
-// One pair of the split form in FP64.
-__device__ __forceinline__ void pair_f64(const double *p, const double *t, const double4 o, double k, double *acc)
+// Naive FP32 form, one frequency: the whole phase k |R| in FP32 (the table carries no node phase).
+__device__ __forceinline__ void freq_naive(const GeomF &g, float R, const v4f t0, const v4f t1, float k, float *acc)
 {
-    const double dx = p[0] - o.x, dy = p[1] - o.y, dz = p[2] - o.z;
-    const double R2 = __fma_rn(dx, dx, __fma_rn(dy, dy, dz * dz));
-    const double rinv = rsqrt(R2);
-    const double R = R2 * rinv;
+    float s, c;
+    sincosf(k * R, &s, &c);
+    accumulate_f32(g.dx, g.dy, g.dz, g.rinv, c, s, t0, t1, k, acc);
+}
+
+__device__ __forceinline__ void geom_naive(const v4f p, const v4f o, GeomF &g, float &R)
+{
+    g.dx = p.x - o.x;
+    g.dy = p.y - o.y;
+    g.dz = p.z - o.z;
+    const float R2 = __fmaf_rn(g.dx, g.dx, __fmaf_rn(g.dy, g.dy, g.dz * g.dz));
+    g.rinv = __builtin_amdgcn_rsqf(R2);
+    R = R2 * g.rinv;
+    g.delta = 0.0f;
+}
+
+// Geometry and per-frequency term of the split form in FP64.
+struct GeomD {
+    double dx, dy, dz, rinv, delta;
+};
+
+__device__ __forceinline__ GeomD geom_f64(const double *p, const double4 o)
+{
+    GeomD g;
+    g.dx = p[0] - o.x;
+    g.dy = p[1] - o.y;
+    g.dz = p[2] - o.z;
+    const double R2 = __fma_rn(g.dx, g.dx, __fma_rn(g.dy, g.dy, g.dz * g.dz));
+    g.rinv = rsqrt(R2);
+    const double R = R2 * g.rinv;
     const double dot = __fma_rn(p[0], o.x, __fma_rn(p[1], o.y, p[2] * o.z));
     const double num = __fma_rn(-2.0, dot, o.w);
-    const double delta = num / (R + p[3]);
+    g.delta = num / (R + p[3]);
+    return g;
+}
+
+__device__ __forceinline__ void freq_f64(const GeomD &g, const double *t, double k, double *acc)
+{
     double s, c;
-    sincos(k * delta, &s, &c);
+    sincos(k * g.delta, &s, &c);
+    const double dx = g.dx, dy = g.dy, dz = g.dz, rinv = g.rinv;
     const double gr = c * rinv, gi = s * rinv;
     const double a = -(rinv * rinv), b = k * rinv;
     const double hr = __fma_rn(gr, a, -(gi * b));
@@ -397,12 +416,12 @@ __device__ __forceinline__ int find_job(cjob *jobs, int n_jobs, int64_t t)
 
 constexpr int KAHAN_BLOCK = 32;   // nodes summed plainly before each compensated add (FP32)
 
-// Persistent quadrature kernel: every wave repeatedly takes the next tile from
-// a device counter and sums one node chunk for 64*OPL observation points at
-// one frequency.  Node and table data are wave-uniform (scalar loads); each
-// lane owns OPL observation points and 12 real accumulators per point.
+// Persistent quadrature kernel.  Every wave repeatedly takes the next tile
+// from a device counter: one node chunk, 64*OPL observation points, FPB
+// consecutive frequencies.  Node and table data are wave-uniform (scalar
+// loads); each lane owns OPL points x FPB frequencies x 12 accumulators.
 // Every wave exits once the counter passes n_tiles.
-template <int MODE, int OPL>
+template <int MODE, int OPL, int FPB>
 __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_, int n_jobs, int64_t n_tiles,
                                               unsigned int *__restrict__ counter)
 {
@@ -419,90 +438,140 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
         const int ob = (int)(local % obs_blocks);
         const int64_t rest = local / obs_blocks;
         const int chunk = (int)(rest % n_chunks);
-        const int kidx = (int)(rest / n_chunks);
+        const int kb = (int)(rest / n_chunks);
         const int n_tot = jobs[j].n_tot, n_k = jobs[j].n_k, n_obs_pad = jobs[j].n_obs_pad;
         const int n0 = chunk * jobs[j].chunk;
         const int n1 = min(n0 + jobs[j].chunk, n_tot);
-        const double k64 = ((cdouble *)jobs[j].k)[kidx];
         const int obase = ob * 64 * OPL + lane;
-        const size_t pbase = ((size_t)chunk * n_k + kidx) * 12 * (size_t)n_obs_pad;
+        // frequencies of this tile; past the last one, repeat it and skip the store
+        int kidx[FPB];
+        double k64[FPB];
+#pragma unroll
+        for (int f = 0; f < FPB; ++f) {
+            kidx[f] = min(kb * FPB + f, n_k - 1);
+            k64[f] = ((cdouble *)jobs[j].k)[kidx[f]];
+        }
+        const int n_valid = min(FPB, n_k - kb * FPB);
 
         if constexpr (MODE == MODE_FP64) {
-            const double *pos = (const double *)jobs[j].pos;
-            const double *tab = (const double *)jobs[j].tab + (size_t)kidx * n_tot * 8;
+            cdouble *pos = (cdouble *)jobs[j].pos;
+            cdouble *tab[FPB];
+#pragma unroll
+            for (int f = 0; f < FPB; ++f) tab[f] = (cdouble *)jobs[j].tab + (size_t)kidx[f] * n_tot * 8;
             const double4 *obs = (const double4 *)jobs[j].obs;
             double4 o[OPL];
-            double acc[OPL][12];
+            double acc[OPL][FPB][12];
 #pragma unroll
             for (int s = 0; s < OPL; ++s) {
                 o[s] = obs[obase + 64 * s];
 #pragma unroll
-                for (int c = 0; c < 12; ++c) acc[s][c] = 0.0;
+                for (int f = 0; f < FPB; ++f)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) acc[s][f][c] = 0.0;
             }
             for (int n = n0; n < n1; ++n) {
-                double pn[4], tn[8];
+                double pn[4], tn[FPB][8];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) pn[c] = ((cdouble *)pos)[4 * (size_t)n + c];
+                for (int c = 0; c < 4; ++c) pn[c] = pos[4 * (size_t)n + c];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) tn[c] = ((cdouble *)tab)[8 * (size_t)n + c];
+                for (int f = 0; f < FPB; ++f)
 #pragma unroll
-                for (int s = 0; s < OPL; ++s) pair_f64(pn, tn, o[s], k64, acc[s]);
+                    for (int c = 0; c < 8; ++c) tn[f][c] = tab[f][8 * (size_t)n + c];
+#pragma unroll
+                for (int s = 0; s < OPL; ++s) {
+                    const GeomD g = geom_f64(pn, o[s]);
+#pragma unroll
+                    for (int f = 0; f < FPB; ++f) freq_f64(g, tn[f], k64[f], acc[s][f]);
+                }
             }
-            double *part = (double *)jobs[j].partial + pbase;
 #pragma unroll
-            for (int s = 0; s < OPL; ++s)
+            for (int f = 0; f < FPB; ++f) {
+                if (f >= n_valid) break;
+                double *part = (double *)jobs[j].partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
 #pragma unroll
-                for (int c = 0; c < 12; ++c) part[(size_t)c * n_obs_pad + obase + 64 * s] = acc[s][c];
+                for (int s = 0; s < OPL; ++s)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) part[(size_t)c * n_obs_pad + obase + 64 * s] = acc[s][f][c];
+            }
         } else {
             cv4f *pos = (cv4f *)jobs[j].pos;
-            cv4f *tab = (cv4f *)jobs[j].tab + (size_t)kidx * n_tot * 2;
+            cv4f *tab[FPB];
+            float k[FPB], kt[FPB];
+#pragma unroll
+            for (int f = 0; f < FPB; ++f) {
+                tab[f] = (cv4f *)jobs[j].tab + (size_t)kidx[f] * n_tot * 2;
+                k[f] = (float)k64[f];
+                kt[f] = (float)(k64[f] * INV_TWO_PI);
+            }
             const v4f *obs = (const v4f *)jobs[j].obs;
-            const float k = (float)k64;
-            const float kt = (float)(k64 * INV_TWO_PI);
             v4f o[OPL];
-            float sum[OPL][12], cmp[OPL][12];
+            float sum[OPL][FPB][12], cmp[OPL][FPB][12];
 #pragma unroll
             for (int s = 0; s < OPL; ++s) {
                 o[s] = obs[obase + 64 * s];
 #pragma unroll
-                for (int c = 0; c < 12; ++c) {
-                    sum[s][c] = 0.0f;
-                    cmp[s][c] = 0.0f;
-                }
+                for (int f = 0; f < FPB; ++f)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        sum[s][f][c] = 0.0f;
+                        cmp[s][f][c] = 0.0f;
+                    }
             }
             for (int nb = n0; nb < n1; nb += KAHAN_BLOCK) {
                 const int ne = min(nb + KAHAN_BLOCK, n1);
-                float blk[OPL][12];
+                float blk[OPL][FPB][12];
 #pragma unroll
                 for (int s = 0; s < OPL; ++s)
 #pragma unroll
-                    for (int c = 0; c < 12; ++c) blk[s][c] = 0.0f;
+                    for (int f = 0; f < FPB; ++f)
+#pragma unroll
+                        for (int c = 0; c < 12; ++c) blk[s][f][c] = 0.0f;
                 for (int n = nb; n < ne; ++n) {
                     const v4f pn = pos[n];
-                    const v4f t0 = tab[2 * n], t1 = tab[2 * n + 1];
+                    v4f t0[FPB], t1[FPB];
+#pragma unroll
+                    for (int f = 0; f < FPB; ++f) {
+                        t0[f] = tab[f][2 * n];
+                        t1[f] = tab[f][2 * n + 1];
+                    }
 #pragma unroll
                     for (int s = 0; s < OPL; ++s) {
-                        if constexpr (MODE == MODE_SPLIT) pair_split(pn, t0, t1, o[s], k, kt, blk[s]);
-                        else pair_naive(pn, t0, t1, o[s], k, blk[s]);
+                        if constexpr (MODE == MODE_SPLIT) {
+                            const GeomF g = geom_split(pn, o[s]);
+#pragma unroll
+                            for (int f = 0; f < FPB; ++f) freq_split(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
+                        } else {
+                            GeomF g;
+                            float R;
+                            geom_naive(pn, o[s], g, R);
+#pragma unroll
+                            for (int f = 0; f < FPB; ++f) freq_naive(g, R, t0[f], t1[f], k[f], blk[s][f]);
+                        }
                     }
                 }
-                // compensated add of the block partial
+                // compensated add of the block partials
 #pragma unroll
                 for (int s = 0; s < OPL; ++s)
 #pragma unroll
-                    for (int c = 0; c < 12; ++c) {
-                        const float y = blk[s][c] - cmp[s][c];
-                        const float tsum = sum[s][c] + y;
-                        cmp[s][c] = (tsum - sum[s][c]) - y;
-                        sum[s][c] = tsum;
-                    }
+                    for (int f = 0; f < FPB; ++f)
+#pragma unroll
+                        for (int c = 0; c < 12; ++c) {
+                            const float y = blk[s][f][c] - cmp[s][f][c];
+                            const float tsum = sum[s][f][c] + y;
+                            cmp[s][f][c] = (tsum - sum[s][f][c]) - y;
+                            sum[s][f][c] = tsum;
+                        }
             }
-            float *part = (float *)jobs[j].partial + pbase;
 #pragma unroll
-            for (int s = 0; s < OPL; ++s)
+            for (int f = 0; f < FPB; ++f) {
+                if (f >= n_valid) break;
+                float *part = (float *)jobs[j].partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
 #pragma unroll
-                for (int c = 0; c < 12; ++c)
-                    part[(size_t)c * n_obs_pad + obase + 64 * s] = sum[s][c] - cmp[s][c];
+                for (int s = 0; s < OPL; ++s)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c)
+                        part[(size_t)c * n_obs_pad + obase + 64 * s] = sum[s][f][c] - cmp[s][f][c];
+            }
         }
     }
 }
@@ -633,42 +702,49 @@ hipError_t launch_tables_cast(hipStream_t st, int n_k, int n_tot, const double *
     return hipGetLastError();
 }
 
-template <int MODE, int OPL>
-static const void *quad_fn()
+// Instantiated shapes (obs per lane x frequencies per lane).
+#define SC_QUAD_SHAPES(X, M) X(M, 1, 1) X(M, 2, 1) X(M, 1, 2) X(M, 2, 2) X(M, 1, 4)
+
+static bool shape_ok(int opl, int fpb)
 {
-    return (const void *)&k_quad<MODE, OPL>;
+    return (opl == 1 && (fpb == 1 || fpb == 2 || fpb == 4)) || (opl == 2 && (fpb == 1 || fpb == 2));
 }
 
-static const void *quad_fn_dyn(int mode, int opl)
+static const void *quad_fn_dyn(int mode, int opl, int fpb)
 {
-    if (mode == MODE_FP64) return opl == 2 ? quad_fn<MODE_FP64, 2>() : quad_fn<MODE_FP64, 1>();
-    if (mode == MODE_SPLIT) return opl == 2 ? quad_fn<MODE_SPLIT, 2>() : quad_fn<MODE_SPLIT, 1>();
-    return opl == 2 ? quad_fn<MODE_NAIVE, 2>() : quad_fn<MODE_NAIVE, 1>();
+#define SC_QUAD_FN(M, O, F) \
+    if (mode == M && opl == O && fpb == F) return (const void *)&k_quad<M, O, F>;
+    SC_QUAD_SHAPES(SC_QUAD_FN, MODE_FP64)
+    SC_QUAD_SHAPES(SC_QUAD_FN, MODE_SPLIT)
+    SC_QUAD_SHAPES(SC_QUAD_FN, MODE_NAIVE)
+#undef SC_QUAD_FN
+    return nullptr;
 }
 
-int quad_max_blocks_per_cu(int mode, int opl, int waves_per_block)
+int quad_max_blocks_per_cu(int mode, int opl, int fpb, int waves_per_block)
 {
+    const void *fn = quad_fn_dyn(mode, opl, fpb);
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, quad_fn_dyn(mode, opl), 64 * waves_per_block, 0) !=
-        hipSuccess)
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * waves_per_block, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_quad(hipStream_t st, int mode, int opl, int waves_per_block, int grid, const QuadJob *jobs,
-                       int n_jobs, int64_t n_tiles, unsigned int *counter)
+hipError_t launch_quad(hipStream_t st, int mode, int opl, int fpb, int waves_per_block, int grid,
+                       const QuadJob *jobs, int n_jobs, int64_t n_tiles, unsigned int *counter)
 {
+    if (!shape_ok(opl, fpb)) return hipErrorInvalidValue;
     dim3 g(grid), b(64 * waves_per_block);
-#define SC_LAUNCH_QUAD(M, O) hipLaunchKernelGGL((k_quad<M, O>), g, b, 0, st, jobs, n_jobs, n_tiles, counter)
-    if (mode == MODE_FP64) {
-        if (opl == 2) SC_LAUNCH_QUAD(MODE_FP64, 2); else SC_LAUNCH_QUAD(MODE_FP64, 1);
-    } else if (mode == MODE_SPLIT) {
-        if (opl == 2) SC_LAUNCH_QUAD(MODE_SPLIT, 2); else SC_LAUNCH_QUAD(MODE_SPLIT, 1);
-    } else {
-        if (opl == 2) SC_LAUNCH_QUAD(MODE_NAIVE, 2); else SC_LAUNCH_QUAD(MODE_NAIVE, 1);
+#define SC_QUAD_LAUNCH(M, O, F)                                                                          \
+    if (mode == M && opl == O && fpb == F) {                                                            \
+        hipLaunchKernelGGL((k_quad<M, O, F>), g, b, 0, st, jobs, n_jobs, n_tiles, counter);             \
+        return hipGetLastError();                                                                       \
     }
-#undef SC_LAUNCH_QUAD
-    return hipGetLastError();
+    SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_FP64)
+    SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_SPLIT)
+    SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_NAIVE)
+#undef SC_QUAD_LAUNCH
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce(hipStream_t st, int mode, const void *partial, int n_chunks, int n_k, int n_obs,

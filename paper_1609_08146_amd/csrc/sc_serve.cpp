@@ -119,7 +119,9 @@ static void release_prob(Req *r)
     }
 }
 
+// One kernel shape per precision, so that requests of a precision share launches.
 static int server_opl(sc_precision prec) { return prec == SC_FP64 ? 1 : 2; }
+static int server_fpb(sc_precision) { return 1; }
 
 // Build the request's device state on the preparation stream.
 static sc_status setup_request(sc_server *s, Req *r)
@@ -133,6 +135,7 @@ static sc_status setup_request(sc_server *s, Req *r)
     SC_TRY(sc_set_observation(p, r->obs.data(), r->n_obs, 0));
     sc_launch l = resolve_launch(p, r->prec);
     l.obs_per_lane = server_opl(r->prec);
+    l.freq_per_lane = server_fpb(r->prec);
     SC_TRY(prepare(p, r->prec, l, r->job));
     const int n_k = (int)r->k.size();
     const size_t rs = real_size(r->prec);
@@ -202,13 +205,14 @@ static sc_status launch_quantum(sc_server *s)
     for (Req *r : s->active)
         if (r->state == R_RUNNING && r->cursor < r->job.n_tiles && r->prec == prec) group.push_back(r);
     const int opl = server_opl(prec);
+    const int fpb = server_fpb(prec);
     const double budget_evals = std::max(1.0, s->quantum_ms * s->evals_per_ms);
     const double share = budget_evals / (double)group.size();
     std::vector<QuadJob> jobs;
     std::vector<Req *> finals;
     int64_t total = 0, evals = 0;
     for (Req *r : group) {
-        const double per_tile = 64.0 * opl * std::min<double>(r->job.chunk, r->job.n_tot);
+        const double per_tile = 64.0 * opl * fpb * std::min<double>(r->job.chunk, r->job.n_tot);
         int64_t n = (int64_t)std::ceil(share / per_tile);
         n = std::max<int64_t>(1, std::min<int64_t>(n, r->job.n_tiles - r->cursor));
         QuadJob j = r->job;
@@ -249,11 +253,11 @@ static sc_status launch_quantum(sc_server *s)
     HIP_TRY(launch_fill_u32(st, s->ctx->counter.as<unsigned int>(), 0u, 1));
     const int mode = mode_of(prec);
     const int wpb = 4;
-    const int occ = quad_max_blocks_per_cu(mode, opl, wpb);
+    const int occ = quad_max_blocks_per_cu(mode, opl, fpb, wpb);
     int64_t grid = std::min<int64_t>((int64_t)occ * s->ctx->n_cu, (total + wpb - 1) / wpb);
     grid = std::max<int64_t>(grid, 1);
-    HIP_TRY(launch_quad(st, mode, opl, wpb, (int)grid, s->jobbuf[slot].as<QuadJob>(), (int)jobs.size(), total,
-                        s->ctx->counter.as<unsigned int>()));
+    HIP_TRY(launch_quad(st, mode, opl, fpb, wpb, (int)grid, s->jobbuf[slot].as<QuadJob>(), (int)jobs.size(),
+                        total, s->ctx->counter.as<unsigned int>()));
     HIP_TRY(hipEventRecord(s->slot_ev[slot], st));
     s->slot_busy[slot] = true;
     s->inflight.push_back({slot, evals, Clock::now()});

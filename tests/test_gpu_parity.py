@@ -149,23 +149,24 @@ def test_time_transform(ctx, orc):
 
 
 def test_launch_shape_does_not_change_bits(ctx):
-    w = workloads.broadband(n_k=4, n_nodes=64)
+    # 5 frequencies: frequency blocks of 2 and 4 leave a ragged last block
+    w = workloads.broadband(n_k=5, n_nodes=64)
     from paper_1609_08146_amd import problem_from_workload
     p = problem_from_workload(ctx, w)
-    ref = None
-    for opl in (1, 2):
+    ref = {}
+    shapes = [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4)]
+    for opl, fpb in shapes:
         for wpb in (1, 2, 4):
             for bpc in (0, 1):
-                p.set_launch(obs_per_lane=opl, waves_per_block=wpb, chunk=1024, blocks_per_cu=bpc)
-                for prec in ("fp32_split", "fp64"):
+                p.set_launch(obs_per_lane=opl, freq_per_lane=fpb, waves_per_block=wpb, chunk=1024,
+                             blocks_per_cu=bpc)
+                for prec in ("fp32_split", "fp64", "fp32"):
                     E, B = p.evaluate(prec)
-                    key = prec
-                    if ref is None:
-                        ref = {}
-                    if key not in ref:
-                        ref[key] = (E, B)
+                    if prec not in ref:
+                        ref[prec] = (E, B)
                     else:
-                        assert np.array_equal(E, ref[key][0]) and np.array_equal(B, ref[key][1]), (opl, wpb, bpc)
+                        assert np.array_equal(E, ref[prec][0]) and np.array_equal(B, ref[prec][1]), \
+                            (prec, opl, fpb, wpb, bpc)
     p.close()
 
 
