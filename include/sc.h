@@ -174,6 +174,13 @@ sc_status sc_set_incident(sc_prob *p, const double *E, const double *B, int on_d
 sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_angle,
                                    const double *spectrum, int consistent);
 
+/* Table storage.  keep_fp64 = 1 (default) keeps the FP64 tables (64 B per
+ * (k, node)) so every precision can be evaluated; keep_fp64 = 0 casts them to
+ * the FP32 split tables (32 B per record) as soon as they are built and frees
+ * them, halving resident memory; SC_FP64 evaluation then fails with
+ * SC_E_STATE until the incident field is set again with keep_fp64 = 1.     */
+sc_status sc_set_table_storage(sc_prob *p, int keep_fp64);
+
 /* Observation points, [n_obs][3] doubles, n_obs >= 1.                       */
 sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs, int on_device);
 

@@ -176,6 +176,9 @@ class Problem:
         sp = None if spectrum is None else _host_c128(spectrum).ravel()
         call("sc_set_incident_gaussian", self.h, float(w0), float(pol), _ptr(sp), int(bool(consistent)))
 
+    def set_table_storage(self, keep_fp64: bool):
+        call("sc_set_table_storage", self.h, int(bool(keep_fp64)))
+
     def set_observation(self, xyz):
         dev = _is_device(xyz)
         if not dev:

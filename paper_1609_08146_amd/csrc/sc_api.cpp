@@ -227,8 +227,34 @@ static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w
 
 static void invalidate_tables(sc_prob *p)
 {
-    p->has_tab = p->tab32_ok = p->tab32n_ok = false;
+    p->has_tab = p->tab32_ok = p->tab32n_ok = p->has_tab64 = false;
     p->res_prec = -1;
+}
+
+// After tab64 was (re)built: with keep_fp64 off, cast to the FP32 split tables now and release tab64.
+static sc_status finish_tables(sc_prob *p)
+{
+    p->has_tab = true;
+    p->has_tab64 = true;
+    if (p->keep_fp64) return SC_OK;
+    const size_t nrec = p->k.size() * (size_t)p->n_tot;
+    SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
+    HIP_TRY(launch_tables_cast(p->ctx->stream, (int)p->k.size(), p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
+                               p->tab64.as<double>(), nullptr, p->tab32.as<float>(), 0));
+    p->tab32_ok = true;
+    HIP_TRY(hipStreamSynchronize(p->ctx->stream));
+    p->tab64.release();
+    p->has_tab64 = false;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_set_table_storage(sc_prob *p, int keep_fp64)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_set_table_storage: prob is NULL");
+    DeviceGuard g(p->ctx->device);
+    p->keep_fp64 = keep_fp64 != 0;
+    if (!p->keep_fp64 && p->has_tab64) return finish_tables(p);
+    return SC_OK;
 }
 
 extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, int n_phi)
@@ -360,8 +386,7 @@ extern "C" sc_status sc_set_incident(sc_prob *p, const double *E, const double *
     ev_record(p, EV_PREP1);
     p->ev_prep = p->ctx->profiling;
     if (!on_device) HIP_TRY(hipStreamSynchronize(st));   // staging buffers are freed on return
-    p->has_tab = true;
-    return SC_OK;
+    return finish_tables(p);
 }
 
 extern "C" sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_angle, const double *spectrum,
@@ -390,8 +415,7 @@ extern "C" sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_
     ev_record(p, EV_PREP1);
     p->ev_prep = p->ctx->profiling;
     HIP_TRY(hipStreamSynchronize(st));   // dspec is freed on return
-    p->has_tab = true;
-    return SC_OK;
+    return finish_tables(p);
 }
 
 extern "C" sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs, int on_device)
@@ -510,11 +534,13 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
     const int n_k = (int)p->k.size();
     const size_t nrec = (size_t)n_k * p->n_tot;
     const void *tab = p->tab64.p;
+    if (prec == SC_FP64 && !p->has_tab64)
+        return fail(SC_E_STATE, "evaluate: FP64 tables were not kept (sc_set_table_storage(p, 0))");
     if (prec == SC_FP32_SPLIT) {
         if (!p->tab32_ok) {
             SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
             HIP_TRY(launch_tables_cast(st, n_k, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
-                                       p->tab64.as<double>(), p->tab32.as<float>(), 0));
+                                       p->tab64.as<double>(), nullptr, p->tab32.as<float>(), 0));
             p->tab32_ok = true;
         }
         tab = p->tab32.p;
@@ -522,7 +548,8 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
         if (!p->tab32n_ok) {
             SC_TRY(p->tab32n.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
             HIP_TRY(launch_tables_cast(st, n_k, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
-                                       p->tab64.as<double>(), p->tab32n.as<float>(), 1));
+                                       p->has_tab64 ? p->tab64.as<double>() : nullptr, p->tab32.as<float>(),
+                                       p->tab32n.as<float>(), 1));
             p->tab32n_ok = true;
         }
         tab = p->tab32n.p;
@@ -559,7 +586,8 @@ size_t sc::footprint_bytes(int n_r, int n_phi, int n_k, int n_obs, int n_t, sc_p
     b += sizeof(double) * (2 * (size_t)n_r + 1 + 2 * (size_t)n_phi + 3 * (size_t)n_phi);   // 1-D rule, rim tangents
     b += n_tot * (sizeof(double) * (4 + 3 + 1) + sizeof(float) * 4);                        // node records
     b += sizeof(double) * n_k;
-    b += (size_t)n_k * n_tot * sizeof(double) * 8;                                          // FP64 tables
+    // FP64 tables (kept for SC_FP64; for the FP32 forms they exist only while the FP32 tables are cast)
+    b += (size_t)n_k * n_tot * sizeof(double) * 8;
     if (prec != SC_FP64) b += (size_t)n_k * n_tot * sizeof(float) * 8;                      // FP32 tables
     b += pad * (sizeof(double) + sizeof(float)) * 4;                                        // observation records
     b += rs * 12 * (size_t)n_k * n_obs;                                                      // results E, B

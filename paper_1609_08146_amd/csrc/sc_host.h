@@ -129,8 +129,9 @@ struct sc_prob {
     // frequencies
     std::vector<double> k;
     sc::DevBuf d_k;
-    // tables
+    // tables (tab64 may be released after casting when keep_fp64 is off)
     bool has_tab = false, tab32_ok = false, tab32n_ok = false;
+    bool keep_fp64 = true, has_tab64 = false;
     sc::DevBuf tab64, tab32, tab32n;
     // observation points
     int n_obs = 0, n_obs_pad = 0;

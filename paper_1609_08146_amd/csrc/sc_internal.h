@@ -43,8 +43,9 @@ hipError_t launch_tables_gaussian(hipStream_t st, int n_k, int n_surf, int n_tot
                                   const double *pos64, const double *nrm, const double *wgt,
                                   const double *tan, double w0, double pol, const double *spectrum,
                                   int consistent, double *tab64);
+// FP32 tables from the FP64 ones (tab64), or from FP32 split tables (src32, when tab64 is null)
 hipError_t launch_tables_cast(hipStream_t st, int n_k, int n_tot, const double *k, const double *pos64,
-                              const double *tab64, float *tab32, int naive);
+                              const double *tab64, const float *src32, float *tab32, int naive);
 hipError_t launch_quad(hipStream_t st, int mode, int obs_per_lane, int freq_per_lane, int waves_per_block,
                        int grid, const QuadJob *jobs, int n_jobs, int64_t n_tiles, unsigned int *counter);
 hipError_t launch_reduce(hipStream_t st, int mode, const void *partial, int n_chunks, int n_k, int n_obs,

@@ -213,14 +213,16 @@ __global__ void k_tables_gaussian(int n_k, int n_surf, int n_tot, const double *
 }
 
 __global__ void k_tables_cast(int n_k, int n_tot, const double *__restrict__ kv, const double *__restrict__ pos64,
-                              const double *__restrict__ tab64, float *__restrict__ tab32, int naive)
+                              const double *__restrict__ tab64, const float *__restrict__ src32,
+                              float *__restrict__ tab32, int naive)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n_k * n_tot) return;
-    const double *src = tab64 + idx * 8;
+    double v[8];
+    for (int c = 0; c < 8; ++c) v[c] = tab64 ? tab64[idx * 8 + c] : (double)src32[idx * 8 + c];
     float *dst = tab32 + idx * 8;
     if (!naive) {
-        for (int c = 0; c < 8; ++c) dst[c] = (float)src[c];
+        for (int c = 0; c < 8; ++c) dst[c] = (float)v[c];
         return;
     }
     // remove the folded node phase: multiply by e^{-ik|r_s|}
@@ -232,9 +234,9 @@ __global__ void k_tables_cast(int n_k, int n_tot, const double *__restrict__ kv,
     sincos(phase_mod_2pi(kv[kk], rs), &sp, &cp);
     const c64 P = {cp, -sp};
     for (int c = 0; c < 4; ++c) {
-        c64 v = cmul({src[2 * c], src[2 * c + 1]}, P);
-        dst[2 * c] = (float)v.re;
-        dst[2 * c + 1] = (float)v.im;
+        c64 w = cmul({v[2 * c], v[2 * c + 1]}, P);
+        dst[2 * c] = (float)w.re;
+        dst[2 * c + 1] = (float)w.im;
     }
 }
 
@@ -695,10 +697,10 @@ hipError_t launch_tables_gaussian(hipStream_t st, int n_k, int n_surf, int n_tot
 }
 
 hipError_t launch_tables_cast(hipStream_t st, int n_k, int n_tot, const double *k, const double *pos64,
-                              const double *tab64, float *tab32, int naive)
+                              const double *tab64, const float *src32, float *tab32, int naive)
 {
     hipLaunchKernelGGL(k_tables_cast, dim3(nblocks((int64_t)n_k * n_tot, 256)), dim3(256), 0, st, n_k, n_tot, k,
-                       pos64, tab64, tab32, naive);
+                       pos64, tab64, src32, tab32, naive);
     return hipGetLastError();
 }
 

@@ -129,6 +129,7 @@ static sc_status setup_request(sc_server *s, Req *r)
     SC_TRY(sc_prob_create(s->prep, &r->prob));
     sc_prob *p = r->prob;
     p->alloc_stream = s->prep->stream;
+    p->keep_fp64 = r->prec == SC_FP64;   // FP32 requests keep only their FP32 tables
     SC_TRY(sc_set_mirror(p, r->f, r->a, r->n_r, r->n_phi));
     SC_TRY(sc_set_frequencies(p, r->k.data(), (int)r->k.size()));
     SC_TRY(sc_set_incident_gaussian(p, r->w0, r->pol, r->spec.empty() ? nullptr : r->spec.data(), r->consistent));

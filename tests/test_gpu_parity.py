@@ -225,3 +225,30 @@ def test_full_size_broadband_sampled(ctx, orc):
     # full-grid consistency of the split form against the FP64 GPU form
     assert rel_l2(E, E64) < 1e-5 and rel_l2(B, B64) < 1e-5
     p.close()
+
+
+def test_fp32_only_table_storage(ctx):
+    from paper_1609_08146_amd import ScError, problem_from_workload
+    from paper_1609_08146_amd._abi import SC_E_STATE
+    w = workloads.broadband(n_k=3, n_nodes=80).subset(obs_idx=np.arange(0, 4160, 13))
+    p = problem_from_workload(ctx, w)
+    E0, B0 = p.evaluate("fp32_split")
+    N0, _ = p.evaluate("fp32")
+    full = p.device_bytes()
+    p.set_table_storage(False)          # cast now, release the FP64 tables
+    E1, B1 = p.evaluate("fp32_split")
+    assert np.array_equal(E0, E1) and np.array_equal(B0, B1)
+    with pytest.raises(ScError) as e:
+        p.evaluate("fp64")
+    assert e.value.status == SC_E_STATE
+    assert p.device_bytes() < full
+    p.close()
+    # the same from the start: tables built, cast and released inside set_incident
+    q = problem_from_workload(ctx, w)
+    q.set_table_storage(False)
+    q.set_incident_gaussian(w.w0, w.pol, w.spectrum, False)
+    E2, B2 = q.evaluate("fp32_split")
+    assert np.array_equal(E0, E2) and np.array_equal(B0, B2)
+    N2, _ = q.evaluate("fp32")          # naive tables derived from the FP32 split tables
+    assert rel_l2(N2, N0) < 1e-6
+    q.close()
