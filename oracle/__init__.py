@@ -37,7 +37,7 @@ def compile_source(src: str, out: str) -> str:
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
-                           "-o", tmp, src, "-lm"])
+                           "-o", tmp, src, "-lquadmath", "-lm"])
     os.replace(tmp, out)
     return out
 

@@ -8,7 +8,8 @@
  *
  * It is deliberately plain and slow: one loop per sum, FP64 everywhere, and
  * the large phase k*R (up to ~1e6 rad) plus the accumulations in x87
- * long double (64-bit mantissa), with glibc's sincosl for the exponentials.
+ * long double (64-bit mantissa), with glibc's sincosl for the exponentials;
+ * the quadrature roots are refined in quad precision (__float128).
  *
  * What it computes (units c = 1, Lorentz-Heaviside, time factor e^{-ikt}):
  *
@@ -51,13 +52,15 @@
 #endif
 
 typedef long double ld;
+typedef __float128 qd;
 
 static const ld PI_L = 3.141592653589793238462643383279502884L;
 
 /* ------------------------------------------------------------------------ */
 /* Gauss-Legendre rule on [-1, 1]: roots of P_n by Newton's method from the  */
-/* usual cosine initial guess, in long double, then rounded to double.       */
-/* Nodes are returned in increasing order.                                   */
+/* usual cosine initial guess, iterated in long double and finished with two */
+/* Newton steps in quad precision (__float128), so that every node and weight */
+/* is the correctly rounded double of the exact rule.  Ascending order.      */
 /* ------------------------------------------------------------------------ */
 static void legendre_p(int n, ld x, ld *p, ld *dp)
 {
@@ -74,6 +77,18 @@ static void legendre_p(int n, ld x, ld *p, ld *dp)
     *dp = (ld)n * (x * p1 - p0) / (x * x - 1.0L);
 }
 
+static void legendre_p_q(int n, qd x, qd *p, qd *dp)
+{
+    qd p0 = 1.0Q, p1 = x;
+    for (int m = 1; m < n; ++m) {
+        qd p2 = ((2.0Q * m + 1.0Q) * x * p1 - (qd)m * p0) / (qd)(m + 1);
+        p0 = p1;
+        p1 = p2;
+    }
+    *p = p1;
+    *dp = (qd)n * (x * p1 - p0) / (x * x - 1.0Q);
+}
+
 int orc_gauss_legendre(int n, double *x, double *w)
 {
     if (n < 1) return -1;
@@ -85,12 +100,19 @@ int orc_gauss_legendre(int n, double *x, double *w)
             legendre_p(n, z, &p, &dp);
             ld dz = p / dp;
             z -= dz;
-            if (fabsl(dz) < 1e-19L) break;
+            if (fabsl(dz) < 1e-18L) break;
         }
-        legendre_p(n, z, &p, &dp);
-        ld wi = 2.0L / ((1.0L - z * z) * dp * dp);
+        qd zq = (qd)z, pq, dpq;
+        for (int it = 0; it < 2; ++it) {
+            if (n == 1) { zq = 0.0Q; break; }
+            legendre_p_q(n, zq, &pq, &dpq);
+            zq -= pq / dpq;
+        }
+        if (n == 1) dpq = 1.0Q;
+        else legendre_p_q(n, zq, &pq, &dpq);
+        qd wi = 2.0Q / ((1.0Q - zq * zq) * dpq * dpq);
         /* store ascending */
-        x[n - 1 - i] = (double)z;
+        x[n - 1 - i] = (double)zq;
         w[n - 1 - i] = (double)wi;
     }
     return 0;

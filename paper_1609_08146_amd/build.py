@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libsc.so")
-SOURCES = ["sc_kernels.hip", "sc_api.cpp", "sc_serve.cpp"]
+SOURCES = ["sc_kernels.hip", "sc_api.cpp", "sc_serve.cpp", "sc_gauss_host.cpp"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [
@@ -46,9 +46,13 @@ def build(verbose: bool = False) -> str:
         if not os.path.exists(path):
             continue
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [cc, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", path, "-o", obj]
-        if src.endswith(".cpp"):
-            cmd[1:1] = ["-x", "hip"]
+        if src.endswith("_host.cpp"):
+            # host-only code (needs __float128): the system C++ compiler
+            cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", path, "-o", obj]
+        else:
+            cmd = [cc, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", path, "-o", obj]
+            if src.endswith(".cpp"):
+                cmd[1:1] = ["-x", "hip"]
         if verbose:
             print(" ".join(cmd), flush=True)
         res = subprocess.run(cmd, capture_output=True, text=True)
@@ -57,7 +61,7 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed on {src}")
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lquadmath", "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

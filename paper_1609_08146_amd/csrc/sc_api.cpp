@@ -166,63 +166,17 @@ extern "C" sc_status sc_prob_destroy(sc_prob *p)
     return SC_OK;
 }
 
-// Gauss-Legendre rule on [-1, 1] (ascending).  Roots of P_n from Tricomi's
-// asymptotic initial guess, refined by Newton's method in long double with
-// P_n and P_n' from their three-term recurrences; the rule is symmetric, so
-// only the positive half is computed.  Weights 2 / ((1 - x^2) P_n'(x)^2).
-static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+// Gauss-Legendre rules are computed once per order and kept by the context.
+static void gauss_rule_cached(sc_ctx *c, int n, const std::vector<double> *out[2])
 {
-    x.assign(n, 0.0);
-    w.assign(n, 0.0);
-    const long double pi = 3.141592653589793238462643383279502884L;
-    const long double nn = (long double)n;
-    for (int i = 1; i <= (n + 1) / 2; ++i) {
-        long double th = pi * (4.0L * i - 1.0L) / (4.0L * nn + 2.0L);
-        long double z = (1.0L - (nn - 1.0L) / (8.0L * nn * nn * nn)) * cosl(th);
-        long double dp = 1.0L;
-        int polish = 0;
-        for (int it = 0; it < 64; ++it) {
-            long double p0 = 1.0L, p1 = z, d0 = 0.0L, d1 = 1.0L;
-            for (int m = 1; m < n; ++m) {
-                long double p2 = ((2.0L * m + 1.0L) * z * p1 - m * p0) / (m + 1.0L);
-                long double d2 = d0 + (2.0L * m + 1.0L) * p1;   // P'_{m+1} = P'_{m-1} + (2m+1) P_m
-                p0 = p1;
-                p1 = p2;
-                d0 = d1;
-                d1 = d2;
-            }
-            if (n == 1) {
-                p1 = z;
-                d1 = 1.0L;
-            }
-            dp = d1;
-            long double step = p1 / d1;
-            z -= step;
-            if (fabsl(step) < 1e-11L) {
-                // quadratic convergence: one more step reaches long-double precision
-                if (++polish == 2) break;
-            }
-        }
-        // final derivative at the converged root
-        {
-            long double p0 = 1.0L, p1 = z, d0 = 0.0L, d1 = 1.0L;
-            for (int m = 1; m < n; ++m) {
-                long double p2 = ((2.0L * m + 1.0L) * z * p1 - m * p0) / (m + 1.0L);
-                long double d2 = d0 + (2.0L * m + 1.0L) * p1;
-                p0 = p1;
-                p1 = p2;
-                d0 = d1;
-                d1 = d2;
-            }
-            dp = (n == 1) ? 1.0L : d1;
-        }
-        long double wi = 2.0L / ((1.0L - z * z) * dp * dp);
-        if (2 * i - 1 == n) z = 0.0L;   // middle node of an odd rule
-        x[n - i] = (double)z;
-        x[i - 1] = -(double)z;
-        w[n - i] = (double)wi;
-        w[i - 1] = (double)wi;
+    auto it = c->gauss.find(n);
+    if (it == c->gauss.end()) {
+        std::pair<std::vector<double>, std::vector<double>> r;
+        gauss_legendre_rule(n, r.first, r.second);
+        it = c->gauss.emplace(n, std::move(r)).first;
     }
+    out[0] = &it->second.first;
+    out[1] = &it->second.second;
 }
 
 static void invalidate_tables(sc_prob *p)
@@ -267,8 +221,9 @@ extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, 
         return fail(SC_E_INVAL, "sc_set_mirror: (n_r+1)*n_phi must be < 2^31");
     DeviceGuard g(p->ctx->device);
     hipStream_t st = p->ctx->stream;
-    std::vector<double> x, w;
-    gauss_legendre(n_r, x, w);
+    const std::vector<double> *xw[2];
+    gauss_rule_cached(p->ctx, n_r, xw);
+    const std::vector<double> &x = *xw[0], &w = *xw[1];
     std::vector<double> r(n_r + 1), wr(n_r), c(n_phi), s(n_phi);
     for (int i = 0; i < n_r; ++i) {
         r[i] = r_max * (1.0 + x[i]) / 2.0;
@@ -452,9 +407,12 @@ extern "C" sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs
 
 static sc_launch default_launch(sc_precision prec)
 {
+    // measured fastest on MI355X for the broadband workload, both precisions:
+    // one point x two frequencies per lane (the geometry is shared by the two)
+    (void)prec;
     sc_launch l{};
-    l.obs_per_lane = (prec == SC_FP64) ? 1 : 2;
-    l.freq_per_lane = 1;
+    l.obs_per_lane = 1;
+    l.freq_per_lane = 2;
     l.waves_per_block = 4;
     l.chunk = 4096;
     l.blocks_per_cu = 0;   // 0 = occupancy limit

@@ -114,6 +114,7 @@ struct sc_ctx {
     std::vector<sc::QuadJob> host_jobs;
     hipEvent_t upload_done = nullptr;
     std::map<sc::TuneKey, sc_launch> tune;
+    std::map<int, std::pair<std::vector<double>, std::vector<double>>> gauss;   // Gauss-Legendre rules by order
     int n_probs = 0;   // live problems (a context outlives its problems)
 };
 
@@ -154,6 +155,9 @@ struct sc_prob {
 namespace sc {
 
 constexpr int OBS_PAD = 128;   // observation padding (64 lanes x up to 2 points per lane)
+
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1], correctly rounded (sc_gauss_host.cpp).
+void gauss_legendre_rule(int n, std::vector<double> &x, std::vector<double> &w);
 
 // Launch shape for a problem and precision (override > tuned > default).
 sc_launch resolve_launch(const sc_prob *p, sc_precision prec);

@@ -120,8 +120,8 @@ static void release_prob(Req *r)
 }
 
 // One kernel shape per precision, so that requests of a precision share launches.
-static int server_opl(sc_precision prec) { return prec == SC_FP64 ? 1 : 2; }
-static int server_fpb(sc_precision) { return 1; }
+static int server_opl(sc_precision) { return 1; }
+static int server_fpb(sc_precision) { return 2; }
 
 // Build the request's device state on the preparation stream.
 static sc_status setup_request(sc_server *s, Req *r)

@@ -46,10 +46,10 @@ def make_problem(ctx, f, a, n_r, n_phi, k, obs, launch=None):
 
 
 def test_nodes_match_oracle(ctx, orc):
-    # Independent implementations of the same rule.  Each side rounds its
-    # long-double Gauss-Legendre roots to double; a root lying within ~1e-19 of
-    # a rounding boundary can round differently (one radial ring then differs
-    # by an ulp), so coordinates agree to 2 ulp of the mirror's length scale.
+    # Independent implementations of the same rule; both round quad-precision
+    # Gauss-Legendre roots, so the rules are bitwise equal and the node records
+    # (IEEE products and quotients of them) should be too.  Asserted to 2 ulp
+    # of the mirror's length scale; the count of inexact entries is printed.
     for (f, a, nr, nphi) in [(20.0, 40.0, 200, 200), (0.1, 0.075, 37, 24), (0.05, 0.15, 801, 16)]:
         p = make_problem(ctx, f, a, nr, nphi, [K], np.zeros((1, 3)))
         xyz, nrm, w = p.get_nodes()

@@ -65,9 +65,11 @@ MUTANTS = [
     ("consistent_c1", [("- 4.0 * y * y / (kw2 * kw2)", "- 4.0 * x * x / (kw2 * kw2)", 1)]),
     ("gauss_width", [("exp(-(x * x + y * y) / (w0 * w0))", "exp(-(x * x + y * y) / (2.0 * w0 * w0))", 1)]),
     ("pol_rotation", [("double y = -sp * X + cp * Y;", "double y = sp * X + cp * Y;", 1)]),
-    ("gl_weight", [("ld wi = 2.0L / ((1.0L - z * z) * dp * dp);", "ld wi = 2.0L / ((1.0L + z * z) * dp * dp);", 1)]),
+    ("gl_weight", [("qd wi = 2.0Q / ((1.0Q - zq * zq) * dpq * dpq);", "qd wi = 2.0Q / ((1.0Q + zq * zq) * dpq * dpq);", 1)]),
     ("gl_recurrence", [("ld p2 = ((2.0L * m + 1.0L) * x * p1 - (ld)m * p0) / (ld)(m + 1);",
-                        "ld p2 = ((2.0L * m + 1.0L) * x * p1 - (ld)m * p0) / (ld)(m + 2);", 1)]),
+                        "ld p2 = ((2.0L * m + 1.0L) * x * p1 - (ld)m * p0) / (ld)(m + 2);", 1),
+                       ("qd p2 = ((2.0Q * m + 1.0Q) * x * p1 - (qd)m * p0) / (qd)(m + 1);",
+                        "qd p2 = ((2.0Q * m + 1.0Q) * x * p1 - (qd)m * p0) / (qd)(m + 2);", 1)]),
     ("output_transpose", [("size_t off = ((size_t)ik * n_obs + o) * 6;", "size_t off = ((size_t)o * n_k + ik) * 6;", -2)]),
     ("dgrad_sign", [("cld c1 = { -1.0L / (R * R), k / R };", "cld c1 = { 1.0L / (R * R), k / R };", 1)]),
     ("time_sign", [("sincosl(-(ld)kv[n] * (ld)t[m], &s, &c);", "sincosl((ld)kv[n] * (ld)t[m], &s, &c);", 1)]),
