@@ -93,7 +93,7 @@ extern "C" sc_status sc_ctx_destroy(sc_ctx *c)
 {
     if (!c) return SC_OK;
     if (c->n_probs > 0)
-        return fail(SC_E_STATE, "sc_ctx_destroy: %d problem(s) still alive on this context", c->n_probs);
+        return fail(SC_E_STATE, "sc_ctx_destroy: %d problem(s) still alive on this context", c->n_probs.load());
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);

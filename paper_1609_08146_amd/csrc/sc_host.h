@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
 #include <string>
 #include <tuple>
@@ -115,7 +116,7 @@ struct sc_ctx {
     hipEvent_t upload_done = nullptr;
     std::map<sc::TuneKey, sc_launch> tune;
     std::map<int, std::pair<std::vector<double>, std::vector<double>>> gauss;   // Gauss-Legendre rules by order
-    int n_probs = 0;   // live problems (a context outlives its problems)
+    std::atomic<int> n_probs{0};   // live problems and servers (a context outlives them)
 };
 
 struct sc_prob {

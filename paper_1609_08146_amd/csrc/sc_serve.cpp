@@ -1,10 +1,11 @@
 // sc_serve.cpp -- continuous-batching serving loop for field solves.
 //
 // Requests (mirror + beam + spectrum + observation points) arrive from any
-// host thread.  A worker thread admits them in arrival order while their HBM
-// footprint fits the budget and the running count allows, builds their
-// mirror / incident tables on a preparation stream (tables stay resident for
-// the request's lifetime), and schedules the quadrature tiles of ALL running
+// host thread.  A scheduler thread admits them in arrival order while their
+// HBM footprint fits the budget and the running count allows; a preparation
+// thread builds their mirror / incident tables on a preparation stream
+// (tables stay resident for the request's lifetime); the scheduler launches
+// the quadrature tiles of ALL running
 // requests together: each scheduling quantum is one persistent launch whose
 // tile list holds a share of every running request's remaining tiles, sized to
 // about `quantum_ms` of work.  A request that arrives while others are on the
@@ -78,10 +79,13 @@ struct sc_server {
     size_t budget = 0;
     int max_running = 1;
     double quantum_ms = 20.0;
-    std::thread worker;
+    std::thread worker;     // scheduler: admission, quanta, completion
+    std::thread preparer;   // builds admitted requests' tables off the scheduling path
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_prep;
     bool stop = false;
+    std::deque<Req *> to_prepare;   // admitted, tables not built yet
+    int preparing = 0;
     uint64_t next_ticket = 1;
     std::deque<Req *> queue;
     std::vector<Req *> active;
@@ -91,7 +95,8 @@ struct sc_server {
     DevBuf jobbuf[RING];
     QuadJob *hjobs[RING] = {};
     size_t hjobs_cap[RING] = {};
-    hipEvent_t slot_ev[RING] = {};
+    hipEvent_t slot_ev[RING] = {};     // end of the quantum launched from this slot (timed)
+    hipEvent_t slot_start[RING] = {};  // start of that quantum (timed)
     bool slot_busy[RING] = {};
     std::deque<Quantum> inflight;
     double evals_per_ms = 1.0e8;   // running throughput estimate used to size quanta
@@ -252,6 +257,7 @@ static sc_status launch_quantum(sc_server *s)
     HIP_TRY(hipMemcpyAsync(s->jobbuf[slot].p, s->hjobs[slot], sizeof(QuadJob) * jobs.size(), hipMemcpyHostToDevice,
                            st));
     HIP_TRY(launch_fill_u32(st, s->ctx->counter.as<unsigned int>(), 0u, 1));
+    HIP_TRY(hipEventRecord(s->slot_start[slot], st));
     const int mode = mode_of(prec);
     const int wpb = 4;
     const int occ = quad_max_blocks_per_cu(mode, opl, fpb, wpb);
@@ -287,14 +293,41 @@ static void complete_request(sc_server *s, Req *r, ReqState state, sc_status st,
     s->cv_done.notify_all();
 }
 
+// Preparation thread: builds the tables of admitted requests on the preparation
+// stream, then hands them to the scheduler.
+static void prep_main(sc_server *s)
+{
+    (void)hipSetDevice(s->ctx->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        s->cv_prep.wait(lk, [s] { return s->stop || !s->to_prepare.empty(); });
+        if (s->to_prepare.empty()) {
+            if (s->stop) break;
+            continue;
+        }
+        Req *r = s->to_prepare.front();
+        s->to_prepare.pop_front();
+        s->preparing++;
+        lk.unlock();
+        const sc_status st = setup_request(s, r);
+        const std::string err = st == SC_OK ? std::string() : std::string(sc_last_error());
+        lk.lock();
+        s->preparing--;
+        if (st == SC_OK) s->active.push_back(r);
+        else complete_request(s, r, R_FAILED, st, err);
+        s->cv_work.notify_one();
+    }
+}
+
 static void worker_main(sc_server *s)
 {
     (void)hipSetDevice(s->ctx->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         // 1. admission, in arrival order, while memory and running slots allow
-        std::vector<Req *> admitted;
-        while (!s->queue.empty() && (int)(s->active.size() + admitted.size()) < s->max_running) {
+        bool admitted = false;
+        while (!s->queue.empty() &&
+               (int)(s->active.size() + s->to_prepare.size()) + s->preparing < s->max_running) {
             Req *r = s->queue.front();
             if (s->stats.hbm_in_use + r->bytes > s->budget) break;
             s->queue.pop_front();
@@ -304,21 +337,10 @@ static void worker_main(sc_server *s)
             s->stats.admitted++;
             s->stats.queued--;
             s->stats.running++;
-            admitted.push_back(r);
+            s->to_prepare.push_back(r);
+            admitted = true;
         }
-        if (!admitted.empty()) {
-            lk.unlock();
-            std::vector<std::pair<sc_status, std::string>> res;
-            for (Req *r : admitted) {
-                sc_status st = setup_request(s, r);
-                res.push_back({st, st == SC_OK ? std::string() : std::string(sc_last_error())});
-            }
-            lk.lock();
-            for (size_t i = 0; i < admitted.size(); ++i) {
-                if (res[i].first == SC_OK) s->active.push_back(admitted[i]);
-                else complete_request(s, admitted[i], R_FAILED, res[i].first, res[i].second);
-            }
-        }
+        if (admitted) s->cv_prep.notify_one();
         // 2. requests whose results reached the host
         for (size_t i = 0; i < s->active.size();) {
             Req *r = s->active[i];
@@ -329,11 +351,12 @@ static void worker_main(sc_server *s)
                 ++i;
             }
         }
-        // 3. finished quanta update the throughput estimate
+        // 3. finished quanta: their measured device time sizes the next ones
         while (!s->inflight.empty() && hipEventQuery(s->slot_ev[s->inflight.front().slot]) == hipSuccess) {
             const Quantum &q = s->inflight.front();
-            const double ms = ms_between(q.t_launch, Clock::now());
-            if (ms > 0.5 && s->inflight.size() == 1) s->evals_per_ms = 0.7 * s->evals_per_ms + 0.3 * (q.evals / ms);
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, s->slot_start[q.slot], s->slot_ev[q.slot]) == hipSuccess && ms > 0.05f)
+                s->evals_per_ms = 0.7 * s->evals_per_ms + 0.3 * (q.evals / (double)ms);
             s->slot_busy[q.slot] = false;
             s->inflight.pop_front();
         }
@@ -352,9 +375,11 @@ static void worker_main(sc_server *s)
             }
             continue;
         }
-        if (s->stop && s->queue.empty() && s->active.empty() && s->inflight.empty()) break;
-        // 5. wait for a submission, or poll the device
-        if (s->active.empty() && s->inflight.empty() && (s->queue.empty() || !s->stop))
+        if (s->stop && s->queue.empty() && s->active.empty() && s->inflight.empty() && s->to_prepare.empty() &&
+            s->preparing == 0)
+            break;
+        // 5. wait for a submission or a prepared request, or poll the device
+        if (s->active.empty() && s->inflight.empty())
             s->cv_work.wait_for(lk, std::chrono::milliseconds(s->queue.empty() ? 50 : 1));
         else
             s->cv_work.wait_for(lk, std::chrono::microseconds(200));
@@ -385,14 +410,18 @@ extern "C" sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_ru
     }
     s->prep->tune = ctx->tune;
     for (int i = 0; i < sc_server::RING; ++i)
-        if (hipEventCreateWithFlags(&s->slot_ev[i], hipEventDisableTiming) != hipSuccess) {
-            for (int j = 0; j < i; ++j) (void)hipEventDestroy(s->slot_ev[j]);
+        if (hipEventCreate(&s->slot_ev[i]) != hipSuccess || hipEventCreate(&s->slot_start[i]) != hipSuccess) {
+            for (int j = 0; j <= i; ++j) {
+                if (s->slot_ev[j]) (void)hipEventDestroy(s->slot_ev[j]);
+                if (s->slot_start[j]) (void)hipEventDestroy(s->slot_start[j]);
+            }
             (void)sc_ctx_destroy(s->prep);
             delete s;
             return fail(SC_E_DEVICE, "sc_server_create: hipEventCreate failed");
         }
     ctx->n_probs++;   // the context must outlive the server
     s->worker = std::thread(worker_main, s);
+    s->preparer = std::thread(prep_main, s);
     *out = s;
     return SC_OK;
 }
@@ -542,7 +571,13 @@ extern "C" sc_status sc_server_destroy(sc_server *s)
         s->cv_done.notify_all();
     }
     s->cv_work.notify_all();
+    s->cv_prep.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->cv_prep.notify_all();
+    }
+    if (s->preparer.joinable()) s->preparer.join();
     DeviceGuard g(s->ctx->device);
     (void)hipStreamSynchronize(s->ctx->stream);
     for (auto &kv : s->all) {
@@ -553,6 +588,7 @@ extern "C" sc_status sc_server_destroy(sc_server *s)
     s->all.clear();
     for (int i = 0; i < sc_server::RING; ++i) {
         if (s->slot_ev[i]) (void)hipEventDestroy(s->slot_ev[i]);
+        if (s->slot_start[i]) (void)hipEventDestroy(s->slot_start[i]);
         if (s->hjobs[i]) (void)hipHostFree(s->hjobs[i]);
         s->jobbuf[i].release();
     }
