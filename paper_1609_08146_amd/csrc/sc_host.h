@@ -10,7 +10,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/sc.h"
+#include "sc.h"
 #include "sc_internal.h"
 
 namespace sc {

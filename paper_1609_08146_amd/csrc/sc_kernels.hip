@@ -249,10 +249,11 @@ typedef __attribute__((address_space(4))) const v4f cv4f;
 typedef __attribute__((address_space(4))) const double cdouble;
 typedef __attribute__((address_space(4))) const QuadJob cjob;
 
-// sin and cos of theta = 2 pi * t, t in turns (hardware v_sin/v_cos on [-0.5, 0.5] turns)
+// sin and cos of theta = 2 pi * t, t in turns: hardware v_sin / v_cos on the
+// fractional part (the exact reduction modulo one turn, in [0, 1)).
 __device__ __forceinline__ void sincos_turns(float t, float &s, float &c)
 {
-    const float r = t - rintf(t);
+    const float r = __builtin_amdgcn_fractf(t);
     s = __builtin_amdgcn_sinf(r);
     c = __builtin_amdgcn_cosf(r);
 }
@@ -519,50 +520,65 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
                         cmp[s][f][c] = 0.0f;
                     }
             }
-            for (int nb = n0; nb < n1; nb += KAHAN_BLOCK) {
-                const int ne = min(nb + KAHAN_BLOCK, n1);
-                float blk[OPL][FPB][12];
+            float blk[OPL][FPB][12];
 #pragma unroll
-                for (int s = 0; s < OPL; ++s)
+            for (int s = 0; s < OPL; ++s)
 #pragma unroll
-                    for (int f = 0; f < FPB; ++f)
+                for (int f = 0; f < FPB; ++f)
 #pragma unroll
-                        for (int c = 0; c < 12; ++c) blk[s][f][c] = 0.0f;
-                for (int n = nb; n < ne; ++n) {
-                    const v4f pn = pos[n];
-                    v4f t0[FPB], t1[FPB];
+                    for (int c = 0; c < 12; ++c) blk[s][f][c] = 0.0f;
+            // node data of node n+1 is loaded while node n is computed
+            v4f pn = pos[n0];
+            v4f t0[FPB], t1[FPB];
 #pragma unroll
-                    for (int f = 0; f < FPB; ++f) {
-                        t0[f] = tab[f][2 * n];
-                        t1[f] = tab[f][2 * n + 1];
-                    }
+            for (int f = 0; f < FPB; ++f) {
+                t0[f] = tab[f][2 * n0];
+                t1[f] = tab[f][2 * n0 + 1];
+            }
+            for (int n = n0; n < n1; ++n) {
+                const int nx = min(n + 1, n1 - 1);
+                const v4f pnx = pos[nx];
+                v4f t0x[FPB], t1x[FPB];
 #pragma unroll
-                    for (int s = 0; s < OPL; ++s) {
-                        if constexpr (MODE == MODE_SPLIT) {
-                            const GeomF g = geom_split(pn, o[s]);
+                for (int f = 0; f < FPB; ++f) {
+                    t0x[f] = tab[f][2 * nx];
+                    t1x[f] = tab[f][2 * nx + 1];
+                }
 #pragma unroll
-                            for (int f = 0; f < FPB; ++f) freq_split(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
-                        } else {
-                            GeomF g;
-                            float R;
-                            geom_naive(pn, o[s], g, R);
+                for (int s = 0; s < OPL; ++s) {
+                    if constexpr (MODE == MODE_SPLIT) {
+                        const GeomF g = geom_split(pn, o[s]);
 #pragma unroll
-                            for (int f = 0; f < FPB; ++f) freq_naive(g, R, t0[f], t1[f], k[f], blk[s][f]);
-                        }
+                        for (int f = 0; f < FPB; ++f) freq_split(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
+                    } else {
+                        GeomF g;
+                        float R;
+                        geom_naive(pn, o[s], g, R);
+#pragma unroll
+                        for (int f = 0; f < FPB; ++f) freq_naive(g, R, t0[f], t1[f], k[f], blk[s][f]);
                     }
                 }
-                // compensated add of the block partials
+                // every KAHAN_BLOCK nodes (counted from the chunk start), a compensated add
+                if ((n - n0) % KAHAN_BLOCK == KAHAN_BLOCK - 1 || n == n1 - 1) {
 #pragma unroll
-                for (int s = 0; s < OPL; ++s)
+                    for (int s = 0; s < OPL; ++s)
 #pragma unroll
-                    for (int f = 0; f < FPB; ++f)
+                        for (int f = 0; f < FPB; ++f)
 #pragma unroll
-                        for (int c = 0; c < 12; ++c) {
-                            const float y = blk[s][f][c] - cmp[s][f][c];
-                            const float tsum = sum[s][f][c] + y;
-                            cmp[s][f][c] = (tsum - sum[s][f][c]) - y;
-                            sum[s][f][c] = tsum;
-                        }
+                            for (int c = 0; c < 12; ++c) {
+                                const float y = blk[s][f][c] - cmp[s][f][c];
+                                const float tsum = sum[s][f][c] + y;
+                                cmp[s][f][c] = (tsum - sum[s][f][c]) - y;
+                                sum[s][f][c] = tsum;
+                                blk[s][f][c] = 0.0f;
+                            }
+                }
+                pn = pnx;
+#pragma unroll
+                for (int f = 0; f < FPB; ++f) {
+                    t0[f] = t0x[f];
+                    t1[f] = t1x[f];
+                }
             }
 #pragma unroll
             for (int f = 0; f < FPB; ++f) {
