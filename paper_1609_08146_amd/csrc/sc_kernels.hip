@@ -508,18 +508,22 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
             }
             const v4f *obs = (const v4f *)jobs[j].obs;
             v4f o[OPL];
-            float sum[OPL][FPB][12], cmp[OPL][FPB][12];
+            // Running sums stay in registers; their Kahan compensations live in LDS
+            // (touched once per KAHAN_BLOCK nodes), which frees VGPRs for occupancy.
+            // dynamic LDS: [waves per block][OPL * FPB * 12][64] floats
+            extern __shared__ float lds_dyn[];
+            float(*cmp)[64] = (float(*)[64])(lds_dyn + (size_t)(threadIdx.x >> 6) * (OPL * FPB * 12 * 64));
+            float sum[OPL][FPB][12];
 #pragma unroll
             for (int s = 0; s < OPL; ++s) {
                 o[s] = obs[obase + 64 * s];
 #pragma unroll
                 for (int f = 0; f < FPB; ++f)
 #pragma unroll
-                    for (int c = 0; c < 12; ++c) {
-                        sum[s][f][c] = 0.0f;
-                        cmp[s][f][c] = 0.0f;
-                    }
+                    for (int c = 0; c < 12; ++c) sum[s][f][c] = 0.0f;
             }
+#pragma unroll
+            for (int a = 0; a < OPL * FPB * 12; ++a) cmp[a][lane] = 0.0f;
             float blk[OPL][FPB][12];
 #pragma unroll
             for (int s = 0; s < OPL; ++s)
@@ -566,9 +570,10 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
                         for (int f = 0; f < FPB; ++f)
 #pragma unroll
                             for (int c = 0; c < 12; ++c) {
-                                const float y = blk[s][f][c] - cmp[s][f][c];
+                                const int a = (s * FPB + f) * 12 + c;
+                                const float y = blk[s][f][c] - cmp[a][lane];
                                 const float tsum = sum[s][f][c] + y;
-                                cmp[s][f][c] = (tsum - sum[s][f][c]) - y;
+                                cmp[a][lane] = (tsum - sum[s][f][c]) - y;
                                 sum[s][f][c] = tsum;
                                 blk[s][f][c] = 0.0f;
                             }
@@ -588,7 +593,7 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
                 for (int s = 0; s < OPL; ++s)
 #pragma unroll
                     for (int c = 0; c < 12; ++c)
-                        part[(size_t)c * n_obs_pad + obase + 64 * s] = sum[s][f][c] - cmp[s][f][c];
+                        part[(size_t)c * n_obs_pad + obase + 64 * s] = sum[s][f][c] - cmp[(s * FPB + f) * 12 + c][lane];
             }
         }
     }
@@ -739,11 +744,19 @@ static const void *quad_fn_dyn(int mode, int opl, int fpb)
     return nullptr;
 }
 
+// Dynamic LDS of one quadrature block: the FP32 forms keep their Kahan compensations there.
+static size_t quad_lds_bytes(int mode, int opl, int fpb, int waves_per_block)
+{
+    return mode == MODE_FP64 ? 0 : sizeof(float) * 64 * 12 * (size_t)opl * fpb * waves_per_block;
+}
+
 int quad_max_blocks_per_cu(int mode, int opl, int fpb, int waves_per_block)
 {
     const void *fn = quad_fn_dyn(mode, opl, fpb);
     int nb = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * waves_per_block, 0) != hipSuccess)
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * waves_per_block,
+                                                            quad_lds_bytes(mode, opl, fpb, waves_per_block)) !=
+                   hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
@@ -753,9 +766,10 @@ hipError_t launch_quad(hipStream_t st, int mode, int opl, int fpb, int waves_per
 {
     if (!shape_ok(opl, fpb)) return hipErrorInvalidValue;
     dim3 g(grid), b(64 * waves_per_block);
+    const size_t lds = quad_lds_bytes(mode, opl, fpb, waves_per_block);
 #define SC_QUAD_LAUNCH(M, O, F)                                                                          \
     if (mode == M && opl == O && fpb == F) {                                                            \
-        hipLaunchKernelGGL((k_quad<M, O, F>), g, b, 0, st, jobs, n_jobs, n_tiles, counter);             \
+        hipLaunchKernelGGL((k_quad<M, O, F>), g, b, lds, st, jobs, n_jobs, n_tiles, counter);           \
         return hipGetLastError();                                                                       \
     }
     SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_FP64)
