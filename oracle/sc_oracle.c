@@ -140,7 +140,8 @@ int orc_mirror(int kind, double f, double a, int n_r, int n_phi,
         double wr = (i < n_r) ? a * wg[i] / 2.0 : 0.0;
         for (int j = 0; j < n_phi; ++j) {
             double phi = 2.0 * M_PI * (double)j / (double)n_phi;
-            double c = cos(phi), s = sin(phi);
+            double c, s;
+            sincos(phi, &s, &c);   /* glibc sincos (sin and cos may differ from it in the last bit) */
             size_t q = (size_t)i * n_phi + j;
             double x = r * c, y = r * s;
             double z = (kind == 0) ? r * r / (4.0 * f) - f : 0.0;

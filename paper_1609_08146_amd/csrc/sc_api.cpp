@@ -232,8 +232,7 @@ extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, 
     r[n_r] = r_max;
     for (int j = 0; j < n_phi; ++j) {
         double phi = 2.0 * M_PI * (double)j / (double)n_phi;
-        c[j] = cos(phi);
-        s[j] = sin(phi);
+        sincos(phi, &s[j], &c[j]);   // libm sincos: one correctly paired evaluation
     }
     const int n_tot = (n_r + 1) * n_phi;
     invalidate_tables(p);

@@ -46,19 +46,20 @@ def make_problem(ctx, f, a, n_r, n_phi, k, obs, launch=None):
 
 
 def test_nodes_match_oracle(ctx, orc):
-    # Independent implementations of the same rule; both round quad-precision
-    # Gauss-Legendre roots, so the rules are bitwise equal and the node records
-    # (IEEE products and quotients of them) should be too.  Asserted to 2 ulp
-    # of the mirror's length scale; the count of inexact entries is printed.
-    for (f, a, nr, nphi) in [(20.0, 40.0, 200, 200), (0.1, 0.075, 37, 24), (0.05, 0.15, 801, 16)]:
+    # Independent implementations of the same rule: both round quad-precision
+    # Gauss-Legendre roots and evaluate the phi nodes with libm's sincos, and
+    # the device forms the node records with IEEE products and quotients, so
+    # the node sets are bitwise equal.  (A 1-ulp node difference moves a phase
+    # by ~1e-10 rad at k ~ 1e7 / m, which is visible at the FP64 tolerance.)
+    for (f, a, nr, nphi) in [(20.0, 40.0, 200, 200), (0.1, 0.075, 60, 60), (0.1, 0.075, 37, 24),
+                             (0.05, 0.15, 801, 16)]:
         p = make_problem(ctx, f, a, nr, nphi, [K], np.zeros((1, 3)))
         xyz, nrm, w = p.get_nodes()
         m = orc.mirror(f, a, nr, nphi)
-        scale = {"xyz": a + f, "normal": 1.0 + a / (2 * f), "weight": np.abs(m.wgt).max()}
         for name, g, o in (("xyz", xyz, m.pos), ("normal", nrm, m.nrm), ("weight", w, m.wgt)):
-            d = np.abs(g - o) / np.spacing(scale[name])
-            print(f"{name}: {np.count_nonzero(d)} of {d.size} entries differ, max {d.max():.2f} ulp of scale")
-            assert d.max() <= 2.0, name
+            n_diff = int(np.count_nonzero(g != o))
+            print(f"{name}: {n_diff} of {g.size} entries differ")
+            assert n_diff == 0, name
         p.close()
 
 
