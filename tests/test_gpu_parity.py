@@ -149,7 +149,8 @@ def test_time_transform(ctx, orc):
         e_all = max(rel_l2(Et, Eto), rel_l2(Bt, Bto))
         print(f"{prec}: spectrum {e_spec:.2e}, transform {e_tr:.2e}, end to end {e_all:.2e}")
         assert e_spec < tol, prec
-        assert e_tr < (1e-14 if prec == "fp64" else 1e-6), prec
+        # the oracle rounds k t (~1.6e6 rad) to a 64-bit mantissa: up to ~8.5e-14 rad per twiddle
+        assert e_tr < (2e-13 if prec == "fp64" else 1e-6), prec
         assert e_all < tol, prec
     p.close()
 
