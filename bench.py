@@ -52,6 +52,38 @@ PEAK_FP32 = 256 * 4 * 32 * 2 * 2.4e9 / 1e12   # 157.3 TFLOP/s
 PEAK_FP64 = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6 TFLOP/s
 
 
+# HBM traffic of the quadrature kernel, from the committed rocprofv3 counter
+# summary; reported only while the kernel sources are the ones it was taken on.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_quad_broadband_hbm_traffic.md")
+KERNEL_SOURCES = ["paper_1609_08146_amd/csrc/sc_kernels.hip", "paper_1609_08146_amd/csrc/sc_device.h",
+                  "paper_1609_08146_amd/csrc/sc_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Calibrated HBM bytes per quadrature launch, or None if the kernel changed since the counters."""
+    try:
+        fields = {}
+        with open(TRAFFIC_PROFILE) as fh:
+            for line in fh:
+                key, sep, val = line.strip().partition(":")
+                if sep and key in ("kernel_source_sha256", "traffic_bytes_per_launch"):
+                    fields[key] = val.strip()
+        if fields.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +315,8 @@ def main():
     fpe = flops_per_eval()
     achieved = fpe * evals / (quad_avg * 1e-3) / 1e12
     peak = PEAK_FP64 if args.precision == "fp64" else PEAK_FP32
+    # the counters were taken on the full FP32-split workload with the default launch
+    traffic = measured_traffic() if (args.precision == "fp32_split" and args.shard == 1) else None
     out = {
         "metric": "integrand evals/s (obs x freq x node), whole step, one GPU",
         "value": value,
@@ -311,7 +345,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flops_per_eval": fpe,
             "quad_ms_avg": quad_avg,
             "quad_launches": len(quad_ms),

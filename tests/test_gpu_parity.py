@@ -177,6 +177,42 @@ def test_launch_shape_does_not_change_bits(ctx):
     p.close()
 
 
+def test_autotune_keeps_the_bits_and_its_cache_round_trips(ctx, tmp_path):
+    """The tuner searches launch shapes at a fixed node chunk, so the tuned launch must give the
+    default launch's bits; its cache file must load back into a fresh context and reject junk."""
+    from paper_1609_08146_amd import Context, ScError, problem_from_workload
+    w = workloads.broadband(n_k=6, n_nodes=96).subset(obs_idx=np.arange(0, 4160, 13))
+    p = problem_from_workload(ctx, w)
+    E0, B0 = p.evaluate("fp32_split")
+    best = p.autotune("fp32_split", budget_ms=20000)
+    assert best["obs_per_lane"] in (1, 2) and best["freq_per_lane"] in (1, 2, 4)
+    assert best["waves_per_block"] in (1, 2, 4) and best["blocks_per_cu"] in (0, 1, 2)
+    E1, B1 = p.evaluate("fp32_split")        # resolved from the context's tuning cache
+    assert np.array_equal(E0, E1) and np.array_equal(B0, B1)
+    path = tmp_path / "tune.txt"
+    ctx.autotune_save(str(path))
+    rows = [ln.split() for ln in path.read_text().splitlines() if not ln.startswith("#")]
+    assert any([int(x) for x in r[4:]] == [best["obs_per_lane"], best["waves_per_block"], best["chunk"],
+                                          best["blocks_per_cu"], best["freq_per_lane"]] for r in rows)
+    ctx2 = Context(0)
+    try:
+        ctx2.autotune_load(str(path))
+        p2 = problem_from_workload(ctx2, w)
+        E2, B2 = p2.evaluate("fp32_split")
+        assert np.array_equal(E0, E2) and np.array_equal(B0, B2)
+        p2.close()
+        bad = tmp_path / "bad.txt"
+        bad.write_text("1 2 3\n")
+        with pytest.raises(ScError):
+            ctx2.autotune_load(str(bad))
+        bad.write_text("1 8 2 17 3 4 4096 0 2\n")     # 3 observation points per lane: not a kernel shape
+        with pytest.raises(ScError):
+            ctx2.autotune_load(str(bad))
+    finally:
+        ctx2.close()
+    p.close()
+
+
 def test_batch_equals_alone_bitwise(ctx):
     from paper_1609_08146_amd import problem_from_workload
     ws = workloads.sweep(5)
