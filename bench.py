@@ -55,8 +55,8 @@ PEAK_FP64 = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6 TFLOP/s
 # HBM traffic of the quadrature kernel, from the committed rocprofv3 counter
 # summary; reported only while the kernel sources are the ones it was taken on.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_quad_broadband_hbm_traffic.md")
-KERNEL_SOURCES = ["paper_1609_08146_amd/csrc/sc_kernels.hip", "paper_1609_08146_amd/csrc/sc_device.h",
-                  "paper_1609_08146_amd/csrc/sc_internal.h"]
+KERNEL_SOURCES = ["paper_1609_08146_amd/csrc/sc_quad.hip", "paper_1609_08146_amd/csrc/sc_device.h",
+                  "paper_1609_08146_amd/csrc/sc_quadjob.h"]
 
 
 def kernel_source_hash() -> str:

@@ -174,6 +174,32 @@ sc_status sc_set_incident(sc_prob *p, const double *E, const double *B, int on_d
 sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_angle,
                                    const double *spectrum, int consistent);
 
+/* Power carried by each frequency component of the incident field through
+ * the mirror aperture (Sec. III-B, the Poynting integral that fixes the
+ * energy of a component):
+ *   P[n] = 4 pi SS Re(E_n x B_n^*) . dA,   dA = -z dx dy over r <= r_max
+ * (the beam travels along -z), by the same quadrature as the mirror integrals
+ * projected on the aperture plane (surface weights w_r r dphi; rim nodes do
+ * not enter).  Computed on the device whenever the incident field is set and
+ * kept up to date by sc_scale_spectrum / sc_normalize_energy.
+ * P: host [n_k].  SC_E_STATE without an incident field.                     */
+sc_status sc_get_incident_power(const sc_prob *p, double *P);
+/* Multiply frequency n of the incident field by factor[n] (complex128 [n_k],
+ * host): a spectral amplitude and phase, e.g. a chirp e^{i phi(omega)}
+ * (Sec. III-B).  Earlier results are discarded; P[n] scales by |factor[n]|^2.
+ * SC_E_STATE without an incident field; SC_E_INVAL for non-finite factors. */
+sc_status sc_scale_spectrum(sc_prob *p, const double *factor);
+/* Energy normalisation of the incident spectrum (Sec. III-B, eqs.
+ * normalizationAmplitude and totalEnergy).  eps: host [n_k] power spectrum
+ * samples eps(k_n) >= 0 (energy per unit k).  If e_tot > 0 they are first
+ * rescaled so that sum_n eps_n dk = e_tot (the discrete total-energy
+ * condition; dk > 0 required), else taken as given.  Frequency n is then
+ * multiplied by E0_n = sqrt(eps_n / P[n]) with P[n] the current incident
+ * power, so that afterwards sc_get_incident_power returns eps_n.  A sample
+ * with eps_n = 0 removes its component.  SC_E_INVAL for negative or
+ * non-finite eps, or a component with eps_n > 0 but no power (P[n] <= 0).  */
+sc_status sc_normalize_energy(sc_prob *p, const double *eps, double e_tot, double dk);
+
 /* Table storage.  keep_fp64 = 1 (default) keeps the FP64 tables (64 B per
  * (k, node)) so every precision can be evaluated; keep_fp64 = 0 casts them to
  * the FP32 split tables (32 B per record) as soon as they are built and frees

@@ -60,6 +60,7 @@ def open_library(path: str):
     lib.orc_reflected_field.argtypes = [I, I, P, P, P, P, I, P, P, P, I, P, P, P, I, I]
     lib.orc_reflected_field_dgrad.argtypes = [I, P, P, P, I, I, P, P, I, P, P, I]
     lib.orc_time_transform.argtypes = [I, P, D, I, P, ctypes.c_long, P, P, I]
+    lib.orc_incident_power.argtypes = [I, I, I, P, P, P, P]
     lib.orc_max_threads.restype = I
     return lib
 
@@ -221,6 +222,27 @@ def time_transform(k, dk: float, t, F, threads: int = 0):
     _load().orc_time_transform(k.shape[0], _p(k), float(dk), t.shape[0], _p(t), n_x,
                                _p(F.reshape(k.shape[0], n_x)), _p(Ft), int(threads))
     return Ft
+
+
+def incident_power(m: Mirror, Einc, Binc):
+    """P_n = 4 pi SS Re(E_n x B_n^*) . dA over the aperture, dA along -z (Sec. III-B); [n_k]."""
+    E = _c128(Einc)
+    B = _c128(Binc)
+    n_k = E.shape[0]
+    P = np.empty(n_k)
+    _load().orc_incident_power(n_k, m.n_surf, m.n_tot, _p(m.wgt), _p(E.reshape(n_k, -1)), _p(B.reshape(n_k, -1)),
+                               _p(P))
+    return P
+
+
+def energy_amplitudes(P, eps, e_tot: float = 0.0, dk: float = 0.0):
+    """Amplitudes E0_n = sqrt(eps_n / P_n) that give component n the power eps_n
+    (Sec. III-B, eq. normalizationAmplitude); with e_tot > 0 the power spectrum is
+    first scaled so that sum_n eps_n dk = e_tot (the discrete eq. totalEnergy)."""
+    eps = np.asarray(eps, dtype=np.float64)
+    if e_tot > 0:
+        eps = eps * (e_tot / (np.sum(eps) * dk))
+    return np.sqrt(eps / np.asarray(P, dtype=np.float64))
 
 
 def solve(w, kind: int = GAUSSIAN, threads: int = 0, line_term: bool = True):

@@ -79,6 +79,9 @@ SIGNATURES = {
     "sc_set_frequencies": [V, P, I],
     "sc_set_incident": [V, P, P, I],
     "sc_set_incident_gaussian": [V, D, D, P, I],
+    "sc_get_incident_power": [V, P],
+    "sc_scale_spectrum": [V, P],
+    "sc_normalize_energy": [V, P, D, D],
     "sc_set_table_storage": [V, I],
     "sc_set_observation": [V, P, I, I],
     "sc_evaluate": [V, I, P, P, I],

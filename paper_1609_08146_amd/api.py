@@ -176,6 +176,26 @@ class Problem:
         sp = None if spectrum is None else _host_c128(spectrum).ravel()
         call("sc_set_incident_gaussian", self.h, float(w0), float(pol), _ptr(sp), int(bool(consistent)))
 
+    def incident_power(self):
+        """Power of each frequency component through the aperture, [n_k] (sc_get_incident_power)."""
+        P = np.empty(self.n_k, np.float64)
+        call("sc_get_incident_power", self.h, _ptr(P))
+        return P
+
+    def scale_spectrum(self, factor):
+        """Multiply frequency n of the incident field by factor[n] (complex)."""
+        f = _host_c128(factor).ravel()
+        if f.shape[0] != self.n_k:
+            raise ValueError(f"factor has {f.shape[0]} entries, expected {self.n_k}")
+        call("sc_scale_spectrum", self.h, _ptr(f))
+
+    def normalize_energy(self, eps, e_tot: float = 0.0, dk: float = 0.0):
+        """Scale the spectrum to the power spectrum eps (optionally normalised to e_tot)."""
+        e = _host_f64(eps, (-1,))
+        if e.shape[0] != self.n_k:
+            raise ValueError(f"eps has {e.shape[0]} entries, expected {self.n_k}")
+        call("sc_normalize_energy", self.h, _ptr(e), float(e_tot), float(dk))
+
     def set_table_storage(self, keep_fp64: bool):
         call("sc_set_table_storage", self.h, int(bool(keep_fp64)))
 

@@ -181,8 +181,14 @@ static void gauss_rule_cached(sc_ctx *c, int n, const std::vector<double> *out[2
 
 static void invalidate_tables(sc_prob *p)
 {
-    p->has_tab = p->tab32_ok = p->tab32n_ok = p->has_tab64 = false;
+    p->has_tab = p->tab32_ok = p->tab32n_ok = p->has_tab64 = p->has_power = false;
     p->res_prec = -1;
+}
+
+static sc_status reserve_power(sc_prob *p)
+{
+    const size_t n = p->k.size() + (size_t)power_partial_count((int)p->k.size());
+    return p->d_power.reserve(sizeof(double) * n, p->alloc_stream);
 }
 
 // After tab64 was (re)built: with keep_fp64 off, cast to the FP32 split tables now and release tab64.
@@ -337,6 +343,10 @@ extern "C" sc_status sc_set_incident(sc_prob *p, const double *E, const double *
     HIP_TRY(launch_tables_from_fields(st, n_k, p->n_surf, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
                                       p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>(), dE, dB,
                                       p->tab64.as<double>()));
+    SC_TRY(reserve_power(p));
+    HIP_TRY(launch_power_fields(st, n_k, p->n_surf, p->n_tot, p->wgt.as<double>(), dE, dB,
+                                p->d_power.as<double>() + n_k, p->d_power.as<double>()));
+    p->has_power = true;
     ev_record(p, EV_PREP1);
     p->ev_prep = p->ctx->profiling;
     if (!on_device) HIP_TRY(hipStreamSynchronize(st));   // staging buffers are freed on return
@@ -366,10 +376,91 @@ extern "C" sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_
                                    p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>(), w0, pol_angle,
                                    spectrum ? dspec.as<double>() : nullptr, consistent ? 1 : 0,
                                    p->tab64.as<double>()));
+    SC_TRY(reserve_power(p));
+    HIP_TRY(launch_power_gaussian(st, n_k, p->n_surf, p->d_k.as<double>(), p->pos64.as<double>(),
+                                  p->wgt.as<double>(), w0, pol_angle, spectrum ? dspec.as<double>() : nullptr,
+                                  consistent ? 1 : 0, p->d_power.as<double>() + n_k, p->d_power.as<double>()));
+    p->has_power = true;
     ev_record(p, EV_PREP1);
     p->ev_prep = p->ctx->profiling;
     HIP_TRY(hipStreamSynchronize(st));   // dspec is freed on return
     return finish_tables(p);
+}
+
+extern "C" sc_status sc_get_incident_power(const sc_prob *p, double *P)
+{
+    if (!p || !P) return fail(SC_E_INVAL, "sc_get_incident_power: NULL argument");
+    if (!p->has_power) return fail(SC_E_STATE, "sc_get_incident_power: no incident field set");
+    DeviceGuard g(p->ctx->device);
+    HIP_TRY(hipStreamSynchronize(p->ctx->stream));
+    HIP_TRY(hipMemcpy(P, p->d_power.p, sizeof(double) * p->k.size(), hipMemcpyDeviceToHost));
+    return SC_OK;
+}
+
+// Multiply frequency n of the tables by fac[n] (complex, host) and its power by |fac[n]|^2.
+static sc_status scale_tables(sc_prob *p, const std::vector<double> &fac)
+{
+    hipStream_t st = p->ctx->stream;
+    const int n_k = (int)p->k.size();
+    DevBuf dfac;
+    SC_TRY(dfac.reserve(sizeof(double) * 2 * n_k, p->alloc_stream));
+    HIP_TRY(hipMemcpyAsync(dfac.p, fac.data(), sizeof(double) * 2 * n_k, hipMemcpyHostToDevice, st));
+    if (p->has_tab64) {
+        HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, dfac.as<double>(), p->tab64.as<double>(), nullptr));
+        p->tab32_ok = false;   // rebuilt from the scaled FP64 tables when needed
+    } else if (p->tab32_ok) {
+        HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, dfac.as<double>(), nullptr, p->tab32.as<float>()));
+    }
+    p->tab32n_ok = false;
+    p->res_prec = -1;
+    std::vector<double> P(n_k);
+    HIP_TRY(hipMemcpyAsync(P.data(), p->d_power.p, sizeof(double) * n_k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));   // fac and P are host memory, dfac is freed on return
+    for (int i = 0; i < n_k; ++i) P[i] *= fac[2 * i] * fac[2 * i] + fac[2 * i + 1] * fac[2 * i + 1];
+    HIP_TRY(hipMemcpy(p->d_power.p, P.data(), sizeof(double) * n_k, hipMemcpyHostToDevice));
+    return SC_OK;
+}
+
+extern "C" sc_status sc_scale_spectrum(sc_prob *p, const double *factor)
+{
+    if (!p || !factor) return fail(SC_E_INVAL, "sc_scale_spectrum: NULL argument");
+    if (!p->has_tab || !p->has_power) return fail(SC_E_STATE, "sc_scale_spectrum: set the incident field first");
+    const int n_k = (int)p->k.size();
+    for (int i = 0; i < 2 * n_k; ++i)
+        if (!std::isfinite(factor[i])) return fail(SC_E_INVAL, "sc_scale_spectrum: factor[%d] is not finite", i / 2);
+    DeviceGuard g(p->ctx->device);
+    return scale_tables(p, std::vector<double>(factor, factor + 2 * n_k));
+}
+
+extern "C" sc_status sc_normalize_energy(sc_prob *p, const double *eps, double e_tot, double dk)
+{
+    if (!p || !eps) return fail(SC_E_INVAL, "sc_normalize_energy: NULL argument");
+    if (!p->has_tab || !p->has_power) return fail(SC_E_STATE, "sc_normalize_energy: set the incident field first");
+    const int n_k = (int)p->k.size();
+    if (!std::isfinite(e_tot) || e_tot < 0.0) return fail(SC_E_INVAL, "sc_normalize_energy: e_tot must be >= 0");
+    if (e_tot > 0.0 && !(dk > 0.0 && std::isfinite(dk)))
+        return fail(SC_E_INVAL, "sc_normalize_energy: dk must be > 0 when e_tot is given");
+    double sum = 0.0;
+    for (int i = 0; i < n_k; ++i) {
+        if (!(eps[i] >= 0.0) || !std::isfinite(eps[i]))
+            return fail(SC_E_INVAL, "sc_normalize_energy: eps[%d] = %g is not a power (>= 0)", i, eps[i]);
+        sum += eps[i];
+    }
+    if (e_tot > 0.0 && !(sum > 0.0)) return fail(SC_E_INVAL, "sc_normalize_energy: eps is zero everywhere");
+    const double scale = e_tot > 0.0 ? e_tot / (sum * dk) : 1.0;   // sum_n eps_n dk = e_tot
+    DeviceGuard g(p->ctx->device);
+    std::vector<double> P(n_k);
+    HIP_TRY(hipStreamSynchronize(p->ctx->stream));
+    HIP_TRY(hipMemcpy(P.data(), p->d_power.p, sizeof(double) * n_k, hipMemcpyDeviceToHost));
+    std::vector<double> fac(2 * (size_t)n_k, 0.0);
+    for (int i = 0; i < n_k; ++i) {
+        const double target = eps[i] * scale;
+        if (target == 0.0) continue;   // a component with no energy is removed
+        if (!(P[i] > 0.0))
+            return fail(SC_E_INVAL, "sc_normalize_energy: the incident field carries no power at k[%d]", i);
+        fac[2 * i] = std::sqrt(target / P[i]);   // E_0^n, eq. normalizationAmplitude
+    }
+    return scale_tables(p, fac);
 }
 
 extern "C" sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs, int on_device)
@@ -493,6 +584,8 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
     const void *tab = p->tab64.p;
     if (prec == SC_FP64 && !p->has_tab64)
         return fail(SC_E_STATE, "evaluate: FP64 tables were not kept (sc_set_table_storage(p, 0))");
+    if (prec != SC_FP64 && !p->tab32_ok && !p->has_tab64)
+        return fail(SC_E_STATE, "evaluate: no tables to build the FP32 tables from");
     if (prec == SC_FP32_SPLIT) {
         if (!p->tab32_ok) {
             SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
@@ -543,6 +636,7 @@ size_t sc::footprint_bytes(int n_r, int n_phi, int n_k, int n_obs, int n_t, sc_p
     b += sizeof(double) * (2 * (size_t)n_r + 1 + 2 * (size_t)n_phi + 3 * (size_t)n_phi);   // 1-D rule, rim tangents
     b += n_tot * (sizeof(double) * (4 + 3 + 1) + sizeof(float) * 4);                        // node records
     b += sizeof(double) * n_k;
+    b += sizeof(double) * (size_t)n_k * (1 + (size_t)power_partial_count(1));                // incident power
     // FP64 tables (kept for SC_FP64; for the FP32 forms they exist only while the FP32 tables are cast)
     b += (size_t)n_k * n_tot * sizeof(double) * 8;
     if (prec != SC_FP64) b += (size_t)n_k * n_tot * sizeof(float) * 8;                      // FP32 tables
@@ -721,7 +815,7 @@ extern "C" sc_status sc_prob_device_bytes(const sc_prob *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(SC_E_INVAL, "sc_prob_device_bytes: NULL argument");
     const DevBuf *bufs[] = {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->nrm, &p->wgt,
-                            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->obs64, &p->obs32,
+                            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->d_power, &p->obs64, &p->obs32,
                             &p->resE, &p->resB, &p->partial, &p->d_t, &p->tw, &p->timeE, &p->timeB};
     size_t s = 0;
     for (const DevBuf *b : bufs) s += b->bytes;

@@ -135,6 +135,9 @@ struct sc_prob {
     bool has_tab = false, tab32_ok = false, tab32n_ok = false;
     bool keep_fp64 = true, has_tab64 = false;
     sc::DevBuf tab64, tab32, tab32n;
+    // incident power per frequency through the aperture: [n_k] then the reduction scratch
+    bool has_power = false;
+    sc::DevBuf d_power;
     // observation points
     int n_obs = 0, n_obs_pad = 0;
     sc::DevBuf obs64, obs32;

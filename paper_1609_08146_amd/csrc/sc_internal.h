@@ -5,30 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sc_quadjob.h"
+
 namespace sc {
-
-// One problem instance as seen by the quadrature kernel.  All pointers are
-// device pointers.  Tiles of a job are numbered
-//   local = (k * n_chunks + chunk) * obs_blocks + obs_block
-// so that waves running side by side share (k, chunk) table data.
-struct QuadJob {
-    const void *tab;      // [n_k][n_tot][8] real (float or double)
-    const void *pos;      // [n_tot][4] real
-    const void *obs;      // [n_obs_pad][4] real
-    const double *k;      // [n_k]
-    void *partial;        // [n_chunks][n_k][12][n_obs_pad] real
-    int n_tot;            // surface + rim nodes
-    int n_obs_pad;        // observation points, padded to the obs block
-    int n_k;
-    int chunk;            // nodes per split-K chunk
-    int n_chunks;
-    int obs_blocks;       // n_obs_pad / (64 * obs_per_lane)
-    int64_t tile0;        // first global tile of this job in the launch
-    int64_t tile_offset;  // first job-local tile covered (a launch may cover a sub-range)
-    int64_t n_tiles;      // tiles covered by this launch
-};
-
-enum QuadMode { MODE_FP64 = 0, MODE_SPLIT = 1, MODE_NAIVE = 2 };
 
 // ---- launchers (all asynchronous on `stream`; return hipError_t)
 hipError_t launch_node_tables(hipStream_t st, int n_r, int n_phi, double f, const double *r,
@@ -46,6 +25,17 @@ hipError_t launch_tables_gaussian(hipStream_t st, int n_k, int n_surf, int n_tot
 // FP32 tables from the FP64 ones (tab64), or from FP32 split tables (src32, when tab64 is null)
 hipError_t launch_tables_cast(hipStream_t st, int n_k, int n_tot, const double *k, const double *pos64,
                               const double *tab64, const float *src32, float *tab32, int naive);
+// Incident power per frequency through the aperture, P[k] = 4 pi sum_surface W Re(E x B^*).(-z):
+// from field tables E, B [n_k][n_tot][3] complex, or from the built-in Gaussian beam.
+// `part` holds power_partial_count(n_k) doubles of scratch; P is [n_k] (device).
+hipError_t launch_power_fields(hipStream_t st, int n_k, int n_surf, int n_tot, const double *wgt,
+                               const double *E, const double *B, double *part, double *P);
+hipError_t launch_power_gaussian(hipStream_t st, int n_k, int n_surf, const double *k, const double *pos64,
+                                 const double *wgt, double w0, double pol, const double *spectrum, int consistent,
+                                 double *part, double *P);
+int power_partial_count(int n_k);
+// tab[k][node] *= fac[k] (complex128 [n_k]); exactly one of tab64, tab32 non-null
+hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, const double *fac, double *tab64, float *tab32);
 hipError_t launch_quad(hipStream_t st, int mode, int obs_per_lane, int freq_per_lane, int waves_per_block,
                        int grid, const QuadJob *jobs, int n_jobs, int64_t n_tiles, unsigned int *counter);
 hipError_t launch_reduce(hipStream_t st, int mode, const void *partial, int n_chunks, int n_k, int n_obs,

@@ -5,14 +5,16 @@
 //  k_tables_from_fields  POA current / charge tables from given E_inc, B_inc
 //  k_tables_gaussian     same for the built-in collimated Gaussian (Sec. III-A)
 //  k_tables_cast         FP64 tables -> FP32 (split: as is; naive: node phase removed)
-//  k_quad<MODE,OPL>      the surface quadrature, persistent over (job, k, chunk, obs) tiles
+//  k_power_*             incident power per frequency through the aperture (Sec. III-B)
+//  k_tables_scale        spectral amplitude / phase applied to the tables (Sec. III-B)
 //  k_reduce<MODE>        deterministic split-K reduction into E, B
+//  (the quadrature kernel itself is in sc_quad.hip)
 //  k_twiddles, k_time    semi-discrete transform to time (Sec. III-B)
 //
 // All floating-point expressions are written with explicit fma/mul/add and
 // the file is compiled with -ffp-contract=off, so the rounding sequence of
 // every observation point is fixed by the source: results do not depend on
-// the launch shape (obs per lane, waves per block, grid), only on the chunking.
+// the launch shape, only on the chunking.
 #include "sc_device.h"
 #include "sc_internal.h"
 
@@ -153,27 +155,21 @@ __global__ void k_tables_from_fields(int n_k, int n_surf, int n_tot, const doubl
                  {cp, sp});
 }
 
-__global__ void k_tables_gaussian(int n_k, int n_surf, int n_tot, const double *__restrict__ kv,
-                                  const double *__restrict__ pos64, const double *__restrict__ nrm,
-                                  const double *__restrict__ wgt, const double *__restrict__ tan, double w0,
-                                  double pol, const double *__restrict__ spectrum, int consistent,
-                                  double *__restrict__ tab64)
+// Incident collimated Gaussian beam travelling along -z at node (X, Y), without
+// its propagation phase e^{-ikz} (the table kernel fuses that with the node
+// phase; the power kernel does not need it).  Sec. III-A; the curl-consistent
+// variant has B = psi (0, -1, -2iy/(k w0^2)), E = (i/k) curl B, the literal one
+// E = x psi, B = -y psi.  `pol` rotates the polarisation about z.
+__device__ __forceinline__ void gaussian_fields(double k, double X, double Y, double w0, double pol, c64 amp,
+                                                int consistent, c64 *E, c64 *B)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)n_k * n_tot) return;
-    const int kk = (int)(idx / n_tot);
-    const int q = (int)(idx - (int64_t)kk * n_tot);
-    const double k = kv[kk];
-    const double *p = pos64 + 4 * q;
-    const double X = p[0], Y = p[1], Z = p[2];
     double sl, cl;
     sincos(pol, &sl, &cl);
     // frame where the polarisation is along x
     const double x = cl * X + sl * Y;
     const double y = -sl * X + cl * Y;
     const double G = exp(-(x * x + y * y) / (w0 * w0));
-    const c64 amp = spectrum ? c64{spectrum[2 * kk], spectrum[2 * kk + 1]} : c64{1.0, 0.0};
-    const c64 psi = {G * amp.re, G * amp.im};   // without the propagation phase e^{-ikz}
+    const c64 psi = {G * amp.re, G * amp.im};
     c64 e[3], bb[3];
     if (consistent) {
         const double kw2 = k * w0 * w0;
@@ -195,13 +191,30 @@ __global__ void k_tables_gaussian(int n_k, int n_surf, int n_tot, const double *
         bb[1] = {-psi.re, -psi.im};
         bb[2] = {0.0, 0.0};
     }
-    c64 E[3], B[3];
     E[0] = {cl * e[0].re - sl * e[1].re, cl * e[0].im - sl * e[1].im};
     E[1] = {sl * e[0].re + cl * e[1].re, sl * e[0].im + cl * e[1].im};
     E[2] = e[2];
     B[0] = {cl * bb[0].re - sl * bb[1].re, cl * bb[0].im - sl * bb[1].im};
     B[1] = {sl * bb[0].re + cl * bb[1].re, sl * bb[0].im + cl * bb[1].im};
     B[2] = bb[2];
+}
+
+__global__ void k_tables_gaussian(int n_k, int n_surf, int n_tot, const double *__restrict__ kv,
+                                  const double *__restrict__ pos64, const double *__restrict__ nrm,
+                                  const double *__restrict__ wgt, const double *__restrict__ tan, double w0,
+                                  double pol, const double *__restrict__ spectrum, int consistent,
+                                  double *__restrict__ tab64)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n_k * n_tot) return;
+    const int kk = (int)(idx / n_tot);
+    const int q = (int)(idx - (int64_t)kk * n_tot);
+    const double k = kv[kk];
+    const double *p = pos64 + 4 * q;
+    const double X = p[0], Y = p[1], Z = p[2];
+    const c64 amp = spectrum ? c64{spectrum[2 * kk], spectrum[2 * kk + 1]} : c64{1.0, 0.0};
+    c64 E[3], B[3];
+    gaussian_fields(k, X, Y, w0, pol, amp, consistent, E, B);
     // propagation phase e^{-ikz} fused with the node phase e^{ik|r_s|}: e^{ik(|r_s| - z)},
     // formed in double-double so that no ~1e6 rad phase is ever rounded to double
     const dd rs = dd_norm3(X, Y, Z);
@@ -210,6 +223,106 @@ __global__ void k_tables_gaussian(int n_k, int n_surf, int n_tot, const double *
     const bool rim = q >= n_surf;
     write_record(tab64 + idx * 8, rim, k, wgt[q], nrm + 3 * q, rim ? tan + 3 * (q - n_surf) : nullptr, E, B,
                  {cp, sp});
+}
+
+// ------------------------------------------------------------ incident power
+// Power of one frequency component of the incident beam through the mirror
+// aperture (Sec. III-B, the Poynting integral that fixes each component's
+// energy):  P_n = 4 pi SS Re(E_n x B_n^*) . dA  with dA = -z dx dy, since the
+// beam travels along -z.  The surface weights W = w_r r dphi integrate over the
+// aperture disk in the (x, y) plane, so P_n = 4 pi sum_q W_q Re(E x B^*) . (-z)
+// over the surface nodes.  Deterministic: block b of frequency k sums a fixed
+// node range in a fixed order; k_power_finish adds the blocks in order.
+constexpr int POWER_BLOCKS = 16;
+
+__device__ __forceinline__ double flux_minus_z(const c64 *E, const c64 *B)
+{
+    // Re(E x B^*)_z = Re(E_x B_y^*) - Re(E_y B_x^*)
+    return -((E[0].re * B[1].re + E[0].im * B[1].im) - (E[1].re * B[0].re + E[1].im * B[0].im));
+}
+
+__device__ __forceinline__ void block_sum_256(double v, double *out)
+{
+    __shared__ double red[256];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// grid (POWER_BLOCKS, n_k), 256 threads; E, B: [n_k][n_tot][3] complex
+__global__ void __launch_bounds__(256) k_power_fields(int n_surf, int n_tot, const double *__restrict__ wgt,
+                                                      const double *__restrict__ Ein,
+                                                      const double *__restrict__ Bin, double *__restrict__ part)
+{
+    const int kk = blockIdx.y;
+    const int span = (n_surf + POWER_BLOCKS - 1) / POWER_BLOCKS;
+    const int q0 = blockIdx.x * span, q1 = min(q0 + span, n_surf);
+    double acc = 0.0;
+    for (int q = q0 + (int)threadIdx.x; q < q1; q += 256) {
+        const double *e = Ein + ((size_t)kk * n_tot + q) * 6, *b = Bin + ((size_t)kk * n_tot + q) * 6;
+        c64 E[3], B[3];
+        for (int c = 0; c < 3; ++c) {
+            E[c] = {e[2 * c], e[2 * c + 1]};
+            B[c] = {b[2 * c], b[2 * c + 1]};
+        }
+        acc += wgt[q] * flux_minus_z(E, B);
+    }
+    block_sum_256(acc, part + (size_t)kk * POWER_BLOCKS + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_power_gaussian(int n_surf, const double *__restrict__ kv,
+                                                        const double *__restrict__ pos64,
+                                                        const double *__restrict__ wgt, double w0, double pol,
+                                                        const double *__restrict__ spectrum, int consistent,
+                                                        double *__restrict__ part)
+{
+    const int kk = blockIdx.y;
+    const int span = (n_surf + POWER_BLOCKS - 1) / POWER_BLOCKS;
+    const int q0 = blockIdx.x * span, q1 = min(q0 + span, n_surf);
+    const double k = kv[kk];
+    const c64 amp = spectrum ? c64{spectrum[2 * kk], spectrum[2 * kk + 1]} : c64{1.0, 0.0};
+    double acc = 0.0;
+    for (int q = q0 + (int)threadIdx.x; q < q1; q += 256) {
+        c64 E[3], B[3];
+        gaussian_fields(k, pos64[4 * q], pos64[4 * q + 1], w0, pol, amp, consistent, E, B);
+        acc += wgt[q] * flux_minus_z(E, B);
+    }
+    block_sum_256(acc, part + (size_t)kk * POWER_BLOCKS + blockIdx.x);
+}
+
+__global__ void k_power_finish(int n_k, const double *__restrict__ part, double *__restrict__ P)
+{
+    const int kk = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kk >= n_k) return;
+    double s = 0.0;
+    for (int b = 0; b < POWER_BLOCKS; ++b) s += part[(size_t)kk * POWER_BLOCKS + b];
+    P[kk] = FOUR_PI * s;
+}
+
+// Multiply every record of frequency k by the complex factor fac[k] (spectral
+// amplitude and phase, Sec. III-B); tab64 in FP64, or tab32 (FP32 storage).
+__global__ void k_tables_scale(int n_k, int n_tot, const double *__restrict__ fac, double *__restrict__ tab64,
+                               float *__restrict__ tab32)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n_k * n_tot) return;
+    const int kk = (int)(idx / n_tot);
+    const c64 f = {fac[2 * kk], fac[2 * kk + 1]};
+    for (int c = 0; c < 4; ++c) {
+        if (tab64) {
+            const c64 v = cmul({tab64[idx * 8 + 2 * c], tab64[idx * 8 + 2 * c + 1]}, f);
+            tab64[idx * 8 + 2 * c] = v.re;
+            tab64[idx * 8 + 2 * c + 1] = v.im;
+        } else {
+            const c64 v = cmul({(double)tab32[idx * 8 + 2 * c], (double)tab32[idx * 8 + 2 * c + 1]}, f);
+            tab32[idx * 8 + 2 * c] = (float)v.re;
+            tab32[idx * 8 + 2 * c + 1] = (float)v.im;
+        }
+    }
 }
 
 __global__ void k_tables_cast(int n_k, int n_tot, const double *__restrict__ kv, const double *__restrict__ pos64,
@@ -237,365 +350,6 @@ __global__ void k_tables_cast(int n_k, int n_tot, const double *__restrict__ kv,
         c64 w = cmul({v[2 * c], v[2 * c + 1]}, P);
         dst[2 * c] = (float)w.re;
         dst[2 * c + 1] = (float)w.im;
-    }
-}
-
-// ================================================================= quadrature
-
-// Constant-address-space views: uniform loads through them become scalar
-// (SMEM) loads into SGPRs, so node data costs no VGPRs and no LDS traffic.
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(4))) const v4f cv4f;
-typedef __attribute__((address_space(4))) const double cdouble;
-typedef __attribute__((address_space(4))) const QuadJob cjob;
-
-// sin and cos of theta = 2 pi * t, t in turns: hardware v_sin / v_cos on the
-// fractional part (the exact reduction modulo one turn, in [0, 1)).
-__device__ __forceinline__ void sincos_turns(float t, float &s, float &c)
-{
-    const float r = __builtin_amdgcn_fractf(t);
-    s = __builtin_amdgcn_sinf(r);
-    c = __builtin_amdgcn_cosf(r);
-}
-
-// The per-pair work is split into a geometry part (one per node and
-// observation point) and a per-frequency part, so that a lane holding several
-// frequencies reuses the geometry.  The arithmetic sequence of one (point,
-// frequency) pair is the same whatever the blocking.
-
-// Geometry of the split form in FP32:  R = r_s - r',  1/|R|,
-//   delta = |R| - |r_s| = (|r'|^2 - 2 r_s.r') / (|R| + |r_s|)  (no cancellation).
-//   p = (x, y, z, |r_s|), o = (x, y, z, |r'|^2).
-struct GeomF {
-    float dx, dy, dz, rinv, delta;
-};
-
-__device__ __forceinline__ GeomF geom_split(const v4f p, const v4f o)
-{
-    GeomF g;
-    g.dx = p.x - o.x;
-    g.dy = p.y - o.y;
-    g.dz = p.z - o.z;
-    const float R2 = __fmaf_rn(g.dx, g.dx, __fmaf_rn(g.dy, g.dy, g.dz * g.dz));
-    g.rinv = __builtin_amdgcn_rsqf(R2);
-    const float R = R2 * g.rinv;
-    const float dot = __fmaf_rn(p.x, o.x, __fmaf_rn(p.y, o.y, p.z * o.z));
-    const float num = __fmaf_rn(-2.0f, dot, o.w);
-    g.delta = num * __builtin_amdgcn_rcpf(R + p.w);
-    return g;
-}
-
-// Accumulate one (node, point, frequency) term given e^{i theta} = (c, s):
-//   gt = e^{i theta} / R,  ht = (ik - 1/R) gt / R,
-//   acc[0..5] += Jt gt + rho_t ht R   (E),   acc[6..11] += (Jt ht) x R   (B before 1/ik).
-//   t0 = (Jt.x, Jt.y), t1 = (Jt.z, rho_t), each complex as (re, im).
-__device__ __forceinline__ void accumulate_f32(float dx, float dy, float dz, float rinv, float c, float s,
-                                               const v4f t0, const v4f t1, float k, float *acc)
-{
-    const float gr = c * rinv, gi = s * rinv;
-    const float a = -(rinv * rinv), b = k * rinv;
-    const float hr = __fmaf_rn(gr, a, -(gi * b));
-    const float hi = __fmaf_rn(gr, b, gi * a);
-    // E += Jt gt
-    acc[0] = __fmaf_rn(t0.x, gr, __fmaf_rn(-t0.y, gi, acc[0]));
-    acc[1] = __fmaf_rn(t0.x, gi, __fmaf_rn(t0.y, gr, acc[1]));
-    acc[2] = __fmaf_rn(t0.z, gr, __fmaf_rn(-t0.w, gi, acc[2]));
-    acc[3] = __fmaf_rn(t0.z, gi, __fmaf_rn(t0.w, gr, acc[3]));
-    acc[4] = __fmaf_rn(t1.x, gr, __fmaf_rn(-t1.y, gi, acc[4]));
-    acc[5] = __fmaf_rn(t1.x, gi, __fmaf_rn(t1.y, gr, acc[5]));
-    // E += rho_t ht R
-    const float tr = __fmaf_rn(t1.z, hr, -(t1.w * hi));
-    const float ti = __fmaf_rn(t1.z, hi, t1.w * hr);
-    acc[0] = __fmaf_rn(tr, dx, acc[0]);
-    acc[1] = __fmaf_rn(ti, dx, acc[1]);
-    acc[2] = __fmaf_rn(tr, dy, acc[2]);
-    acc[3] = __fmaf_rn(ti, dy, acc[3]);
-    acc[4] = __fmaf_rn(tr, dz, acc[4]);
-    acc[5] = __fmaf_rn(ti, dz, acc[5]);
-    // B += (Jt ht) x R
-    const float qxr = __fmaf_rn(t0.x, hr, -(t0.y * hi)), qxi = __fmaf_rn(t0.x, hi, t0.y * hr);
-    const float qyr = __fmaf_rn(t0.z, hr, -(t0.w * hi)), qyi = __fmaf_rn(t0.z, hi, t0.w * hr);
-    const float qzr = __fmaf_rn(t1.x, hr, -(t1.y * hi)), qzi = __fmaf_rn(t1.x, hi, t1.y * hr);
-    acc[6] = __fmaf_rn(qyr, dz, __fmaf_rn(-qzr, dy, acc[6]));
-    acc[7] = __fmaf_rn(qyi, dz, __fmaf_rn(-qzi, dy, acc[7]));
-    acc[8] = __fmaf_rn(qzr, dx, __fmaf_rn(-qxr, dz, acc[8]));
-    acc[9] = __fmaf_rn(qzi, dx, __fmaf_rn(-qxi, dz, acc[9]));
-    acc[10] = __fmaf_rn(qxr, dy, __fmaf_rn(-qyr, dx, acc[10]));
-    acc[11] = __fmaf_rn(qxi, dy, __fmaf_rn(-qyi, dx, acc[11]));
-}
-
-// Split form, one frequency: phase k delta (kt = k / 2 pi, in turns).
-__device__ __forceinline__ void freq_split(const GeomF &g, const v4f t0, const v4f t1, float k, float kt, float *acc)
-{
-    float s, c;
-    sincos_turns(kt * g.delta, s, c);
-    accumulate_f32(g.dx, g.dy, g.dz, g.rinv, c, s, t0, t1, k, acc);
-}
-
-// Naive FP32 form, one frequency: the whole phase k |R| in FP32 (the table carries no node phase).
-__device__ __forceinline__ void freq_naive(const GeomF &g, float R, const v4f t0, const v4f t1, float k, float *acc)
-{
-    float s, c;
-    sincosf(k * R, &s, &c);
-    accumulate_f32(g.dx, g.dy, g.dz, g.rinv, c, s, t0, t1, k, acc);
-}
-
-__device__ __forceinline__ void geom_naive(const v4f p, const v4f o, GeomF &g, float &R)
-{
-    g.dx = p.x - o.x;
-    g.dy = p.y - o.y;
-    g.dz = p.z - o.z;
-    const float R2 = __fmaf_rn(g.dx, g.dx, __fmaf_rn(g.dy, g.dy, g.dz * g.dz));
-    g.rinv = __builtin_amdgcn_rsqf(R2);
-    R = R2 * g.rinv;
-    g.delta = 0.0f;
-}
-
-// Geometry and per-frequency term of the split form in FP64.
-struct GeomD {
-    double dx, dy, dz, rinv, delta;
-};
-
-__device__ __forceinline__ GeomD geom_f64(const double *p, const double4 o)
-{
-    GeomD g;
-    g.dx = p[0] - o.x;
-    g.dy = p[1] - o.y;
-    g.dz = p[2] - o.z;
-    const double R2 = __fma_rn(g.dx, g.dx, __fma_rn(g.dy, g.dy, g.dz * g.dz));
-    g.rinv = rsqrt(R2);
-    const double R = R2 * g.rinv;
-    const double dot = __fma_rn(p[0], o.x, __fma_rn(p[1], o.y, p[2] * o.z));
-    const double num = __fma_rn(-2.0, dot, o.w);
-    g.delta = num / (R + p[3]);
-    return g;
-}
-
-__device__ __forceinline__ void freq_f64(const GeomD &g, const double *t, double k, double *acc)
-{
-    double s, c;
-    sincos(k * g.delta, &s, &c);
-    const double dx = g.dx, dy = g.dy, dz = g.dz, rinv = g.rinv;
-    const double gr = c * rinv, gi = s * rinv;
-    const double a = -(rinv * rinv), b = k * rinv;
-    const double hr = __fma_rn(gr, a, -(gi * b));
-    const double hi = __fma_rn(gr, b, gi * a);
-    acc[0] = __fma_rn(t[0], gr, __fma_rn(-t[1], gi, acc[0]));
-    acc[1] = __fma_rn(t[0], gi, __fma_rn(t[1], gr, acc[1]));
-    acc[2] = __fma_rn(t[2], gr, __fma_rn(-t[3], gi, acc[2]));
-    acc[3] = __fma_rn(t[2], gi, __fma_rn(t[3], gr, acc[3]));
-    acc[4] = __fma_rn(t[4], gr, __fma_rn(-t[5], gi, acc[4]));
-    acc[5] = __fma_rn(t[4], gi, __fma_rn(t[5], gr, acc[5]));
-    const double tr = __fma_rn(t[6], hr, -(t[7] * hi));
-    const double ti = __fma_rn(t[6], hi, t[7] * hr);
-    acc[0] = __fma_rn(tr, dx, acc[0]);
-    acc[1] = __fma_rn(ti, dx, acc[1]);
-    acc[2] = __fma_rn(tr, dy, acc[2]);
-    acc[3] = __fma_rn(ti, dy, acc[3]);
-    acc[4] = __fma_rn(tr, dz, acc[4]);
-    acc[5] = __fma_rn(ti, dz, acc[5]);
-    const double qxr = __fma_rn(t[0], hr, -(t[1] * hi)), qxi = __fma_rn(t[0], hi, t[1] * hr);
-    const double qyr = __fma_rn(t[2], hr, -(t[3] * hi)), qyi = __fma_rn(t[2], hi, t[3] * hr);
-    const double qzr = __fma_rn(t[4], hr, -(t[5] * hi)), qzi = __fma_rn(t[4], hi, t[5] * hr);
-    acc[6] = __fma_rn(qyr, dz, __fma_rn(-qzr, dy, acc[6]));
-    acc[7] = __fma_rn(qyi, dz, __fma_rn(-qzi, dy, acc[7]));
-    acc[8] = __fma_rn(qzr, dx, __fma_rn(-qxr, dz, acc[8]));
-    acc[9] = __fma_rn(qzi, dx, __fma_rn(-qxi, dz, acc[9]));
-    acc[10] = __fma_rn(qxr, dy, __fma_rn(-qyr, dx, acc[10]));
-    acc[11] = __fma_rn(qxi, dy, __fma_rn(-qyi, dx, acc[11]));
-}
-
-// Map a global tile index to its job (binary search over tile0; uniform).
-__device__ __forceinline__ int find_job(cjob *jobs, int n_jobs, int64_t t)
-{
-    int lo = 0, hi = n_jobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile0 <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-constexpr int KAHAN_BLOCK = 32;   // nodes summed plainly before each compensated add (FP32)
-
-// Persistent quadrature kernel.  Every wave repeatedly takes the next tile
-// from a device counter: one node chunk, 64*OPL observation points, FPB
-// consecutive frequencies.  Node and table data are wave-uniform (scalar
-// loads); each lane owns OPL points x FPB frequencies x 12 accumulators.
-// Every wave exits once the counter passes n_tiles.
-template <int MODE, int OPL, int FPB>
-__global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_, int n_jobs, int64_t n_tiles,
-                                              unsigned int *__restrict__ counter)
-{
-    cjob *jobs = (cjob *)jobs_;
-    const int lane = threadIdx.x & 63;
-    for (;;) {
-        unsigned int tt = 0;
-        if (lane == 0) tt = atomicAdd(counter, 1u);
-        const int64_t t = (int64_t)__builtin_amdgcn_readfirstlane(tt);
-        if (t >= n_tiles) break;
-        const int j = find_job(jobs, n_jobs, t);
-        const int64_t local = t - jobs[j].tile0 + jobs[j].tile_offset;
-        const int obs_blocks = jobs[j].obs_blocks, n_chunks = jobs[j].n_chunks;
-        const int ob = (int)(local % obs_blocks);
-        const int64_t rest = local / obs_blocks;
-        const int chunk = (int)(rest % n_chunks);
-        const int kb = (int)(rest / n_chunks);
-        const int n_tot = jobs[j].n_tot, n_k = jobs[j].n_k, n_obs_pad = jobs[j].n_obs_pad;
-        const int n0 = chunk * jobs[j].chunk;
-        const int n1 = min(n0 + jobs[j].chunk, n_tot);
-        const int obase = ob * 64 * OPL + lane;
-        // frequencies of this tile; past the last one, repeat it and skip the store
-        int kidx[FPB];
-        double k64[FPB];
-#pragma unroll
-        for (int f = 0; f < FPB; ++f) {
-            kidx[f] = min(kb * FPB + f, n_k - 1);
-            k64[f] = ((cdouble *)jobs[j].k)[kidx[f]];
-        }
-        const int n_valid = min(FPB, n_k - kb * FPB);
-
-        if constexpr (MODE == MODE_FP64) {
-            cdouble *pos = (cdouble *)jobs[j].pos;
-            cdouble *tab[FPB];
-#pragma unroll
-            for (int f = 0; f < FPB; ++f) tab[f] = (cdouble *)jobs[j].tab + (size_t)kidx[f] * n_tot * 8;
-            const double4 *obs = (const double4 *)jobs[j].obs;
-            double4 o[OPL];
-            double acc[OPL][FPB][12];
-#pragma unroll
-            for (int s = 0; s < OPL; ++s) {
-                o[s] = obs[obase + 64 * s];
-#pragma unroll
-                for (int f = 0; f < FPB; ++f)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) acc[s][f][c] = 0.0;
-            }
-            for (int n = n0; n < n1; ++n) {
-                double pn[4], tn[FPB][8];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) pn[c] = pos[4 * (size_t)n + c];
-#pragma unroll
-                for (int f = 0; f < FPB; ++f)
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) tn[f][c] = tab[f][8 * (size_t)n + c];
-#pragma unroll
-                for (int s = 0; s < OPL; ++s) {
-                    const GeomD g = geom_f64(pn, o[s]);
-#pragma unroll
-                    for (int f = 0; f < FPB; ++f) freq_f64(g, tn[f], k64[f], acc[s][f]);
-                }
-            }
-#pragma unroll
-            for (int f = 0; f < FPB; ++f) {
-                if (f >= n_valid) break;
-                double *part = (double *)jobs[j].partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
-#pragma unroll
-                for (int s = 0; s < OPL; ++s)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) part[(size_t)c * n_obs_pad + obase + 64 * s] = acc[s][f][c];
-            }
-        } else {
-            cv4f *pos = (cv4f *)jobs[j].pos;
-            cv4f *tab[FPB];
-            float k[FPB], kt[FPB];
-#pragma unroll
-            for (int f = 0; f < FPB; ++f) {
-                tab[f] = (cv4f *)jobs[j].tab + (size_t)kidx[f] * n_tot * 2;
-                k[f] = (float)k64[f];
-                kt[f] = (float)(k64[f] * INV_TWO_PI);
-            }
-            const v4f *obs = (const v4f *)jobs[j].obs;
-            v4f o[OPL];
-            // Running sums stay in registers; their Kahan compensations live in LDS
-            // (touched once per KAHAN_BLOCK nodes), which frees VGPRs for occupancy.
-            // dynamic LDS: [waves per block][OPL * FPB * 12][64] floats
-            extern __shared__ float lds_dyn[];
-            float(*cmp)[64] = (float(*)[64])(lds_dyn + (size_t)(threadIdx.x >> 6) * (OPL * FPB * 12 * 64));
-            float sum[OPL][FPB][12];
-#pragma unroll
-            for (int s = 0; s < OPL; ++s) {
-                o[s] = obs[obase + 64 * s];
-#pragma unroll
-                for (int f = 0; f < FPB; ++f)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) sum[s][f][c] = 0.0f;
-            }
-#pragma unroll
-            for (int a = 0; a < OPL * FPB * 12; ++a) cmp[a][lane] = 0.0f;
-            float blk[OPL][FPB][12];
-#pragma unroll
-            for (int s = 0; s < OPL; ++s)
-#pragma unroll
-                for (int f = 0; f < FPB; ++f)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) blk[s][f][c] = 0.0f;
-            // node data of node n+1 is loaded while node n is computed
-            v4f pn = pos[n0];
-            v4f t0[FPB], t1[FPB];
-#pragma unroll
-            for (int f = 0; f < FPB; ++f) {
-                t0[f] = tab[f][2 * n0];
-                t1[f] = tab[f][2 * n0 + 1];
-            }
-            for (int n = n0; n < n1; ++n) {
-                const int nx = min(n + 1, n1 - 1);
-                const v4f pnx = pos[nx];
-                v4f t0x[FPB], t1x[FPB];
-#pragma unroll
-                for (int f = 0; f < FPB; ++f) {
-                    t0x[f] = tab[f][2 * nx];
-                    t1x[f] = tab[f][2 * nx + 1];
-                }
-#pragma unroll
-                for (int s = 0; s < OPL; ++s) {
-                    if constexpr (MODE == MODE_SPLIT) {
-                        const GeomF g = geom_split(pn, o[s]);
-#pragma unroll
-                        for (int f = 0; f < FPB; ++f) freq_split(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
-                    } else {
-                        GeomF g;
-                        float R;
-                        geom_naive(pn, o[s], g, R);
-#pragma unroll
-                        for (int f = 0; f < FPB; ++f) freq_naive(g, R, t0[f], t1[f], k[f], blk[s][f]);
-                    }
-                }
-                // every KAHAN_BLOCK nodes (counted from the chunk start), a compensated add
-                if ((n - n0) % KAHAN_BLOCK == KAHAN_BLOCK - 1 || n == n1 - 1) {
-#pragma unroll
-                    for (int s = 0; s < OPL; ++s)
-#pragma unroll
-                        for (int f = 0; f < FPB; ++f)
-#pragma unroll
-                            for (int c = 0; c < 12; ++c) {
-                                const int a = (s * FPB + f) * 12 + c;
-                                const float y = blk[s][f][c] - cmp[a][lane];
-                                const float tsum = sum[s][f][c] + y;
-                                cmp[a][lane] = (tsum - sum[s][f][c]) - y;
-                                sum[s][f][c] = tsum;
-                                blk[s][f][c] = 0.0f;
-                            }
-                }
-                pn = pnx;
-#pragma unroll
-                for (int f = 0; f < FPB; ++f) {
-                    t0[f] = t0x[f];
-                    t1[f] = t1x[f];
-                }
-            }
-#pragma unroll
-            for (int f = 0; f < FPB; ++f) {
-                if (f >= n_valid) break;
-                float *part = (float *)jobs[j].partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
-#pragma unroll
-                for (int s = 0; s < OPL; ++s)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c)
-                        part[(size_t)c * n_obs_pad + obase + 64 * s] = sum[s][f][c] - cmp[(s * FPB + f) * 12 + c][lane];
-            }
-        }
     }
 }
 
@@ -638,6 +392,9 @@ __global__ void k_twiddles(int n_k, const double *__restrict__ kv, int n_t, cons
     tw[2 * idx] = dk * c;
     tw[2 * idx + 1] = dk * s;
 }
+
+// Constant-address-space view: wave-uniform loads through it become scalar loads.
+typedef __attribute__((address_space(4))) const double cdouble;
 
 constexpr int TIME_MT = 8;   // time samples per thread (register tile)
 
@@ -717,66 +474,39 @@ hipError_t launch_tables_gaussian(hipStream_t st, int n_k, int n_surf, int n_tot
     return hipGetLastError();
 }
 
+hipError_t launch_power_fields(hipStream_t st, int n_k, int n_surf, int n_tot, const double *wgt,
+                               const double *E, const double *B, double *part, double *P)
+{
+    hipLaunchKernelGGL(k_power_fields, dim3(POWER_BLOCKS, n_k), dim3(256), 0, st, n_surf, n_tot, wgt, E, B, part);
+    hipLaunchKernelGGL(k_power_finish, dim3(nblocks(n_k, 256)), dim3(256), 0, st, n_k, part, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_gaussian(hipStream_t st, int n_k, int n_surf, const double *k, const double *pos64,
+                                 const double *wgt, double w0, double pol, const double *spectrum, int consistent,
+                                 double *part, double *P)
+{
+    hipLaunchKernelGGL(k_power_gaussian, dim3(POWER_BLOCKS, n_k), dim3(256), 0, st, n_surf, k, pos64, wgt, w0, pol,
+                       spectrum, consistent, part);
+    hipLaunchKernelGGL(k_power_finish, dim3(nblocks(n_k, 256)), dim3(256), 0, st, n_k, part, P);
+    return hipGetLastError();
+}
+
+int power_partial_count(int n_k) { return POWER_BLOCKS * n_k; }
+
+hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, const double *fac, double *tab64, float *tab32)
+{
+    hipLaunchKernelGGL(k_tables_scale, dim3(nblocks((int64_t)n_k * n_tot, 256)), dim3(256), 0, st, n_k, n_tot, fac,
+                       tab64, tab32);
+    return hipGetLastError();
+}
+
 hipError_t launch_tables_cast(hipStream_t st, int n_k, int n_tot, const double *k, const double *pos64,
                               const double *tab64, const float *src32, float *tab32, int naive)
 {
     hipLaunchKernelGGL(k_tables_cast, dim3(nblocks((int64_t)n_k * n_tot, 256)), dim3(256), 0, st, n_k, n_tot, k,
                        pos64, tab64, src32, tab32, naive);
     return hipGetLastError();
-}
-
-// Instantiated shapes (obs per lane x frequencies per lane).
-#define SC_QUAD_SHAPES(X, M) X(M, 1, 1) X(M, 2, 1) X(M, 1, 2) X(M, 2, 2) X(M, 1, 4)
-
-static bool shape_ok(int opl, int fpb)
-{
-    return (opl == 1 && (fpb == 1 || fpb == 2 || fpb == 4)) || (opl == 2 && (fpb == 1 || fpb == 2));
-}
-
-static const void *quad_fn_dyn(int mode, int opl, int fpb)
-{
-#define SC_QUAD_FN(M, O, F) \
-    if (mode == M && opl == O && fpb == F) return (const void *)&k_quad<M, O, F>;
-    SC_QUAD_SHAPES(SC_QUAD_FN, MODE_FP64)
-    SC_QUAD_SHAPES(SC_QUAD_FN, MODE_SPLIT)
-    SC_QUAD_SHAPES(SC_QUAD_FN, MODE_NAIVE)
-#undef SC_QUAD_FN
-    return nullptr;
-}
-
-// Dynamic LDS of one quadrature block: the FP32 forms keep their Kahan compensations there.
-static size_t quad_lds_bytes(int mode, int opl, int fpb, int waves_per_block)
-{
-    return mode == MODE_FP64 ? 0 : sizeof(float) * 64 * 12 * (size_t)opl * fpb * waves_per_block;
-}
-
-int quad_max_blocks_per_cu(int mode, int opl, int fpb, int waves_per_block)
-{
-    const void *fn = quad_fn_dyn(mode, opl, fpb);
-    int nb = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * waves_per_block,
-                                                            quad_lds_bytes(mode, opl, fpb, waves_per_block)) !=
-                   hipSuccess)
-        return 1;
-    return nb > 0 ? nb : 1;
-}
-
-hipError_t launch_quad(hipStream_t st, int mode, int opl, int fpb, int waves_per_block, int grid,
-                       const QuadJob *jobs, int n_jobs, int64_t n_tiles, unsigned int *counter)
-{
-    if (!shape_ok(opl, fpb)) return hipErrorInvalidValue;
-    dim3 g(grid), b(64 * waves_per_block);
-    const size_t lds = quad_lds_bytes(mode, opl, fpb, waves_per_block);
-#define SC_QUAD_LAUNCH(M, O, F)                                                                          \
-    if (mode == M && opl == O && fpb == F) {                                                            \
-        hipLaunchKernelGGL((k_quad<M, O, F>), g, b, lds, st, jobs, n_jobs, n_tiles, counter);           \
-        return hipGetLastError();                                                                       \
-    }
-    SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_FP64)
-    SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_SPLIT)
-    SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_NAIVE)
-#undef SC_QUAD_LAUNCH
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce(hipStream_t st, int mode, const void *partial, int n_chunks, int n_k, int n_obs,

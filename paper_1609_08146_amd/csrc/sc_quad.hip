@@ -1,0 +1,432 @@
+// sc_quad.hip -- the surface quadrature of the Stratton-Chu mirror-focusing
+// path on gfx950: k_quad<MODE,OPL,FPB>, persistent over (job, frequency block,
+// node chunk, observation block) tiles, and its launcher.
+//
+//   MODE_SPLIT  per-pair FP32 with the node phase folded into the tables
+//   MODE_FP64   the same split form in FP64
+//   MODE_NAIVE  the whole phase k|R| per pair in FP32 (the precision ablation)
+//
+// All floating-point expressions are written with explicit fma/mul/add and
+// the file is compiled with -ffp-contract=off, so the rounding sequence of
+// every observation point is fixed by the source: results do not depend on
+// the launch shape (obs per lane, frequencies per lane, waves per block,
+// grid), only on the node chunking.
+#include "sc_device.h"
+#include "sc_internal.h"
+
+namespace sc {
+
+// ================================================================= quadrature
+
+// Constant-address-space views: uniform loads through them become scalar
+// (SMEM) loads into SGPRs, so node data costs no VGPRs and no LDS traffic.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(4))) const v4f cv4f;
+typedef __attribute__((address_space(4))) const double cdouble;
+typedef __attribute__((address_space(4))) const QuadJob cjob;
+
+// sin and cos of theta = 2 pi * t, t in turns: hardware v_sin / v_cos on the
+// fractional part (the exact reduction modulo one turn, in [0, 1)).
+__device__ __forceinline__ void sincos_turns(float t, float &s, float &c)
+{
+    const float r = __builtin_amdgcn_fractf(t);
+    s = __builtin_amdgcn_sinf(r);
+    c = __builtin_amdgcn_cosf(r);
+}
+
+// The per-pair work is split into a geometry part (one per node and
+// observation point) and a per-frequency part, so that a lane holding several
+// frequencies reuses the geometry.  The arithmetic sequence of one (point,
+// frequency) pair is the same whatever the blocking.
+
+// Geometry of the split form in FP32:  R = r_s - r',  1/|R|,
+//   delta = |R| - |r_s| = (|r'|^2 - 2 r_s.r') / (|R| + |r_s|)  (no cancellation).
+//   p = (x, y, z, |r_s|), o = (x, y, z, |r'|^2).
+struct GeomF {
+    float dx, dy, dz, rinv, delta;
+};
+
+__device__ __forceinline__ GeomF geom_split(const v4f p, const v4f o)
+{
+    GeomF g;
+    g.dx = p.x - o.x;
+    g.dy = p.y - o.y;
+    g.dz = p.z - o.z;
+    const float R2 = __fmaf_rn(g.dx, g.dx, __fmaf_rn(g.dy, g.dy, g.dz * g.dz));
+    g.rinv = __builtin_amdgcn_rsqf(R2);
+    const float R = R2 * g.rinv;
+    const float dot = __fmaf_rn(p.x, o.x, __fmaf_rn(p.y, o.y, p.z * o.z));
+    const float num = __fmaf_rn(-2.0f, dot, o.w);
+    g.delta = num * __builtin_amdgcn_rcpf(R + p.w);
+    return g;
+}
+
+// Accumulate one (node, point, frequency) term given e^{i theta} = (c, s):
+//   gt = e^{i theta} / R,  ht = (ik - 1/R) gt / R,
+//   acc[0..5] += Jt gt + rho_t ht R   (E),   acc[6..11] += (Jt ht) x R   (B before 1/ik).
+//   t0 = (Jt.x, Jt.y), t1 = (Jt.z, rho_t), each complex as (re, im).
+__device__ __forceinline__ void accumulate_f32(float dx, float dy, float dz, float rinv, float c, float s,
+                                               const v4f t0, const v4f t1, float k, float *acc)
+{
+    const float gr = c * rinv, gi = s * rinv;
+    const float a = -(rinv * rinv), b = k * rinv;
+    const float hr = __fmaf_rn(gr, a, -(gi * b));
+    const float hi = __fmaf_rn(gr, b, gi * a);
+    // E += Jt gt
+    acc[0] = __fmaf_rn(t0.x, gr, __fmaf_rn(-t0.y, gi, acc[0]));
+    acc[1] = __fmaf_rn(t0.x, gi, __fmaf_rn(t0.y, gr, acc[1]));
+    acc[2] = __fmaf_rn(t0.z, gr, __fmaf_rn(-t0.w, gi, acc[2]));
+    acc[3] = __fmaf_rn(t0.z, gi, __fmaf_rn(t0.w, gr, acc[3]));
+    acc[4] = __fmaf_rn(t1.x, gr, __fmaf_rn(-t1.y, gi, acc[4]));
+    acc[5] = __fmaf_rn(t1.x, gi, __fmaf_rn(t1.y, gr, acc[5]));
+    // E += rho_t ht R
+    const float tr = __fmaf_rn(t1.z, hr, -(t1.w * hi));
+    const float ti = __fmaf_rn(t1.z, hi, t1.w * hr);
+    acc[0] = __fmaf_rn(tr, dx, acc[0]);
+    acc[1] = __fmaf_rn(ti, dx, acc[1]);
+    acc[2] = __fmaf_rn(tr, dy, acc[2]);
+    acc[3] = __fmaf_rn(ti, dy, acc[3]);
+    acc[4] = __fmaf_rn(tr, dz, acc[4]);
+    acc[5] = __fmaf_rn(ti, dz, acc[5]);
+    // B += (Jt ht) x R
+    const float qxr = __fmaf_rn(t0.x, hr, -(t0.y * hi)), qxi = __fmaf_rn(t0.x, hi, t0.y * hr);
+    const float qyr = __fmaf_rn(t0.z, hr, -(t0.w * hi)), qyi = __fmaf_rn(t0.z, hi, t0.w * hr);
+    const float qzr = __fmaf_rn(t1.x, hr, -(t1.y * hi)), qzi = __fmaf_rn(t1.x, hi, t1.y * hr);
+    acc[6] = __fmaf_rn(qyr, dz, __fmaf_rn(-qzr, dy, acc[6]));
+    acc[7] = __fmaf_rn(qyi, dz, __fmaf_rn(-qzi, dy, acc[7]));
+    acc[8] = __fmaf_rn(qzr, dx, __fmaf_rn(-qxr, dz, acc[8]));
+    acc[9] = __fmaf_rn(qzi, dx, __fmaf_rn(-qxi, dz, acc[9]));
+    acc[10] = __fmaf_rn(qxr, dy, __fmaf_rn(-qyr, dx, acc[10]));
+    acc[11] = __fmaf_rn(qxi, dy, __fmaf_rn(-qyi, dx, acc[11]));
+}
+
+// Split form, one frequency: phase k delta (kt = k / 2 pi, in turns).
+__device__ __forceinline__ void freq_split(const GeomF &g, const v4f t0, const v4f t1, float k, float kt, float *acc)
+{
+    float s, c;
+    sincos_turns(kt * g.delta, s, c);
+    accumulate_f32(g.dx, g.dy, g.dz, g.rinv, c, s, t0, t1, k, acc);
+}
+
+// Naive FP32 form, one frequency: the whole phase k |R| in FP32 (the table carries no node phase).
+__device__ __forceinline__ void freq_naive(const GeomF &g, float R, const v4f t0, const v4f t1, float k, float *acc)
+{
+    float s, c;
+    sincosf(k * R, &s, &c);
+    accumulate_f32(g.dx, g.dy, g.dz, g.rinv, c, s, t0, t1, k, acc);
+}
+
+__device__ __forceinline__ void geom_naive(const v4f p, const v4f o, GeomF &g, float &R)
+{
+    g.dx = p.x - o.x;
+    g.dy = p.y - o.y;
+    g.dz = p.z - o.z;
+    const float R2 = __fmaf_rn(g.dx, g.dx, __fmaf_rn(g.dy, g.dy, g.dz * g.dz));
+    g.rinv = __builtin_amdgcn_rsqf(R2);
+    R = R2 * g.rinv;
+    g.delta = 0.0f;
+}
+
+// Geometry and per-frequency term of the split form in FP64.
+struct GeomD {
+    double dx, dy, dz, rinv, delta;
+};
+
+__device__ __forceinline__ GeomD geom_f64(const double *p, const double4 o)
+{
+    GeomD g;
+    g.dx = p[0] - o.x;
+    g.dy = p[1] - o.y;
+    g.dz = p[2] - o.z;
+    const double R2 = __fma_rn(g.dx, g.dx, __fma_rn(g.dy, g.dy, g.dz * g.dz));
+    g.rinv = rsqrt(R2);
+    const double R = R2 * g.rinv;
+    const double dot = __fma_rn(p[0], o.x, __fma_rn(p[1], o.y, p[2] * o.z));
+    const double num = __fma_rn(-2.0, dot, o.w);
+    g.delta = num / (R + p[3]);
+    return g;
+}
+
+__device__ __forceinline__ void freq_f64(const GeomD &g, const double *t, double k, double *acc)
+{
+    double s, c;
+    sincos(k * g.delta, &s, &c);
+    const double dx = g.dx, dy = g.dy, dz = g.dz, rinv = g.rinv;
+    const double gr = c * rinv, gi = s * rinv;
+    const double a = -(rinv * rinv), b = k * rinv;
+    const double hr = __fma_rn(gr, a, -(gi * b));
+    const double hi = __fma_rn(gr, b, gi * a);
+    acc[0] = __fma_rn(t[0], gr, __fma_rn(-t[1], gi, acc[0]));
+    acc[1] = __fma_rn(t[0], gi, __fma_rn(t[1], gr, acc[1]));
+    acc[2] = __fma_rn(t[2], gr, __fma_rn(-t[3], gi, acc[2]));
+    acc[3] = __fma_rn(t[2], gi, __fma_rn(t[3], gr, acc[3]));
+    acc[4] = __fma_rn(t[4], gr, __fma_rn(-t[5], gi, acc[4]));
+    acc[5] = __fma_rn(t[4], gi, __fma_rn(t[5], gr, acc[5]));
+    const double tr = __fma_rn(t[6], hr, -(t[7] * hi));
+    const double ti = __fma_rn(t[6], hi, t[7] * hr);
+    acc[0] = __fma_rn(tr, dx, acc[0]);
+    acc[1] = __fma_rn(ti, dx, acc[1]);
+    acc[2] = __fma_rn(tr, dy, acc[2]);
+    acc[3] = __fma_rn(ti, dy, acc[3]);
+    acc[4] = __fma_rn(tr, dz, acc[4]);
+    acc[5] = __fma_rn(ti, dz, acc[5]);
+    const double qxr = __fma_rn(t[0], hr, -(t[1] * hi)), qxi = __fma_rn(t[0], hi, t[1] * hr);
+    const double qyr = __fma_rn(t[2], hr, -(t[3] * hi)), qyi = __fma_rn(t[2], hi, t[3] * hr);
+    const double qzr = __fma_rn(t[4], hr, -(t[5] * hi)), qzi = __fma_rn(t[4], hi, t[5] * hr);
+    acc[6] = __fma_rn(qyr, dz, __fma_rn(-qzr, dy, acc[6]));
+    acc[7] = __fma_rn(qyi, dz, __fma_rn(-qzi, dy, acc[7]));
+    acc[8] = __fma_rn(qzr, dx, __fma_rn(-qxr, dz, acc[8]));
+    acc[9] = __fma_rn(qzi, dx, __fma_rn(-qxi, dz, acc[9]));
+    acc[10] = __fma_rn(qxr, dy, __fma_rn(-qyr, dx, acc[10]));
+    acc[11] = __fma_rn(qxi, dy, __fma_rn(-qyi, dx, acc[11]));
+}
+
+// Map a global tile index to its job (binary search over tile0; uniform).
+__device__ __forceinline__ int find_job(cjob *jobs, int n_jobs, int64_t t)
+{
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile0 <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+constexpr int KAHAN_BLOCK = 32;   // nodes summed plainly before each compensated add (FP32)
+
+// Persistent quadrature kernel.  Every wave repeatedly takes the next tile
+// from a device counter: one node chunk, 64*OPL observation points, FPB
+// consecutive frequencies.  Node and table data are wave-uniform (scalar
+// loads); each lane owns OPL points x FPB frequencies x 12 accumulators.
+// Every wave exits once the counter passes n_tiles.
+template <int MODE, int OPL, int FPB>
+__global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_, int n_jobs, int64_t n_tiles,
+                                              unsigned int *__restrict__ counter)
+{
+    cjob *jobs = (cjob *)jobs_;
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned int tt = 0;
+        if (lane == 0) tt = atomicAdd(counter, 1u);
+        const int64_t t = (int64_t)__builtin_amdgcn_readfirstlane(tt);
+        if (t >= n_tiles) break;
+        const int j = find_job(jobs, n_jobs, t);
+        const int64_t local = t - jobs[j].tile0 + jobs[j].tile_offset;
+        const int obs_blocks = jobs[j].obs_blocks, n_chunks = jobs[j].n_chunks;
+        const int ob = (int)(local % obs_blocks);
+        const int64_t rest = local / obs_blocks;
+        const int chunk = (int)(rest % n_chunks);
+        const int kb = (int)(rest / n_chunks);
+        const int n_tot = jobs[j].n_tot, n_k = jobs[j].n_k, n_obs_pad = jobs[j].n_obs_pad;
+        const int n0 = chunk * jobs[j].chunk;
+        const int n1 = min(n0 + jobs[j].chunk, n_tot);
+        const int obase = ob * 64 * OPL + lane;
+        // frequencies of this tile; past the last one, repeat it and skip the store
+        int kidx[FPB];
+        double k64[FPB];
+#pragma unroll
+        for (int f = 0; f < FPB; ++f) {
+            kidx[f] = min(kb * FPB + f, n_k - 1);
+            k64[f] = ((cdouble *)jobs[j].k)[kidx[f]];
+        }
+        const int n_valid = min(FPB, n_k - kb * FPB);
+
+        if constexpr (MODE == MODE_FP64) {
+            cdouble *pos = (cdouble *)jobs[j].pos;
+            cdouble *tab[FPB];
+#pragma unroll
+            for (int f = 0; f < FPB; ++f) tab[f] = (cdouble *)jobs[j].tab + (size_t)kidx[f] * n_tot * 8;
+            const double4 *obs = (const double4 *)jobs[j].obs;
+            double4 o[OPL];
+            double acc[OPL][FPB][12];
+#pragma unroll
+            for (int s = 0; s < OPL; ++s) {
+                o[s] = obs[obase + 64 * s];
+#pragma unroll
+                for (int f = 0; f < FPB; ++f)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) acc[s][f][c] = 0.0;
+            }
+            for (int n = n0; n < n1; ++n) {
+                double pn[4], tn[FPB][8];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) pn[c] = pos[4 * (size_t)n + c];
+#pragma unroll
+                for (int f = 0; f < FPB; ++f)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) tn[f][c] = tab[f][8 * (size_t)n + c];
+#pragma unroll
+                for (int s = 0; s < OPL; ++s) {
+                    const GeomD g = geom_f64(pn, o[s]);
+#pragma unroll
+                    for (int f = 0; f < FPB; ++f) freq_f64(g, tn[f], k64[f], acc[s][f]);
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < FPB; ++f) {
+                if (f >= n_valid) break;
+                double *part = (double *)jobs[j].partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
+#pragma unroll
+                for (int s = 0; s < OPL; ++s)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) part[(size_t)c * n_obs_pad + obase + 64 * s] = acc[s][f][c];
+            }
+        } else {
+            cv4f *pos = (cv4f *)jobs[j].pos;
+            cv4f *tab[FPB];
+            float k[FPB], kt[FPB];
+#pragma unroll
+            for (int f = 0; f < FPB; ++f) {
+                tab[f] = (cv4f *)jobs[j].tab + (size_t)kidx[f] * n_tot * 2;
+                k[f] = (float)k64[f];
+                kt[f] = (float)(k64[f] * INV_TWO_PI);
+            }
+            const v4f *obs = (const v4f *)jobs[j].obs;
+            v4f o[OPL];
+            // Running sums stay in registers; their Kahan compensations live in LDS
+            // (touched once per KAHAN_BLOCK nodes), which frees VGPRs for occupancy.
+            // dynamic LDS: [waves per block][OPL * FPB * 12][64] floats
+            extern __shared__ float lds_dyn[];
+            float(*cmp)[64] = (float(*)[64])(lds_dyn + (size_t)(threadIdx.x >> 6) * (OPL * FPB * 12 * 64));
+            float sum[OPL][FPB][12];
+#pragma unroll
+            for (int s = 0; s < OPL; ++s) {
+                o[s] = obs[obase + 64 * s];
+#pragma unroll
+                for (int f = 0; f < FPB; ++f)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) sum[s][f][c] = 0.0f;
+            }
+#pragma unroll
+            for (int a = 0; a < OPL * FPB * 12; ++a) cmp[a][lane] = 0.0f;
+            float blk[OPL][FPB][12];
+#pragma unroll
+            for (int s = 0; s < OPL; ++s)
+#pragma unroll
+                for (int f = 0; f < FPB; ++f)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) blk[s][f][c] = 0.0f;
+            // node data of node n+1 is loaded while node n is computed
+            v4f pn = pos[n0];
+            v4f t0[FPB], t1[FPB];
+#pragma unroll
+            for (int f = 0; f < FPB; ++f) {
+                t0[f] = tab[f][2 * n0];
+                t1[f] = tab[f][2 * n0 + 1];
+            }
+            for (int n = n0; n < n1; ++n) {
+                const int nx = min(n + 1, n1 - 1);
+                const v4f pnx = pos[nx];
+                v4f t0x[FPB], t1x[FPB];
+#pragma unroll
+                for (int f = 0; f < FPB; ++f) {
+                    t0x[f] = tab[f][2 * nx];
+                    t1x[f] = tab[f][2 * nx + 1];
+                }
+#pragma unroll
+                for (int s = 0; s < OPL; ++s) {
+                    if constexpr (MODE == MODE_SPLIT) {
+                        const GeomF g = geom_split(pn, o[s]);
+#pragma unroll
+                        for (int f = 0; f < FPB; ++f) freq_split(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
+                    } else {
+                        GeomF g;
+                        float R;
+                        geom_naive(pn, o[s], g, R);
+#pragma unroll
+                        for (int f = 0; f < FPB; ++f) freq_naive(g, R, t0[f], t1[f], k[f], blk[s][f]);
+                    }
+                }
+                // every KAHAN_BLOCK nodes (counted from the chunk start), a compensated add
+                if ((n - n0) % KAHAN_BLOCK == KAHAN_BLOCK - 1 || n == n1 - 1) {
+#pragma unroll
+                    for (int s = 0; s < OPL; ++s)
+#pragma unroll
+                        for (int f = 0; f < FPB; ++f)
+#pragma unroll
+                            for (int c = 0; c < 12; ++c) {
+                                const int a = (s * FPB + f) * 12 + c;
+                                const float y = blk[s][f][c] - cmp[a][lane];
+                                const float tsum = sum[s][f][c] + y;
+                                cmp[a][lane] = (tsum - sum[s][f][c]) - y;
+                                sum[s][f][c] = tsum;
+                                blk[s][f][c] = 0.0f;
+                            }
+                }
+                pn = pnx;
+#pragma unroll
+                for (int f = 0; f < FPB; ++f) {
+                    t0[f] = t0x[f];
+                    t1[f] = t1x[f];
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < FPB; ++f) {
+                if (f >= n_valid) break;
+                float *part = (float *)jobs[j].partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
+#pragma unroll
+                for (int s = 0; s < OPL; ++s)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c)
+                        part[(size_t)c * n_obs_pad + obase + 64 * s] = sum[s][f][c] - cmp[(s * FPB + f) * 12 + c][lane];
+            }
+        }
+    }
+}
+
+// Instantiated shapes (obs per lane x frequencies per lane).
+#define SC_QUAD_SHAPES(X, M) X(M, 1, 1) X(M, 2, 1) X(M, 1, 2) X(M, 2, 2) X(M, 1, 4)
+
+static bool shape_ok(int opl, int fpb)
+{
+    return (opl == 1 && (fpb == 1 || fpb == 2 || fpb == 4)) || (opl == 2 && (fpb == 1 || fpb == 2));
+}
+
+static const void *quad_fn_dyn(int mode, int opl, int fpb)
+{
+#define SC_QUAD_FN(M, O, F) \
+    if (mode == M && opl == O && fpb == F) return (const void *)&k_quad<M, O, F>;
+    SC_QUAD_SHAPES(SC_QUAD_FN, MODE_FP64)
+    SC_QUAD_SHAPES(SC_QUAD_FN, MODE_SPLIT)
+    SC_QUAD_SHAPES(SC_QUAD_FN, MODE_NAIVE)
+#undef SC_QUAD_FN
+    return nullptr;
+}
+
+// Dynamic LDS of one quadrature block: the FP32 forms keep their Kahan compensations there.
+static size_t quad_lds_bytes(int mode, int opl, int fpb, int waves_per_block)
+{
+    return mode == MODE_FP64 ? 0 : sizeof(float) * 64 * 12 * (size_t)opl * fpb * waves_per_block;
+}
+
+int quad_max_blocks_per_cu(int mode, int opl, int fpb, int waves_per_block)
+{
+    const void *fn = quad_fn_dyn(mode, opl, fpb);
+    int nb = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * waves_per_block,
+                                                            quad_lds_bytes(mode, opl, fpb, waves_per_block)) !=
+                   hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_quad(hipStream_t st, int mode, int opl, int fpb, int waves_per_block, int grid,
+                       const QuadJob *jobs, int n_jobs, int64_t n_tiles, unsigned int *counter)
+{
+    if (!shape_ok(opl, fpb)) return hipErrorInvalidValue;
+    dim3 g(grid), b(64 * waves_per_block);
+    const size_t lds = quad_lds_bytes(mode, opl, fpb, waves_per_block);
+#define SC_QUAD_LAUNCH(M, O, F)                                                                          \
+    if (mode == M && opl == O && fpb == F) {                                                            \
+        hipLaunchKernelGGL((k_quad<M, O, F>), g, b, lds, st, jobs, n_jobs, n_tiles, counter);           \
+        return hipGetLastError();                                                                       \
+    }
+    SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_FP64)
+    SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_SPLIT)
+    SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_NAIVE)
+#undef SC_QUAD_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+}  // namespace sc

@@ -1,0 +1,32 @@
+// sc_quadjob.h -- the work description shared by the quadrature kernel
+// (sc_quad.hip) and the host code that builds it.  Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+
+namespace sc {
+
+// One problem instance as seen by the quadrature kernel.  All pointers are
+// device pointers.  Tiles of a job are numbered
+//   local = (k * n_chunks + chunk) * obs_blocks + obs_block
+// so that waves running side by side share (k, chunk) table data.
+struct QuadJob {
+    const void *tab;      // [n_k][n_tot][8] real (float or double)
+    const void *pos;      // [n_tot][4] real
+    const void *obs;      // [n_obs_pad][4] real
+    const double *k;      // [n_k]
+    void *partial;        // [n_chunks][n_k][12][n_obs_pad] real
+    int n_tot;            // surface + rim nodes
+    int n_obs_pad;        // observation points, padded to the obs block
+    int n_k;
+    int chunk;            // nodes per split-K chunk
+    int n_chunks;
+    int obs_blocks;       // n_obs_pad / (64 * obs_per_lane)
+    int64_t tile0;        // first global tile of this job in the launch
+    int64_t tile_offset;  // first job-local tile covered (a launch may cover a sub-range)
+    int64_t n_tiles;      // tiles covered by this launch
+};
+
+enum QuadMode { MODE_FP64 = 0, MODE_SPLIT = 1, MODE_NAIVE = 2 };
+
+}  // namespace sc

@@ -74,6 +74,12 @@ MUTANTS = [
     ("dgrad_sign", [("cld c1 = { -1.0L / (R * R), k / R };", "cld c1 = { 1.0L / (R * R), k / R };", 1)]),
     ("time_sign", [("sincosl(-(ld)kv[n] * (ld)t[m], &s, &c);", "sincosl((ld)kv[n] * (ld)t[m], &s, &c);", 1)]),
     ("time_dk", [("(double)(acc.re * (ld)dk)", "(double)(acc.re)", 1), ("(double)(acc.im * (ld)dk)", "(double)(acc.im)", 1)]),
+    ("power_sign", [("acc += (ld)wgt[q] * (-sz);", "acc += (ld)wgt[q] * sz;", 1)]),
+    ("power_drop_EyBx", [("- ((ld)e[2] * b[0] + (ld)e[3] * b[1])", "", 1)]),
+    ("power_no_4pi", [("P[n] = (double)(4.0L * PI_L * acc);", "P[n] = (double)(acc);", 1)]),
+    ("power_unweighted", [("acc += (ld)wgt[q] * (-sz);", "acc += -sz;", 1)]),
+    ("power_with_rim", [("for (int q = 0; q < n_surf; ++q) {\n            const double *e = E + 6",
+                         "for (int q = 0; q < n_tot; ++q) {\n            const double *e = E + 6", 1)]),
 ]
 
 
@@ -237,7 +243,29 @@ def pin_time(orc):
     return np.abs(Ft - np.exp(-1j * k0 * t) * dk * (1 - z ** n) / (1 - z)).max() < 1e-12
 
 
-BATTERY = [pin_p1, pin_p2, pin_forms, pin_maxwell, pin_symmetry, pin_paraxial, pin_flux, pin_rules, pin_time]
+def pin_power(orc):
+    # aperture power of the incident beam: closed forms for the plane wave, the
+    # literal Gaussian (x- and y-polarised) and the curl-consistent Gaussian
+    f, a, w0 = 20.0, 25.0, 10.0
+    m = orc.mirror(f, a, 60, 32)
+    ks = [K, 1.3 * K]
+    Ei, Bi = orc.incident_tables(m, ks, orc.PLANE)
+    if np.abs(orc.incident_power(m, Ei, Bi) / (4 * math.pi * math.pi * a * a) - 1).max() > 1e-12:
+        return False
+    lit = 4 * math.pi * (math.pi * w0 * w0 / 2) * (1 - math.exp(-2 * a * a / (w0 * w0)))
+    for pol in (0.0, math.pi / 2):
+        Ei, Bi = orc.incident_tables(m, ks, orc.GAUSSIAN, w0, pol=pol)
+        if np.abs(orc.incident_power(m, Ei, Bi) / lit - 1).max() > 1e-12:
+            return False
+    w0 = 5.0   # a = 5 w0: the clipped tail is exp(-50)
+    Ei, Bi = orc.incident_tables(m, ks, orc.GAUSSIAN_CONSISTENT, w0)
+    P = orc.incident_power(m, Ei, Bi)
+    ex = [4 * math.pi * (math.pi * w0 * w0 / 2) * (1 + 1 / (k * w0) ** 2) for k in ks]
+    return np.abs(P / np.array(ex) - 1).max() < 1e-12
+
+
+BATTERY = [pin_p1, pin_p2, pin_forms, pin_maxwell, pin_symmetry, pin_paraxial, pin_flux, pin_rules, pin_time,
+           pin_power]
 
 
 def run_battery(orc):

@@ -22,6 +22,9 @@ public dataset.  The configurations below stand in for them:
                    64 axial points, 256 time samples about the focal arrival 2f.
 * ``stress``    -- f = 5 cm, aperture radius 15 cm, w0 = 7 cm, 64 samples,
                    800x800 nodes, 128x128 focal plane over +-2 lambda0.
+* ``table1``    -- the Table I parameters: f = 6.75 cm, aperture 12.5 cm,
+                   w0 = 10 cm, super-Gaussian power spectrum (820 nm, 70 nm,
+                   order 3, 100 samples) normalised to 150 J.
 * ``sweep``     -- 256 seeded instances of uneven size (batched launch).
 * ``serving``   -- a seeded Poisson stream of requests drawn like ``sweep``.
 """
@@ -93,8 +96,11 @@ class Workload:
         obs = self.obs if obs_idx is None else self.obs[np.asarray(obs_idx)]
         k = self.k if k_idx is None else self.k[np.asarray(k_idx)]
         sp = self.spectrum if k_idx is None else self.spectrum[np.asarray(k_idx)]
+        meta = dict(self.meta)
+        if k_idx is not None and "eps" in meta:
+            meta["eps"] = np.ascontiguousarray(meta["eps"][np.asarray(k_idx)])
         return replace(self, name=name or self.name + "-subset", obs=np.ascontiguousarray(obs),
-                       k=np.ascontiguousarray(k), spectrum=np.ascontiguousarray(sp))
+                       k=np.ascontiguousarray(k), spectrum=np.ascontiguousarray(sp), meta=meta)
 
     def with_nodes(self, n_r: int, n_phi: int) -> "Workload":
         return replace(self, n_r=int(n_r), n_phi=int(n_phi))
@@ -135,6 +141,22 @@ def gaussian_spectrum(n_k: int, lam0: float = LAMBDA0, tau: float = TAU_FWHM, n_
     return k, amp, float(k[1] - k[0])
 
 
+def super_gaussian_power(n_k: int, lam_c: float, dlam: float, order: int, cut: float = 1.5):
+    """Uniform wavenumber samples of a super-Gaussian power spectrum in wavelength.
+
+    eps(lambda) = exp(-((lambda - lam_c) / dlam)^(2 order)) -- the form of
+    Sec. IV-B with the minus sign of the exponent restored -- read as energy
+    per unit k at lambda = 2 pi / k (unnormalised; the library scales it to the
+    total energy).  Samples are uniform in k over lambda in
+    [lam_c - cut dlam, lam_c + cut dlam], end points included (at cut = 1.5 and
+    order 3 the edges sit at exp(-11.4) of the peak).  Returns (k, eps, dk).
+    """
+    k = np.linspace(2.0 * math.pi / (lam_c + cut * dlam), 2.0 * math.pi / (lam_c - cut * dlam), n_k)
+    lam = 2.0 * math.pi / k
+    eps = np.exp(-(((lam - lam_c) / dlam) ** (2 * order)))
+    return k, eps, float(k[1] - k[0]) if n_k > 1 else 1.0
+
+
 def time_window(dk: float, n_t: int, t_center: float) -> np.ndarray:
     """n_t samples t_m = t_c + (m - n_t/2) dt with dt = 2 pi / (n_t dk) (one period of the sum)."""
     dt = 2.0 * math.pi / (n_t * dk)
@@ -142,6 +164,30 @@ def time_window(dk: float, n_t: int, t_center: float) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------- named configs
+
+# Table I of the paper: parabola r_max = 0.125 m, f = 0.0675 m; incident beam
+# w0 = 0.100 m, lambda_c = 820 nm, delta lambda = 70 nm, super-Gaussian order
+# n = 3, total energy 150 J; 100 frequency samples (Fig. 1 caption).
+TABLE1 = dict(r_max=0.125, f=0.0675, w0=0.100, lam_c=820e-9, dlam=70e-9, order=3, e_tot=150.0, n_freq=100)
+
+
+def table1(n_k: int = TABLE1["n_freq"], n_nodes: int = 400, n_plane: int = 64) -> Workload:
+    """The Table I configuration (x-polarised literal Gaussian beam, Sec. IV-B).
+
+    The power spectrum samples are in ``meta["eps"]`` (unnormalised) with the
+    total energy ``meta["e_tot"]``; ``spectrum`` is 1, the energy
+    normalisation is part of the method.  Focal plane +-2 lambda_c and 64 axial
+    points over +-4 lambda_c; 256 time samples about the focal arrival 2f.
+    """
+    T = TABLE1
+    k, eps, dk = super_gaussian_power(n_k, T["lam_c"], T["dlam"], T["order"])
+    lam_c = T["lam_c"]
+    obs = np.concatenate([focal_plane(2.0 * lam_c, n_plane), axial_line(4.0 * lam_c, 64)])
+    return Workload(name="table1", f=T["f"], a=T["r_max"], n_r=n_nodes, n_phi=n_nodes, k=k,
+                    spectrum=np.ones(n_k, np.complex128), obs=obs, w0=T["w0"],
+                    t=time_window(dk, 256, 2.0 * T["f"]), dk=dk,
+                    meta=dict(eps=eps, e_tot=T["e_tot"]))
+
 
 def mono() -> Workload:
     """Monochromatic unit-wavelength case: lambda = 1, f = 20, aperture 40 (NA = 1)."""
