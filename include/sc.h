@@ -225,6 +225,37 @@ sc_status sc_get_result(const sc_prob *p, void *E, void *B, int on_device);
  * Et, Bt: [n_t][n_obs][3], same complex type as the result.                 */
 sc_status sc_to_time(sc_prob *p, double dk, const double *t, int n_t, void *Et, void *Bt, int on_device);
 
+/* ------------------------------------------------------------ diagnostics */
+/* Verification of the reflected field as in Sec. IV-A: Maxwell residuals in
+ * the frequency and time domains and the energy in the observation volume.
+ * The residuals use 4th-order central differences on a 13-point stencil per
+ * point: the point itself, then offsets -2h, -h, +h, +2h along x, then along
+ * y, then along z.  Workflow: sc_stencil_points -> sc_set_observation with
+ * the 13 n_pts stencil points -> sc_evaluate (any precision) -> the calls
+ * below, which read the problem's last result.                              */
+
+/* Host helper: out [n_pts * 13][3] = the stencil of each point of xyz [n_pts][3]. */
+sc_status sc_stencil_points(const double *xyz, int n_pts, double h, double *out);
+/* Frequency-domain residual (eq. relDiffMaxwellFreq), for every k and point:
+ *   e_f = 2 (curl E - ik B) / (max|curl E| + max|ik B|)
+ *       + 2 (curl B + ik E) / (max|curl B| + max|ik E|),
+ * maxima over the n_pts points at the same k; ef [n_k][n_pts] (host) = |e_f|.
+ * SC_E_STATE without a result, or if the observation set is not 13 n_pts.   */
+sc_status sc_maxwell_residual_freq(sc_prob *p, int n_pts, double h, double *ef);
+/* Time-domain residual (eq. relDiffMaxwellTime) at times t [n_t] (host), on
+ * the physical fields 2 Re F(t), F(t) = dk sum_n F_n e^{-i k_n t}:
+ *   e_t = 2 (curl E + dB/dt) / (max|curl E| + max|dB/dt|)
+ *       + 2 (curl B - dE/dt) / (max|curl B| + max|dE/dt|),
+ * time derivatives by 4th-order central differences of step dt;
+ * et [n_t][n_pts] (host) = |e_t|.                                            */
+sc_status sc_maxwell_residual_time(sc_prob *p, int n_pts, double h, const double *t, int n_t, double dt,
+                                   double dk, double *et);
+/* Electromagnetic energy of the observation set at times t [n_t] (host), each
+ * point standing for a cell of volume dV (Lorentz-Heaviside, c = 1, Sec. IV-A):
+ *   W(t) = 1/2 dV sum_points ( |2 Re E(t)|^2 + |2 Re B(t)|^2 ).
+ * W [n_t] (host).  Reads the last result; any observation set.              */
+sc_status sc_field_energy(sc_prob *p, const double *t, int n_t, double dk, double dV, double *W);
+
 /* Evaluate several problems in ONE persistent launch (tiles of all problems
  * share the device), then reduce each; results are kept per problem (read
  * with sc_get_result).  Each problem's result is bitwise identical to what

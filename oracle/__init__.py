@@ -245,6 +245,77 @@ def energy_amplitudes(P, eps, e_tot: float = 0.0, dk: float = 0.0):
     return np.sqrt(eps / np.asarray(P, dtype=np.float64))
 
 
+# --------------------------------------------------------------------------- diagnostics (Sec. IV-A)
+# Fields on 13-point stencils: the point, then offsets -2h, -h, +h, +2h along x, y and z.
+# Derivatives are 4th-order central differences (f(-2h) - 8 f(-h) + 8 f(h) - f(2h)) / (12 h).
+
+_STENCIL_OFFSETS = (-2.0, -1.0, 1.0, 2.0)
+
+
+def stencil(xyz, h: float) -> np.ndarray:
+    """The 13-point stencil of every point of xyz [n, 3], as [13 n, 3]."""
+    xyz = _f64(xyz).reshape(-1, 3)
+    out = np.repeat(xyz[:, None, :], 13, axis=1)
+    for a in range(3):
+        for j, o in enumerate(_STENCIL_OFFSETS):
+            out[:, 1 + 4 * a + j, a] += o * h
+    return out.reshape(-1, 3)
+
+
+def _fd4(m2, m1, p1, p2, step):
+    return (m2 - 8.0 * m1 + 8.0 * p1 - p2) / (12.0 * step)
+
+
+def _curl(F, h):
+    """curl at the stencil centres of F [..., n_pts, 13, 3]."""
+    d = [_fd4(*(F[..., 1 + 4 * a + j, :] for j in range(4)), h) for a in range(3)]   # d[a][..., c] = d_a F_c
+    return np.stack([d[1][..., 2] - d[2][..., 1], d[2][..., 0] - d[0][..., 2], d[0][..., 1] - d[1][..., 0]],
+                    axis=-1)
+
+
+def _vnorm(v):
+    return np.sqrt(np.sum(np.abs(v) ** 2, axis=-1))
+
+
+def _residual(r1, r2, n1, n2, n3, n4):
+    """|2 r1 / (max n1 + max n2) + 2 r2 / (max n3 + max n4)|, maxima over the points (axis 1)."""
+    d1 = (n1.max(axis=1) + n2.max(axis=1))[:, None, None]
+    d2 = (n3.max(axis=1) + n4.max(axis=1))[:, None, None]
+    return _vnorm(2.0 * r1 / d1 + 2.0 * r2 / d2)
+
+
+def maxwell_residual_freq(k, E, B, n_pts: int, h: float):
+    """|e_f| [n_k, n_pts] (eq. relDiffMaxwellFreq) from E, B [n_k, 13 n_pts, 3] on the stencils:
+    e_f = 2 (curl E - ik B) / (max|curl E| + max|ik B|) + 2 (curl B + ik E) / (max|curl B| + max|ik E|)."""
+    k = _f64(k).reshape(-1, 1, 1)
+    E = _c128(E).reshape(k.shape[0], n_pts, 13, 3)
+    B = _c128(B).reshape(k.shape[0], n_pts, 13, 3)
+    cE, cB = _curl(E, h), _curl(B, h)
+    ikB, ikE = 1j * k * B[:, :, 0], 1j * k * E[:, :, 0]
+    return _residual(cE - ikB, cB + ikE, _vnorm(cE), _vnorm(ikB), _vnorm(cB), _vnorm(ikE))
+
+
+def maxwell_residual_time(k, dk: float, t, dt: float, E, B, n_pts: int, h: float, threads: int = 0):
+    """|e_t| [n_t, n_pts] (eq. relDiffMaxwellTime) on the physical fields 2 Re F(t), F(t) the
+    semi-discrete sum of E, B [n_k, 13 n_pts, 3]; time derivatives by differences of step dt:
+    e_t = 2 (curl E + dB/dt) / (max|curl E| + max|dB/dt|) + 2 (curl B - dE/dt) / (max|curl B| + max|dE/dt|)."""
+    t = _f64(t).ravel()
+    ts = (t[:, None] + dt * np.arange(-2, 3)[None, :]).ravel()
+    Et = 2.0 * time_transform(k, dk, ts, E, threads).real.reshape(t.shape[0], 5, n_pts, 13, 3)
+    Bt = 2.0 * time_transform(k, dk, ts, B, threads).real.reshape(t.shape[0], 5, n_pts, 13, 3)
+    cE, cB = _curl(Et[:, 2], h), _curl(Bt[:, 2], h)
+    dE = _fd4(Et[:, 0, :, 0], Et[:, 1, :, 0], Et[:, 3, :, 0], Et[:, 4, :, 0], dt)
+    dB = _fd4(Bt[:, 0, :, 0], Bt[:, 1, :, 0], Bt[:, 3, :, 0], Bt[:, 4, :, 0], dt)
+    return _residual(cE + dB, cB - dE, _vnorm(cE), _vnorm(dB), _vnorm(cB), _vnorm(dE))
+
+
+def field_energy(k, dk: float, t, E, B, dV: float, threads: int = 0):
+    """W(t) = 1/2 dV sum_points (|2 Re E(t)|^2 + |2 Re B(t)|^2) (Lorentz-Heaviside, c = 1), [n_t]."""
+    Et = 2.0 * time_transform(k, dk, t, E, threads).real
+    Bt = 2.0 * time_transform(k, dk, t, B, threads).real
+    return 0.5 * dV * (np.sum(Et ** 2, axis=(1, 2)) + np.sum(Bt ** 2, axis=(1, 2)))
+
+
 def solve(w, kind: int = GAUSSIAN, threads: int = 0, line_term: bool = True):
     """Mirror + Gaussian incident tables + reflected field for a ``workloads.Workload``."""
     kind = GAUSSIAN_CONSISTENT if (kind == GAUSSIAN and getattr(w, "consistent", 0)) else kind

@@ -87,6 +87,10 @@ SIGNATURES = {
     "sc_evaluate": [V, I, P, P, I],
     "sc_get_result": [V, P, P, I],
     "sc_to_time": [V, D, P, I, P, P, I],
+    "sc_stencil_points": [P, I, D, P],
+    "sc_maxwell_residual_freq": [V, I, D, P],
+    "sc_maxwell_residual_time": [V, I, D, P, I, D, D, P],
+    "sc_field_energy": [V, P, I, D, D, P],
     "sc_evaluate_batch": [V, PP, I, I],
     "sc_prob_device_bytes": [V, ctypes.POINTER(ctypes.c_size_t)],
     "sc_server_create": [V, ctypes.c_size_t, I, D, PP],

@@ -196,6 +196,28 @@ class Problem:
             raise ValueError(f"eps has {e.shape[0]} entries, expected {self.n_k}")
         call("sc_normalize_energy", self.h, _ptr(e), float(e_tot), float(dk))
 
+    # ---- diagnostics (the observation set must be the 13-point stencils of n_pts points)
+    def maxwell_residual_freq(self, n_pts: int, h: float):
+        """|e_f| [n_k][n_pts] from the last result (sc_maxwell_residual_freq)."""
+        out = np.empty((self.n_k, n_pts), np.float64)
+        call("sc_maxwell_residual_freq", self.h, int(n_pts), float(h), _ptr(out))
+        return out
+
+    def maxwell_residual_time(self, n_pts: int, h: float, t, dt: float, dk: float):
+        """|e_t| [n_t][n_pts] from the last result (sc_maxwell_residual_time)."""
+        t = _host_f64(t, (-1,))
+        out = np.empty((t.shape[0], n_pts), np.float64)
+        call("sc_maxwell_residual_time", self.h, int(n_pts), float(h), _ptr(t), int(t.shape[0]), float(dt),
+             float(dk), _ptr(out))
+        return out
+
+    def field_energy(self, t, dk: float, dV: float):
+        """Energy of the observation set at times t [n_t] (sc_field_energy)."""
+        t = _host_f64(t, (-1,))
+        out = np.empty(t.shape[0], np.float64)
+        call("sc_field_energy", self.h, _ptr(t), int(t.shape[0]), float(dk), float(dV), _ptr(out))
+        return out
+
     def set_table_storage(self, keep_fp64: bool):
         call("sc_set_table_storage", self.h, int(bool(keep_fp64)))
 
@@ -265,6 +287,14 @@ class Problem:
         b = ctypes.c_size_t()
         call("sc_prob_device_bytes", self.h, ctypes.byref(b))
         return b.value
+
+
+def stencil_points(xyz, h: float) -> np.ndarray:
+    """The 13-point finite-difference stencils of points xyz [n, 3] (sc_stencil_points), [13 n, 3]."""
+    xyz = _host_f64(xyz, (-1, 3))
+    out = np.empty((13 * xyz.shape[0], 3), np.float64)
+    call("sc_stencil_points", _ptr(xyz), int(xyz.shape[0]), float(h), _ptr(out))
+    return out
 
 
 def problem_from_workload(ctx: Context, w, consistent: Optional[bool] = None) -> Problem:

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libsc.so")
-SOURCES = ["sc_quad.hip", "sc_kernels.hip", "sc_api.cpp", "sc_serve.cpp", "sc_gauss_host.cpp"]
+SOURCES = ["sc_quad.hip", "sc_kernels.hip", "sc_diag.hip", "sc_api.cpp", "sc_serve.cpp", "sc_gauss_host.cpp"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [

@@ -793,6 +793,124 @@ extern "C" sc_status sc_to_time(sc_prob *p, double dk, const double *t, int n_t,
     return SC_OK;
 }
 
+// ================================================================ diagnostics
+
+extern "C" sc_status sc_stencil_points(const double *xyz, int n_pts, double h, double *out)
+{
+    if (!xyz || !out) return fail(SC_E_INVAL, "sc_stencil_points: NULL argument");
+    if (n_pts < 1) return fail(SC_E_INVAL, "sc_stencil_points: n_pts must be >= 1");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(SC_E_INVAL, "sc_stencil_points: h must be > 0");
+    static const double off[4] = {-2.0, -1.0, 1.0, 2.0};
+    for (int i = 0; i < n_pts; ++i) {
+        double *o = out + (size_t)i * 13 * 3;
+        for (int c = 0; c < 3; ++c) o[c] = xyz[3 * (size_t)i + c];
+        for (int a = 0; a < 3; ++a)
+            for (int j = 0; j < 4; ++j) {
+                double *q = o + 3 * (1 + 4 * a + j);
+                for (int c = 0; c < 3; ++c) q[c] = xyz[3 * (size_t)i + c];
+                q[a] += off[j] * h;
+            }
+    }
+    return SC_OK;
+}
+
+static sc_status check_stencil_result(const sc_prob *p, int n_pts, double h, const char *who)
+{
+    if (n_pts < 1) return fail(SC_E_INVAL, "%s: n_pts must be >= 1", who);
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(SC_E_INVAL, "%s: h must be > 0", who);
+    if (p->res_prec < 0) return fail(SC_E_STATE, "%s: no spectral result (evaluate first)", who);
+    if ((int64_t)p->n_obs != 13LL * n_pts)
+        return fail(SC_E_STATE, "%s: the observation set has %d points, not the 13 x %d of a stencil", who, p->n_obs,
+                    n_pts);
+    return SC_OK;
+}
+
+extern "C" sc_status sc_maxwell_residual_freq(sc_prob *p, int n_pts, double h, double *ef)
+{
+    if (!p || !ef) return fail(SC_E_INVAL, "sc_maxwell_residual_freq: NULL argument");
+    SC_TRY(check_stencil_result(p, n_pts, h, "sc_maxwell_residual_freq"));
+    DeviceGuard g(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    const int n_k = (int)p->k.size();
+    const size_t cells = (size_t)n_k * n_pts;
+    DevBuf work, mx, out;
+    SC_TRY(work.reserve(sizeof(double) * diag_slots() * cells, p->alloc_stream));
+    SC_TRY(mx.reserve(sizeof(double) * 4 * n_k, p->alloc_stream));
+    SC_TRY(out.reserve(sizeof(double) * cells, p->alloc_stream));
+    HIP_TRY(launch_maxwell_freq(st, p->res_prec == SC_FP64, n_k, n_pts, h, p->d_k.as<double>(), p->resE.p, p->resB.p,
+                                work.as<double>(), mx.as<double>(), out.as<double>()));
+    HIP_TRY(hipMemcpyAsync(ef, out.p, sizeof(double) * cells, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));   // scratch is freed on return
+    return SC_OK;
+}
+
+// Time-domain fields of the last result at times t (host, n_t) into E, B ([n_t][n_obs][3], result type).
+static sc_status time_fields(sc_prob *p, double dk, const std::vector<double> &t, DevBuf &E, DevBuf &B)
+{
+    hipStream_t st = p->ctx->stream;
+    const int n_k = (int)p->k.size(), n_t = (int)t.size();
+    const int f64 = p->res_prec == SC_FP64;
+    const size_t rs = f64 ? sizeof(double) : sizeof(float);
+    const int64_t n_x = (int64_t)p->n_obs * 3;
+    DevBuf dt, tw;
+    SC_TRY(dt.reserve(sizeof(double) * n_t, p->alloc_stream));
+    SC_TRY(tw.reserve(sizeof(double) * 2 * (size_t)n_t * n_k, p->alloc_stream));
+    SC_TRY(E.reserve(rs * 2 * (size_t)n_t * n_x, p->alloc_stream));
+    SC_TRY(B.reserve(rs * 2 * (size_t)n_t * n_x, p->alloc_stream));
+    HIP_TRY(hipMemcpyAsync(dt.p, t.data(), sizeof(double) * n_t, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_twiddles(st, n_k, p->d_k.as<double>(), n_t, dt.as<double>(), dk, tw.as<double>()));
+    HIP_TRY(launch_time(st, f64, n_k, n_t, n_x, tw.as<double>(), p->resE.p, E.p));
+    HIP_TRY(launch_time(st, f64, n_k, n_t, n_x, tw.as<double>(), p->resB.p, B.p));
+    HIP_TRY(hipStreamSynchronize(st));   // t, dt and tw go out of scope
+    return SC_OK;
+}
+
+extern "C" sc_status sc_maxwell_residual_time(sc_prob *p, int n_pts, double h, const double *t, int n_t, double dt,
+                                              double dk, double *et)
+{
+    if (!p || !t || !et) return fail(SC_E_INVAL, "sc_maxwell_residual_time: NULL argument");
+    SC_TRY(check_stencil_result(p, n_pts, h, "sc_maxwell_residual_time"));
+    if (n_t < 1) return fail(SC_E_INVAL, "sc_maxwell_residual_time: n_t must be >= 1");
+    if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(dk))
+        return fail(SC_E_INVAL, "sc_maxwell_residual_time: dt must be > 0 and dk finite");
+    DeviceGuard g(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    std::vector<double> ts(5 * (size_t)n_t);
+    for (int m = 0; m < n_t; ++m)
+        for (int j = 0; j < 5; ++j) ts[5 * (size_t)m + j] = t[m] + (double)(j - 2) * dt;
+    DevBuf E, B, work, mx, out;
+    SC_TRY(time_fields(p, dk, ts, E, B));
+    const size_t cells = (size_t)n_t * n_pts;
+    SC_TRY(work.reserve(sizeof(double) * diag_slots() * cells, p->alloc_stream));
+    SC_TRY(mx.reserve(sizeof(double) * 4 * n_t, p->alloc_stream));
+    SC_TRY(out.reserve(sizeof(double) * cells, p->alloc_stream));
+    HIP_TRY(launch_maxwell_time(st, p->res_prec == SC_FP64, n_t, n_pts, h, dt, E.p, B.p, work.as<double>(),
+                                mx.as<double>(), out.as<double>()));
+    HIP_TRY(hipMemcpyAsync(et, out.p, sizeof(double) * cells, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SC_OK;
+}
+
+extern "C" sc_status sc_field_energy(sc_prob *p, const double *t, int n_t, double dk, double dV, double *W)
+{
+    if (!p || !t || !W) return fail(SC_E_INVAL, "sc_field_energy: NULL argument");
+    if (n_t < 1) return fail(SC_E_INVAL, "sc_field_energy: n_t must be >= 1");
+    if (!(dV > 0.0) || !std::isfinite(dV) || !std::isfinite(dk))
+        return fail(SC_E_INVAL, "sc_field_energy: dV must be > 0 and dk finite");
+    if (p->res_prec < 0) return fail(SC_E_STATE, "sc_field_energy: no spectral result (evaluate first)");
+    DeviceGuard g(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    DevBuf E, B, part, dW;
+    SC_TRY(time_fields(p, dk, std::vector<double>(t, t + n_t), E, B));
+    SC_TRY(part.reserve(sizeof(double) * energy_partial_count(n_t), p->alloc_stream));
+    SC_TRY(dW.reserve(sizeof(double) * n_t, p->alloc_stream));
+    HIP_TRY(launch_energy(st, p->res_prec == SC_FP64, n_t, p->n_obs, E.p, B.p, 0.5 * dV, part.as<double>(),
+                          dW.as<double>()));
+    HIP_TRY(hipMemcpyAsync(W, dW.p, sizeof(double) * n_t, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SC_OK;
+}
+
 extern "C" sc_status sc_get_timing(const sc_prob *p, sc_timing *out)
 {
     if (!p || !out) return fail(SC_E_INVAL, "sc_get_timing: NULL argument");

@@ -36,6 +36,18 @@ hipError_t launch_power_gaussian(hipStream_t st, int n_k, int n_surf, const doub
 int power_partial_count(int n_k);
 // tab[k][node] *= fac[k] (complex128 [n_k]); exactly one of tab64, tab32 non-null
 hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, const double *fac, double *tab64, float *tab32);
+// Maxwell-residual diagnostics (sc_diag.hip).  Stencil results [rows][13 n_pts][3] complex (double
+// if is_f64, else float); work holds diag_slots() doubles per (row, point), mx 4 per row, out 1 per
+// (row, point).  The time form reads [n_t * 5][13 n_pts][3] (times t_m + (j - 2) dt).
+hipError_t launch_maxwell_freq(hipStream_t st, int is_f64, int n_k, int n_pts, double h, const double *k,
+                               const void *E, const void *B, double *work, double *mx, double *out);
+hipError_t launch_maxwell_time(hipStream_t st, int is_f64, int n_t, int n_pts, double h, double dt, const void *E,
+                               const void *B, double *work, double *mx, double *out);
+int diag_slots();
+// Energy 1/2 dV sum (|2 Re E|^2 + |2 Re B|^2) per time row of [n_t][n_obs][3]; part: energy_partial_count(n_t).
+int energy_partial_count(int n_t);
+hipError_t launch_energy(hipStream_t st, int is_f64, int n_t, int n_obs, const void *E, const void *B, double half_dv,
+                         double *part, double *W);
 hipError_t launch_quad(hipStream_t st, int mode, int obs_per_lane, int freq_per_lane, int waves_per_block,
                        int grid, const QuadJob *jobs, int n_jobs, int64_t n_tiles, unsigned int *counter);
 hipError_t launch_reduce(hipStream_t st, int mode, const void *partial, int n_chunks, int n_k, int n_obs,

@@ -1,0 +1,125 @@
+"""GPU tests of the verification diagnostics (Sec. IV-A): Maxwell residuals in
+the frequency and time domains and the field energy, through the C ABI,
+against the oracle's own diagnostics on the oracle's fields."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+K = 2 * math.pi
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_08146_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _problem(ctx, f, a, n_r, n_phi, ks, w0, consistent, obs, spectrum=None):
+    from paper_1609_08146_amd import Problem
+    p = Problem(ctx)
+    p.set_mirror(f, a, n_r, n_phi)
+    p.set_frequencies(ks)
+    p.set_incident_gaussian(w0, 0.0, spectrum, consistent)
+    p.set_observation(obs)
+    return p
+
+
+def test_maxwell_residual_freq_matches_oracle(ctx, orc):
+    from paper_1609_08146_amd import stencil_points
+    pts = np.array([[0.3, 0.2, 0.1], [-0.5, 0.1, 0.4], [0.0, 0.0, 0.0], [0.7, -0.6, -0.3], [0.1, 0.9, 0.2]])
+    h = 0.02
+    st = stencil_points(pts, h)
+    ks = np.array([K, 1.2 * K])
+    m = orc.mirror(20.0, 40.0, 80, 64)
+    for consistent in (True, False):
+        kind = orc.GAUSSIAN_CONSISTENT if consistent else orc.GAUSSIAN
+        Ei, Bi = orc.incident_tables(m, ks, kind, 20.0)
+        Eo, Bo = orc.reflected_field(m, ks, Ei, Bi, st)
+        efo = orc.maxwell_residual_freq(ks, Eo, Bo, len(pts), h)
+        p = _problem(ctx, 20.0, 40.0, 80, 64, ks, 20.0, consistent, st)
+        p.evaluate("fp64")
+        ef = p.maxwell_residual_freq(len(pts), h)
+        print(f"consistent={consistent}: oracle max {efo.max():.3e}, fp64 rel diff {np.abs(ef / efo - 1).max():.1e}")
+        np.testing.assert_allclose(ef, efo, rtol=1e-5)
+        if not consistent:
+            # FP32 fields: a residual floor near 1e-5 relative, far below the literal beam's 1e-2
+            p.evaluate("fp32_split")
+            np.testing.assert_allclose(p.maxwell_residual_freq(len(pts), h), efo, rtol=2e-2)
+        p.close()
+
+
+def test_maxwell_residual_time_matches_oracle(ctx, orc):
+    from paper_1609_08146_amd import stencil_points
+    w = workloads.broadband(n_k=16, n_nodes=60)
+    lam0 = workloads.LAMBDA0
+    pts = np.array([[0.0, 0.0, 0.0], [0.5, 0.3, 0.0], [-0.8, 0.2, 0.6], [0.3, -1.0, -0.4]]) * lam0
+    h, dt = lam0 / 40, lam0 / 55
+    st = stencil_points(pts, h)
+    t = 2 * w.f + np.array([-3.0, 0.0, 1.5, 4.0]) * lam0
+    m = orc.mirror(w.f, w.a, w.n_r, w.n_phi)
+    for consistent in (True, False):
+        kind = orc.GAUSSIAN_CONSISTENT if consistent else orc.GAUSSIAN
+        Ei, Bi = orc.incident_tables(m, w.k, kind, w.w0, 0.0, w.spectrum)
+        Eo, Bo = orc.reflected_field(m, w.k, Ei, Bi, st)
+        eto = orc.maxwell_residual_time(w.k, w.dk, t, dt, Eo, Bo, len(pts), h)
+        p = _problem(ctx, w.f, w.a, w.n_r, w.n_phi, w.k, w.w0, consistent, st, w.spectrum)
+        p.evaluate("fp64")
+        et = p.maxwell_residual_time(len(pts), h, t, dt, w.dk)
+        print(f"consistent={consistent}: oracle max {eto.max():.3e}, fp64 max rel diff {np.abs(et / eto - 1).max():.1e}")
+        np.testing.assert_allclose(et, eto, rtol=1e-4)
+        p.close()
+
+
+def test_field_energy_matches_oracle(ctx, orc):
+    w = workloads.broadband(n_k=12, n_nodes=60).subset(obs_idx=np.arange(0, 4160, 29))
+    m = orc.mirror(w.f, w.a, w.n_r, w.n_phi)
+    Ei, Bi = orc.incident_tables(m, w.k, orc.GAUSSIAN, w.w0, 0.0, w.spectrum)
+    Eo, Bo = orc.reflected_field(m, w.k, Ei, Bi, w.obs)
+    t = 2 * w.f + np.array([-4.0, 0.0, 2.0]) * workloads.LAMBDA0
+    dV = 1.7e-20
+    Wo = orc.field_energy(w.k, w.dk, t, Eo, Bo, dV)
+    p = _problem(ctx, w.f, w.a, w.n_r, w.n_phi, w.k, w.w0, False, w.obs, w.spectrum)
+    p.evaluate("fp64")
+    np.testing.assert_allclose(p.field_energy(t, w.dk, dV), Wo, rtol=1e-12)
+    p.evaluate("fp32_split")
+    np.testing.assert_allclose(p.field_energy(t, w.dk, dV), Wo, rtol=1e-5)
+    p.close()
+
+
+def test_diagnostics_error_paths(ctx):
+    from paper_1609_08146_amd import Problem, ScError, stencil_points
+    from paper_1609_08146_amd._abi import SC_E_INVAL, SC_E_STATE
+    p = Problem(ctx)
+    p.set_mirror(20.0, 40.0, 20, 16)
+    p.set_frequencies([K])
+    p.set_incident_gaussian(20.0)
+    st = stencil_points(np.zeros((2, 3)), 0.1)
+    p.set_observation(st)
+    cases = [(lambda: p.maxwell_residual_freq(2, 0.1), SC_E_STATE),      # no result yet
+             (lambda: p.field_energy([0.0], 1.0, 1.0), SC_E_STATE)]
+    for fn, status in cases:
+        with pytest.raises(ScError) as e:
+            fn()
+        assert e.value.status == status
+    p.evaluate("fp64")
+    cases = [(lambda: p.maxwell_residual_freq(3, 0.1), SC_E_STATE),      # 26 points are not 13 x 3
+             (lambda: p.maxwell_residual_freq(2, 0.0), SC_E_INVAL),
+             (lambda: p.maxwell_residual_time(2, 0.1, [0.0], 0.0, 1.0), SC_E_INVAL),
+             (lambda: p.field_energy([0.0], 1.0, -1.0), SC_E_INVAL)]
+    for fn, status in cases:
+        with pytest.raises(ScError) as e:
+            fn()
+        assert e.value.status == status
+    assert p.maxwell_residual_freq(2, 0.1).shape == (1, 2)
+    with pytest.raises(ScError):
+        stencil_points(np.zeros((1, 3)), -1.0)
+    p.close()
