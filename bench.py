@@ -95,9 +95,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "copy"],
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "copy", "table1"],
                     help="step: the hot path on the broadband workload (default); batch: the seeded sweep of "
-                         "uneven instances in one persistent launch; serve: a Poisson request stream")
+                         "uneven instances in one persistent launch; serve: a Poisson request stream; "
+                         "table1: the Table I workload with energy normalisation and diagnostics")
     ap.add_argument("--instances", type=int, default=256, help="batch: instances of the sweep")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
@@ -258,6 +259,80 @@ def bench_serve(args):
         "hbm_budget_gb": args.budget_gb}), flush=True)
 
 
+def bench_table1(args):
+    """The Table I workload end to end with the diagnostics of Sec. IV-A: energy-normalised
+    super-Gaussian spectrum (100 samples, 150 J), 400 x 400 nodes, focal plane + axis, time
+    transform; then Maxwell residuals on 13-point stencils around a focal-region grid and the
+    field energy of a focal volume.  Reports rates and per-phase times."""
+    import torch
+    from paper_1609_08146_amd import Context, problem_from_workload, stencil_points
+    torch.cuda.init()
+    w = workloads.table1()
+    lam = workloads.TABLE1["lam_c"]
+    ctx = Context(0)
+    ctx.set_profiling(True)
+    prec = args.precision
+    out = {"metric": "Table I workload: whole-path evaluations/s and diagnostics", "precision": prec,
+           "n_freq": w.n_k, "n_nodes": w.n_nodes}
+    for rep in range(2):                       # the first pass warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = problem_from_workload(ctx, w)
+        p.normalize_energy(w.meta["eps"], w.meta["e_tot"], w.dk)
+        p.evaluate(prec, keep_on_device=True)
+        Et, Bt = _time_out(w, prec)
+        p.to_time(w.dk, w.t, out=(Et, Bt))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tm = p.timing()
+        p.close()
+    out["path"] = {"evals": w.evals, "seconds": dt, "evals_per_s": w.evals / dt,
+                   "phases_ms": {k: tm[k] for k in ("prep_ms", "quad_ms", "reduce_ms", "time_ms")}}
+    # Maxwell residuals (Fig. 5 methodology): 8 x 8 x 8 points over +-2 lambda_c, h = lambda_c / 20
+    g = np.linspace(-2 * lam, 2 * lam, 8)
+    pts = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    h = lam / 20
+    st = stencil_points(pts, h)
+    wd = workloads.Workload(name="table1-stencil", f=w.f, a=w.a, n_r=w.n_r, n_phi=w.n_phi, k=w.k,
+                            spectrum=w.spectrum, obs=st, w0=w.w0, t=w.t, dk=w.dk, meta=w.meta)
+    p = problem_from_workload(ctx, wd)
+    p.normalize_energy(w.meta["eps"], w.meta["e_tot"], w.dk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.evaluate(prec, keep_on_device=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ef = p.maxwell_residual_freq(len(pts), h)
+    t2 = time.perf_counter()
+    tt = 2 * w.f + np.linspace(-10, 10, 9) * lam
+    et = p.maxwell_residual_time(len(pts), h, tt, lam / 20, w.dk)
+    t3 = time.perf_counter()
+    out["maxwell"] = {"points": len(pts), "stencil_evals": wd.evals, "evaluate_s": t1 - t0,
+                      "residual_freq_ms": (t2 - t1) * 1e3, "residual_time_ms": (t3 - t2) * 1e3,
+                      "mean_e_f": float(ef.mean()), "mean_e_t": float(et.mean())}
+    p.close()
+    # field energy of a focal volume of 24 lambda_c per side at the focal arrival t = 2f, cells of
+    # (lambda_c / 3)^3 (Sec. IV-A: it should hold the 150 J that the normalisation put on the mirror)
+    g = np.arange(-36, 37) * (lam / 3)
+    vol = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    wv = workloads.Workload(name="table1-volume", f=w.f, a=w.a, n_r=w.n_r, n_phi=w.n_phi, k=w.k,
+                            spectrum=w.spectrum, obs=vol, w0=w.w0, t=w.t, dk=w.dk, meta=w.meta)
+    p = problem_from_workload(ctx, wv)
+    p.normalize_energy(w.meta["eps"], w.meta["e_tot"], w.dk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.evaluate(prec, keep_on_device=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    W = p.field_energy(np.array([2 * w.f]), w.dk, float(lam / 3) ** 3)
+    t2 = time.perf_counter()
+    out["energy"] = {"points": len(vol), "evals": wv.evals, "evaluate_s": t1 - t0, "energy_ms": (t2 - t1) * 1e3,
+                     "W_focus_J": float(W[0]), "E_tot_J": w.meta["e_tot"]}
+    p.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy(args):
     """A plain device copy of known size (calibrates the HBM byte counters)."""
     import torch
@@ -279,6 +354,8 @@ def main():
         return bench_batch(args)
     if args.mode == "serve":
         return bench_serve(args)
+    if args.mode == "table1":
+        return bench_table1(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the frequency-sharded multi-GPU "
                                    "design is described but not built, so --gpus must be 1"}))

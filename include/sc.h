@@ -164,13 +164,26 @@ sc_status sc_set_frequencies(sc_prob *p, const double *k, int n_k);
  * n . E_inc are formed on the device.  Needs mirror and frequencies
  * (SC_E_STATE).  Device tables of ~64 B per (k, node) are kept resident.    */
 sc_status sc_set_incident(sc_prob *p, const double *E, const double *B, int on_device);
-/* Built-in collimated Gaussian beam travelling along -z, evaluated on the
- * device at every node and frequency:
- *   consistent = 0: E = p G e^{-ikz}, B = (-z) x E, G = exp(-(x^2+y^2)/w0^2)
- *   consistent = 1: B = psi (0, -1, -2iy/(k w0^2)), E = (i/k) curl B, psi = G e^{-ikz}
- *                   (written in the frame where the polarisation is along x)
- * w0 = +inf gives a plane wave.  pol_angle rotates the beam about z.
- * spectrum: complex128 [n_k] amplitudes (NULL = all 1).                     */
+/* Built-in collimated beams travelling along -z, evaluated on the device at
+ * every node and frequency (Sec. III-A; the radially polarised beam is the
+ * one of the numerical checks of Sec. IV-A, the linearly polarised one that
+ * of Sec. IV-B).  With psi = G e^{-ikz}:
+ *   SC_BEAM_LINEAR, G = exp(-(x^2+y^2)/w0^2), in the frame where the
+ *     polarisation is along x (pol_angle rotates the beam about z):
+ *     consistent = 0: E = x psi, B = (-z) x E = -y psi
+ *     consistent = 1: B = psi (0, -1, -2iy/(k w0^2)), E = (i/k) curl B
+ *     w0 = +inf gives a plane wave;
+ *   SC_BEAM_RADIAL, G = exp(-r^2/w0^2) / w0:
+ *     E = psi (x, y, c), B = psi (y, -x, 0);
+ *   SC_BEAM_AZIMUTHAL: E = psi (-y, x, 0), B = psi (x, y, c);
+ *   c = (2i/k)(r^2/w0^2 - 1) when consistent (then E = (i/k) curl B for the
+ *   radial and B = (-i/k) curl E for the azimuthal beam), else c = 0
+ *   (B = (-z) x E).  The cylindrical beams need a finite w0 and do not
+ *   depend on pol_angle.  spectrum: complex128 [n_k] amplitudes (NULL = 1). */
+typedef enum { SC_BEAM_LINEAR = 0, SC_BEAM_RADIAL = 1, SC_BEAM_AZIMUTHAL = 2 } sc_beam;
+sc_status sc_set_incident_beam(sc_prob *p, int beam, double w0, double pol_angle,
+                               const double *spectrum, int consistent);
+/* The linearly polarised Gaussian: sc_set_incident_beam(p, SC_BEAM_LINEAR, ...). */
 sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_angle,
                                    const double *spectrum, int consistent);
 
@@ -274,14 +287,15 @@ typedef struct {
     int n_k;                  /* frequencies                                  */
     const double *k;          /* [n_k]                                        */
     const double *spectrum;   /* complex128 [n_k] or NULL                     */
-    double w0, pol_angle;     /* Gaussian beam (w0 = inf: plane wave)         */
-    int consistent;           /* beam variant, see sc_set_incident_gaussian   */
+    double w0, pol_angle;     /* beam waist and polarisation (see below)      */
+    int consistent;           /* beam variant, see sc_set_incident_beam       */
     int n_obs;                /* observation points                           */
     const double *obs;        /* [n_obs][3]                                   */
     sc_precision prec;        /* arithmetic                                   */
     int n_t;                  /* 0, or number of time samples                 */
     const double *t;          /* [n_t] time samples                           */
     double dk;                /* transform weight                             */
+    int beam;                 /* sc_beam of the incident field                */
 } sc_request;
 
 typedef struct {

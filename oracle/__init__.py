@@ -29,6 +29,7 @@ _LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
 _lib = None
 
 PLANE, GAUSSIAN, GAUSSIAN_CONSISTENT = 0, 1, 2
+RADIAL, RADIAL_CONSISTENT, AZIMUTHAL, AZIMUTHAL_CONSISTENT = 3, 4, 5, 6
 PARABOLOID, FLAT = 0, 1
 
 
@@ -318,7 +319,11 @@ def field_energy(k, dk: float, t, E, B, dV: float, threads: int = 0):
 
 def solve(w, kind: int = GAUSSIAN, threads: int = 0, line_term: bool = True):
     """Mirror + Gaussian incident tables + reflected field for a ``workloads.Workload``."""
-    kind = GAUSSIAN_CONSISTENT if (kind == GAUSSIAN and getattr(w, "consistent", 0)) else kind
+    beam = getattr(w, "beam", 0)
+    if kind == GAUSSIAN and beam:
+        kind = {1: RADIAL, 2: AZIMUTHAL}[beam] + (1 if getattr(w, "consistent", 0) else 0)
+    else:
+        kind = GAUSSIAN_CONSISTENT if (kind == GAUSSIAN and getattr(w, "consistent", 0)) else kind
     m = mirror(w.f, w.a, w.n_r, w.n_phi)
     Ei, Bi = incident_tables(m, w.k, kind, w.w0, w.pol, w.spectrum)
     return reflected_field(m, w.k, Ei, Bi, w.obs, line_term=line_term, threads=threads)

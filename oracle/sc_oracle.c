@@ -175,13 +175,54 @@ int orc_mirror(int kind, double f, double a, int n_r, int n_phi,
 /*         E = psi (1 + 2/(k^2 w0^2) - 4y^2/(k^2 w0^4), 4xy/(k^2 w0^4),        */
 /*                  2ix/(k w0^2))                                            */
 /* pol rotates the polarisation (and the field pattern) about z.              */
+/* kinds 3-6: cylindrical vector beams, g = exp(-r^2/w0^2) / w0 e^{-ikz}:    */
+/*   3 radial (literal)        E = g (x, y, 0),  B = g (y, -x, 0) = (-z^) x E  */
+/*   4 radial, consistent      E gains E_z = (2i/k)(r^2/w0^2 - 1) g, so that  */
+/*                             E = (i/k) curl B with the same B               */
+/*   5 azimuthal (literal)     E = g (-y, x, 0), B = g (x, y, 0) = (-z^) x E  */
+/*   6 azimuthal, consistent   B gains B_z = (2i/k)(r^2/w0^2 - 1) g, so that  */
+/*                             B = (-i/k) curl E with the same E              */
+/* (pol does not enter: these beams are axisymmetric).                        */
 /* amp is a complex factor (spectral amplitude and phase).                    */
 /* ------------------------------------------------------------------------ */
+static void cylindrical_beam(int kind, double X, double Y, double Z, double k, double w0, double amp_re,
+                             double amp_im, double *E, double *B)
+{
+    double r2 = X * X + Y * Y;
+    double G = exp(-r2 / (w0 * w0)) / w0;
+    ld sl, cl;
+    sincosl(-(ld)k * (ld)Z, &sl, &cl);
+    double gr = G * (double)(cl * amp_re - sl * amp_im);
+    double gi = G * (double)(cl * amp_im + sl * amp_re);
+    double c = (kind == 4 || kind == 6) ? (2.0 / k) * (r2 / (w0 * w0) - 1.0) : 0.0;   /* i c g */
+    double lr = -c * gi, li = c * gr;
+    if (kind == 3 || kind == 4) {
+        E[0] = X * gr; E[1] = X * gi;
+        E[2] = Y * gr; E[3] = Y * gi;
+        E[4] = lr;     E[5] = li;
+        B[0] = Y * gr;  B[1] = Y * gi;
+        B[2] = -X * gr; B[3] = -X * gi;
+        B[4] = 0.0;     B[5] = 0.0;
+    } else {
+        E[0] = -Y * gr; E[1] = -Y * gi;
+        E[2] = X * gr;  E[3] = X * gi;
+        E[4] = 0.0;     E[5] = 0.0;
+        B[0] = X * gr; B[1] = X * gi;
+        B[2] = Y * gr; B[3] = Y * gi;
+        B[4] = lr;     B[5] = li;
+    }
+}
+
 int orc_incident(int kind, int n_pts, const double *pts, double k, double w0, double pol,
                  double amp_re, double amp_im, double *E, double *B)
 {
     const double cp = cos(pol), sp = sin(pol);
     for (int q = 0; q < n_pts; ++q) {
+        if (kind >= 3) {
+            cylindrical_beam(kind, pts[3 * q], pts[3 * q + 1], pts[3 * q + 2], k, w0, amp_re, amp_im, E + 6 * q,
+                             B + 6 * q);
+            continue;
+        }
         double X = pts[3 * q], Y = pts[3 * q + 1], Z = pts[3 * q + 2];
         /* coordinates in the frame where the polarisation is along x */
         double x = cp * X + sp * Y;

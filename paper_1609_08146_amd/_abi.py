@@ -14,6 +14,7 @@ LIB_PATH = os.environ.get("SC_LIBRARY", os.path.join(HERE, "lib", "libsc.so"))
 SC_OK, SC_E_INVAL, SC_E_NOMEM, SC_E_DEVICE, SC_E_STATE, SC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 SC_E_TIMEOUT, SC_E_CANCELLED, SC_E_REJECTED = -6, -7, -8
 SC_FP64, SC_FP32_SPLIT, SC_FP32 = 0, 1, 2
+SC_BEAM_LINEAR, SC_BEAM_RADIAL, SC_BEAM_AZIMUTHAL = 0, 1, 2
 
 STATUS_NAMES = {0: "SC_OK", -1: "SC_E_INVAL", -2: "SC_E_NOMEM", -3: "SC_E_DEVICE", -4: "SC_E_STATE",
                 -5: "SC_E_UNSUPPORTED", -6: "SC_E_TIMEOUT", -7: "SC_E_CANCELLED", -8: "SC_E_REJECTED"}
@@ -40,7 +41,7 @@ class sc_request(ctypes.Structure):
                 ("n_k", ctypes.c_int), ("k", ctypes.c_void_p), ("spectrum", ctypes.c_void_p),
                 ("w0", ctypes.c_double), ("pol_angle", ctypes.c_double), ("consistent", ctypes.c_int),
                 ("n_obs", ctypes.c_int), ("obs", ctypes.c_void_p), ("prec", ctypes.c_int), ("n_t", ctypes.c_int),
-                ("t", ctypes.c_void_p), ("dk", ctypes.c_double)]
+                ("t", ctypes.c_void_p), ("dk", ctypes.c_double), ("beam", ctypes.c_int)]
 
 
 class sc_request_stats(ctypes.Structure):
@@ -79,6 +80,7 @@ SIGNATURES = {
     "sc_set_frequencies": [V, P, I],
     "sc_set_incident": [V, P, P, I],
     "sc_set_incident_gaussian": [V, D, D, P, I],
+    "sc_set_incident_beam": [V, I, D, D, P, I],
     "sc_get_incident_power": [V, P],
     "sc_scale_spectrum": [V, P],
     "sc_normalize_energy": [V, P, D, D],

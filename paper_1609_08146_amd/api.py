@@ -48,6 +48,13 @@ def _host_c128(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
 
 
+_BEAMS = {"linear": 0, "radial": 1, "azimuthal": 2}
+
+
+def _beam(b) -> int:
+    return _BEAMS[b] if isinstance(b, str) else int(b)
+
+
 def _ptr(a) -> int:
     if a is None:
         return None
@@ -176,6 +183,11 @@ class Problem:
         sp = None if spectrum is None else _host_c128(spectrum).ravel()
         call("sc_set_incident_gaussian", self.h, float(w0), float(pol), _ptr(sp), int(bool(consistent)))
 
+    def set_incident_beam(self, beam, w0: float, pol: float = 0.0, spectrum=None, consistent: bool = False):
+        """beam: 0/'linear', 1/'radial', 2/'azimuthal' (sc_set_incident_beam)."""
+        sp = None if spectrum is None else _host_c128(spectrum).ravel()
+        call("sc_set_incident_beam", self.h, _beam(beam), float(w0), float(pol), _ptr(sp), int(bool(consistent)))
+
     def incident_power(self):
         """Power of each frequency component through the aperture, [n_k] (sc_get_incident_power)."""
         P = np.empty(self.n_k, np.float64)
@@ -302,7 +314,8 @@ def problem_from_workload(ctx: Context, w, consistent: Optional[bool] = None) ->
     p = Problem(ctx)
     p.set_mirror(w.f, w.a, w.n_r, w.n_phi)
     p.set_frequencies(w.k)
-    p.set_incident_gaussian(w.w0, w.pol, w.spectrum, bool(w.consistent if consistent is None else consistent))
+    p.set_incident_beam(getattr(w, "beam", 0), w.w0, w.pol, w.spectrum,
+                        bool(w.consistent if consistent is None else consistent))
     p.set_observation(w.obs)
     return p
 
@@ -342,7 +355,7 @@ class Server:
             k=_ptr(k), spectrum=_ptr(spec), w0=float(w.w0), pol_angle=float(w.pol),
             consistent=int(bool(w.consistent if consistent is None else consistent)), n_obs=int(obs.shape[0]),
             obs=_ptr(obs), prec=_prec(precision), n_t=0 if tt is None else int(tt.shape[0]), t=_ptr(tt),
-            dk=float(dk))
+            dk=float(dk), beam=_beam(getattr(w, "beam", 0)))
         ticket = ctypes.c_uint64()
         call("sc_server_submit", self.h, ctypes.byref(req), ctypes.byref(ticket))
         self._meta[ticket.value] = (_prec(precision), int(k.shape[0]), int(obs.shape[0]),

@@ -353,14 +353,18 @@ extern "C" sc_status sc_set_incident(sc_prob *p, const double *E, const double *
     return finish_tables(p);
 }
 
-extern "C" sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_angle, const double *spectrum,
-                                              int consistent)
+extern "C" sc_status sc_set_incident_beam(sc_prob *p, int beam, double w0, double pol_angle, const double *spectrum,
+                                          int consistent)
 {
-    if (!p) return fail(SC_E_INVAL, "sc_set_incident_gaussian: prob is NULL");
-    if (!(w0 > 0.0)) return fail(SC_E_INVAL, "sc_set_incident_gaussian: w0 must be > 0 (inf = plane wave)");
-    if (!std::isfinite(pol_angle)) return fail(SC_E_INVAL, "sc_set_incident_gaussian: bad polarisation angle");
+    if (!p) return fail(SC_E_INVAL, "sc_set_incident_beam: prob is NULL");
+    if (beam != SC_BEAM_LINEAR && beam != SC_BEAM_RADIAL && beam != SC_BEAM_AZIMUTHAL)
+        return fail(SC_E_INVAL, "sc_set_incident_beam: unknown beam %d", beam);
+    if (!(w0 > 0.0)) return fail(SC_E_INVAL, "sc_set_incident_beam: w0 must be > 0");
+    if (beam != SC_BEAM_LINEAR && !std::isfinite(w0))
+        return fail(SC_E_INVAL, "sc_set_incident_beam: a radially or azimuthally polarised beam needs a finite w0");
+    if (!std::isfinite(pol_angle)) return fail(SC_E_INVAL, "sc_set_incident_beam: bad polarisation angle");
     if (!p->has_mirror || p->k.empty())
-        return fail(SC_E_STATE, "sc_set_incident_gaussian: set mirror and frequencies first");
+        return fail(SC_E_STATE, "sc_set_incident_beam: set mirror and frequencies first");
     DeviceGuard g(p->ctx->device);
     hipStream_t st = p->ctx->stream;
     const int n_k = (int)p->k.size();
@@ -373,18 +377,24 @@ extern "C" sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_
     }
     ev_record(p, EV_PREP0);
     HIP_TRY(launch_tables_gaussian(st, n_k, p->n_surf, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
-                                   p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>(), w0, pol_angle,
+                                   p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>(), beam, w0, pol_angle,
                                    spectrum ? dspec.as<double>() : nullptr, consistent ? 1 : 0,
                                    p->tab64.as<double>()));
     SC_TRY(reserve_power(p));
     HIP_TRY(launch_power_gaussian(st, n_k, p->n_surf, p->d_k.as<double>(), p->pos64.as<double>(),
-                                  p->wgt.as<double>(), w0, pol_angle, spectrum ? dspec.as<double>() : nullptr,
+                                  p->wgt.as<double>(), beam, w0, pol_angle, spectrum ? dspec.as<double>() : nullptr,
                                   consistent ? 1 : 0, p->d_power.as<double>() + n_k, p->d_power.as<double>()));
     p->has_power = true;
     ev_record(p, EV_PREP1);
     p->ev_prep = p->ctx->profiling;
     HIP_TRY(hipStreamSynchronize(st));   // dspec is freed on return
     return finish_tables(p);
+}
+
+extern "C" sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_angle, const double *spectrum,
+                                              int consistent)
+{
+    return sc_set_incident_beam(p, SC_BEAM_LINEAR, w0, pol_angle, spectrum, consistent);
 }
 
 extern "C" sc_status sc_get_incident_power(const sc_prob *p, double *P)

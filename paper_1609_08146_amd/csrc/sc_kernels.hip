@@ -3,7 +3,8 @@
 //  k_node_tables         mirror nodes, normals, weights            (Sec. III-C)
 //  k_obs_prep            observation records
 //  k_tables_from_fields  POA current / charge tables from given E_inc, B_inc
-//  k_tables_gaussian     same for the built-in collimated Gaussian (Sec. III-A)
+//  k_tables_gaussian     same for the built-in collimated beams: linearly, radially or
+//                        azimuthally polarised Gaussian (Sec. III-A, IV-A)
 //  k_tables_cast         FP64 tables -> FP32 (split: as is; naive: node phase removed)
 //  k_power_*             incident power per frequency through the aperture (Sec. III-B)
 //  k_tables_scale        spectral amplitude / phase applied to the tables (Sec. III-B)
@@ -155,14 +156,47 @@ __global__ void k_tables_from_fields(int n_k, int n_surf, int n_tot, const doubl
                  {cp, sp});
 }
 
-// Incident collimated Gaussian beam travelling along -z at node (X, Y), without
-// its propagation phase e^{-ikz} (the table kernel fuses that with the node
-// phase; the power kernel does not need it).  Sec. III-A; the curl-consistent
-// variant has B = psi (0, -1, -2iy/(k w0^2)), E = (i/k) curl B, the literal one
-// E = x psi, B = -y psi.  `pol` rotates the polarisation about z.
-__device__ __forceinline__ void gaussian_fields(double k, double X, double Y, double w0, double pol, c64 amp,
-                                                int consistent, c64 *E, c64 *B)
+// Incident collimated beams travelling along -z at node (X, Y), without their
+// propagation phase e^{-ikz} (the table kernel fuses that with the node phase;
+// the power kernel does not need it).  Sec. III-A.
+//   beam 0, linearly polarised Gaussian, psi = amp exp(-(x^2+y^2)/w0^2) in the
+//     frame where the polarisation is along x (`pol` rotates it about z):
+//     literal E = x psi, B = -y psi; curl-consistent B = psi (0, -1, -2iy/(k w0^2)),
+//     E = (i/k) curl B;
+//   beam 1, radially polarised, g = amp exp(-r^2/w0^2) / w0:
+//     E = (x, y, c) g, B = (y, -x, 0) g;
+//   beam 2, azimuthally polarised: E = (-y, x, 0) g, B = (x, y, c) g;
+//   with c = (2i/k)(r^2/w0^2 - 1) for the curl-consistent variants (E = (i/k) curl B,
+//   resp. B = (-i/k) curl E) and c = 0 for the literal ones (B = -z x E).  The
+//   cylindrical beams are axisymmetric, so `pol` does not enter.
+__device__ __forceinline__ void beam_fields(int beam, double k, double X, double Y, double w0, double pol, c64 amp,
+                                            int consistent, c64 *E, c64 *B)
 {
+    if (beam != 0) {
+        const double r2 = X * X + Y * Y;
+        const double G = exp(-r2 / (w0 * w0)) / w0;
+        const c64 g = {G * amp.re, G * amp.im};
+        const double c = consistent ? 2.0 / k * (r2 / (w0 * w0) - 1.0) : 0.0;   // longitudinal: i c g
+        const c64 lg = {-c * g.im, c * g.re};
+        const c64 zero = {0.0, 0.0};
+        const c64 rx = {X * g.re, X * g.im}, ry = {Y * g.re, Y * g.im};
+        if (beam == 1) {
+            E[0] = rx;
+            E[1] = ry;
+            E[2] = lg;
+            B[0] = ry;
+            B[1] = {-rx.re, -rx.im};
+            B[2] = zero;
+        } else {
+            E[0] = {-ry.re, -ry.im};
+            E[1] = rx;
+            E[2] = zero;
+            B[0] = rx;
+            B[1] = ry;
+            B[2] = lg;
+        }
+        return;
+    }
     double sl, cl;
     sincos(pol, &sl, &cl);
     // frame where the polarisation is along x
@@ -201,7 +235,7 @@ __device__ __forceinline__ void gaussian_fields(double k, double X, double Y, do
 
 __global__ void k_tables_gaussian(int n_k, int n_surf, int n_tot, const double *__restrict__ kv,
                                   const double *__restrict__ pos64, const double *__restrict__ nrm,
-                                  const double *__restrict__ wgt, const double *__restrict__ tan, double w0,
+                                  const double *__restrict__ wgt, const double *__restrict__ tan, int beam, double w0,
                                   double pol, const double *__restrict__ spectrum, int consistent,
                                   double *__restrict__ tab64)
 {
@@ -214,7 +248,7 @@ __global__ void k_tables_gaussian(int n_k, int n_surf, int n_tot, const double *
     const double X = p[0], Y = p[1], Z = p[2];
     const c64 amp = spectrum ? c64{spectrum[2 * kk], spectrum[2 * kk + 1]} : c64{1.0, 0.0};
     c64 E[3], B[3];
-    gaussian_fields(k, X, Y, w0, pol, amp, consistent, E, B);
+    beam_fields(beam, k, X, Y, w0, pol, amp, consistent, E, B);
     // propagation phase e^{-ikz} fused with the node phase e^{ik|r_s|}: e^{ik(|r_s| - z)},
     // formed in double-double so that no ~1e6 rad phase is ever rounded to double
     const dd rs = dd_norm3(X, Y, Z);
@@ -276,7 +310,8 @@ __global__ void __launch_bounds__(256) k_power_fields(int n_surf, int n_tot, con
 
 __global__ void __launch_bounds__(256) k_power_gaussian(int n_surf, const double *__restrict__ kv,
                                                         const double *__restrict__ pos64,
-                                                        const double *__restrict__ wgt, double w0, double pol,
+                                                        const double *__restrict__ wgt, int beam, double w0,
+                                                        double pol,
                                                         const double *__restrict__ spectrum, int consistent,
                                                         double *__restrict__ part)
 {
@@ -288,7 +323,7 @@ __global__ void __launch_bounds__(256) k_power_gaussian(int n_surf, const double
     double acc = 0.0;
     for (int q = q0 + (int)threadIdx.x; q < q1; q += 256) {
         c64 E[3], B[3];
-        gaussian_fields(k, pos64[4 * q], pos64[4 * q + 1], w0, pol, amp, consistent, E, B);
+        beam_fields(beam, k, pos64[4 * q], pos64[4 * q + 1], w0, pol, amp, consistent, E, B);
         acc += wgt[q] * flux_minus_z(E, B);
     }
     block_sum_256(acc, part + (size_t)kk * POWER_BLOCKS + blockIdx.x);
@@ -467,10 +502,11 @@ hipError_t launch_tables_from_fields(hipStream_t st, int n_k, int n_surf, int n_
 
 hipError_t launch_tables_gaussian(hipStream_t st, int n_k, int n_surf, int n_tot, const double *k,
                                   const double *pos64, const double *nrm, const double *wgt, const double *tan,
-                                  double w0, double pol, const double *spectrum, int consistent, double *tab64)
+                                  int beam, double w0, double pol, const double *spectrum, int consistent,
+                                  double *tab64)
 {
     hipLaunchKernelGGL(k_tables_gaussian, dim3(nblocks((int64_t)n_k * n_tot, 256)), dim3(256), 0, st, n_k, n_surf,
-                       n_tot, k, pos64, nrm, wgt, tan, w0, pol, spectrum, consistent, tab64);
+                       n_tot, k, pos64, nrm, wgt, tan, beam, w0, pol, spectrum, consistent, tab64);
     return hipGetLastError();
 }
 
@@ -483,11 +519,11 @@ hipError_t launch_power_fields(hipStream_t st, int n_k, int n_surf, int n_tot, c
 }
 
 hipError_t launch_power_gaussian(hipStream_t st, int n_k, int n_surf, const double *k, const double *pos64,
-                                 const double *wgt, double w0, double pol, const double *spectrum, int consistent,
-                                 double *part, double *P)
+                                 const double *wgt, int beam, double w0, double pol, const double *spectrum,
+                                 int consistent, double *part, double *P)
 {
-    hipLaunchKernelGGL(k_power_gaussian, dim3(POWER_BLOCKS, n_k), dim3(256), 0, st, n_surf, k, pos64, wgt, w0, pol,
-                       spectrum, consistent, part);
+    hipLaunchKernelGGL(k_power_gaussian, dim3(POWER_BLOCKS, n_k), dim3(256), 0, st, n_surf, k, pos64, wgt, beam, w0,
+                       pol, spectrum, consistent, part);
     hipLaunchKernelGGL(k_power_finish, dim3(nblocks(n_k, 256)), dim3(256), 0, st, n_k, part, P);
     return hipGetLastError();
 }

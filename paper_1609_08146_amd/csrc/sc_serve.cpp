@@ -42,7 +42,7 @@ enum ReqState { R_QUEUED, R_RUNNING, R_FINISHING, R_DONE, R_FAILED, R_CANCELLED 
 struct Req {
     uint64_t ticket = 0;
     double f = 0, a = 0, w0 = 0, pol = 0, dk = 0;
-    int n_r = 0, n_phi = 0, consistent = 0, n_t = 0, n_obs = 0;
+    int n_r = 0, n_phi = 0, consistent = 0, n_t = 0, n_obs = 0, beam = 0;
     sc_precision prec = SC_FP32_SPLIT;
     std::vector<double> k, spec, obs, t;
     size_t bytes = 0;
@@ -137,7 +137,8 @@ static sc_status setup_request(sc_server *s, Req *r)
     p->keep_fp64 = r->prec == SC_FP64;   // FP32 requests keep only their FP32 tables
     SC_TRY(sc_set_mirror(p, r->f, r->a, r->n_r, r->n_phi));
     SC_TRY(sc_set_frequencies(p, r->k.data(), (int)r->k.size()));
-    SC_TRY(sc_set_incident_gaussian(p, r->w0, r->pol, r->spec.empty() ? nullptr : r->spec.data(), r->consistent));
+    SC_TRY(sc_set_incident_beam(p, r->beam, r->w0, r->pol, r->spec.empty() ? nullptr : r->spec.data(),
+                                r->consistent));
     SC_TRY(sc_set_observation(p, r->obs.data(), r->n_obs, 0));
     sc_launch l = resolve_launch(p, r->prec);
     l.obs_per_lane = server_opl(r->prec);
@@ -436,6 +437,10 @@ static sc_status validate_request(const sc_request *q)
     for (int i = 0; i < q->n_k; ++i)
         if (!(q->k[i] > 0.0) || !std::isfinite(q->k[i])) return fail(SC_E_INVAL, "request: k[%d] invalid", i);
     if (!(q->w0 > 0.0)) return fail(SC_E_INVAL, "request: w0 must be > 0");
+    if (q->beam != SC_BEAM_LINEAR && q->beam != SC_BEAM_RADIAL && q->beam != SC_BEAM_AZIMUTHAL)
+        return fail(SC_E_INVAL, "request: unknown beam %d", q->beam);
+    if (q->beam != SC_BEAM_LINEAR && !std::isfinite(q->w0))
+        return fail(SC_E_INVAL, "request: a cylindrical beam needs a finite w0");
     if (q->n_obs < 1 || !q->obs) return fail(SC_E_INVAL, "request: need n_obs >= 1 points");
     if (q->prec != SC_FP64 && q->prec != SC_FP32_SPLIT && q->prec != SC_FP32)
         return fail(SC_E_INVAL, "request: unknown precision");
@@ -458,6 +463,7 @@ extern "C" sc_status sc_server_submit(sc_server *s, const sc_request *q, uint64_
     r->w0 = q->w0;
     r->pol = q->pol_angle;
     r->consistent = q->consistent;
+    r->beam = q->beam;
     r->n_obs = q->n_obs;
     r->obs.assign(q->obs, q->obs + 3 * (size_t)q->n_obs);
     r->prec = q->prec;

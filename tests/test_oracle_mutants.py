@@ -78,6 +78,10 @@ MUTANTS = [
     ("power_drop_EyBx", [("- ((ld)e[2] * b[0] + (ld)e[3] * b[1])", "", 1)]),
     ("power_no_4pi", [("P[n] = (double)(4.0L * PI_L * acc);", "P[n] = (double)(acc);", 1)]),
     ("power_unweighted", [("acc += (ld)wgt[q] * (-sz);", "acc += -sz;", 1)]),
+    ("cyl_radial_B_sign", [("B[2] = -X * gr; B[3] = -X * gi;", "B[2] = X * gr; B[3] = X * gi;", 1)]),
+    ("cyl_longitudinal_sign", [("double lr = -c * gi, li = c * gr;", "double lr = c * gi, li = -c * gr;", 1)]),
+    ("cyl_longitudinal_coeff", [("(2.0 / k) * (r2 / (w0 * w0) - 1.0)", "(2.0 / k) * (r2 / (w0 * w0) + 1.0)", 1)]),
+    ("cyl_azimuthal_E", [("E[0] = -Y * gr; E[1] = -Y * gi;", "E[0] = Y * gr; E[1] = Y * gi;", 1)]),
     ("power_with_rim", [("for (int q = 0; q < n_surf; ++q) {\n            const double *e = E + 6",
                          "for (int q = 0; q < n_tot; ++q) {\n            const double *e = E + 6", 1)]),
 ]
@@ -264,8 +268,30 @@ def pin_power(orc):
     return np.abs(P / np.array(ex) - 1).max() < 1e-12
 
 
+def pin_cylindrical(orc):
+    # aperture power closed form of the radial and azimuthal beams, and Maxwell's equations
+    # of their curl-consistent variants
+    a, w0 = 25.0, 6.0
+    m = orc.mirror(20.0, a, 60, 32)
+    b = 2 * a * a / (w0 * w0)
+    ex = math.pi ** 2 * w0 * w0 * (1 - math.exp(-b) * (1 + b))
+    for kind in (orc.RADIAL, orc.AZIMUTHAL):
+        Ei, Bi = orc.incident_tables(m, [K], kind, w0)
+        if abs(orc.incident_power(m, Ei, Bi)[0] / ex - 1) > 1e-12:
+            return False
+    h = 1e-3
+    pts = _stencil(np.array([0.7, -0.4, 0.3]), h)
+    E, B = orc.incident(orc.RADIAL_CONSISTENT, pts, K, 3.0)
+    s = K * np.abs(E[0]).max()
+    if np.abs(_curl(_fd_jac(B, h)) + 1j * K * E[0]).max() / s > 1e-9:
+        return False
+    E, B = orc.incident(orc.AZIMUTHAL_CONSISTENT, pts, K, 3.0)
+    s = K * np.abs(B[0]).max()
+    return np.abs(_curl(_fd_jac(E, h)) - 1j * K * B[0]).max() / s < 1e-9
+
+
 BATTERY = [pin_p1, pin_p2, pin_forms, pin_maxwell, pin_symmetry, pin_paraxial, pin_flux, pin_rules, pin_time,
-           pin_power]
+           pin_power, pin_cylindrical]
 
 
 def run_battery(orc):

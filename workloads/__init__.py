@@ -54,6 +54,7 @@ class Workload:
     ``w0``       Gaussian waist of the collimated incident beam (inf = plane wave)
     ``pol``      polarisation angle about z (0 = x-polarised)
     ``consistent`` 0: E_x = G e^{-ikz}, B = -y G e^{-ikz};  1: curl-consistent pair
+    ``beam``     0 linearly polarised Gaussian, 1 radially, 2 azimuthally polarised
     ``t``        time samples (c*t) for the semi-discrete transform, or None
     ``dk``       frequency spacing used as the transform weight
     """
@@ -72,6 +73,7 @@ class Workload:
     t: Optional[np.ndarray] = None
     dk: float = 1.0
     meta: dict = field(default_factory=dict)
+    beam: int = 0                 # 0 linearly, 1 radially, 2 azimuthally polarised
 
     @property
     def n_k(self) -> int:
