@@ -145,11 +145,12 @@ def cpu_baseline(w, target_s):
     oracle.build()
     threads = oracle.max_threads()
     # calibrate on a tiny sample, then size the sample to ~target_s of work
-    probe = w.subset(obs_idx=np.arange(0, w.n_obs, w.n_obs // 8)[:8], k_idx=[0])
+    n_probe = max(threads, 16)
+    probe = w.subset(obs_idx=np.linspace(0, w.n_obs - 1, n_probe).astype(int), k_idx=[0])
     t0 = time.perf_counter()
     oracle.solve(probe)
     rate = probe.evals / (time.perf_counter() - t0)
-    n_obs = int(max(8, min(w.n_obs, target_s * rate / (w.n_k * w.n_nodes))))
+    n_obs = int(max(threads, min(w.n_obs, target_s * rate / (w.n_k * w.n_nodes))))
     idx = np.linspace(0, w.n_obs - 1, n_obs).astype(int)
     sample = w.subset(obs_idx=idx)
     t0 = time.perf_counter()

@@ -77,6 +77,7 @@ extern "C" sc_status sc_ctx_create(int device, void *stream, sc_ctx **out)
         }
         c->own_stream = true;
     }
+    static_assert(QUAD_SEGMENTS * sizeof(unsigned int) <= 256, "work counters must fit the counter buffer");
     sc_status st = c->counter.reserve(256);
     if (st == SC_OK && hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess)
         st = fail(SC_E_DEVICE, "sc_ctx_create: hipEventCreate failed");
@@ -676,7 +677,7 @@ sc_status sc::run_quad(sc_ctx *c, std::vector<QuadJob> &jobs, sc_precision prec,
     HIP_TRY(hipMemcpyAsync(c->jobs.p, c->host_jobs.data(), sizeof(QuadJob) * jobs.size(), hipMemcpyHostToDevice,
                            st));
     HIP_TRY(hipEventRecord(c->upload_done, st));
-    HIP_TRY(launch_fill_u32(st, c->counter.as<unsigned int>(), 0u, 1));
+    HIP_TRY(launch_fill_u32(st, c->counter.as<unsigned int>(), 0u, QUAD_SEGMENTS));
     const int mode = mode_of(prec);
     int bpc = l.blocks_per_cu;
     const int occ = quad_max_blocks_per_cu(mode, l.obs_per_lane, l.freq_per_lane, l.waves_per_block);

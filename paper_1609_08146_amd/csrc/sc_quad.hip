@@ -196,21 +196,37 @@ __device__ __forceinline__ int find_job(cjob *jobs, int n_jobs, int64_t t)
 constexpr int KAHAN_BLOCK = 32;   // nodes summed plainly before each compensated add (FP32)
 
 // Persistent quadrature kernel.  Every wave repeatedly takes the next tile
-// from a device counter: one node chunk, 64*OPL observation points, FPB
-// consecutive frequencies.  Node and table data are wave-uniform (scalar
-// loads); each lane owns OPL points x FPB frequencies x 12 accumulators.
-// Every wave exits once the counter passes n_tiles.
+// (one node chunk, 64*OPL observation points, FPB consecutive frequencies)
+// from the device counters counter[QUAD_SEGMENTS], zeroed before the launch.
+// Node and table data are wave-uniform (scalar loads); each lane owns OPL
+// points x FPB frequencies x 12 accumulators.  Every wave exits once all
+// segments are exhausted.
 template <int MODE, int OPL, int FPB>
 __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_, int n_jobs, int64_t n_tiles,
                                               unsigned int *__restrict__ counter)
 {
     cjob *jobs = (cjob *)jobs_;
     const int lane = threadIdx.x & 63;
+    // The tile list is cut into QUAD_SEGMENTS contiguous segments with a counter
+    // each.  Workgroups are dispatched to the 8 XCDs round robin, so block b
+    // starts on segment b % 8: the tiles that share a (frequency block, node
+    // chunk) run on one XCD and its L2 serves their table reads.  A wave that
+    // drains its segment moves on to the next one; it leaves when every
+    // segment it has visited (all of them, in the end) is exhausted.
+    int seg = (int)(blockIdx.x % QUAD_SEGMENTS), visited = 1;
     for (;;) {
-        unsigned int tt = 0;
-        if (lane == 0) tt = atomicAdd(counter, 1u);
-        const int64_t t = (int64_t)__builtin_amdgcn_readfirstlane(tt);
-        if (t >= n_tiles) break;
+        int64_t t, s1;
+        for (;;) {
+            unsigned int tt = 0;
+            if (lane == 0) tt = atomicAdd(counter + seg, 1u);
+            const int64_t s0 = (int64_t)seg * n_tiles / QUAD_SEGMENTS;
+            s1 = (int64_t)(seg + 1) * n_tiles / QUAD_SEGMENTS;
+            t = s0 + (int64_t)__builtin_amdgcn_readfirstlane(tt);
+            if (t < s1 || visited == QUAD_SEGMENTS) break;
+            seg = (seg + 1) % QUAD_SEGMENTS;
+            ++visited;
+        }
+        if (t >= s1) break;
         const int j = find_job(jobs, n_jobs, t);
         const int64_t local = t - jobs[j].tile0 + jobs[j].tile_offset;
         const int obs_blocks = jobs[j].obs_blocks, n_chunks = jobs[j].n_chunks;

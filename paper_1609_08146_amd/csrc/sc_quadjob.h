@@ -29,4 +29,7 @@ struct QuadJob {
 
 enum QuadMode { MODE_FP64 = 0, MODE_SPLIT = 1, MODE_NAIVE = 2 };
 
+// Work counters of one quadrature launch (one per XCD-sized segment of the tile list).
+constexpr int QUAD_SEGMENTS = 8;
+
 }  // namespace sc

@@ -257,7 +257,7 @@ static sc_status launch_quantum(sc_server *s)
     for (Req *r : group) HIP_TRY(hipStreamWaitEvent(st, r->ready_ev, 0));
     HIP_TRY(hipMemcpyAsync(s->jobbuf[slot].p, s->hjobs[slot], sizeof(QuadJob) * jobs.size(), hipMemcpyHostToDevice,
                            st));
-    HIP_TRY(launch_fill_u32(st, s->ctx->counter.as<unsigned int>(), 0u, 1));
+    HIP_TRY(launch_fill_u32(st, s->ctx->counter.as<unsigned int>(), 0u, QUAD_SEGMENTS));
     HIP_TRY(hipEventRecord(s->slot_start[slot], st));
     const int mode = mode_of(prec);
     const int wpb = 4;
