@@ -145,6 +145,25 @@ sc_status sc_prob_destroy(sc_prob *p);
  * f > 0, r_max > 0, 1 <= n_r, 1 <= n_phi, (n_r+1)*n_phi < 2^31 (SC_E_INVAL).
  * Invalidates the incident tables and results.                             */
 sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, int n_phi);
+/* A general mirror given by its own quadrature, for surfaces other than the
+ * built-in paraboloid (the method holds for any perfectly conducting
+ * surface, Sec. II; Sec. III-C-1 discusses why the paraboloid needs no
+ * sub-wavelength mesh and other shapes may).  Host arrays:
+ *   xyz [n_surf][3]      surface nodes;
+ *   ndS [n_surf][3]      area-weighted normals n dS (quadrature weight times
+ *                        the normal, pointing from the mirror toward the
+ *                        focus and the incoming beam);
+ *   rim_xyz [n_rim][3]   nodes of the boundary curve;
+ *   rim_n [n_rim][3]     the surface normal there (direction only);
+ *   rim_dl [n_rim][3]    oriented line elements dl (weight times tangent,
+ *                        right-handed about the normal: counter-clockwise seen
+ *                        from the beam on the outer edge, clockwise on holes).
+ * n_rim = 0 drops the line integral (a surface without boundary).  Replaces
+ * the mirror and invalidates the tables.  The split form is accurate when the
+ * observation points lie near the origin (|r'| << |r_s|); the node phase is
+ * folded as for the paraboloid.  SC_E_INVAL for bad sizes or non-finite data. */
+sc_status sc_set_surface(sc_prob *p, int n_surf, const double *xyz, const double *ndS, int n_rim,
+                         const double *rim_xyz, const double *rim_n, const double *rim_dl);
 /* Number of surface nodes (n_r*n_phi) and rim nodes (n_phi).                */
 sc_status sc_get_num_nodes(const sc_prob *p, int *n_surface, int *n_rim);
 /* Copy node data to host arrays (any may be NULL):

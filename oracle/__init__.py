@@ -61,7 +61,7 @@ def open_library(path: str):
     lib.orc_reflected_field.argtypes = [I, I, P, P, P, P, I, P, P, P, I, P, P, P, I, I]
     lib.orc_reflected_field_dgrad.argtypes = [I, P, P, P, I, I, P, P, I, P, P, I]
     lib.orc_time_transform.argtypes = [I, P, D, I, P, ctypes.c_long, P, P, I]
-    lib.orc_incident_power.argtypes = [I, I, I, P, P, P, P]
+    lib.orc_incident_power.argtypes = [I, I, I, P, P, P, P, P]
     lib.orc_max_threads.restype = I
     return lib
 
@@ -135,15 +135,17 @@ class Mirror:
     pos: np.ndarray   # [n_tot, 3]
     nrm: np.ndarray   # [n_tot, 3] unnormalised normal n~ (n dS = n~ r dr dphi)
     wgt: np.ndarray   # [n_tot] surface weights, then the trapezoid step for rim nodes
-    tan: np.ndarray   # [n_phi, 3] rim tangent dr_s/dphi
+    tan: np.ndarray   # [n_phi, 3] rim tangent dr_s/dphi (a general surface: [n_rim, 3] line elements dl)
+    n_surface: int = -1    # general surfaces only (then n_r = n_phi = 0)
+    n_boundary: int = -1
 
     @property
     def n_surf(self) -> int:
-        return self.n_r * self.n_phi
+        return self.n_surface if self.n_surface >= 0 else self.n_r * self.n_phi
 
     @property
     def n_rim(self) -> int:
-        return self.n_phi
+        return self.n_boundary if self.n_boundary >= 0 else self.n_phi
 
     @property
     def n_tot(self) -> int:
@@ -161,6 +163,20 @@ def mirror(f: float, a: float, n_r: int, n_phi: int, kind: int = PARABOLOID) -> 
     if rc != 0:
         raise ValueError("invalid mirror parameters")
     return Mirror(f, a, n_r, n_phi, kind, pos, nrm, wgt, tan)
+
+
+def surface(xyz, ndS, rim_xyz=None, rim_n=None, rim_dl=None) -> Mirror:
+    """A general mirror from its quadrature: surface nodes with n dS (weight 1), boundary nodes with
+    the surface normal (direction) and the oriented line element dl (weight 1)."""
+    xyz, ndS = _f64(xyz).reshape(-1, 3), _f64(ndS).reshape(-1, 3)
+    if rim_xyz is None:
+        rim_xyz, rim_n, rim_dl = np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 3))
+    rim_xyz, rim_n, rim_dl = (_f64(a).reshape(-1, 3) for a in (rim_xyz, rim_n, rim_dl))
+    pos = np.ascontiguousarray(np.concatenate([xyz, rim_xyz]))
+    nrm = np.ascontiguousarray(np.concatenate([ndS, rim_n]))
+    wgt = np.ones(pos.shape[0])
+    return Mirror(np.nan, np.nan, 0, 0, -1, pos, nrm, wgt, np.ascontiguousarray(rim_dl), xyz.shape[0],
+                  rim_xyz.shape[0])
 
 
 def incident(kind: int, pts, k: float, w0: float = np.inf, pol: float = 0.0, amp: complex = 1.0):
@@ -231,8 +247,8 @@ def incident_power(m: Mirror, Einc, Binc):
     B = _c128(Binc)
     n_k = E.shape[0]
     P = np.empty(n_k)
-    _load().orc_incident_power(n_k, m.n_surf, m.n_tot, _p(m.wgt), _p(E.reshape(n_k, -1)), _p(B.reshape(n_k, -1)),
-                               _p(P))
+    _load().orc_incident_power(n_k, m.n_surf, m.n_tot, _p(m.nrm), _p(m.wgt), _p(E.reshape(n_k, -1)),
+                               _p(B.reshape(n_k, -1)), _p(P))
     return P
 
 

@@ -463,14 +463,15 @@ int orc_time_transform(int n_k, const double *kv, double dk, int n_t, const doub
 /* ------------------------------------------------------------------------ */
 /* Power of each frequency component of the incident beam through the mirror */
 /* aperture (Sec. III-B): P_n = 4 pi SS Re(E_n x B_n^*) . dA with dA = -z    */
-/* dx dy, the beam travelling along -z.  The surface weights W = w_r r dphi  */
-/* are the quadrature of the aperture disk in the (x, y) plane, so           */
-/*   P_n = 4 pi sum_q W_q [ -Re(E_x B_y^*) + Re(E_y B_x^*) ]                 */
+/* dx dy, the beam travelling along -z.  A surface node's share of the       */
+/* aperture is the z component of its n dS = n~ W: on the paraboloid n~_z = 1 */
+/* and W = w_r r dphi is the quadrature of the aperture disk, so             */
+/*   P_n = 4 pi sum_q (n~_z W)_q [ -Re(E_x B_y^*) + Re(E_y B_x^*) ]          */
 /* over the n_surf surface nodes (rim nodes carry the line term only).       */
 /* E, B: [n_k][n_tot][3] complex; P: [n_k].                                   */
 /* ------------------------------------------------------------------------ */
-int orc_incident_power(int n_k, int n_surf, int n_tot, const double *wgt, const double *E, const double *B,
-                       double *P)
+int orc_incident_power(int n_k, int n_surf, int n_tot, const double *nrm, const double *wgt, const double *E,
+                       const double *B, double *P)
 {
     for (int n = 0; n < n_k; ++n) {
         ld acc = 0.0L;
@@ -478,7 +479,7 @@ int orc_incident_power(int n_k, int n_surf, int n_tot, const double *wgt, const 
             const double *e = E + 6 * ((size_t)n * n_tot + q), *b = B + 6 * ((size_t)n * n_tot + q);
             /* (E x B^*)_z = E_x B_y^* - E_y B_x^*;  Re(a b^*) = a.re b.re + a.im b.im */
             ld sz = ((ld)e[0] * b[2] + (ld)e[1] * b[3]) - ((ld)e[2] * b[0] + (ld)e[3] * b[1]);
-            acc += (ld)wgt[q] * (-sz);
+            acc += (ld)wgt[q] * (ld)nrm[3 * q + 2] * (-sz);
         }
         P[n] = (double)(4.0L * PI_L * acc);
     }

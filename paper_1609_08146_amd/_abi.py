@@ -75,6 +75,7 @@ SIGNATURES = {
     "sc_prob_create": [V, PP],
     "sc_prob_destroy": [V],
     "sc_set_mirror": [V, D, D, I, I],
+    "sc_set_surface": [V, I, P, P, I, P, P, P],
     "sc_get_num_nodes": [V, ctypes.POINTER(I), ctypes.POINTER(I)],
     "sc_get_nodes": [V, P, P, P],
     "sc_set_frequencies": [V, P, I],

@@ -155,6 +155,19 @@ class Problem:
         call("sc_set_mirror", self.h, float(f), float(r_max), int(n_r), int(n_phi))
         self.n_r, self.n_phi = int(n_r), int(n_phi)
 
+    def set_surface(self, xyz, ndS, rim_xyz=None, rim_n=None, rim_dl=None):
+        """A general mirror from its quadrature (sc_set_surface): nodes, n dS, and the oriented boundary."""
+        xyz, ndS = _host_f64(xyz, (-1, 3)), _host_f64(ndS, (-1, 3))
+        n_rim = 0 if rim_xyz is None else int(np.asarray(rim_xyz).reshape(-1, 3).shape[0])
+        rx = rn = rdl = None
+        if n_rim:
+            rx, rn, rdl = _host_f64(rim_xyz, (-1, 3)), _host_f64(rim_n, (-1, 3)), _host_f64(rim_dl, (-1, 3))
+            if rn.shape[0] != n_rim or rdl.shape[0] != n_rim:
+                raise ValueError("rim arrays must have the same length")
+        if ndS.shape != xyz.shape:
+            raise ValueError("xyz and ndS must have the same shape")
+        call("sc_set_surface", self.h, int(xyz.shape[0]), _ptr(xyz), _ptr(ndS), n_rim, _ptr(rx), _ptr(rn), _ptr(rdl))
+
     def num_nodes(self):
         ns, nr = ctypes.c_int(), ctypes.c_int()
         call("sc_get_num_nodes", self.h, ctypes.byref(ns), ctypes.byref(nr))

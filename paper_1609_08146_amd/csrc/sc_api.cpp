@@ -273,6 +273,59 @@ extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, 
     return SC_OK;
 }
 
+extern "C" sc_status sc_set_surface(sc_prob *p, int n_surf, const double *xyz, const double *ndS, int n_rim,
+                                    const double *rim_xyz, const double *rim_n, const double *rim_dl)
+{
+    if (!p || !xyz || !ndS) return fail(SC_E_INVAL, "sc_set_surface: NULL argument");
+    if (n_surf < 1 || n_rim < 0) return fail(SC_E_INVAL, "sc_set_surface: need n_surf >= 1 and n_rim >= 0");
+    if (n_rim > 0 && (!rim_xyz || !rim_n || !rim_dl)) return fail(SC_E_INVAL, "sc_set_surface: NULL rim array");
+    if ((int64_t)n_surf + n_rim >= (1LL << 31)) return fail(SC_E_INVAL, "sc_set_surface: too many nodes");
+    for (int64_t i = 0; i < 3LL * n_surf; ++i)
+        if (!std::isfinite(xyz[i]) || !std::isfinite(ndS[i]))
+            return fail(SC_E_INVAL, "sc_set_surface: surface node %lld is not finite", (long long)(i / 3));
+    for (int64_t i = 0; i < 3LL * n_rim; ++i)
+        if (!std::isfinite(rim_xyz[i]) || !std::isfinite(rim_n[i]) || !std::isfinite(rim_dl[i]))
+            return fail(SC_E_INVAL, "sc_set_surface: rim node %lld is not finite", (long long)(i / 3));
+    for (int j = 0; j < n_rim; ++j)
+        if (!(rim_n[3 * j] * rim_n[3 * j] + rim_n[3 * j + 1] * rim_n[3 * j + 1] + rim_n[3 * j + 2] * rim_n[3 * j + 2] >
+              0.0))
+            return fail(SC_E_INVAL, "sc_set_surface: rim normal %d is zero", j);
+    DeviceGuard g(p->ctx->device);
+    hipStream_t st = p->ctx->stream;
+    const int n_tot = n_surf + n_rim;
+    invalidate_tables(p);
+    p->has_mirror = false;
+    DevBuf d_xyz, d_nds, d_rx, d_rn, d_rdl;
+    SC_TRY(d_xyz.reserve(sizeof(double) * 3 * n_surf, p->alloc_stream));
+    SC_TRY(d_nds.reserve(sizeof(double) * 3 * n_surf, p->alloc_stream));
+    SC_TRY(d_rx.reserve(sizeof(double) * 3 * std::max(n_rim, 1), p->alloc_stream));
+    SC_TRY(d_rn.reserve(sizeof(double) * 3 * std::max(n_rim, 1), p->alloc_stream));
+    SC_TRY(d_rdl.reserve(sizeof(double) * 3 * std::max(n_rim, 1), p->alloc_stream));
+    SC_TRY(p->pos64.reserve(sizeof(double) * 4 * n_tot, p->alloc_stream));
+    SC_TRY(p->pos32.reserve(sizeof(float) * 4 * n_tot, p->alloc_stream));
+    SC_TRY(p->nrm.reserve(sizeof(double) * 3 * n_tot, p->alloc_stream));
+    SC_TRY(p->wgt.reserve(sizeof(double) * n_tot, p->alloc_stream));
+    SC_TRY(p->tan.reserve(sizeof(double) * 3 * std::max(n_rim, 1), p->alloc_stream));
+    HIP_TRY(hipMemcpyAsync(d_xyz.p, xyz, sizeof(double) * 3 * n_surf, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_nds.p, ndS, sizeof(double) * 3 * n_surf, hipMemcpyHostToDevice, st));
+    if (n_rim > 0) {
+        HIP_TRY(hipMemcpyAsync(d_rx.p, rim_xyz, sizeof(double) * 3 * n_rim, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_rn.p, rim_n, sizeof(double) * 3 * n_rim, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_rdl.p, rim_dl, sizeof(double) * 3 * n_rim, hipMemcpyHostToDevice, st));
+    }
+    HIP_TRY(launch_surface_records(st, n_surf, n_rim, d_xyz.as<double>(), d_nds.as<double>(), d_rx.as<double>(),
+                                   d_rn.as<double>(), d_rdl.as<double>(), p->pos64.as<double>(), p->pos32.as<float>(),
+                                   p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>()));
+    HIP_TRY(hipStreamSynchronize(st));   // staging buffers are freed on return
+    p->f = p->a = 0.0;
+    p->n_r = p->n_phi = 0;
+    p->n_surf = n_surf;
+    p->n_rim = n_rim;
+    p->n_tot = n_tot;
+    p->has_mirror = true;
+    return SC_OK;
+}
+
 extern "C" sc_status sc_get_num_nodes(const sc_prob *p, int *n_surface, int *n_rim)
 {
     if (!p) return fail(SC_E_INVAL, "sc_get_num_nodes: prob is NULL");
@@ -345,7 +398,7 @@ extern "C" sc_status sc_set_incident(sc_prob *p, const double *E, const double *
                                       p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>(), dE, dB,
                                       p->tab64.as<double>()));
     SC_TRY(reserve_power(p));
-    HIP_TRY(launch_power_fields(st, n_k, p->n_surf, p->n_tot, p->wgt.as<double>(), dE, dB,
+    HIP_TRY(launch_power_fields(st, n_k, p->n_surf, p->n_tot, p->nrm.as<double>(), p->wgt.as<double>(), dE, dB,
                                 p->d_power.as<double>() + n_k, p->d_power.as<double>()));
     p->has_power = true;
     ev_record(p, EV_PREP1);
@@ -383,7 +436,7 @@ extern "C" sc_status sc_set_incident_beam(sc_prob *p, int beam, double w0, doubl
                                    p->tab64.as<double>()));
     SC_TRY(reserve_power(p));
     HIP_TRY(launch_power_gaussian(st, n_k, p->n_surf, p->d_k.as<double>(), p->pos64.as<double>(),
-                                  p->wgt.as<double>(), beam, w0, pol_angle, spectrum ? dspec.as<double>() : nullptr,
+                                  p->nrm.as<double>(), p->wgt.as<double>(), beam, w0, pol_angle, spectrum ? dspec.as<double>() : nullptr,
                                   consistent ? 1 : 0, p->d_power.as<double>() + n_k, p->d_power.as<double>()));
     p->has_power = true;
     ev_record(p, EV_PREP1);

@@ -13,6 +13,10 @@ namespace sc {
 hipError_t launch_node_tables(hipStream_t st, int n_r, int n_phi, double f, const double *r,
                               const double *wr, const double *cphi, const double *sphi, double dphi,
                               double *pos64, float *pos32, double *nrm, double *wgt, double *tan);
+// General surface: node records from surface nodes + n dS and boundary nodes + normal + dl.
+hipError_t launch_surface_records(hipStream_t st, int n_surf, int n_rim, const double *xyz, const double *ndS,
+                                  const double *rim_xyz, const double *rim_n, const double *rim_dl, double *pos64,
+                                  float *pos32, double *nrm, double *wgt, double *tan);
 hipError_t launch_obs_prep(hipStream_t st, const double *xyz, int n_obs, int n_obs_pad, double *obs64,
                            float *obs32);
 hipError_t launch_tables_from_fields(hipStream_t st, int n_k, int n_surf, int n_tot, const double *k,
@@ -29,11 +33,11 @@ hipError_t launch_tables_cast(hipStream_t st, int n_k, int n_tot, const double *
 // Incident power per frequency through the aperture, P[k] = 4 pi sum_surface W Re(E x B^*).(-z):
 // from field tables E, B [n_k][n_tot][3] complex, or from the built-in Gaussian beam.
 // `part` holds power_partial_count(n_k) doubles of scratch; P is [n_k] (device).
-hipError_t launch_power_fields(hipStream_t st, int n_k, int n_surf, int n_tot, const double *wgt,
+hipError_t launch_power_fields(hipStream_t st, int n_k, int n_surf, int n_tot, const double *nrm, const double *wgt,
                                const double *E, const double *B, double *part, double *P);
 hipError_t launch_power_gaussian(hipStream_t st, int n_k, int n_surf, const double *k, const double *pos64,
-                                 const double *wgt, int beam, double w0, double pol, const double *spectrum,
-                                 int consistent, double *part, double *P);
+                                 const double *nrm, const double *wgt, int beam, double w0, double pol,
+                                 const double *spectrum, int consistent, double *part, double *P);
 int power_partial_count(int n_k);
 // tab[k][node] *= fac[k] (complex128 [n_k]); exactly one of tab64, tab32 non-null
 hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, const double *fac, double *tab64, float *tab32);

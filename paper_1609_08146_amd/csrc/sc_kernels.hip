@@ -62,6 +62,38 @@ __global__ void k_node_tables(int n_r, int n_phi, double f, const double *__rest
     }
 }
 
+// Node records of a general surface given by its quadrature: surface nodes with
+// their area-weighted normals n dS (weight 1), then the boundary nodes with the
+// surface normal there (direction only), weight 1 and the oriented line
+// element dl in `tan`.
+__global__ void k_surface_records(int n_surf, int n_rim, const double *__restrict__ xyz,
+                                  const double *__restrict__ ndS, const double *__restrict__ rim_xyz,
+                                  const double *__restrict__ rim_n, const double *__restrict__ rim_dl,
+                                  double *__restrict__ pos64, float *__restrict__ pos32, double *__restrict__ nrm,
+                                  double *__restrict__ wgt, double *__restrict__ tan)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_surf + n_rim) return;
+    const bool rim = q >= n_surf;
+    const int j = q - n_surf;
+    const double *src = rim ? rim_xyz + 3 * j : xyz + 3 * q;
+    const double *nv = rim ? rim_n + 3 * j : ndS + 3 * q;
+    const double x = src[0], y = src[1], z = src[2];
+    const dd rs = dd_norm3(x, y, z);
+    pos64[4 * q + 0] = x;
+    pos64[4 * q + 1] = y;
+    pos64[4 * q + 2] = z;
+    pos64[4 * q + 3] = rs.hi;
+    pos32[4 * q + 0] = (float)x;
+    pos32[4 * q + 1] = (float)y;
+    pos32[4 * q + 2] = (float)z;
+    pos32[4 * q + 3] = (float)rs.hi;
+    for (int c = 0; c < 3; ++c) nrm[3 * q + c] = nv[c];
+    wgt[q] = 1.0;
+    if (rim)
+        for (int c = 0; c < 3; ++c) tan[3 * j + c] = rim_dl[3 * j + c];
+}
+
 __global__ void k_obs_prep(const double *__restrict__ xyz, int n_obs, int n_obs_pad, double *__restrict__ obs64,
                            float *__restrict__ obs32)
 {
@@ -265,7 +297,8 @@ __global__ void k_tables_gaussian(int n_k, int n_surf, int n_tot, const double *
 // energy):  P_n = 4 pi SS Re(E_n x B_n^*) . dA  with dA = -z dx dy, since the
 // beam travels along -z.  The surface weights W = w_r r dphi integrate over the
 // aperture disk in the (x, y) plane, so P_n = 4 pi sum_q W_q Re(E x B^*) . (-z)
-// over the surface nodes.  Deterministic: block b of frequency k sums a fixed
+// over the surface nodes; for a general surface the aperture element of a node
+// is the z component of its n dS, (n~ W).z (n~.z = 1 on the paraboloid).  Deterministic: block b of frequency k sums a fixed
 // node range in a fixed order; k_power_finish adds the blocks in order.
 constexpr int POWER_BLOCKS = 16;
 
@@ -288,7 +321,8 @@ __device__ __forceinline__ void block_sum_256(double v, double *out)
 }
 
 // grid (POWER_BLOCKS, n_k), 256 threads; E, B: [n_k][n_tot][3] complex
-__global__ void __launch_bounds__(256) k_power_fields(int n_surf, int n_tot, const double *__restrict__ wgt,
+__global__ void __launch_bounds__(256) k_power_fields(int n_surf, int n_tot, const double *__restrict__ nrm,
+                                                      const double *__restrict__ wgt,
                                                       const double *__restrict__ Ein,
                                                       const double *__restrict__ Bin, double *__restrict__ part)
 {
@@ -303,13 +337,14 @@ __global__ void __launch_bounds__(256) k_power_fields(int n_surf, int n_tot, con
             E[c] = {e[2 * c], e[2 * c + 1]};
             B[c] = {b[2 * c], b[2 * c + 1]};
         }
-        acc += wgt[q] * flux_minus_z(E, B);
+        acc += (nrm[3 * q + 2] * wgt[q]) * flux_minus_z(E, B);
     }
     block_sum_256(acc, part + (size_t)kk * POWER_BLOCKS + blockIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_power_gaussian(int n_surf, const double *__restrict__ kv,
                                                         const double *__restrict__ pos64,
+                                                        const double *__restrict__ nrm,
                                                         const double *__restrict__ wgt, int beam, double w0,
                                                         double pol,
                                                         const double *__restrict__ spectrum, int consistent,
@@ -324,7 +359,7 @@ __global__ void __launch_bounds__(256) k_power_gaussian(int n_surf, const double
     for (int q = q0 + (int)threadIdx.x; q < q1; q += 256) {
         c64 E[3], B[3];
         beam_fields(beam, k, pos64[4 * q], pos64[4 * q + 1], w0, pol, amp, consistent, E, B);
-        acc += wgt[q] * flux_minus_z(E, B);
+        acc += (nrm[3 * q + 2] * wgt[q]) * flux_minus_z(E, B);
     }
     block_sum_256(acc, part + (size_t)kk * POWER_BLOCKS + blockIdx.x);
 }
@@ -484,6 +519,15 @@ hipError_t launch_node_tables(hipStream_t st, int n_r, int n_phi, double f, cons
     return hipGetLastError();
 }
 
+hipError_t launch_surface_records(hipStream_t st, int n_surf, int n_rim, const double *xyz, const double *ndS,
+                                  const double *rim_xyz, const double *rim_n, const double *rim_dl, double *pos64,
+                                  float *pos32, double *nrm, double *wgt, double *tan)
+{
+    hipLaunchKernelGGL(k_surface_records, dim3(nblocks((int64_t)n_surf + n_rim, 256)), dim3(256), 0, st, n_surf,
+                       n_rim, xyz, ndS, rim_xyz, rim_n, rim_dl, pos64, pos32, nrm, wgt, tan);
+    return hipGetLastError();
+}
+
 hipError_t launch_obs_prep(hipStream_t st, const double *xyz, int n_obs, int n_obs_pad, double *obs64, float *obs32)
 {
     hipLaunchKernelGGL(k_obs_prep, dim3(nblocks(n_obs_pad, 256)), dim3(256), 0, st, xyz, n_obs, n_obs_pad, obs64,
@@ -510,20 +554,21 @@ hipError_t launch_tables_gaussian(hipStream_t st, int n_k, int n_surf, int n_tot
     return hipGetLastError();
 }
 
-hipError_t launch_power_fields(hipStream_t st, int n_k, int n_surf, int n_tot, const double *wgt,
+hipError_t launch_power_fields(hipStream_t st, int n_k, int n_surf, int n_tot, const double *nrm, const double *wgt,
                                const double *E, const double *B, double *part, double *P)
 {
-    hipLaunchKernelGGL(k_power_fields, dim3(POWER_BLOCKS, n_k), dim3(256), 0, st, n_surf, n_tot, wgt, E, B, part);
+    hipLaunchKernelGGL(k_power_fields, dim3(POWER_BLOCKS, n_k), dim3(256), 0, st, n_surf, n_tot, nrm, wgt, E, B,
+                       part);
     hipLaunchKernelGGL(k_power_finish, dim3(nblocks(n_k, 256)), dim3(256), 0, st, n_k, part, P);
     return hipGetLastError();
 }
 
 hipError_t launch_power_gaussian(hipStream_t st, int n_k, int n_surf, const double *k, const double *pos64,
-                                 const double *wgt, int beam, double w0, double pol, const double *spectrum,
-                                 int consistent, double *part, double *P)
+                                 const double *nrm, const double *wgt, int beam, double w0, double pol,
+                                 const double *spectrum, int consistent, double *part, double *P)
 {
-    hipLaunchKernelGGL(k_power_gaussian, dim3(POWER_BLOCKS, n_k), dim3(256), 0, st, n_surf, k, pos64, wgt, beam, w0,
-                       pol, spectrum, consistent, part);
+    hipLaunchKernelGGL(k_power_gaussian, dim3(POWER_BLOCKS, n_k), dim3(256), 0, st, n_surf, k, pos64, nrm, wgt, beam,
+                       w0, pol, spectrum, consistent, part);
     hipLaunchKernelGGL(k_power_finish, dim3(nblocks(n_k, 256)), dim3(256), 0, st, n_k, part, P);
     return hipGetLastError();
 }

@@ -74,10 +74,10 @@ MUTANTS = [
     ("dgrad_sign", [("cld c1 = { -1.0L / (R * R), k / R };", "cld c1 = { 1.0L / (R * R), k / R };", 1)]),
     ("time_sign", [("sincosl(-(ld)kv[n] * (ld)t[m], &s, &c);", "sincosl((ld)kv[n] * (ld)t[m], &s, &c);", 1)]),
     ("time_dk", [("(double)(acc.re * (ld)dk)", "(double)(acc.re)", 1), ("(double)(acc.im * (ld)dk)", "(double)(acc.im)", 1)]),
-    ("power_sign", [("acc += (ld)wgt[q] * (-sz);", "acc += (ld)wgt[q] * sz;", 1)]),
+    ("power_sign", [("acc += (ld)wgt[q] * (ld)nrm[3 * q + 2] * (-sz);", "acc += (ld)wgt[q] * (ld)nrm[3 * q + 2] * sz;", 1)]),
     ("power_drop_EyBx", [("- ((ld)e[2] * b[0] + (ld)e[3] * b[1])", "", 1)]),
     ("power_no_4pi", [("P[n] = (double)(4.0L * PI_L * acc);", "P[n] = (double)(acc);", 1)]),
-    ("power_unweighted", [("acc += (ld)wgt[q] * (-sz);", "acc += -sz;", 1)]),
+    ("power_unweighted", [("acc += (ld)wgt[q] * (ld)nrm[3 * q + 2] * (-sz);", "acc += -sz;", 1)]),
     ("cyl_radial_B_sign", [("B[2] = -X * gr; B[3] = -X * gi;", "B[2] = X * gr; B[3] = X * gi;", 1)]),
     ("cyl_longitudinal_sign", [("double lr = -c * gi, li = c * gr;", "double lr = c * gi, li = -c * gr;", 1)]),
     ("cyl_longitudinal_coeff", [("(2.0 / k) * (r2 / (w0 * w0) - 1.0)", "(2.0 / k) * (r2 / (w0 * w0) + 1.0)", 1)]),

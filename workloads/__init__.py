@@ -258,6 +258,75 @@ def serving_arrivals(rate_hz: float, duration_s: float, seed: int = SERVING_SEED
 
 # --------------------------------------------------------------------------- random tables
 
+# --------------------------------------------------------------------------- general mirror surfaces
+# A general surface is handed to the method as its quadrature: nodes, area-weighted
+# normals n dS (pointing toward the incoming beam), and the boundary as nodes with the
+# surface normal and oriented line elements dl.  These build such data for pieces of
+# the paraboloid z = (x^2 + y^2)/4f - f: off-axis segments and annuli.
+
+def _paraboloid_piece(f, cx, rho_lo, rho_hi, n_rho, n_psi):
+    """Polar tensor grid (Gauss-Legendre in rho, trapezoid in psi) of the projected region
+    cx + rho e^{i psi}, rho in [rho_lo, rho_hi], lifted onto the paraboloid."""
+    xg, wg = np.polynomial.legendre.leggauss(n_rho)
+    rho = rho_lo + (rho_hi - rho_lo) * (xg + 1.0) / 2.0
+    wr = (rho_hi - rho_lo) * wg / 2.0
+    psi = 2.0 * math.pi * np.arange(n_psi) / n_psi
+    dpsi = 2.0 * math.pi / n_psi
+    R, P = np.meshgrid(rho, psi, indexing="ij")
+    W = (wr[:, None] * rho[:, None] * dpsi) * np.ones_like(P)
+    x = cx + R * np.cos(P)
+    y = R * np.sin(P)
+    z = (x * x + y * y) / (4.0 * f) - f
+    xyz = np.stack([x, y, z], axis=-1).reshape(-1, 3)
+    n = np.stack([-x / (2.0 * f), -y / (2.0 * f), np.ones_like(x)], axis=-1).reshape(-1, 3)
+    return xyz, n * W.reshape(-1, 1)
+
+
+def _paraboloid_circle(f, cx, rho, n_psi, outer=True):
+    """Boundary circle cx + rho e^{i psi} on the paraboloid: nodes, normals, dl (counter-clockwise
+    seen from +z for an outer edge, clockwise for a hole)."""
+    psi = 2.0 * math.pi * np.arange(n_psi) / n_psi
+    dpsi = 2.0 * math.pi / n_psi
+    c, s = np.cos(psi), np.sin(psi)
+    x, y = cx + rho * c, rho * s
+    z = (x * x + y * y) / (4.0 * f) - f
+    n = np.stack([-x / (2.0 * f), -y / (2.0 * f), np.ones_like(x)], axis=-1)
+    dx, dy = -rho * s, rho * c
+    dz = (x * dx + y * dy) / (2.0 * f)
+    dl = np.stack([dx, dy, dz], axis=-1) * dpsi * (1.0 if outer else -1.0)
+    return np.stack([x, y, z], axis=-1), n, dl
+
+
+def oap_segment(f: float, cx: float, radius: float, n_rho: int, n_psi: int):
+    """Off-axis paraboloid segment whose aperture is the disk of `radius` about (cx, 0):
+    (xyz, ndS, rim_xyz, rim_n, rim_dl)."""
+    xyz, ndS = _paraboloid_piece(f, cx, 0.0, radius, n_rho, n_psi)
+    return (xyz, ndS) + _paraboloid_circle(f, cx, radius, n_psi)
+
+
+def paraboloid_annulus(f: float, a_in: float, a_out: float, n_rho: int, n_psi: int):
+    """On-axis paraboloid annulus a_in <= r <= a_out with its two boundary circles."""
+    xyz, ndS = _paraboloid_piece(f, 0.0, a_in, a_out, n_rho, n_psi)
+    o = _paraboloid_circle(f, 0.0, a_out, n_psi, outer=True)
+    i = _paraboloid_circle(f, 0.0, a_in, n_psi, outer=False)
+    return (xyz, ndS) + tuple(np.concatenate([u, v]) for u, v in zip(o, i))
+
+
+def shifted_gaussian_fields(pts, k, w0: float, cx: float, spectrum=None):
+    """Literal x-polarised collimated Gaussian beam along -z centred on (cx, 0):
+    E = x G e^{-ikz}, B = -y G e^{-ikz}, G = exp(-((x - cx)^2 + y^2)/w0^2); [n_k, n_pts, 3] each."""
+    pts = np.asarray(pts, float).reshape(-1, 3)
+    k = np.asarray(k, float).ravel()
+    amp = np.ones(k.shape[0], complex) if spectrum is None else np.asarray(spectrum, complex)
+    G = np.exp(-((pts[:, 0] - cx) ** 2 + pts[:, 1] ** 2) / (w0 * w0))
+    ph = np.exp(-1j * np.outer(k, pts[:, 2])) * G[None, :] * amp[:, None]
+    E = np.zeros((k.shape[0], pts.shape[0], 3), complex)
+    B = np.zeros_like(E)
+    E[:, :, 0] = ph
+    B[:, :, 1] = -ph
+    return E, B
+
+
 def random_incident_tables(n_k: int, n_nodes_total: int, seed: int):
     """Seeded complex tables E_inc, B_inc of shape [n_k, n_nodes_total, 3] (complex128).
 
