@@ -172,7 +172,12 @@ sc_status sc_get_num_nodes(const sc_prob *p, int *n_surface, int *n_rim);
  *   weight [(n_r+1)*n_phi]    surface weights w_r(i) r_i 2pi/n_phi, then 2pi/n_phi. */
 sc_status sc_get_nodes(const sc_prob *p, double *xyz, double *normal, double *weight);
 
-/* Wavenumbers k_n > 0 (c = 1), n_k >= 1.  Invalidates incident tables.     */
+/* Size limits (grid dimensions of the per-frequency and time kernels).      */
+#define SC_MAX_FREQUENCIES 65535
+#define SC_MAX_TIMES 524280
+
+/* Wavenumbers k_n > 0 (c = 1), 1 <= n_k <= SC_MAX_FREQUENCIES.  Invalidates
+ * incident tables.                                                          */
 sc_status sc_set_frequencies(sc_prob *p, const double *k, int n_k);
 
 /* Incident field on the mirror nodes (Sec. III-A): E and B are complex128
@@ -251,7 +256,7 @@ sc_status sc_evaluate(sc_prob *p, sc_precision prec, void *E, void *B, int on_de
 /* Copy the last result (same layout and type as sc_evaluate).              */
 sc_status sc_get_result(const sc_prob *p, void *E, void *B, int on_device);
 
-/* Semi-discrete transform of the last result to n_t times t[] (host array):
+/* Semi-discrete transform of the last result to n_t <= SC_MAX_TIMES times t[] (host array):
  *   F(t_m) = dk * sum_n F_n e^{-i k_n t_m}    (complex; the physical field is
  * 2 Re F(t) when the samples cover positive frequencies only).
  * Et, Bt: [n_t][n_obs][3], same complex type as the result.                 */
@@ -279,13 +284,14 @@ sc_status sc_maxwell_residual_freq(sc_prob *p, int n_pts, double h, double *ef);
  *   e_t = 2 (curl E + dB/dt) / (max|curl E| + max|dB/dt|)
  *       + 2 (curl B - dE/dt) / (max|curl B| + max|dE/dt|),
  * time derivatives by 4th-order central differences of step dt;
- * et [n_t][n_pts] (host) = |e_t|.                                            */
+ * et [n_t][n_pts] (host) = |e_t|; n_t <= SC_MAX_TIMES / 5.                   */
 sc_status sc_maxwell_residual_time(sc_prob *p, int n_pts, double h, const double *t, int n_t, double dt,
                                    double dk, double *et);
 /* Electromagnetic energy of the observation set at times t [n_t] (host), each
  * point standing for a cell of volume dV (Lorentz-Heaviside, c = 1, Sec. IV-A):
  *   W(t) = 1/2 dV sum_points ( |2 Re E(t)|^2 + |2 Re B(t)|^2 ).
- * W [n_t] (host).  Reads the last result; any observation set.              */
+ * W [n_t] (host), n_t <= SC_MAX_FREQUENCIES.  Reads the last result; any
+ * observation set.                                                          */
 sc_status sc_field_energy(sc_prob *p, const double *t, int n_t, double dk, double dV, double *W);
 
 /* Evaluate several problems in ONE persistent launch (tiles of all problems

@@ -357,6 +357,8 @@ extern "C" sc_status sc_set_frequencies(sc_prob *p, const double *k, int n_k)
 {
     if (!p) return fail(SC_E_INVAL, "sc_set_frequencies: prob is NULL");
     if (!k || n_k < 1) return fail(SC_E_INVAL, "sc_set_frequencies: need n_k >= 1 wavenumbers");
+    if (n_k > SC_MAX_FREQUENCIES)
+        return fail(SC_E_INVAL, "sc_set_frequencies: at most %d wavenumbers per problem", SC_MAX_FREQUENCIES);
     for (int i = 0; i < n_k; ++i)
         if (!(k[i] > 0.0) || !std::isfinite(k[i]))
             return fail(SC_E_INVAL, "sc_set_frequencies: k[%d] = %g is not a positive wavenumber", i, k[i]);
@@ -828,7 +830,7 @@ extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, 
 extern "C" sc_status sc_to_time(sc_prob *p, double dk, const double *t, int n_t, void *Et, void *Bt, int on_device)
 {
     if (!p || !t) return fail(SC_E_INVAL, "sc_to_time: NULL argument");
-    if (n_t < 1) return fail(SC_E_INVAL, "sc_to_time: n_t must be >= 1");
+    if (n_t < 1 || n_t > SC_MAX_TIMES) return fail(SC_E_INVAL, "sc_to_time: need 1 <= n_t <= %d", SC_MAX_TIMES);
     if (!std::isfinite(dk)) return fail(SC_E_INVAL, "sc_to_time: dk must be finite");
     if (p->res_prec < 0) return fail(SC_E_STATE, "sc_to_time: no spectral result (evaluate first)");
     DeviceGuard g(p->ctx->device);
@@ -934,7 +936,8 @@ extern "C" sc_status sc_maxwell_residual_time(sc_prob *p, int n_pts, double h, c
 {
     if (!p || !t || !et) return fail(SC_E_INVAL, "sc_maxwell_residual_time: NULL argument");
     SC_TRY(check_stencil_result(p, n_pts, h, "sc_maxwell_residual_time"));
-    if (n_t < 1) return fail(SC_E_INVAL, "sc_maxwell_residual_time: n_t must be >= 1");
+    if (n_t < 1 || 5LL * n_t > SC_MAX_TIMES)
+        return fail(SC_E_INVAL, "sc_maxwell_residual_time: need 1 <= n_t <= %d", SC_MAX_TIMES / 5);
     if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(dk))
         return fail(SC_E_INVAL, "sc_maxwell_residual_time: dt must be > 0 and dk finite");
     DeviceGuard g(p->ctx->device);
@@ -958,7 +961,8 @@ extern "C" sc_status sc_maxwell_residual_time(sc_prob *p, int n_pts, double h, c
 extern "C" sc_status sc_field_energy(sc_prob *p, const double *t, int n_t, double dk, double dV, double *W)
 {
     if (!p || !t || !W) return fail(SC_E_INVAL, "sc_field_energy: NULL argument");
-    if (n_t < 1) return fail(SC_E_INVAL, "sc_field_energy: n_t must be >= 1");
+    if (n_t < 1 || n_t > SC_MAX_FREQUENCIES)
+        return fail(SC_E_INVAL, "sc_field_energy: need 1 <= n_t <= %d", SC_MAX_FREQUENCIES);
     if (!(dV > 0.0) || !std::isfinite(dV) || !std::isfinite(dk))
         return fail(SC_E_INVAL, "sc_field_energy: dV must be > 0 and dk finite");
     if (p->res_prec < 0) return fail(SC_E_STATE, "sc_field_energy: no spectral result (evaluate first)");

@@ -434,6 +434,8 @@ static sc_status validate_request(const sc_request *q)
     if (q->n_r < 1 || q->n_phi < 1 || (int64_t)(q->n_r + 1) * q->n_phi >= (1LL << 31))
         return fail(SC_E_INVAL, "request: bad quadrature size");
     if (q->n_k < 1 || !q->k) return fail(SC_E_INVAL, "request: need n_k >= 1 wavenumbers");
+    if (q->n_k > SC_MAX_FREQUENCIES) return fail(SC_E_INVAL, "request: at most %d wavenumbers", SC_MAX_FREQUENCIES);
+    if (q->n_t < 0 || q->n_t > SC_MAX_TIMES) return fail(SC_E_INVAL, "request: at most %d time samples", SC_MAX_TIMES);
     for (int i = 0; i < q->n_k; ++i)
         if (!(q->k[i] > 0.0) || !std::isfinite(q->k[i])) return fail(SC_E_INVAL, "request: k[%d] invalid", i);
     if (!(q->w0 > 0.0)) return fail(SC_E_INVAL, "request: w0 must be > 0");

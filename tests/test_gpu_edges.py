@@ -120,9 +120,18 @@ def test_rejected_sizes_and_empty_inputs(ctx):
              lambda: p.set_mirror(20.0, 40.0, 0, 8),
              lambda: p.set_frequencies([]),
              lambda: p.set_observation(np.zeros((0, 3))),
-             lambda: p.set_launch(chunk=100)]
+             lambda: p.set_launch(chunk=100),
+             lambda: p.set_frequencies(K * np.linspace(1.0, 2.0, 65536))]         # more than SC_MAX_FREQUENCIES
     for fn in cases:
         with pytest.raises(ScError) as e:
             fn()
         assert e.value.status == SC_E_INVAL
+    p.close()
+    p = _problem(ctx, 20.0, 40.0, 4, 4, [K], 20.0, np.zeros((1, 3)))
+    p.evaluate("fp64")
+    with pytest.raises(ScError) as e:
+        p.to_time(1.0, np.zeros(524281))                                          # more than SC_MAX_TIMES
+    assert e.value.status == SC_E_INVAL
+    Et, _ = p.to_time(1.0, np.zeros(524280))
+    assert Et.shape == (524280, 1, 3)
     p.close()
