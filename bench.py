@@ -257,6 +257,8 @@ def bench_serve(args):
         "completed": int(s["completed"]), "cancelled": int(s["cancelled"]), "rejected": int(s["rejected"]),
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "evals_per_s": s["evals_done"] / elapsed, "elapsed_s": elapsed, "launches": int(s["launches"]),
+        "launched_evals_per_s": s["evals_launched"] / elapsed,
+        "quanta_evals_per_device_s": s["evals_launched"] / max(s["quad_ms"] * 1e-3, 1e-9),
         "hbm_budget_gb": args.budget_gb}), flush=True)
 
 

@@ -335,7 +335,9 @@ typedef struct {
     int64_t submitted, admitted, completed, rejected, cancelled, queued, running;
     size_t hbm_in_use, hbm_budget;
     int64_t launches;         /* scheduling quanta launched                    */
-    int64_t evals_done;
+    int64_t evals_done;       /* evaluations of completed requests            */
+    int64_t evals_launched;   /* evaluations in the launched quanta           */
+    double quad_ms;           /* device time of the completed quanta (events) */
 } sc_server_stats;
 
 /* Start a serving loop on `ctx`: requests are admitted while their HBM

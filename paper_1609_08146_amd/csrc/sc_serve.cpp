@@ -270,6 +270,7 @@ static sc_status launch_quantum(sc_server *s)
     s->slot_busy[slot] = true;
     s->inflight.push_back({slot, evals, Clock::now()});
     s->stats.launches++;
+    s->stats.evals_launched += evals;
     for (Req *r : finals) {
         sc_status fs = finish_request(s, r);
         if (fs != SC_OK) return fs;
@@ -356,8 +357,10 @@ static void worker_main(sc_server *s)
         while (!s->inflight.empty() && hipEventQuery(s->slot_ev[s->inflight.front().slot]) == hipSuccess) {
             const Quantum &q = s->inflight.front();
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, s->slot_start[q.slot], s->slot_ev[q.slot]) == hipSuccess && ms > 0.05f)
-                s->evals_per_ms = 0.7 * s->evals_per_ms + 0.3 * (q.evals / (double)ms);
+            if (hipEventElapsedTime(&ms, s->slot_start[q.slot], s->slot_ev[q.slot]) == hipSuccess) {
+                s->stats.quad_ms += ms;
+                if (ms > 0.05f) s->evals_per_ms = 0.7 * s->evals_per_ms + 0.3 * (q.evals / (double)ms);
+            }
             s->slot_busy[q.slot] = false;
             s->inflight.pop_front();
         }
