@@ -70,6 +70,24 @@ def _is_device(a) -> bool:
     return a is not None and not isinstance(a, np.ndarray)
 
 
+def _check_device(t, dtype: str, numel: int, what: str):
+    """The library writes or reads `numel` elements through a raw pointer: check the tensor first."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what}: expected a torch tensor on the device")
+    if t.dtype != getattr(torch, dtype):
+        raise TypeError(f"{what}: expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: device tensors must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{what}: needs {numel} elements, got {t.numel()}")
+
+
+def _check_host(a: np.ndarray, numel: int, what: str):
+    if a.size != numel:
+        raise ValueError(f"{what}: expected {numel} elements, got {a.size}")
+
+
 class Context:
     """sc_ctx: one HIP device + stream.  stream=None uses torch's current stream on `device`."""
 
@@ -188,8 +206,15 @@ class Problem:
     def set_incident(self, E, B):
         """E, B: complex128 [n_k][n_nodes_total][3] (numpy, or complex128 torch tensors on the device)."""
         dev = _is_device(E)
-        if not dev:
+        ns, nr = self.num_nodes()
+        numel = self.n_k * (ns + nr) * 3
+        if dev:
+            _check_device(E, "complex128", numel, "set_incident E")
+            _check_device(B, "complex128", numel, "set_incident B")
+        else:
             E, B = _host_c128(E), _host_c128(B)
+            _check_host(E, numel, "set_incident E")
+            _check_host(B, numel, "set_incident B")
         call("sc_set_incident", self.h, _ptr(E), _ptr(B), int(dev))
 
     def set_incident_gaussian(self, w0: float, pol: float = 0.0, spectrum=None, consistent: bool = False):
@@ -250,6 +275,10 @@ class Problem:
         dev = _is_device(xyz)
         if not dev:
             xyz = _host_f64(xyz, (-1, 3))
+        elif xyz.dim() != 2 or xyz.shape[1] != 3:
+            raise ValueError("set_observation: device points must have shape [n, 3]")
+        else:
+            _check_device(xyz, "float64", 3 * xyz.shape[0], "set_observation")
         n = int(xyz.shape[0])
         call("sc_set_observation", self.h, _ptr(xyz), n, int(dev))
         self.n_obs = n
@@ -282,6 +311,9 @@ class Problem:
             return None
         if out is not None:
             E, B = out
+            dt = "complex128" if prec == SC_FP64 else "complex64"
+            for t, name in ((E, "evaluate E"), (B, "evaluate B")):
+                _check_device(t, dt, self.n_k * self.n_obs * 3, name)
             call("sc_evaluate", self.h, prec, _ptr(E), _ptr(B), 1)
             return out
         E, B = self._out_host(prec, self.n_k), self._out_host(prec, self.n_k)
@@ -297,6 +329,9 @@ class Problem:
         t = _host_f64(t).ravel()
         if out is not None:
             Et, Bt = out
+            dt = "complex128" if self._res_prec == SC_FP64 else "complex64"
+            for a, name in ((Et, "to_time Et"), (Bt, "to_time Bt")):
+                _check_device(a, dt, t.shape[0] * self.n_obs * 3, name)
             call("sc_to_time", self.h, float(dk), _ptr(t), int(t.shape[0]), _ptr(Et), _ptr(Bt), 1)
             return out
         Et, Bt = self._out_host(self._res_prec, t.shape[0]), self._out_host(self._res_prec, t.shape[0])

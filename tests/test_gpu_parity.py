@@ -247,6 +247,26 @@ def test_error_paths(ctx):
     with pytest.raises(ScError) as e:
         p.set_launch(obs_per_lane=3)
     assert e.value.status == SC_E_INVAL
+    # buffers the library would read or write through raw pointers are checked before the call
+    import torch
+    p.set_frequencies([1.0, 2.0])
+    n_tot = sum(p.num_nodes())
+    with pytest.raises(ValueError):
+        p.set_incident(np.zeros((2, n_tot - 1, 3), complex), np.zeros((2, n_tot - 1, 3), complex))
+    p.set_incident_gaussian(1.0)
+    p.set_observation(np.zeros((5, 3)) + 0.1)
+    small = torch.empty((2, 4, 3), dtype=torch.complex64, device="cuda")
+    with pytest.raises(ValueError):
+        p.evaluate("fp32_split", out=(small, small))
+    wrong = torch.empty((2, 5, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(TypeError):
+        p.evaluate("fp32_split", out=(wrong, wrong))
+    with pytest.raises(TypeError):
+        p.set_observation(torch.zeros((5, 3), dtype=torch.float32, device="cuda"))
+    good = torch.empty((2, 5, 3), dtype=torch.complex64, device="cuda")
+    p.evaluate("fp32_split", out=(good, good))
+    with pytest.raises(ValueError):
+        p.to_time(1.0, np.zeros(3), out=(good, good))       # 3 times x 5 points do not fit 2 x 5
     p.close()
 
 
