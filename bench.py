@@ -95,10 +95,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "copy", "table1"],
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "copy", "table1", "valu"],
                     help="step: the hot path on the broadband workload (default); batch: the seeded sweep of "
                          "uneven instances in one persistent launch; serve: a Poisson request stream; "
-                         "table1: the Table I workload with energy normalisation and diagnostics")
+                         "table1: the Table I workload with energy normalisation and diagnostics; "
+                         "valu: issue cost of the kernel's vector instructions")
     ap.add_argument("--instances", type=int, default=256, help="batch: instances of the sweep")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
@@ -336,6 +337,20 @@ def bench_table1(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_valu(args):
+    """Issue cost of the vector instructions of the quadrature kernel (the built microbenchmark)."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1609_08146_amd", "lib", "valu_rates")
+    if not os.path.exists(exe):
+        raise SystemExit(f"{exe} is not built (python -m paper_1609_08146_amd.build)")
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    if res.returncode != 0:
+        raise SystemExit(f"valu_rates failed ({res.returncode}): {res.stderr}")
+    out = json.loads(res.stdout)
+    out["metric"] = "gfx950 vector instruction issue cost"
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy(args):
     """A plain device copy of known size (calibrates the HBM byte counters)."""
     import torch
@@ -359,6 +374,8 @@ def main():
         return bench_serve(args)
     if args.mode == "table1":
         return bench_table1(args)
+    if args.mode == "valu":
+        return bench_valu(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the frequency-sharded multi-GPU "
                                    "design is described but not built, so --gpus must be 1"}))
