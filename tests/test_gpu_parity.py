@@ -129,6 +129,51 @@ def test_fp32_split_stress_geometry(ctx, orc):
     p.close()
 
 
+def test_full_size_stress_sampled(ctx, orc):
+    """The precision workload at full size (800 x 800 nodes, 128 x 128 points, 64 frequencies,
+    6.7e11 evaluations) in the default launch: sampled outputs against the oracle, and the whole
+    grid of the split form against the GPU FP64 form."""
+    w = workloads.stress()
+    from paper_1609_08146_amd import problem_from_workload
+    p = problem_from_workload(ctx, w)
+    E, B = p.evaluate("fp32_split")
+    rng = np.random.default_rng(3)
+    oi = np.sort(rng.choice(w.n_obs, 6, replace=False))
+    ki = np.array([0, 21, 42, 63])
+    Eo, Bo = orc.solve(w.subset(obs_idx=oi, k_idx=ki))
+    err = max(rel_l2(E[ki][:, oi], Eo), rel_l2(B[ki][:, oi], Bo))
+    E64, B64 = p.evaluate("fp64")
+    err64 = max(rel_l2(E64[ki][:, oi], Eo), rel_l2(B64[ki][:, oi], Bo))
+    whole = max(rel_l2(E, E64), rel_l2(B, B64))
+    print(f"stress full size: split vs oracle {err:.2e}, fp64 vs oracle {err64:.2e}, split vs fp64 {whole:.2e}")
+    assert err < 1e-5 and err64 < 1e-12 and whole < 1e-5
+    p.close()
+
+
+def test_full_size_sweep_batch_sampled(ctx, orc):
+    """Sweep instances at their full sizes in one persistent launch; sampled outputs per instance."""
+    from paper_1609_08146_amd import problem_from_workload
+    ws = workloads.sweep(24)
+    probs = [problem_from_workload(ctx, w) for w in ws]
+    ctx.evaluate_batch(probs, "fp32_split")
+    rng = np.random.default_rng(9)
+    worst = 0.0
+    for w, p in zip(ws, probs):
+        E, B = p.result()
+        # like the relative L2 norm over a whole output, the sample holds the strong focal field:
+        # the point nearest the focus and the carrier, plus two random points and one random frequency
+        # (a lone point 4 wavelengths out at a band-edge frequency can be 1e-4 of the peak)
+        focus = int(np.argmin(np.linalg.norm(w.obs, axis=1)))
+        oi = np.unique(np.concatenate([[focus], rng.choice(w.n_obs, 2, replace=False)]))
+        ki = np.unique([w.n_k // 2, int(rng.integers(w.n_k))])
+        Eo, Bo = orc.solve(w.subset(obs_idx=oi, k_idx=ki))
+        err = max(rel_l2(E[ki][:, oi], Eo), rel_l2(B[ki][:, oi], Bo))
+        worst = max(worst, err)
+        assert err < 1e-5, (w.name, err)
+        p.close()
+    print(f"sweep full size, 24 instances in one launch: worst sampled relative L2 {worst:.2e}")
+
+
 def test_time_transform(ctx, orc):
     w = workloads.broadband(n_k=32, n_nodes=60)
     sub = w.subset(obs_idx=np.arange(0, w.n_obs, 97))
