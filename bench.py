@@ -112,7 +112,8 @@ def shard_workload(shard: int):
     if shard <= 1:
         return full, "all 128 frequencies"
     kidx = np.arange(0, full.n_k, shard)
-    return full.subset(k_idx=kidx, name="broadband-shard"), f"frequency shard 1/{shard} ({len(kidx)} of 128, every {shard}th)"
+    desc = f"frequency shard 1/{shard} ({len(kidx)} of 128, every {shard}th)"
+    return full.subset(k_idx=kidx, name="broadband-shard"), desc
 
 
 def run_step(ctx, w, precision):

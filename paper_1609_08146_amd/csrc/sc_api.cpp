@@ -421,6 +421,10 @@ extern "C" sc_status sc_set_incident_beam(sc_prob *p, int beam, double w0, doubl
     if (!std::isfinite(pol_angle)) return fail(SC_E_INVAL, "sc_set_incident_beam: bad polarisation angle");
     if (!p->has_mirror || p->k.empty())
         return fail(SC_E_STATE, "sc_set_incident_beam: set mirror and frequencies first");
+    if (spectrum)
+        for (size_t i = 0; i < 2 * p->k.size(); ++i)
+            if (!std::isfinite(spectrum[i]))
+                return fail(SC_E_INVAL, "sc_set_incident_beam: spectrum[%zu] is not finite", i / 2);
     DeviceGuard g(p->ctx->device);
     hipStream_t st = p->ctx->stream;
     const int n_k = (int)p->k.size();
@@ -438,8 +442,9 @@ extern "C" sc_status sc_set_incident_beam(sc_prob *p, int beam, double w0, doubl
                                    p->tab64.as<double>()));
     SC_TRY(reserve_power(p));
     HIP_TRY(launch_power_gaussian(st, n_k, p->n_surf, p->d_k.as<double>(), p->pos64.as<double>(),
-                                  p->nrm.as<double>(), p->wgt.as<double>(), beam, w0, pol_angle, spectrum ? dspec.as<double>() : nullptr,
-                                  consistent ? 1 : 0, p->d_power.as<double>() + n_k, p->d_power.as<double>()));
+                                  p->nrm.as<double>(), p->wgt.as<double>(), beam, w0, pol_angle,
+                                  spectrum ? dspec.as<double>() : nullptr, consistent ? 1 : 0,
+                                  p->d_power.as<double>() + n_k, p->d_power.as<double>()));
     p->has_power = true;
     ev_record(p, EV_PREP1);
     p->ev_prep = p->ctx->profiling;
@@ -797,6 +802,12 @@ extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, 
     // one launch needs one obs-per-lane / waves shape: take it from the first problem
     for (int i = 0; i < n; ++i)
         if (!probs[i] || probs[i]->ctx != c) return fail(SC_E_INVAL, "sc_evaluate_batch: problem %d not on ctx", i);
+    {   // the same partial buffer must not serve two jobs
+        std::vector<const sc_prob *> sorted(probs, probs + n);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(SC_E_INVAL, "sc_evaluate_batch: a problem appears twice");
+    }
     sc_launch l0 = resolve_launch(probs[0], prec);
     SC_TRY(check_launch(l0));
     std::vector<QuadJob> jobs(n);
@@ -809,10 +820,6 @@ extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, 
         SC_TRY(prepare(probs[i], prec, ls[i], jobs[i]));
         probs[i]->res_prec = -1;
     }
-    // the same partial buffer must not serve two jobs
-    for (int i = 0; i < n; ++i)
-        for (int j = i + 1; j < n; ++j)
-            if (probs[i] == probs[j]) return fail(SC_E_INVAL, "sc_evaluate_batch: problem %d repeated", j);
     SC_TRY(run_quad(c, jobs, prec, l0, probs[0]));
     for (int i = 0; i < n; ++i) {
         sc_prob *p = probs[i];

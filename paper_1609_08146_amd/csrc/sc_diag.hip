@@ -208,8 +208,9 @@ __global__ void __launch_bounds__(256) k_energy(int n_obs, const T *__restrict__
 
 __global__ void k_energy_finish(int n_t, double half_dv, const double *__restrict__ part, double *__restrict__ W)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n_t) return;
+    const int64_t gm = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gm >= n_t) return;
+    const int m = (int)gm;
     double s = 0.0;
     for (int b = 0; b < ENERGY_BLOCKS; ++b) s += part[(size_t)m * ENERGY_BLOCKS + b];
     W[m] = half_dv * s;

@@ -36,7 +36,8 @@ void gauss_legendre_rule(int n, std::vector<double> &x, std::vector<double> &w)
     const long double pi = 3.141592653589793238462643383279502884L;
     const long double nn = n;
     for (int i = 1; i <= (n + 1) / 2; ++i) {
-        long double z = (1.0L - (nn - 1.0L) / (8.0L * nn * nn * nn)) * cosl(pi * (4.0L * i - 1.0L) / (4.0L * nn + 2.0L));
+        long double z =
+            (1.0L - (nn - 1.0L) / (8.0L * nn * nn * nn)) * cosl(pi * (4.0L * i - 1.0L) / (4.0L * nn + 2.0L));
         __float128 zq;
         if (2 * i - 1 == n) {
             zq = 0;   // middle node of an odd rule

@@ -30,8 +30,9 @@ __global__ void k_node_tables(int n_r, int n_phi, double f, const double *__rest
                               double *__restrict__ tan)
 {
     const int n_tot = (n_r + 1) * n_phi;
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n_tot) return;
+    const int64_t gq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gq >= n_tot) return;
+    const int q = (int)gq;
     const int i = q / n_phi;
     const int j = q - i * n_phi;
     const bool rim = (i == n_r);
@@ -72,8 +73,9 @@ __global__ void k_surface_records(int n_surf, int n_rim, const double *__restric
                                   double *__restrict__ pos64, float *__restrict__ pos32, double *__restrict__ nrm,
                                   double *__restrict__ wgt, double *__restrict__ tan)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n_surf + n_rim) return;
+    const int64_t gq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gq >= (int64_t)n_surf + n_rim) return;
+    const int q = (int)gq;
     const bool rim = q >= n_surf;
     const int j = q - n_surf;
     const double *src = rim ? rim_xyz + 3 * j : xyz + 3 * q;
@@ -97,8 +99,9 @@ __global__ void k_surface_records(int n_surf, int n_rim, const double *__restric
 __global__ void k_obs_prep(const double *__restrict__ xyz, int n_obs, int n_obs_pad, double *__restrict__ obs64,
                            float *__restrict__ obs32)
 {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= n_obs_pad) return;
+    const int64_t go = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (go >= n_obs_pad) return;
+    const int o = (int)go;
     const int src = (o < n_obs) ? o : 0;   // padding repeats a valid point; its result is discarded
     const double x = xyz[3 * src], y = xyz[3 * src + 1], z = xyz[3 * src + 2];
     const double r2 = __fma_rn(x, x, __fma_rn(y, y, z * z));
@@ -298,8 +301,9 @@ __global__ void k_tables_gaussian(int n_k, int n_surf, int n_tot, const double *
 // beam travels along -z.  The surface weights W = w_r r dphi integrate over the
 // aperture disk in the (x, y) plane, so P_n = 4 pi sum_q W_q Re(E x B^*) . (-z)
 // over the surface nodes; for a general surface the aperture element of a node
-// is the z component of its n dS, (n~ W).z (n~.z = 1 on the paraboloid).  Deterministic: block b of frequency k sums a fixed
-// node range in a fixed order; k_power_finish adds the blocks in order.
+// is the z component of its n dS, (n~ W).z (n~.z = 1 on the paraboloid).
+// Deterministic: block b of frequency k sums a fixed node range in a fixed
+// order; k_power_finish adds the blocks in order.
 constexpr int POWER_BLOCKS = 16;
 
 __device__ __forceinline__ double flux_minus_z(const c64 *E, const c64 *B)
@@ -366,8 +370,9 @@ __global__ void __launch_bounds__(256) k_power_gaussian(int n_surf, const double
 
 __global__ void k_power_finish(int n_k, const double *__restrict__ part, double *__restrict__ P)
 {
-    const int kk = blockIdx.x * blockDim.x + threadIdx.x;
-    if (kk >= n_k) return;
+    const int64_t gk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gk >= n_k) return;
+    const int kk = (int)gk;
     double s = 0.0;
     for (int b = 0; b < POWER_BLOCKS; ++b) s += part[(size_t)kk * POWER_BLOCKS + b];
     P[kk] = FOUR_PI * s;
@@ -454,9 +459,9 @@ __global__ void k_reduce(const PT *__restrict__ partial, int n_chunks, int n_k, 
 __global__ void k_twiddles(int n_k, const double *__restrict__ kv, int n_t, const double *__restrict__ t, double dk,
                            double *__restrict__ tw)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n_k * n_t) return;
-    const int m = idx / n_k, n = idx - m * n_k;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n_k * n_t) return;
+    const int m = (int)(idx / n_k), n = (int)(idx - (int64_t)m * n_k);
     double s, c;
     sincos(phase_mod_2pi(kv[n], dd{-t[m], 0.0}), &s, &c);
     tw[2 * idx] = dk * c;
@@ -501,7 +506,7 @@ __global__ void __launch_bounds__(256) k_time(int n_k, int n_t, int64_t n_x, con
 
 __global__ void k_fill_u32(unsigned int *p, unsigned int v, int n)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 

@@ -74,7 +74,8 @@ def test_maxwell_residual_time_matches_oracle(ctx, orc):
         p = _problem(ctx, w.f, w.a, w.n_r, w.n_phi, w.k, w.w0, consistent, st, w.spectrum)
         p.evaluate("fp64")
         et = p.maxwell_residual_time(len(pts), h, t, dt, w.dk)
-        print(f"consistent={consistent}: oracle max {eto.max():.3e}, fp64 max rel diff {np.abs(et / eto - 1).max():.1e}")
+        print(f"consistent={consistent}: oracle max {eto.max():.3e}, "
+              f"fp64 max rel diff {np.abs(et / eto - 1).max():.1e}")
         np.testing.assert_allclose(et, eto, rtol=1e-4)
         p.close()
 

@@ -268,6 +268,13 @@ def test_batch_equals_alone_bitwise(ctx):
     for p, (E, B) in zip(probs, alone):
         Eb, Bb = p.result()
         assert np.array_equal(E, Eb) and np.array_equal(B, Bb)
+    from paper_1609_08146_amd import ScError
+    from paper_1609_08146_amd._abi import SC_E_INVAL
+    with pytest.raises(ScError) as e:              # one problem twice would share its partial sums
+        ctx.evaluate_batch([probs[0], probs[1], probs[0]], "fp32_split")
+    assert e.value.status == SC_E_INVAL
+    Eb, Bb = probs[0].result()                     # the rejected call left the earlier result alone
+    assert np.array_equal(alone[0][0], Eb)
     for p in probs:
         p.close()
 
