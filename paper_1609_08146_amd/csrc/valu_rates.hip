@@ -4,6 +4,11 @@
 // instruction kind in registers, 8 waves per SIMD, after a warm-up that brings
 // the clocks up; the result is SIMD cycles per wave instruction at the 2.4 GHz
 // peak clock.  Prints one JSON object.
+//
+// Operands differ from lane to lane (as in the quadrature) except in the
+// lane-uniform variant, which shows how much of the FMA cost depends on the
+// data; the interleaved variant alternates FMAs with and without an SGPR
+// operand, as the quadrature's instruction stream does.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -13,22 +18,28 @@ namespace {
 constexpr int CH = 16;          // independent chains per lane
 constexpr int BLOCKS = 4096;    // 256-thread blocks: 16 waves per SIMD on 256 CUs (two rounds of 8)
 
-enum Op { FMAC_V, FMAC_S, MUL_V, ADD_V, SIN_V, RSQ_V, FMA_F64 };
+enum Op { FMAC_V, FMAC_S, MUL_V, ADD_V, SIN_V, RSQ_V, FMA_F64, FMAC_UNIFORM, FMAC_SV };
 
 template <int OP>
 __global__ void __launch_bounds__(256) k_rate(float *out, int iters, float s_y)
 {
-    const float y = 0.999f + threadIdx.x * 1e-9f;   // per-lane value: a VGPR operand
+    float lane_term = (float)threadIdx.x;
+    if (OP == FMAC_UNIFORM) {   // zero in every lane, but opaque: the operands stay in VGPRs
+        lane_term = 0.0f;
+        asm volatile("" : "+v"(lane_term));
+    }
+    const float y = 0.999f + lane_term * 1e-9f;   // a VGPR operand (per-lane unless uniform)
     float acc[CH], x[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-        acc[c] = (float)(threadIdx.x + c) * 1e-3f;
-        x[c] = 1e-4f * (c + 1) + threadIdx.x * 1e-10f;
+        acc[c] = (lane_term + c) * 1e-3f;
+        x[c] = 1e-4f * (c + 1) + lane_term * 1e-10f;
     }
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
-            if (OP == FMAC_V) acc[c] = __builtin_fmaf(x[c], y, acc[c]);
+            if (OP == FMAC_V || OP == FMAC_UNIFORM) acc[c] = __builtin_fmaf(x[c], y, acc[c]);
+            if (OP == FMAC_SV) acc[c] = __builtin_fmaf(x[c], (c & 1) ? y : s_y, acc[c]);
             if (OP == FMAC_S) acc[c] = __builtin_fmaf(x[c], s_y, acc[c]);   // s_y: an SGPR operand
             if (OP == MUL_V) acc[c] = acc[c] * y;
             if (OP == ADD_V) acc[c] = acc[c] + x[c];
@@ -105,11 +116,13 @@ int main()
     const int it = 8192;
     printf("{\"unit\": \"SIMD cycles per wave64 instruction at 2.4 GHz\", "
            "\"v_fmac_f32 (VGPR operands)\": %.3f, \"v_fmac_f32 (SGPR operand)\": %.3f, \"v_mul_f32\": %.3f, "
-           "\"v_add_f32\": %.3f, \"v_sin_f32\": %.3f, \"v_rsq_f32 + v_add_f32\": %.3f, \"v_fma_f64\": %.3f}\n",
+           "\"v_add_f32\": %.3f, \"v_sin_f32\": %.3f, \"v_rsq_f32 + v_add_f32\": %.3f, \"v_fma_f64\": %.3f, "
+           "\"v_fmac_f32 (lane-uniform data)\": %.3f, \"v_fmac_f32 (SGPR and VGPR operands alternating)\": %.3f}\n",
            cycles_per_instruction<FMAC_V>(o, od, it), cycles_per_instruction<FMAC_S>(o, od, it),
            cycles_per_instruction<MUL_V>(o, od, it), cycles_per_instruction<ADD_V>(o, od, it),
            cycles_per_instruction<SIN_V>(o, od, it / 4), cycles_per_instruction<RSQ_V>(o, od, it / 4),
-           cycles_per_instruction<FMA_F64>(o, od, it));
+           cycles_per_instruction<FMA_F64>(o, od, it), cycles_per_instruction<FMAC_UNIFORM>(o, od, it),
+           cycles_per_instruction<FMAC_SV>(o, od, it));
     (void)hipFree(o);
     (void)hipFree(od);
     return 0;
