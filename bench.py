@@ -33,17 +33,27 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 # Algorithmic work of the split form, counted from the kernel source (FMA = 2
-# flops; the transcendental instructions rsq, rcp, sin, cos are not counted):
+# flops; the transcendental instructions rsq, rcp, sin, cos are not counted).
+# General tables:
 #   per (node, point) geometry:  R, |R|^2, R, r_s.r', delta                 18
 #   per (node, point, frequency): phase 2, g 2, (ik - 1/R)/R 2, h 6,
 #                                 E += Jt g 24, rho_t h 6, E += .. R 12,
 #                                 Jt h 18, B += (Jt h) x R 24              96
-# The kernel shares the geometry among the FREQ_PER_LANE frequencies of a lane.
+# Factored current Jt = u s (a real direction u per node):
+#   per (node, point):            geometry 18, w = u x R 9                 27
+#   per (node, point, frequency): phase 2, g 2, (ik - 1/R)/R 2, h 6,
+#                                 s g 6, E += u (s g) 12, rho_t h 6,
+#                                 E += .. R 12, s h 6, B += (s h) w 12     66
+# The kernel shares the per-(node, point) work among the FREQ_PER_LANE
+# frequencies of a lane.
 FLOPS_GEOM, FLOPS_FREQ = 18, 96
+FLOPS_GEOM_FACTORED, FLOPS_FREQ_FACTORED = 27, 66
 FREQ_PER_LANE = 2
 
 
-def flops_per_eval(freq_per_lane: int = FREQ_PER_LANE) -> float:
+def flops_per_eval(factored: bool = False, freq_per_lane: int = FREQ_PER_LANE) -> float:
+    if factored:
+        return FLOPS_FREQ_FACTORED + FLOPS_GEOM_FACTORED / freq_per_lane
     return FLOPS_FREQ + FLOPS_GEOM / freq_per_lane
 
 
@@ -94,7 +104,7 @@ def parse():
     ap.add_argument("--precision", default="fp32_split", choices=["fp32_split", "fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "copy", "table1", "valu"],
                     help="step: the hot path on the broadband workload (default); batch: the seeded sweep of "
                          "uneven instances in one persistent launch; serve: a Poisson request stream; "
@@ -116,10 +126,11 @@ def shard_workload(shard: int):
     return full.subset(k_idx=kidx, name="broadband-shard"), desc
 
 
-def run_step(ctx, w, precision):
+def run_step(ctx, w, precision, factoring=True):
     """One pass of the whole path; returns the problem (kept alive for timing)."""
     from paper_1609_08146_amd import Problem
     p = Problem(ctx)
+    p.set_factoring(factoring)
     p.set_mirror(w.f, w.a, w.n_r, w.n_phi)
     p.set_frequencies(w.k)
     p.set_incident_gaussian(w.w0, w.pol, w.spectrum, False)
@@ -189,11 +200,14 @@ def bench_batch(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     quad_ms = probs[0].timing()["quad_ms"]
+    fact_evals = sum(w.evals for w, p in zip(ws, probs) if p.factored)
+    flops = flops_per_eval(True) * fact_evals + flops_per_eval(False) * (evals - fact_evals)
     out = {"metric": "integrand evals/s, seeded sweep of uneven instances in one persistent launch",
            "value": evals / dt, "unit": "integrand evals/s", "n_gpus": 1, "instances": len(ws),
            "evals": evals, "seconds": dt, "quad_ms": quad_ms, "setup_s": setup,
-           "tflops": flops_per_eval() * evals / (quad_ms * 1e-3) / 1e12,
-           "frac_fp32_peak": flops_per_eval() * evals / (quad_ms * 1e-3) / 1e12 / PEAK_FP32,
+           "factored_instances": sum(1 for p in probs if p.factored),
+           "tflops": flops / (quad_ms * 1e-3) / 1e12,
+           "frac_fp32_peak": flops / (quad_ms * 1e-3) / 1e12 / PEAK_FP32,
            "precision": "fp32_split", "chunk": 16384}
     for p in probs:
         p.close()
@@ -402,6 +416,7 @@ def main():
         tm = p.timing()
         quad_ms.append(tm["quad_ms"])
         last_timing = tm
+        factored = args.precision == "fp32_split" and p.factored
         p.close()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -410,7 +425,7 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = evals * args.steps / elapsed
     quad_avg = float(np.mean(quad_ms))
-    fpe = flops_per_eval()
+    fpe = flops_per_eval(factored)
     achieved = fpe * evals / (quad_avg * 1e-3) / 1e12
     peak = PEAK_FP64 if args.precision == "fp64" else PEAK_FP32
     # the counters were taken on the full FP32-split workload with the default launch
@@ -433,12 +448,14 @@ def main():
                         f"w0=0.05 m, 400x400 GL x trapezoid nodes, 64x64 focal plane +-4 lambda0 + 64 axial, "
                         f"256 time samples; {shard_desc}",
             "precision": args.precision, "launch": "obs_per_lane=1, freq_per_lane=2, 4 waves/block, chunk 4096",
+            "current": "factored (Jt = u s: the current n x B keeps one real direction per node)" if factored
+                       else "general tables",
             "n_obs": w.n_obs, "n_freq": w.n_k, "n_nodes": w.n_nodes, "n_time": len(w.t),
             "evals_per_step": evals,
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_quad (split-form surface quadrature)",
+            "kernel": "k_quad (split-form surface quadrature" + (", factored current)" if factored else ")"),
             "achieved": achieved,
             "peak": peak,
             "unit": "TFLOP/s",
@@ -466,12 +483,25 @@ def main():
         p.close()
         r64 = w64.evals / (q64 * 1e-3)
         rq = evals / (quad_avg * 1e-3)
+        fpg = flops_per_eval(False)
         out["forms"] = {
             "fp64": {"quad_evals_per_s": r64, "quad_ms": q64, "n_freq": w64.n_k,
-                     "tflops": fpe * r64 / 1e12, "frac_fp64_peak": fpe * r64 / 1e12 / PEAK_FP64},
+                     "tflops": fpg * r64 / 1e12, "frac_fp64_peak": fpg * r64 / 1e12 / PEAK_FP64},
             args.precision: {"quad_evals_per_s": rq},
             "speedup_vs_fp64": rq / r64,
         }
+        if factored:
+            # the same split form on the general tables (what an arbitrary incident field costs)
+            qg = []
+            for _ in range(3):
+                p = run_step(ctx, w, args.precision, factoring=False)
+                torch.cuda.synchronize()
+                qg.append(p.timing()["quad_ms"])
+                p.close()
+            rg = evals / (min(qg) * 1e-3)
+            out["forms"]["fp32_split_general_tables"] = {
+                "quad_evals_per_s": rg, "quad_ms": min(qg), "tflops": fpg * rg / 1e12,
+                "frac_fp32_peak": fpg * rg / 1e12 / PEAK_FP32}
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

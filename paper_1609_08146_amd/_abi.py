@@ -87,6 +87,8 @@ SIGNATURES = {
     "sc_scale_spectrum": [V, P],
     "sc_normalize_energy": [V, P, D, D],
     "sc_set_table_storage": [V, I],
+    "sc_set_factoring": [V, I],
+    "sc_get_factoring": [V, ctypes.POINTER(I)],
     "sc_set_observation": [V, P, I, I],
     "sc_evaluate": [V, I, P, P, I],
     "sc_get_result": [V, P, P, I],

@@ -271,6 +271,17 @@ class Problem:
     def set_table_storage(self, keep_fp64: bool):
         call("sc_set_table_storage", self.h, int(bool(keep_fp64)))
 
+    def set_factoring(self, enable: bool):
+        """Use the factored current J~ = u s for "fp32_split" when the tables allow it (sc_set_factoring)."""
+        call("sc_set_factoring", self.h, int(bool(enable)))
+
+    @property
+    def factored(self) -> bool:
+        """True if "fp32_split" evaluation uses the factored tables (sc_get_factoring)."""
+        v = ctypes.c_int(0)
+        call("sc_get_factoring", self.h, ctypes.byref(v))
+        return bool(v.value)
+
     def set_observation(self, xyz):
         dev = _is_device(xyz)
         if not dev:

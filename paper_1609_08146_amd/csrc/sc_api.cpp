@@ -183,7 +183,39 @@ static void gauss_rule_cached(sc_ctx *c, int n, const std::vector<double> *out[2
 static void invalidate_tables(sc_prob *p)
 {
     p->has_tab = p->tab32_ok = p->tab32n_ok = p->has_tab64 = p->has_power = false;
+    p->fact_checked = p->fact_ok = false;
     p->res_prec = -1;
+}
+
+// Relative tolerance of the factoring test: the built-in beams whose current keeps one real
+// direction factor to rounding (~1e-16); the longitudinal magnetic term of the curl-consistent
+// linear beam turns the current by O(1/(k w0)) and is rejected.
+constexpr double FACTOR_TOL = 1e-10;
+
+// Build the factored FP32 split tables from the FP64 tables once per table set, if the current of
+// every node keeps one real direction over the frequencies (otherwise the general tables are used).
+static sc_status ensure_factored(sc_prob *p)
+{
+    if (p->fact_checked || !p->allow_fact || !p->has_tab64) return SC_OK;
+    hipStream_t st = p->ctx->stream;
+    const int n_k = (int)p->k.size();
+    const size_t nrec = (size_t)n_k * p->n_tot;
+    SC_TRY(p->tabf.reserve(sizeof(float) * 4 * nrec, p->alloc_stream));
+    SC_TRY(p->posf.reserve(sizeof(float) * 8 * (size_t)p->n_tot, p->alloc_stream));
+    SC_TRY(p->fact_flag.reserve(sizeof(unsigned int), p->alloc_stream));
+    HIP_TRY(launch_fill_u32(st, p->fact_flag.as<unsigned int>(), 0u, 1));
+    HIP_TRY(launch_tables_factor(st, n_k, p->n_tot, p->tab64.as<double>(), p->pos32.as<float>(), FACTOR_TOL,
+                                 p->tabf.as<float>(), p->posf.as<float>(), p->fact_flag.as<unsigned int>()));
+    unsigned int bad = 1;
+    HIP_TRY(hipMemcpyAsync(&bad, p->fact_flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    p->fact_checked = true;
+    p->fact_ok = bad == 0;
+    if (!p->fact_ok) {
+        p->tabf.release();
+        p->posf.release();
+    }
+    return SC_OK;
 }
 
 static sc_status reserve_power(sc_prob *p)
@@ -198,6 +230,7 @@ static sc_status finish_tables(sc_prob *p)
     p->has_tab = true;
     p->has_tab64 = true;
     if (p->keep_fp64) return SC_OK;
+    SC_TRY(ensure_factored(p));   // needs the FP64 tables
     const size_t nrec = p->k.size() * (size_t)p->n_tot;
     SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
     HIP_TRY(launch_tables_cast(p->ctx->stream, (int)p->k.size(), p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
@@ -215,6 +248,23 @@ extern "C" sc_status sc_set_table_storage(sc_prob *p, int keep_fp64)
     DeviceGuard g(p->ctx->device);
     p->keep_fp64 = keep_fp64 != 0;
     if (!p->keep_fp64 && p->has_tab64) return finish_tables(p);
+    return SC_OK;
+}
+
+extern "C" sc_status sc_set_factoring(sc_prob *p, int enable)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_set_factoring: prob is NULL");
+    p->allow_fact = enable != 0;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_get_factoring(sc_prob *p, int *active)
+{
+    if (!p || !active) return fail(SC_E_INVAL, "sc_get_factoring: NULL argument");
+    if (!p->has_tab) return fail(SC_E_STATE, "sc_get_factoring: no incident field set");
+    DeviceGuard g(p->ctx->device);
+    SC_TRY(ensure_factored(p));
+    *active = p->allow_fact && p->fact_ok ? 1 : 0;
     return SC_OK;
 }
 
@@ -477,10 +527,14 @@ static sc_status scale_tables(sc_prob *p, const std::vector<double> &fac)
     SC_TRY(dfac.reserve(sizeof(double) * 2 * n_k, p->alloc_stream));
     HIP_TRY(hipMemcpyAsync(dfac.p, fac.data(), sizeof(double) * 2 * n_k, hipMemcpyHostToDevice, st));
     if (p->has_tab64) {
-        HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, dfac.as<double>(), p->tab64.as<double>(), nullptr));
+        HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, 4, dfac.as<double>(), p->tab64.as<double>(), nullptr));
         p->tab32_ok = false;   // rebuilt from the scaled FP64 tables when needed
-    } else if (p->tab32_ok) {
-        HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, dfac.as<double>(), nullptr, p->tab32.as<float>()));
+        p->fact_checked = p->fact_ok = false;
+    } else {
+        if (p->tab32_ok)
+            HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, 4, dfac.as<double>(), nullptr, p->tab32.as<float>()));
+        if (p->fact_ok)   // a factor per frequency keeps the direction: scale s and rho_t
+            HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, 2, dfac.as<double>(), nullptr, p->tabf.as<float>()));
     }
     p->tab32n_ok = false;
     p->res_prec = -1;
@@ -657,7 +711,14 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
         return fail(SC_E_STATE, "evaluate: FP64 tables were not kept (sc_set_table_storage(p, 0))");
     if (prec != SC_FP64 && !p->tab32_ok && !p->has_tab64)
         return fail(SC_E_STATE, "evaluate: no tables to build the FP32 tables from");
-    if (prec == SC_FP32_SPLIT) {
+    bool fact = false;
+    if (prec == SC_FP32_SPLIT && p->allow_fact) {
+        SC_TRY(ensure_factored(p));
+        fact = p->fact_ok;
+    }
+    if (fact) {
+        tab = p->tabf.p;
+    } else if (prec == SC_FP32_SPLIT) {
         if (!p->tab32_ok) {
             SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
             HIP_TRY(launch_tables_cast(st, n_k, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
@@ -681,7 +742,8 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
     SC_TRY(p->resE.reserve(rs * 6 * (size_t)n_k * p->n_obs, p->alloc_stream));
     SC_TRY(p->resB.reserve(rs * 6 * (size_t)n_k * p->n_obs, p->alloc_stream));
     job.tab = tab;
-    job.pos = prec == SC_FP64 ? p->pos64.p : p->pos32.p;
+    job.pos = prec == SC_FP64 ? p->pos64.p : (fact ? p->posf.p : p->pos32.p);
+    job.factored = fact ? 1 : 0;
     job.obs = prec == SC_FP64 ? p->obs64.p : p->obs32.p;
     job.k = p->d_k.as<double>();
     job.partial = p->partial.p;
@@ -711,6 +773,8 @@ size_t sc::footprint_bytes(int n_r, int n_phi, int n_k, int n_obs, int n_t, sc_p
     // FP64 tables (kept for SC_FP64; for the FP32 forms they exist only while the FP32 tables are cast)
     b += (size_t)n_k * n_tot * sizeof(double) * 8;
     if (prec != SC_FP64) b += (size_t)n_k * n_tot * sizeof(float) * 8;                      // FP32 tables
+    if (prec == SC_FP32_SPLIT)                                                               // factored tables
+        b += (size_t)n_k * n_tot * sizeof(float) * 4 + n_tot * sizeof(float) * 8;
     b += pad * (sizeof(double) + sizeof(float)) * 4;                                        // observation records
     b += rs * 12 * (size_t)n_k * n_obs;                                                      // results E, B
     b += rs * 12 * n_chunks * (size_t)n_k * pad;                                             // split-K partials
@@ -1008,8 +1072,9 @@ extern "C" sc_status sc_prob_device_bytes(const sc_prob *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(SC_E_INVAL, "sc_prob_device_bytes: NULL argument");
     const DevBuf *bufs[] = {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->nrm, &p->wgt,
-                            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->d_power, &p->obs64, &p->obs32,
-                            &p->resE, &p->resB, &p->partial, &p->d_t, &p->tw, &p->timeE, &p->timeB};
+                            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->tabf, &p->posf,
+                            &p->fact_flag, &p->d_power, &p->obs64, &p->obs32, &p->resE, &p->resB, &p->partial,
+                            &p->d_t, &p->tw, &p->timeE, &p->timeB};
     size_t s = 0;
     for (const DevBuf *b : bufs) s += b->bytes;
     *bytes = s;

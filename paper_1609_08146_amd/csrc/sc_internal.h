@@ -39,8 +39,15 @@ hipError_t launch_power_gaussian(hipStream_t st, int n_k, int n_surf, const doub
                                  const double *nrm, const double *wgt, int beam, double w0, double pol,
                                  const double *spectrum, int consistent, double *part, double *P);
 int power_partial_count(int n_k);
-// tab[k][node] *= fac[k] (complex128 [n_k]); exactly one of tab64, tab32 non-null
-hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, const double *fac, double *tab64, float *tab32);
+// tab[k][node] *= fac[k] (complex128 [n_k]) for the n_cplx complex numbers of each record (4 general,
+// 2 factored); exactly one of tab64, tab32 non-null
+hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, int n_cplx, const double *fac, double *tab64,
+                               float *tab32);
+// Factored FP32 tables (Jt = u s per node): tabf [n_k][n_tot][4] = (s, rho_t), posf [n_tot][8] =
+// (x, y, z, |r_s|, u, 0); *bad (zeroed by the caller) is set when some node's current has no single
+// real direction within tol (relative to its largest |Jt| over k).
+hipError_t launch_tables_factor(hipStream_t st, int n_k, int n_tot, const double *tab64, const float *pos32,
+                                double tol, float *tabf, float *posf, unsigned int *bad);
 // Maxwell-residual diagnostics (sc_diag.hip).  Stencil results [rows][13 n_pts][3] complex (double
 // if is_f64, else float); work holds diag_slots() doubles per (row, point), mx 4 per row, out 1 per
 // (row, point).  The time form reads [n_t * 5][13 n_pts][3] (times t_m + (j - 2) dt).

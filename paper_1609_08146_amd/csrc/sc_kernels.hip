@@ -6,6 +6,8 @@
 //  k_tables_gaussian     same for the built-in collimated beams: linearly, radially or
 //                        azimuthally polarised Gaussian (Sec. III-A, IV-A)
 //  k_tables_cast         FP64 tables -> FP32 (split: as is; naive: node phase removed)
+//  k_tables_factor       FP64 tables -> factored FP32 tables J~ = u s, when the current
+//                        of every node keeps one real direction over the frequencies
 //  k_power_*             incident power per frequency through the aperture (Sec. III-B)
 //  k_tables_scale        spectral amplitude / phase applied to the tables (Sec. III-B)
 //  k_reduce<MODE>        deterministic split-K reduction into E, B
@@ -380,22 +382,24 @@ __global__ void k_power_finish(int n_k, const double *__restrict__ part, double 
 
 // Multiply every record of frequency k by the complex factor fac[k] (spectral
 // amplitude and phase, Sec. III-B); tab64 in FP64, or tab32 (FP32 storage).
-__global__ void k_tables_scale(int n_k, int n_tot, const double *__restrict__ fac, double *__restrict__ tab64,
-                               float *__restrict__ tab32)
+// n_cplx complex numbers per (k, node) record: 4 for the general tables, 2 for the factored ones (s, rho_t).
+__global__ void k_tables_scale(int n_k, int n_tot, int n_cplx, const double *__restrict__ fac,
+                               double *__restrict__ tab64, float *__restrict__ tab32)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n_k * n_tot) return;
     const int kk = (int)(idx / n_tot);
     const c64 f = {fac[2 * kk], fac[2 * kk + 1]};
-    for (int c = 0; c < 4; ++c) {
+    const int64_t base = idx * 2 * n_cplx;
+    for (int c = 0; c < n_cplx; ++c) {
         if (tab64) {
-            const c64 v = cmul({tab64[idx * 8 + 2 * c], tab64[idx * 8 + 2 * c + 1]}, f);
-            tab64[idx * 8 + 2 * c] = v.re;
-            tab64[idx * 8 + 2 * c + 1] = v.im;
+            const c64 v = cmul({tab64[base + 2 * c], tab64[base + 2 * c + 1]}, f);
+            tab64[base + 2 * c] = v.re;
+            tab64[base + 2 * c + 1] = v.im;
         } else {
-            const c64 v = cmul({(double)tab32[idx * 8 + 2 * c], (double)tab32[idx * 8 + 2 * c + 1]}, f);
-            tab32[idx * 8 + 2 * c] = (float)v.re;
-            tab32[idx * 8 + 2 * c + 1] = (float)v.im;
+            const c64 v = cmul({(double)tab32[base + 2 * c], (double)tab32[base + 2 * c + 1]}, f);
+            tab32[base + 2 * c] = (float)v.re;
+            tab32[base + 2 * c + 1] = (float)v.im;
         }
     }
 }
@@ -426,6 +430,68 @@ __global__ void k_tables_cast(int n_k, int n_tot, const double *__restrict__ kv,
         dst[2 * c] = (float)w.re;
         dst[2 * c + 1] = (float)w.im;
     }
+}
+
+// Factored tables.  The surface current of the integrand (Sec. II: J = n x B,
+// folded into Jt with the weights and the node phase) often keeps one real
+// direction at every frequency (e.g. a linearly polarised Gaussian with any
+// spectrum, or a radially or azimuthally polarised beam): then
+// Jt[k][q] = u_q s[k][q] and the quadrature can use u_q and s.  One thread per
+// node q: u_q is the unit vector along the longer of Re Jt, Im Jt at the
+// frequency where |Jt[k][q]| is largest (u_q = 0 if Jt vanishes), s = u_q . Jt;
+// if |Jt[k][q] - u_q s[k][q]| > tol max_k |Jt[k][q]| for any k, *bad is set and
+// the tables must not be used.  Outputs (FP32): tabf[k][q] = (s, rho_t) and
+// posf[q] = (x, y, z, |r_s|, u_q, 0).
+__global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ tab64, const float *__restrict__ pos32,
+                                double tol, float *__restrict__ tabf, float *__restrict__ posf,
+                                unsigned int *__restrict__ bad)
+{
+    const int64_t gq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gq >= n_tot) return;
+    double best = 0.0;
+    int kb = 0;
+    for (int kk = 0; kk < n_k; ++kk) {
+        const double *v = tab64 + ((int64_t)kk * n_tot + gq) * 8;
+        double m = 0.0;
+        for (int c = 0; c < 6; ++c) m += v[c] * v[c];
+        if (m > best) {
+            best = m;
+            kb = kk;
+        }
+    }
+    double u[3] = {0.0, 0.0, 0.0};
+    if (best > 0.0) {
+        const double *v = tab64 + ((int64_t)kb * n_tot + gq) * 8;
+        const double re2 = v[0] * v[0] + v[2] * v[2] + v[4] * v[4];
+        const double im2 = v[1] * v[1] + v[3] * v[3] + v[5] * v[5];
+        const int part = re2 >= im2 ? 0 : 1;
+        const double inv = 1.0 / sqrt(part ? im2 : re2);
+        for (int c = 0; c < 3; ++c) u[c] = v[2 * c + part] * inv;
+    }
+    const double lim = tol * tol * best;
+    bool ok = true;
+    for (int kk = 0; kk < n_k; ++kk) {
+        const int64_t rec = (int64_t)kk * n_tot + gq;
+        const double *v = tab64 + rec * 8;
+        const double sr = u[0] * v[0] + u[1] * v[2] + u[2] * v[4];
+        const double si = u[0] * v[1] + u[1] * v[3] + u[2] * v[5];
+        double r2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double dr = v[2 * c] - u[c] * sr, di = v[2 * c + 1] - u[c] * si;
+            r2 += dr * dr + di * di;
+        }
+        if (!(r2 <= lim)) ok = false;
+        float *t = tabf + rec * 4;
+        t[0] = (float)sr;
+        t[1] = (float)si;
+        t[2] = (float)v[6];
+        t[3] = (float)v[7];
+    }
+    float *pr = posf + gq * 8;
+    for (int c = 0; c < 4; ++c) pr[c] = pos32[gq * 4 + c];
+    for (int c = 0; c < 3; ++c) pr[4 + c] = (float)u[c];
+    pr[7] = 0.0f;
+    if (!ok) atomicOr(bad, 1u);
 }
 
 // Split-K reduction: E[k][o][c] = sum over chunks (in FP64, fixed order); B gets the 1/(ik) factor.
@@ -580,10 +646,19 @@ hipError_t launch_power_gaussian(hipStream_t st, int n_k, int n_surf, const doub
 
 int power_partial_count(int n_k) { return POWER_BLOCKS * n_k; }
 
-hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, const double *fac, double *tab64, float *tab32)
+hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, int n_cplx, const double *fac, double *tab64,
+                               float *tab32)
 {
-    hipLaunchKernelGGL(k_tables_scale, dim3(nblocks((int64_t)n_k * n_tot, 256)), dim3(256), 0, st, n_k, n_tot, fac,
-                       tab64, tab32);
+    hipLaunchKernelGGL(k_tables_scale, dim3(nblocks((int64_t)n_k * n_tot, 256)), dim3(256), 0, st, n_k, n_tot,
+                       n_cplx, fac, tab64, tab32);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables_factor(hipStream_t st, int n_k, int n_tot, const double *tab64, const float *pos32,
+                                double tol, float *tabf, float *posf, unsigned int *bad)
+{
+    hipLaunchKernelGGL(k_tables_factor, dim3(nblocks(n_tot, 256)), dim3(256), 0, st, n_k, n_tot, tab64, pos32, tol,
+                       tabf, posf, bad);
     return hipGetLastError();
 }
 

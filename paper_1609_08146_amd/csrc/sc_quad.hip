@@ -2,7 +2,10 @@
 // path on gfx950: k_quad<MODE,OPL,FPB>, persistent over (job, frequency block,
 // node chunk, observation block) tiles, and its launcher.
 //
-//   MODE_SPLIT  per-pair FP32 with the node phase folded into the tables
+//   MODE_SPLIT  per-pair FP32 with the node phase folded into the tables;
+//               per job either general tables or the factored current
+//               J~ = u s (a real direction u per node, a complex s per
+//               frequency and node), which needs fewer operations per pair
 //   MODE_FP64   the same split form in FP64
 //   MODE_NAIVE  the whole phase k|R| per pair in FP32 (the precision ablation)
 //
@@ -108,6 +111,50 @@ __device__ __forceinline__ void freq_split(const GeomF &g, const v4f t0, const v
     accumulate_f32(g.dx, g.dy, g.dz, g.rinv, c, s, t0, t1, k, acc);
 }
 
+// Factored current, one frequency.  When the surface current of a node has a
+// real direction u for every frequency, J~ = u s, the two J~ terms factor:
+//   J~ gt = u (s gt),   (J~ ht) x R = (s ht) (u x R),
+// and w = u x R is shared by the frequencies of a lane.  t = (s, rho_t) as
+// (re, im) pairs; u = (ux, uy, uz, 0).  acc as in accumulate_f32.
+__device__ __forceinline__ void freq_factored(const GeomF &g, float wx, float wy, float wz, const v4f u, const v4f t,
+                                              float k, float kt, float *acc)
+{
+    float s, c;
+    sincos_turns(kt * g.delta, s, c);
+    const float rinv = g.rinv;
+    const float gr = c * rinv, gi = s * rinv;
+    const float a = -(rinv * rinv), b = k * rinv;
+    const float hr = __fmaf_rn(gr, a, -(gi * b));
+    const float hi = __fmaf_rn(gr, b, gi * a);
+    // E += u (s gt)
+    const float sgr = __fmaf_rn(t.x, gr, -(t.y * gi));
+    const float sgi = __fmaf_rn(t.x, gi, t.y * gr);
+    acc[0] = __fmaf_rn(u.x, sgr, acc[0]);
+    acc[1] = __fmaf_rn(u.x, sgi, acc[1]);
+    acc[2] = __fmaf_rn(u.y, sgr, acc[2]);
+    acc[3] = __fmaf_rn(u.y, sgi, acc[3]);
+    acc[4] = __fmaf_rn(u.z, sgr, acc[4]);
+    acc[5] = __fmaf_rn(u.z, sgi, acc[5]);
+    // E += rho_t ht R
+    const float tr = __fmaf_rn(t.z, hr, -(t.w * hi));
+    const float ti = __fmaf_rn(t.z, hi, t.w * hr);
+    acc[0] = __fmaf_rn(tr, g.dx, acc[0]);
+    acc[1] = __fmaf_rn(ti, g.dx, acc[1]);
+    acc[2] = __fmaf_rn(tr, g.dy, acc[2]);
+    acc[3] = __fmaf_rn(ti, g.dy, acc[3]);
+    acc[4] = __fmaf_rn(tr, g.dz, acc[4]);
+    acc[5] = __fmaf_rn(ti, g.dz, acc[5]);
+    // B += (s ht) w
+    const float qr = __fmaf_rn(t.x, hr, -(t.y * hi));
+    const float qi = __fmaf_rn(t.x, hi, t.y * hr);
+    acc[6] = __fmaf_rn(wx, qr, acc[6]);
+    acc[7] = __fmaf_rn(wx, qi, acc[7]);
+    acc[8] = __fmaf_rn(wy, qr, acc[8]);
+    acc[9] = __fmaf_rn(wy, qi, acc[9]);
+    acc[10] = __fmaf_rn(wz, qr, acc[10]);
+    acc[11] = __fmaf_rn(wz, qi, acc[11]);
+}
+
 // Naive FP32 form, one frequency: the whole phase k |R| in FP32 (the table carries no node phase).
 __device__ __forceinline__ void freq_naive(const GeomF &g, float R, const v4f t0, const v4f t1, float k, float *acc)
 {
@@ -194,6 +241,129 @@ __device__ __forceinline__ int find_job(cjob *jobs, int n_jobs, int64_t t)
 }
 
 constexpr int KAHAN_BLOCK = 32;   // nodes summed plainly before each compensated add (FP32)
+
+// One tile of the FP32 forms: nodes [n0, n1) of a chunk, 64*OPL points, FPB
+// frequencies.  FACT selects the factored layout: node records of two v4f
+// (x, y, z, |r_s|), (u, 0) and one v4f (s, rho_t) per table record, instead of
+// one v4f node record and two v4f (Jt.x, Jt.y), (Jt.z, rho_t) per table record.
+template <int MODE, int OPL, int FPB, bool FACT>
+__device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
+                                         const double *k64, int n_valid)
+{
+    constexpr int PS = FACT ? 2 : 1;   // v4f per node record
+    constexpr int TS = FACT ? 1 : 2;   // v4f per table record
+    const int n_tot = job->n_tot, n_k = job->n_k, n_obs_pad = job->n_obs_pad;
+    cv4f *pos = (cv4f *)job->pos;
+    cv4f *tab[FPB];
+    float k[FPB], kt[FPB];
+#pragma unroll
+    for (int f = 0; f < FPB; ++f) {
+        tab[f] = (cv4f *)job->tab + (size_t)kidx[f] * n_tot * TS;
+        k[f] = (float)k64[f];
+        kt[f] = (float)(k64[f] * INV_TWO_PI);
+    }
+    const v4f *obs = (const v4f *)job->obs;
+    v4f o[OPL];
+    // Running sums stay in registers; their Kahan compensations live in LDS
+    // (touched once per KAHAN_BLOCK nodes), which frees VGPRs for occupancy.
+    // dynamic LDS: [waves per block][OPL * FPB * 12][64] floats
+    extern __shared__ float lds_dyn[];
+    float(*cmp)[64] = (float(*)[64])(lds_dyn + (size_t)(threadIdx.x >> 6) * (OPL * FPB * 12 * 64));
+    float sum[OPL][FPB][12];
+#pragma unroll
+    for (int s = 0; s < OPL; ++s) {
+        o[s] = obs[obase + 64 * s];
+#pragma unroll
+        for (int f = 0; f < FPB; ++f)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) sum[s][f][c] = 0.0f;
+    }
+#pragma unroll
+    for (int a = 0; a < OPL * FPB * 12; ++a) cmp[a][lane] = 0.0f;
+    float blk[OPL][FPB][12];
+#pragma unroll
+    for (int s = 0; s < OPL; ++s)
+#pragma unroll
+        for (int f = 0; f < FPB; ++f)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) blk[s][f][c] = 0.0f;
+    // node data of node n+1 is loaded while node n is computed
+    v4f pn = pos[PS * n0], un = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (FACT) un = pos[PS * n0 + 1];
+    v4f t0[FPB], t1[FPB];
+#pragma unroll
+    for (int f = 0; f < FPB; ++f) {
+        t0[f] = tab[f][TS * n0];
+        if constexpr (!FACT) t1[f] = tab[f][TS * n0 + 1];
+    }
+    for (int n = n0; n < n1; ++n) {
+        const int nx = min(n + 1, n1 - 1);
+        const v4f pnx = pos[PS * nx];
+        v4f unx = un;
+        if constexpr (FACT) unx = pos[PS * nx + 1];
+        v4f t0x[FPB], t1x[FPB];
+#pragma unroll
+        for (int f = 0; f < FPB; ++f) {
+            t0x[f] = tab[f][TS * nx];
+            if constexpr (!FACT) t1x[f] = tab[f][TS * nx + 1];
+        }
+#pragma unroll
+        for (int s = 0; s < OPL; ++s) {
+            if constexpr (MODE == MODE_SPLIT && FACT) {
+                const GeomF g = geom_split(pn, o[s]);
+                // w = u x R, shared by the frequencies
+                const float wx = __fmaf_rn(un.y, g.dz, -(un.z * g.dy));
+                const float wy = __fmaf_rn(un.z, g.dx, -(un.x * g.dz));
+                const float wz = __fmaf_rn(un.x, g.dy, -(un.y * g.dx));
+#pragma unroll
+                for (int f = 0; f < FPB; ++f) freq_factored(g, wx, wy, wz, un, t0[f], k[f], kt[f], blk[s][f]);
+            } else if constexpr (MODE == MODE_SPLIT) {
+                const GeomF g = geom_split(pn, o[s]);
+#pragma unroll
+                for (int f = 0; f < FPB; ++f) freq_split(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
+            } else {
+                GeomF g;
+                float R;
+                geom_naive(pn, o[s], g, R);
+#pragma unroll
+                for (int f = 0; f < FPB; ++f) freq_naive(g, R, t0[f], t1[f], k[f], blk[s][f]);
+            }
+        }
+        // every KAHAN_BLOCK nodes (counted from the chunk start), a compensated add
+        if ((n - n0) % KAHAN_BLOCK == KAHAN_BLOCK - 1 || n == n1 - 1) {
+#pragma unroll
+            for (int s = 0; s < OPL; ++s)
+#pragma unroll
+                for (int f = 0; f < FPB; ++f)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        const int a = (s * FPB + f) * 12 + c;
+                        const float y = blk[s][f][c] - cmp[a][lane];
+                        const float tsum = sum[s][f][c] + y;
+                        cmp[a][lane] = (tsum - sum[s][f][c]) - y;
+                        sum[s][f][c] = tsum;
+                        blk[s][f][c] = 0.0f;
+                    }
+        }
+        pn = pnx;
+        un = unx;
+#pragma unroll
+        for (int f = 0; f < FPB; ++f) {
+            t0[f] = t0x[f];
+            if constexpr (!FACT) t1[f] = t1x[f];
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < FPB; ++f) {
+        if (f >= n_valid) break;
+        float *part = (float *)job->partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
+#pragma unroll
+        for (int s = 0; s < OPL; ++s)
+#pragma unroll
+            for (int c = 0; c < 12; ++c)
+                part[(size_t)c * n_obs_pad + obase + 64 * s] = sum[s][f][c] - cmp[(s * FPB + f) * 12 + c][lane];
+    }
+}
 
 // Persistent quadrature kernel.  Every wave repeatedly takes the next tile
 // (one node chunk, 64*OPL observation points, FPB consecutive frequencies)
@@ -288,105 +458,13 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
 #pragma unroll
                     for (int c = 0; c < 12; ++c) part[(size_t)c * n_obs_pad + obase + 64 * s] = acc[s][f][c];
             }
+        } else if constexpr (MODE == MODE_SPLIT) {
+            if (jobs[j].factored)
+                tile_f32<MODE, OPL, FPB, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+            else
+                tile_f32<MODE, OPL, FPB, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
         } else {
-            cv4f *pos = (cv4f *)jobs[j].pos;
-            cv4f *tab[FPB];
-            float k[FPB], kt[FPB];
-#pragma unroll
-            for (int f = 0; f < FPB; ++f) {
-                tab[f] = (cv4f *)jobs[j].tab + (size_t)kidx[f] * n_tot * 2;
-                k[f] = (float)k64[f];
-                kt[f] = (float)(k64[f] * INV_TWO_PI);
-            }
-            const v4f *obs = (const v4f *)jobs[j].obs;
-            v4f o[OPL];
-            // Running sums stay in registers; their Kahan compensations live in LDS
-            // (touched once per KAHAN_BLOCK nodes), which frees VGPRs for occupancy.
-            // dynamic LDS: [waves per block][OPL * FPB * 12][64] floats
-            extern __shared__ float lds_dyn[];
-            float(*cmp)[64] = (float(*)[64])(lds_dyn + (size_t)(threadIdx.x >> 6) * (OPL * FPB * 12 * 64));
-            float sum[OPL][FPB][12];
-#pragma unroll
-            for (int s = 0; s < OPL; ++s) {
-                o[s] = obs[obase + 64 * s];
-#pragma unroll
-                for (int f = 0; f < FPB; ++f)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) sum[s][f][c] = 0.0f;
-            }
-#pragma unroll
-            for (int a = 0; a < OPL * FPB * 12; ++a) cmp[a][lane] = 0.0f;
-            float blk[OPL][FPB][12];
-#pragma unroll
-            for (int s = 0; s < OPL; ++s)
-#pragma unroll
-                for (int f = 0; f < FPB; ++f)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) blk[s][f][c] = 0.0f;
-            // node data of node n+1 is loaded while node n is computed
-            v4f pn = pos[n0];
-            v4f t0[FPB], t1[FPB];
-#pragma unroll
-            for (int f = 0; f < FPB; ++f) {
-                t0[f] = tab[f][2 * n0];
-                t1[f] = tab[f][2 * n0 + 1];
-            }
-            for (int n = n0; n < n1; ++n) {
-                const int nx = min(n + 1, n1 - 1);
-                const v4f pnx = pos[nx];
-                v4f t0x[FPB], t1x[FPB];
-#pragma unroll
-                for (int f = 0; f < FPB; ++f) {
-                    t0x[f] = tab[f][2 * nx];
-                    t1x[f] = tab[f][2 * nx + 1];
-                }
-#pragma unroll
-                for (int s = 0; s < OPL; ++s) {
-                    if constexpr (MODE == MODE_SPLIT) {
-                        const GeomF g = geom_split(pn, o[s]);
-#pragma unroll
-                        for (int f = 0; f < FPB; ++f) freq_split(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
-                    } else {
-                        GeomF g;
-                        float R;
-                        geom_naive(pn, o[s], g, R);
-#pragma unroll
-                        for (int f = 0; f < FPB; ++f) freq_naive(g, R, t0[f], t1[f], k[f], blk[s][f]);
-                    }
-                }
-                // every KAHAN_BLOCK nodes (counted from the chunk start), a compensated add
-                if ((n - n0) % KAHAN_BLOCK == KAHAN_BLOCK - 1 || n == n1 - 1) {
-#pragma unroll
-                    for (int s = 0; s < OPL; ++s)
-#pragma unroll
-                        for (int f = 0; f < FPB; ++f)
-#pragma unroll
-                            for (int c = 0; c < 12; ++c) {
-                                const int a = (s * FPB + f) * 12 + c;
-                                const float y = blk[s][f][c] - cmp[a][lane];
-                                const float tsum = sum[s][f][c] + y;
-                                cmp[a][lane] = (tsum - sum[s][f][c]) - y;
-                                sum[s][f][c] = tsum;
-                                blk[s][f][c] = 0.0f;
-                            }
-                }
-                pn = pnx;
-#pragma unroll
-                for (int f = 0; f < FPB; ++f) {
-                    t0[f] = t0x[f];
-                    t1[f] = t1x[f];
-                }
-            }
-#pragma unroll
-            for (int f = 0; f < FPB; ++f) {
-                if (f >= n_valid) break;
-                float *part = (float *)jobs[j].partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
-#pragma unroll
-                for (int s = 0; s < OPL; ++s)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c)
-                        part[(size_t)c * n_obs_pad + obase + 64 * s] = sum[s][f][c] - cmp[(s * FPB + f) * 12 + c][lane];
-            }
+            tile_f32<MODE, OPL, FPB, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
         }
     }
 }

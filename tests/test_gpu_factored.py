@@ -1,0 +1,171 @@
+"""GPU: the factored current of the split form (Jt = u s with a real direction u per node).
+
+The factored and the general FP32 split paths compute the same sums with a
+different sequence of FP32 operations, so both are held to the oracle at the
+split tolerance (1e-5 relative L2 per field) and to each other at 2e-6.
+
+Which incident fields factor is fixed by the physics, so the detection is
+tested against it: the surface current n x B (n = (-x/2f, -y/2f, 1) on the
+paraboloid) must keep one real direction per node at every frequency.  It
+does for the literal linearly polarised beam and the plane wave (B along a
+fixed transverse axis, any spectrum), for both radially polarised variants
+(B = (y, -x, 0) g is transverse; only E gains the longitudinal term) and for
+both azimuthally polarised ones: B = (x, y, c) g gives
+n x B = (1 + c/2f) (-y, x, 0) g, azimuthal whatever the longitudinal c.
+The curl-consistent linear beam does not: its B_z = -2iy/(k w0^2) psi adds
+(-y c/2f, x c/2f, 0) to n x (0, -1, 0) psi = (1, 0, x/2f) psi, a direction
+that changes with k.  Random tables have no structure either.
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_08146_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("beam,consistent,w0,expect", [
+    (0, 0, 0.05, True), (0, 0, np.inf, True), (0, 1, 0.05, False),
+    (1, 0, 0.05, True), (1, 1, 0.05, True), (2, 0, 0.05, True), (2, 1, 0.05, True)])
+def test_which_fields_factor(ctx, beam, consistent, w0, expect):
+    from paper_1609_08146_amd import Problem
+    rng = np.random.default_rng(11)
+    k = 7.854e6 * np.array([0.8, 1.0, 1.25])
+    spec = rng.normal(size=3) + 1j * rng.normal(size=3)     # any complex spectrum keeps the direction
+    p = Problem(ctx)
+    p.set_mirror(0.1, 0.075, 24, 16)
+    p.set_frequencies(k)
+    p.set_incident_beam(beam, w0, 0.3 if beam == 0 else 0.0, spec, bool(consistent))
+    p.set_observation(np.zeros((1, 3)))
+    assert p.factored is expect
+    p.set_factoring(False)
+    assert p.factored is False
+    p.set_factoring(True)
+    assert p.factored is expect
+    p.close()
+
+
+def test_random_tables_do_not_factor(ctx):
+    from paper_1609_08146_amd import Problem
+    p = Problem(ctx)
+    p.set_mirror(20.0, 40.0, 12, 8)
+    p.set_frequencies([6.0, 7.0])
+    Ei, Bi = workloads.random_incident_tables(2, 13 * 8, seed=3)
+    p.set_incident(Ei, Bi)
+    assert p.factored is False
+    p.close()
+
+
+@pytest.mark.parametrize("name", ["broadband", "stress"])
+def test_factored_and_general_match_the_oracle(ctx, orc, name):
+    from paper_1609_08146_amd import problem_from_workload
+    if name == "broadband":
+        w = workloads.broadband(n_k=128, n_nodes=120)
+        sub = w.subset(obs_idx=np.arange(0, w.n_obs, 29), k_idx=np.arange(0, 128, 21))
+    else:                                   # kR up to 1.6e6 rad
+        w = workloads.stress(n_k=64, n_nodes=200)
+        sub = w.subset(obs_idx=np.arange(0, w.n_obs, 1023), k_idx=[0, 31, 63])
+    Eo, Bo = orc.solve(sub)
+    p = problem_from_workload(ctx, sub)
+    assert p.factored
+    Ef, Bf = p.evaluate("fp32_split")
+    p.set_factoring(False)
+    assert not p.factored
+    Eg, Bg = p.evaluate("fp32_split")
+    errs = dict(factored=max(rel_l2(Ef, Eo), rel_l2(Bf, Bo)), general=max(rel_l2(Eg, Eo), rel_l2(Bg, Bo)),
+                between=max(rel_l2(Ef, Eg), rel_l2(Bf, Bg)))
+    print(name, {k: f"{v:.2e}" for k, v in errs.items()})
+    assert errs["factored"] < 1e-5 and errs["general"] < 1e-5
+    assert errs["between"] < 2e-6
+    p.close()
+
+
+@pytest.mark.parametrize("beam,consistent", [(1, 0), (1, 1), (2, 0), (2, 1)])
+def test_factored_cylindrical_beams_match_the_oracle(ctx, orc, beam, consistent):
+    from paper_1609_08146_amd import problem_from_workload
+    kind = {(1, 0): orc.RADIAL, (1, 1): orc.RADIAL_CONSISTENT, (2, 0): orc.AZIMUTHAL,
+            (2, 1): orc.AZIMUTHAL_CONSISTENT}[(beam, consistent)]
+    w = replace(workloads.broadband(n_k=6, n_nodes=90).subset(obs_idx=np.arange(0, 4160, 41)),
+                beam=beam, consistent=consistent, w0=0.03)
+    m = orc.mirror(w.f, w.a, w.n_r, w.n_phi)
+    Ei, Bi = orc.incident_tables(m, w.k, kind, w.w0, 0.0, w.spectrum)
+    Eo, Bo = orc.reflected_field(m, w.k, Ei, Bi, w.obs)
+    p = problem_from_workload(ctx, w)
+    assert p.factored
+    E, B = p.evaluate("fp32_split")
+    err = max(rel_l2(E, Eo), rel_l2(B, Bo))
+    print(f"beam {beam} consistent {consistent} factored: {err:.2e}")
+    assert err < 1e-5
+    p.close()
+
+
+def test_factored_launch_shapes_and_batch_bitwise(ctx):
+    """Launch shape never changes the bits of either path, and one persistent launch may mix
+    factored and general problems: each keeps the bits it has alone."""
+    from paper_1609_08146_amd import problem_from_workload
+    w = workloads.broadband(n_k=5, n_nodes=64)
+    p = problem_from_workload(ctx, w)
+    for fact in (True, False):
+        p.set_factoring(fact)
+        assert p.factored is fact
+        ref = None
+        for opl, fpb in [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4)]:
+            for wpb in (1, 4):
+                p.set_launch(obs_per_lane=opl, freq_per_lane=fpb, waves_per_block=wpb, chunk=1024)
+                E, B = p.evaluate("fp32_split")
+                if ref is None:
+                    ref = (E, B)
+                else:
+                    assert np.array_equal(E, ref[0]) and np.array_equal(B, ref[1]), (fact, opl, fpb, wpb)
+    p.close()
+    ws = workloads.sweep(6)
+    ws = [w.with_nodes(min(w.n_r, 80), min(w.n_phi, 48)).subset(k_idx=np.arange(min(w.n_k, 3))) for w in ws]
+    ws[1] = replace(ws[1], consistent=1)          # does not factor
+    probs = [problem_from_workload(ctx, w) for w in ws]
+    probs[2].set_factoring(False)                 # factors, but forced onto the general tables
+    assert [q.factored for q in probs] == [True, False, False, True, True, True]
+    alone = [q.evaluate("fp32_split") for q in probs]
+    ctx.evaluate_batch(probs, "fp32_split")
+    for q, (E, B) in zip(probs, alone):
+        Eb, Bb = q.result()
+        assert np.array_equal(E, Eb) and np.array_equal(B, Bb)
+    for q in probs:
+        q.close()
+
+
+def test_spectrum_scaling_on_fp32_only_factored_tables(ctx, orc):
+    """With the FP64 tables released, a spectral phase (chirp) and amplitude scale the factored
+    FP32 tables in place; the field equals that of the scaled spectrum set directly."""
+    from paper_1609_08146_amd import problem_from_workload
+    w = workloads.broadband(n_k=8, n_nodes=80).subset(obs_idx=np.arange(0, 4160, 37))
+    phase = 40.0 * ((w.k - w.k.mean()) / (w.k.max() - w.k.min())) ** 2
+    fac = 0.5 * np.exp(1j * phase)
+    q = problem_from_workload(ctx, w)
+    q.set_table_storage(False)
+    q.set_incident_gaussian(w.w0, w.pol, w.spectrum, False)
+    assert q.factored
+    q.scale_spectrum(fac)
+    E1, B1 = q.evaluate("fp32_split")
+    w2 = replace(w, spectrum=w.spectrum * fac)
+    Eo, Bo = orc.solve(w2)
+    err = max(rel_l2(E1, Eo), rel_l2(B1, Bo))
+    print(f"scaled factored FP32-only tables vs oracle: {err:.2e}")
+    assert err < 1e-5
+    q.close()
