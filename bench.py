@@ -104,6 +104,8 @@ def parse():
     ap.add_argument("--precision", default="fp32_split", choices=["fp32_split", "fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
+    ap.add_argument("--general-tables", action="store_true",
+                    help="step: never use the factored current (time the general-table layout)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "copy", "table1", "valu"],
                     help="step: the hot path on the broadband workload (default); batch: the seeded sweep of "
@@ -157,9 +159,10 @@ def cpu_baseline(w, target_s):
     import oracle
     oracle.build()
     threads = oracle.max_threads()
-    # calibrate on a tiny sample, then size the sample to ~target_s of work
+    # calibrate on a small sample (long enough that thread start-up does not dominate), then size
+    # the sample to ~target_s of work
     n_probe = max(threads, 16)
-    probe = w.subset(obs_idx=np.linspace(0, w.n_obs - 1, n_probe).astype(int), k_idx=[0])
+    probe = w.subset(obs_idx=np.linspace(0, w.n_obs - 1, n_probe).astype(int), k_idx=np.arange(min(4, w.n_k)))
     t0 = time.perf_counter()
     oracle.solve(probe)
     rate = probe.evals / (time.perf_counter() - t0)
@@ -403,15 +406,16 @@ def main():
     ctx = Context(0)
     ctx.set_profiling(True)
 
+    factoring = not args.general_tables
     for _ in range(args.warmup):
-        run_step(ctx, w, args.precision).close()
+        run_step(ctx, w, args.precision, factoring).close()
     torch.cuda.synchronize()
 
     quad_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        p = run_step(ctx, w, args.precision)
+        p = run_step(ctx, w, args.precision, factoring)
         torch.cuda.synchronize()
         tm = p.timing()
         quad_ms.append(tm["quad_ms"])
