@@ -364,6 +364,7 @@ typedef struct {
     int64_t evals_done;       /* evaluations of completed requests            */
     int64_t evals_launched;   /* evaluations in the launched quanta           */
     double quad_ms;           /* device time of the completed quanta (events) */
+    double prep_ms;           /* host time spent building requests' tables    */
 } sc_server_stats;
 
 /* Start a serving loop on `ctx`: requests are admitted while their HBM
@@ -378,7 +379,9 @@ sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_running, doub
 sc_status sc_server_submit(sc_server *s, const sc_request *req, uint64_t *ticket);
 /* Wait up to timeout_ms (< 0: forever) for a result.  E, B: host arrays
  * [n_k][n_obs][3] (complex128 for SC_FP64, complex64 otherwise); Et, Bt:
- * [n_t][n_obs][3] or NULL.  The ticket is released on SC_OK/SC_E_CANCELLED. */
+ * [n_t][n_obs][3] or NULL.  The ticket is released unless the wait timed
+ * out (SC_E_TIMEOUT).  Any number of threads may wait on different tickets;
+ * all waits must have returned before sc_server_destroy.                   */
 sc_status sc_server_wait(sc_server *s, uint64_t ticket, double timeout_ms, void *E, void *B,
                          void *Et, void *Bt, sc_request_stats *stats);
 /* Cancel a queued request (running requests finish normally).              */

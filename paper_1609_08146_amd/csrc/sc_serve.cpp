@@ -17,6 +17,13 @@
 // Every (chunk, k, observation block) partial of a request is computed by
 // exactly one tile with the same kernel and chunking as sc_evaluate uses, so
 // a request's result does not depend on what it was batched with.
+//
+// Nothing slow runs under the server lock or on the scheduling path: result
+// buffers in pinned host memory come from a pool (pinning memory costs far
+// more than the small requests' compute), the copies to them run on their own
+// stream behind the quantum that finished the request, finished problems are
+// released by the preparation thread, and waiters copy results out after
+// dropping the lock.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -52,9 +59,12 @@ struct Req {
     sc_prob *prob = nullptr;
     QuadJob job{};
     int64_t cursor = 0;
-    hipEvent_t ready_ev = nullptr;
-    hipEvent_t done_ev = nullptr;
-    void *hE = nullptr, *hB = nullptr, *hEt = nullptr, *hBt = nullptr;
+    hipEvent_t ready_ev = nullptr;   // tables built (preparation stream)
+    hipEvent_t fin_ev = nullptr;     // last kernel of the request done (compute stream)
+    hipEvent_t done_ev = nullptr;    // results in host memory (copy stream)
+    void *hE = nullptr, *hB = nullptr, *hEt = nullptr, *hBt = nullptr;   // views into host_block
+    void *host_block = nullptr;
+    size_t host_block_bytes = 0;
     size_t res_bytes = 0, time_bytes = 0;
     Clock::time_point t_submit, t_admit, t_done;
     int64_t evals = 0;
@@ -71,6 +81,61 @@ double ms_between(Clock::time_point a, Clock::time_point b)
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
+// Pinned host blocks for results, reused across requests.  Sizes are rounded
+// up to powers of two (at least 1 MiB); up to CACHE_BYTES of free blocks are
+// kept, larger surpluses are unpinned.
+struct PinnedPool {
+    static constexpr size_t MIN_BLOCK = size_t(1) << 20;
+    static constexpr size_t CACHE_BYTES = size_t(16) << 30;
+    std::mutex mu;
+    std::multimap<size_t, void *> free_blocks;
+    size_t cached = 0;
+
+    static size_t bucket(size_t n)
+    {
+        size_t b = MIN_BLOCK;
+        while (b < n) b <<= 1;
+        return b;
+    }
+    hipError_t get(size_t n, void **p, size_t *got)
+    {
+        const size_t b = bucket(n);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = free_blocks.find(b);
+            if (it != free_blocks.end()) {
+                *p = it->second;
+                *got = b;
+                free_blocks.erase(it);
+                cached -= b;
+                return hipSuccess;
+            }
+        }
+        *got = b;
+        return hipHostMalloc(p, b, hipHostMallocDefault);
+    }
+    void put(void *p, size_t b)
+    {
+        if (!p) return;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (cached + b <= CACHE_BYTES) {
+                free_blocks.emplace(b, p);
+                cached += b;
+                return;
+            }
+        }
+        (void)hipHostFree(p);
+    }
+    void clear()
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &kv : free_blocks) (void)hipHostFree(kv.second);
+        free_blocks.clear();
+        cached = 0;
+    }
+};
+
 }  // namespace
 
 struct sc_server {
@@ -85,7 +150,10 @@ struct sc_server {
     std::condition_variable cv_work, cv_done, cv_prep;
     bool stop = false;
     std::deque<Req *> to_prepare;   // admitted, tables not built yet
+    std::vector<sc_prob *> to_release;   // finished problems, released by the preparation thread
     int preparing = 0;
+    hipStream_t copy_stream = nullptr;   // device-to-host copies of results
+    PinnedPool pinned;
     uint64_t next_ticket = 1;
     std::deque<Req *> queue;
     std::vector<Req *> active;
@@ -104,16 +172,16 @@ struct sc_server {
     std::string worker_error;
 };
 
-static void free_req_host(Req *r)
+static void free_req_host(sc_server *s, Req *r)
 {
-    for (void **p : {&r->hE, &r->hB, &r->hEt, &r->hBt})
-        if (*p) {
-            (void)hipHostFree(*p);
-            *p = nullptr;
+    s->pinned.put(r->host_block, r->host_block_bytes);
+    r->host_block = nullptr;
+    r->hE = r->hB = r->hEt = r->hBt = nullptr;
+    for (hipEvent_t *e : {&r->ready_ev, &r->fin_ev, &r->done_ev})
+        if (*e) {
+            (void)hipEventDestroy(*e);
+            *e = nullptr;
         }
-    if (r->ready_ev) (void)hipEventDestroy(r->ready_ev);
-    if (r->done_ev) (void)hipEventDestroy(r->done_ev);
-    r->ready_ev = r->done_ev = nullptr;
 }
 
 static void release_prob(Req *r)
@@ -156,13 +224,19 @@ static sc_status setup_request(sc_server *s, Req *r)
     }
     r->res_bytes = rs * 6 * (size_t)n_k * r->n_obs;
     r->time_bytes = rs * 6 * (size_t)r->n_t * r->n_obs;
-    HIP_TRY(hipHostMalloc(&r->hE, r->res_bytes, hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(&r->hB, r->res_bytes, hipHostMallocDefault));
-    if (r->n_t > 0) {
-        HIP_TRY(hipHostMalloc(&r->hEt, r->time_bytes, hipHostMallocDefault));
-        HIP_TRY(hipHostMalloc(&r->hBt, r->time_bytes, hipHostMallocDefault));
+    {   // one pinned block: E, B, then Et, Bt (each 256-byte aligned)
+        const size_t re = (r->res_bytes + 255) & ~size_t(255), te = (r->time_bytes + 255) & ~size_t(255);
+        HIP_TRY(s->pinned.get(2 * re + (r->n_t > 0 ? 2 * te : 0), &r->host_block, &r->host_block_bytes));
+        char *b = (char *)r->host_block;
+        r->hE = b;
+        r->hB = b + re;
+        if (r->n_t > 0) {
+            r->hEt = b + 2 * re;
+            r->hBt = b + 2 * re + te;
+        }
     }
     HIP_TRY(hipEventCreateWithFlags(&r->ready_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&r->fin_ev, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(r->ready_ev, s->prep->stream));
     // the time samples were copied from pageable memory
@@ -179,18 +253,24 @@ static sc_status finish_request(sc_server *s, Req *r)
     const int n_k = (int)r->k.size();
     HIP_TRY(launch_reduce(st, mode_of(r->prec), p->partial.p, r->job.n_chunks, n_k, r->n_obs, p->n_obs_pad,
                           p->d_k.as<double>(), p->resE.p, p->resB.p));
-    HIP_TRY(hipMemcpyAsync(r->hE, p->resE.p, r->res_bytes, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(r->hB, p->resB.p, r->res_bytes, hipMemcpyDeviceToHost, st));
     if (r->n_t > 0) {
         const int f64 = r->prec == SC_FP64;
         const int64_t n_x = (int64_t)r->n_obs * 3;
         HIP_TRY(launch_twiddles(st, n_k, p->d_k.as<double>(), r->n_t, p->d_t.as<double>(), r->dk, p->tw.as<double>()));
         HIP_TRY(launch_time(st, f64, n_k, r->n_t, n_x, p->tw.as<double>(), p->resE.p, p->timeE.p));
         HIP_TRY(launch_time(st, f64, n_k, r->n_t, n_x, p->tw.as<double>(), p->resB.p, p->timeB.p));
-        HIP_TRY(hipMemcpyAsync(r->hEt, p->timeE.p, r->time_bytes, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(r->hBt, p->timeB.p, r->time_bytes, hipMemcpyDeviceToHost, st));
     }
-    HIP_TRY(hipEventRecord(r->done_ev, st));
+    // the copies overlap the next quanta: the copy stream waits for this request's last kernel only
+    hipStream_t cs = s->copy_stream;
+    HIP_TRY(hipEventRecord(r->fin_ev, st));
+    HIP_TRY(hipStreamWaitEvent(cs, r->fin_ev, 0));
+    HIP_TRY(hipMemcpyAsync(r->hE, p->resE.p, r->res_bytes, hipMemcpyDeviceToHost, cs));
+    HIP_TRY(hipMemcpyAsync(r->hB, p->resB.p, r->res_bytes, hipMemcpyDeviceToHost, cs));
+    if (r->n_t > 0) {
+        HIP_TRY(hipMemcpyAsync(r->hEt, p->timeE.p, r->time_bytes, hipMemcpyDeviceToHost, cs));
+        HIP_TRY(hipMemcpyAsync(r->hBt, p->timeB.p, r->time_bytes, hipMemcpyDeviceToHost, cs));
+    }
+    HIP_TRY(hipEventRecord(r->done_ev, cs));
     return SC_OK;
 }
 
@@ -291,7 +371,11 @@ static void complete_request(sc_server *s, Req *r, ReqState state, sc_status st,
         s->stats.evals_done += r->evals;
     }
     s->stats.hbm_in_use -= std::min(s->stats.hbm_in_use, r->bytes);
-    release_prob(r);
+    if (r->prob) {   // its device work is complete; freeing it waits on the preparation stream
+        s->to_release.push_back(r->prob);
+        r->prob = nullptr;
+        s->cv_prep.notify_one();
+    }
     s->cv_done.notify_all();
 }
 
@@ -302,7 +386,15 @@ static void prep_main(sc_server *s)
     (void)hipSetDevice(s->ctx->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        s->cv_prep.wait(lk, [s] { return s->stop || !s->to_prepare.empty(); });
+        s->cv_prep.wait(lk, [s] { return s->stop || !s->to_prepare.empty() || !s->to_release.empty(); });
+        if (!s->to_release.empty()) {   // frees first, so the next request's allocations can reuse them
+            std::vector<sc_prob *> rel;
+            rel.swap(s->to_release);
+            lk.unlock();
+            for (sc_prob *p : rel) (void)sc_prob_destroy(p);
+            lk.lock();
+            continue;
+        }
         if (s->to_prepare.empty()) {
             if (s->stop) break;
             continue;
@@ -311,9 +403,12 @@ static void prep_main(sc_server *s)
         s->to_prepare.pop_front();
         s->preparing++;
         lk.unlock();
+        const Clock::time_point t0 = Clock::now();
         const sc_status st = setup_request(s, r);
+        const double prep_ms = ms_between(t0, Clock::now());
         const std::string err = st == SC_OK ? std::string() : std::string(sc_last_error());
         lk.lock();
+        s->stats.prep_ms += prep_ms;
         s->preparing--;
         if (st == SC_OK) s->active.push_back(r);
         else complete_request(s, r, R_FAILED, st, err);
@@ -413,12 +508,18 @@ extern "C" sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_ru
         return st;
     }
     s->prep->tune = ctx->tune;
+    if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)sc_ctx_destroy(s->prep);
+        delete s;
+        return fail(SC_E_DEVICE, "sc_server_create: hipStreamCreateWithFlags failed");
+    }
     for (int i = 0; i < sc_server::RING; ++i)
         if (hipEventCreate(&s->slot_ev[i]) != hipSuccess || hipEventCreate(&s->slot_start[i]) != hipSuccess) {
             for (int j = 0; j <= i; ++j) {
                 if (s->slot_ev[j]) (void)hipEventDestroy(s->slot_ev[j]);
                 if (s->slot_start[j]) (void)hipEventDestroy(s->slot_start[j]);
             }
+            (void)hipStreamDestroy(s->copy_stream);
             (void)sc_ctx_destroy(s->prep);
             delete s;
             return fail(SC_E_DEVICE, "sc_server_create: hipEventCreate failed");
@@ -519,6 +620,9 @@ extern "C" sc_status sc_server_wait(sc_server *s, uint64_t ticket, double timeou
     if (timeout_ms < 0) s->cv_done.wait(lk, ready);
     else if (!s->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), ready))
         return fail(SC_E_TIMEOUT, "sc_server_wait: ticket %llu not ready", (unsigned long long)ticket);
+    // the request leaves the server's books here; its results are copied out without the lock
+    s->all.erase(it);
+    lk.unlock();
     sc_status st = SC_OK;
     if (r->state == R_DONE) {
         if (E) memcpy(E, r->hE, r->res_bytes);
@@ -537,8 +641,7 @@ extern "C" sc_status sc_server_wait(sc_server *s, uint64_t ticket, double timeou
     } else {
         st = fail(r->status, "request failed: %s", r->err.c_str());
     }
-    s->all.erase(it);
-    free_req_host(r);
+    free_req_host(s, r);
     delete r;
     return st;
 }
@@ -591,12 +694,17 @@ extern "C" sc_status sc_server_destroy(sc_server *s)
     if (s->preparer.joinable()) s->preparer.join();
     DeviceGuard g(s->ctx->device);
     (void)hipStreamSynchronize(s->ctx->stream);
+    (void)hipStreamSynchronize(s->copy_stream);
+    for (sc_prob *p : s->to_release) (void)sc_prob_destroy(p);
+    s->to_release.clear();
     for (auto &kv : s->all) {
         release_prob(kv.second);
-        free_req_host(kv.second);
+        free_req_host(s, kv.second);
         delete kv.second;
     }
     s->all.clear();
+    s->pinned.clear();
+    (void)hipStreamDestroy(s->copy_stream);
     for (int i = 0; i < sc_server::RING; ++i) {
         if (s->slot_ev[i]) (void)hipEventDestroy(s->slot_ev[i]);
         if (s->slot_start[i]) (void)hipEventDestroy(s->slot_start[i]);
