@@ -116,6 +116,7 @@ def parse():
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM admission budget")
+    ap.add_argument("--quantum-ms", type=float, default=20.0, help="serve: device time per scheduling quantum")
     return ap.parse_args()
 
 
@@ -232,7 +233,7 @@ def bench_serve(args):
     torch.cuda.init()
     times, draw = workloads.serving_arrivals(args.rate, args.duration)
     ctx = Context(0, use_torch_stream=False)
-    srv = Server(ctx, hbm_budget=int(args.budget_gb * 1e9), max_running=64, quantum_ms=20.0)
+    srv = Server(ctx, hbm_budget=int(args.budget_gb * 1e9), max_running=64, quantum_ms=args.quantum_ms)
     tickets = []
     lock = threading.Lock()
     submitted_all = threading.Event()
@@ -309,7 +310,7 @@ def bench_serve(args):
         "quanta_evals_per_device_s": s["evals_launched"] / max(s["quad_ms"] * 1e-3, 1e-9),
         "device_busy_frac": s["quad_ms"] * 1e-3 / elapsed,
         "prep_ms_per_request": s["prep_ms"] / max(1, int(s["admitted"])),
-        "hbm_budget_gb": args.budget_gb}), flush=True)
+        "hbm_budget_gb": args.budget_gb, "quantum_ms": args.quantum_ms}), flush=True)
 
 
 def bench_table1(args):

@@ -48,7 +48,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         if src.endswith("_host.cpp"):
             # host-only code (needs __float128): the system C++ compiler
-            cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", path, "-o", obj]
+            cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-c", path, "-o", obj]
         else:
             cmd = [cc, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", path, "-o", obj]
             if src.endswith(".cpp"):
