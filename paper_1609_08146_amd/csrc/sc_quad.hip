@@ -179,6 +179,43 @@ struct GeomD {
     double dx, dy, dz, rinv, delta;
 };
 
+// sin and cos of 2 pi t in FP64.  The fractional turn r = t - rint(t) is
+// exact, so is y = r - q/4 with the quadrant q = rint(4 r), |y| <= 1/8; sin
+// and cos of x = 2 pi y (|x| <= pi/4) are their Taylor series through x^17
+// and x^18 (the first omitted terms are below 1e-19 of the result), and the
+// quadrant turns the pair by q pi/2.
+__device__ __forceinline__ void sincos_turns_f64(double t, double &s, double &c)
+{
+    const double r = t - rint(t);
+    const double q = rint(4.0 * r);
+    const double y = __fma_rn(-0.25, q, r);
+    const double x = y * TWO_PI_1;
+    const double x2 = x * x;
+    double ps = 1.0 / 355687428096000.0;   // 1/17!
+    ps = __fma_rn(ps, x2, -1.0 / 1307674368000.0);
+    ps = __fma_rn(ps, x2, 1.0 / 6227020800.0);
+    ps = __fma_rn(ps, x2, -1.0 / 39916800.0);
+    ps = __fma_rn(ps, x2, 1.0 / 362880.0);
+    ps = __fma_rn(ps, x2, -1.0 / 5040.0);
+    ps = __fma_rn(ps, x2, 1.0 / 120.0);
+    ps = __fma_rn(ps, x2, -1.0 / 6.0);
+    const double s0 = __fma_rn(x * x2, ps, x);
+    double pc = -1.0 / 6402373705728000.0;   // -1/18!
+    pc = __fma_rn(pc, x2, 1.0 / 20922789888000.0);
+    pc = __fma_rn(pc, x2, -1.0 / 87178291200.0);
+    pc = __fma_rn(pc, x2, 1.0 / 479001600.0);
+    pc = __fma_rn(pc, x2, -1.0 / 3628800.0);
+    pc = __fma_rn(pc, x2, 1.0 / 40320.0);
+    pc = __fma_rn(pc, x2, -1.0 / 720.0);
+    pc = __fma_rn(pc, x2, 1.0 / 24.0);
+    pc = __fma_rn(pc, x2, -0.5);
+    const double c0 = __fma_rn(x2, pc, 1.0);
+    const int qi = (int)q & 3;   // q in {-2, ..., 2}
+    const double sa = (qi & 1) ? c0 : s0, ca = (qi & 1) ? s0 : c0;
+    s = (qi >= 2) ? -sa : sa;                 // quadrants 2, 3: sin < 0 side
+    c = (qi == 1 || qi == 2) ? -ca : ca;      // quadrants 1, 2
+}
+
 __device__ __forceinline__ GeomD geom_f64(const double *p, const double4 o)
 {
     GeomD g;
@@ -190,14 +227,20 @@ __device__ __forceinline__ GeomD geom_f64(const double *p, const double4 o)
     const double R = R2 * g.rinv;
     const double dot = __fma_rn(p[0], o.x, __fma_rn(p[1], o.y, p[2] * o.z));
     const double num = __fma_rn(-2.0, dot, o.w);
-    g.delta = num / (R + p[3]);
+    // delta = num / den: hardware reciprocal, two Newton steps, one residual correction
+    const double den = R + p[3];
+    double inv = __builtin_amdgcn_rcp(den);
+    inv = __fma_rn(inv, __fma_rn(-den, inv, 1.0), inv);
+    inv = __fma_rn(inv, __fma_rn(-den, inv, 1.0), inv);
+    const double q = num * inv;
+    g.delta = __fma_rn(__fma_rn(-den, q, num), inv, q);
     return g;
 }
 
-__device__ __forceinline__ void freq_f64(const GeomD &g, const double *t, double k, double *acc)
+__device__ __forceinline__ void freq_f64(const GeomD &g, const double *t, double k, double kt, double *acc)
 {
     double s, c;
-    sincos(k * g.delta, &s, &c);
+    sincos_turns_f64(kt * g.delta, s, c);
     const double dx = g.dx, dy = g.dy, dz = g.dz, rinv = g.rinv;
     const double gr = c * rinv, gi = s * rinv;
     const double a = -(rinv * rinv), b = k * rinv;
@@ -424,6 +467,9 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
 #pragma unroll
             for (int f = 0; f < FPB; ++f) tab[f] = (cdouble *)jobs[j].tab + (size_t)kidx[f] * n_tot * 8;
             const double4 *obs = (const double4 *)jobs[j].obs;
+            double kt64[FPB];   // wavenumbers in turns per unit length
+#pragma unroll
+            for (int f = 0; f < FPB; ++f) kt64[f] = k64[f] * INV_TWO_PI;
             double4 o[OPL];
             double acc[OPL][FPB][12];
 #pragma unroll
@@ -446,7 +492,7 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
                 for (int s = 0; s < OPL; ++s) {
                     const GeomD g = geom_f64(pn, o[s]);
 #pragma unroll
-                    for (int f = 0; f < FPB; ++f) freq_f64(g, tn[f], k64[f], acc[s][f]);
+                    for (int f = 0; f < FPB; ++f) freq_f64(g, tn[f], k64[f], kt64[f], acc[s][f]);
                 }
             }
 #pragma unroll

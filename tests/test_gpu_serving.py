@@ -55,8 +55,12 @@ def alone(ctx, w, prec, t=None, dk=1.0):
 
 
 def test_same_result_alone_and_in_the_mix(ctx):
+    from dataclasses import replace
     from paper_1609_08146_amd import Server
     ws = small_requests(8)
+    # two curl-consistent beams: their tables do not factor, so quanta mix factored and general jobs
+    ws[2] = replace(ws[2], consistent=1)
+    ws[5] = replace(ws[5], consistent=1)
     precs = ["fp32_split"] * 6 + ["fp64", "fp32_split"]
     ref = [alone(ctx, w, pr, w.t[::32], w.dk) for w, pr in zip(ws, precs)]
     # at most three running at once, so later arrivals queue and join running work
