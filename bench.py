@@ -129,11 +129,10 @@ def shard_workload(shard: int):
     return full.subset(k_idx=kidx, name="broadband-shard"), desc
 
 
-def run_step(ctx, w, precision, factoring=True):
-    """One pass of the whole path; returns the problem (kept alive for timing)."""
-    from paper_1609_08146_amd import Problem
-    p = Problem(ctx)
-    p.set_factoring(factoring)
+def run_step(p, w, precision):
+    """One pass of the whole path on problem object `p`: mirror nodes, frequencies, incident and
+    current tables, observation points, quadrature, reduction and time transform are all rebuilt
+    from the workload's parameters (the object only keeps its device allocations between steps)."""
     p.set_mirror(w.f, w.a, w.n_r, w.n_phi)
     p.set_frequencies(w.k)
     p.set_incident_gaussian(w.w0, w.pol, w.spectrum, False)
@@ -438,22 +437,23 @@ def main():
     ctx = Context(0)
     ctx.set_profiling(True)
 
-    factoring = not args.general_tables
+    p = Problem(ctx)
+    p.set_factoring(not args.general_tables)
     for _ in range(args.warmup):
-        run_step(ctx, w, args.precision, factoring).close()
+        run_step(p, w, args.precision)
     torch.cuda.synchronize()
 
     quad_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        p = run_step(ctx, w, args.precision, factoring)
+        run_step(p, w, args.precision)
         torch.cuda.synchronize()
         tm = p.timing()
         quad_ms.append(tm["quad_ms"])
         last_timing = tm
-        factored = args.precision == "fp32_split" and p.factored
-        p.close()
+    factored = args.precision == "fp32_split" and p.factored
+    p.close()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -541,11 +541,13 @@ def main():
         if factored:
             # the same split form on the general tables (what an arbitrary incident field costs)
             qg = []
+            p = Problem(ctx)
+            p.set_factoring(False)
             for _ in range(3):
-                p = run_step(ctx, w, args.precision, factoring=False)
+                run_step(p, w, args.precision)
                 torch.cuda.synchronize()
                 qg.append(p.timing()["quad_ms"])
-                p.close()
+            p.close()
             rg = evals / (min(qg) * 1e-3)
             out["forms"]["fp32_split_general_tables"] = {
                 "quad_evals_per_s": rg, "quad_ms": min(qg), "tflops": fpg * rg / 1e12,
