@@ -132,3 +132,32 @@ def test_energy_error_paths(ctx):
     with pytest.raises(ValueError):
         p.normalize_energy(np.ones(3))
     p.close()
+
+
+def test_table1_focal_spot_matches_the_paper(ctx):
+    """The Table I workload (energy-normalised to 150 J, FP32-split) against the focal-spot figures
+    the paper prints in Sec. IV-B: peak electric intensity, eccentricity of the focal spot, and the
+    size of the longitudinal magnetic field (tests/golden/table1_focal_spot.json)."""
+    import json
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    from paper_1609_08146_amd import problem_from_workload
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "table1_focal_spot.json")))
+    w = workloads.table1()
+    lam = workloads.TABLE1["lam_c"]
+    p = problem_from_workload(ctx, w)
+    p.normalize_energy(w.meta["eps"], w.meta["e_tot"], w.dk)
+    p.evaluate("fp32_split", keep_on_device=True)
+    t = 2 * w.f + np.arange(-128, 129) * (lam / 32)
+    Et, Bt = p.to_time(w.dk, t)
+    p.close()
+    r = bench.focal_spot(Et, Bt, 64, 2.0 * lam)
+    print({k: r[k] for k in ("peak_intensity_W_cm2", "eccentricity", "max_Bz_over_max_Ex", "fwhm_x_m",
+                             "fwhm_y_m")})
+    assert abs(r["peak_intensity_W_cm2"] / gold["peak_electric_intensity_W_cm2"] - 1.0) < 0.3
+    assert abs(r["eccentricity"] - gold["focal_spot_eccentricity"]) < 0.05
+    assert r["fwhm_x_m"] > r["fwhm_y_m"]          # major axis along the polarisation
+    assert abs(r["max_Bz_over_max_Ex"] - gold["max_Bz_over_max_Ex"]) < 0.1
