@@ -107,11 +107,13 @@ def parse():
     ap.add_argument("--general-tables", action="store_true",
                     help="step: never use the factored current (time the general-table layout)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "copy", "table1", "valu"],
+    ap.add_argument("--mode", default="step",
+                    choices=["step", "batch", "serve", "copy", "table1", "valu", "convergence"],
                     help="step: the hot path on the broadband workload (default); batch: the seeded sweep of "
                          "uneven instances in one persistent launch; serve: a Poisson request stream; "
                          "table1: the Table I workload with energy normalisation and diagnostics; "
-                         "valu: issue cost of the kernel's vector instructions")
+                         "valu: issue cost of the kernel's vector instructions; "
+                         "convergence: e_rel per component under mesh refinement (Sec. IV-A)")
     ap.add_argument("--instances", type=int, default=256, help="batch: instances of the sweep")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
@@ -441,6 +443,52 @@ def bench_table1(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_convergence(args):
+    """The convergence study of Sec. IV-A with the GPU path: the radially polarised beam on the
+    Table I mirror at the central wavelength, focal-region points, N x N nodes for growing N; per
+    component, e_rel = max |F_ref - F_N| / max |F_ref| against the finest mesh (FP64 form), with the
+    paper's average cell area <A>_N = dtheta dr^2 (N+1)^2 / (2N) as the mesh measure."""
+    import torch
+    from paper_1609_08146_amd import Context, Problem
+    torch.cuda.init()
+    T = workloads.TABLE1
+    lam = T["lam_c"]
+    k = np.array([2 * np.pi / lam])
+    g = np.linspace(-lam, lam, 16)
+    plane = workloads.focal_plane(lam, 16)
+    obs = np.concatenate([plane, np.stack([0 * g, 0 * g, 2 * g], axis=-1)])
+    ctx = Context(0)
+
+    def field(n):
+        p = Problem(ctx)
+        p.set_mirror(T["f"], T["r_max"], n, n)
+        p.set_frequencies(k)
+        p.set_incident_beam("radial", T["w0"], 0.0, None, True)
+        p.set_observation(obs)
+        E, B = p.evaluate("fp64")
+        p.close()
+        return np.concatenate([E[0], B[0]], axis=-1)       # [n_obs][6]
+
+    ns = [8, 12, 16, 20, 25, 30, 40, 50, 100, 200, 400]
+    ref = field(1200)
+    names = ["E_x", "E_y", "E_z", "B_x", "B_y", "B_z"]
+    rows = []
+    for n in ns:
+        F = field(n)
+        dr, dth = T["r_max"] / n, 2 * np.pi / n
+        cell = np.sqrt(dth * dr * dr * (n + 1) ** 2 / (2 * n))
+        peak = np.max(np.abs(ref), axis=0)
+        err = np.max(np.abs(F - ref), axis=0)
+        # a component that vanishes by symmetry (B_z of the radial beam) has no relative error
+        live = peak > 1e-9 * peak.max()
+        rows.append({"n": n, "cell_over_lambda": cell / lam,
+                     "e_rel": {c: (float(err[i] / peak[i]) if live[i] else None) for i, c in enumerate(names)}})
+    ctx.close()
+    print(json.dumps({"metric": "convergence of the FP64 field under refinement (Sec. IV-A)",
+                      "beam": "radially polarised, curl-consistent", "reference_n": 1200, "rows": rows}),
+          flush=True)
+
+
 def bench_valu(args):
     """Issue cost of the vector instructions of the quadrature kernel (the built microbenchmark)."""
     import subprocess
@@ -480,6 +528,8 @@ def main():
         return bench_table1(args)
     if args.mode == "valu":
         return bench_valu(args)
+    if args.mode == "convergence":
+        return bench_convergence(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the frequency-sharded multi-GPU "
                                    "design is described but not built, so --gpus must be 1"}))
