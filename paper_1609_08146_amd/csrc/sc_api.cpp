@@ -162,8 +162,27 @@ extern "C" sc_status sc_prob_destroy(sc_prob *p)
     (void)hipStreamSynchronize(p->ctx->stream);
     for (int i = 0; i < EV_N; ++i)
         if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
+    if (p->stage_ev) (void)hipEventDestroy(p->stage_ev);
     p->ctx->n_probs--;
     delete p;   // DevBufs free themselves
+    return SC_OK;
+}
+
+// The staging vectors of a problem are rewritten only after the last copy from them has run.
+static sc_status staging_wait(sc_prob *p)
+{
+    if (p->stage_pending) {
+        HIP_TRY(hipEventSynchronize(p->stage_ev));
+        p->stage_pending = false;
+    }
+    return SC_OK;
+}
+
+static sc_status staging_mark(sc_prob *p)
+{
+    if (!p->stage_ev) HIP_TRY(hipEventCreateWithFlags(&p->stage_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(p->stage_ev, p->ctx->stream));
+    p->stage_pending = true;
     return SC_OK;
 }
 
@@ -236,7 +255,8 @@ static sc_status finish_tables(sc_prob *p)
     HIP_TRY(launch_tables_cast(p->ctx->stream, (int)p->k.size(), p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
                                p->tab64.as<double>(), nullptr, p->tab32.as<float>(), 0));
     p->tab32_ok = true;
-    HIP_TRY(hipStreamSynchronize(p->ctx->stream));
+    // a stream-ordered free runs after the cast; a plain hipFree needs the cast to have finished
+    if (!p->tab64.stream) HIP_TRY(hipStreamSynchronize(p->ctx->stream));
     p->tab64.release();
     p->has_tab64 = false;
     return SC_OK;
@@ -281,7 +301,11 @@ extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, 
     const std::vector<double> *xw[2];
     gauss_rule_cached(p->ctx, n_r, xw);
     const std::vector<double> &x = *xw[0], &w = *xw[1];
-    std::vector<double> r(n_r + 1), wr(n_r), c(n_phi), s(n_phi);
+    SC_TRY(staging_wait(p));
+    // staging layout: r [n_r + 1], w_r [n_r], cos phi [n_phi], sin phi [n_phi]
+    std::vector<double> &stage = p->h_stage_rule;
+    stage.resize((size_t)2 * n_r + 1 + 2 * (size_t)n_phi);
+    double *r = stage.data(), *wr = r + n_r + 1, *c = wr + n_r, *s = c + n_phi;
     for (int i = 0; i < n_r; ++i) {
         r[i] = r_max * (1.0 + x[i]) / 2.0;
         wr[i] = r_max * w[i] / 2.0;
@@ -303,15 +327,14 @@ extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, 
     SC_TRY(p->nrm.reserve(sizeof(double) * 3 * n_tot, p->alloc_stream));
     SC_TRY(p->wgt.reserve(sizeof(double) * n_tot, p->alloc_stream));
     SC_TRY(p->tan.reserve(sizeof(double) * 3 * n_phi, p->alloc_stream));
-    HIP_TRY(hipMemcpyAsync(p->d_r.p, r.data(), sizeof(double) * (n_r + 1), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(p->d_wr.p, wr.data(), sizeof(double) * n_r, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(p->d_c.p, c.data(), sizeof(double) * n_phi, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(p->d_s.p, s.data(), sizeof(double) * n_phi, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->d_r.p, r, sizeof(double) * (n_r + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->d_wr.p, wr, sizeof(double) * n_r, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->d_c.p, c, sizeof(double) * n_phi, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->d_s.p, s, sizeof(double) * n_phi, hipMemcpyHostToDevice, st));
+    SC_TRY(staging_mark(p));
     HIP_TRY(launch_node_tables(st, n_r, n_phi, f, p->d_r.as<double>(), p->d_wr.as<double>(), p->d_c.as<double>(),
                                p->d_s.as<double>(), 2.0 * M_PI / (double)n_phi, p->pos64.as<double>(),
                                p->pos32.as<float>(), p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>()));
-    // the host vectors above are pageable: make the copies complete before they go out of scope
-    HIP_TRY(hipStreamSynchronize(st));
     p->f = f;
     p->a = r_max;
     p->n_r = n_r;
@@ -480,25 +503,27 @@ extern "C" sc_status sc_set_incident_beam(sc_prob *p, int beam, double w0, doubl
     const int n_k = (int)p->k.size();
     invalidate_tables(p);
     SC_TRY(p->tab64.reserve(sizeof(double) * 8 * (size_t)n_k * p->n_tot, p->alloc_stream));
-    DevBuf dspec;
+    const double *dspec = nullptr;
     if (spectrum) {
-        SC_TRY(dspec.reserve(sizeof(double) * 2 * n_k, p->alloc_stream));
-        HIP_TRY(hipMemcpyAsync(dspec.p, spectrum, sizeof(double) * 2 * n_k, hipMemcpyHostToDevice, st));
+        SC_TRY(staging_wait(p));
+        p->h_stage_spec.assign(spectrum, spectrum + 2 * (size_t)n_k);
+        SC_TRY(p->d_spec.reserve(sizeof(double) * 2 * n_k, p->alloc_stream));
+        HIP_TRY(hipMemcpyAsync(p->d_spec.p, p->h_stage_spec.data(), sizeof(double) * 2 * n_k, hipMemcpyHostToDevice,
+                               st));
+        SC_TRY(staging_mark(p));
+        dspec = p->d_spec.as<double>();
     }
     ev_record(p, EV_PREP0);
     HIP_TRY(launch_tables_gaussian(st, n_k, p->n_surf, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
                                    p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>(), beam, w0, pol_angle,
-                                   spectrum ? dspec.as<double>() : nullptr, consistent ? 1 : 0,
-                                   p->tab64.as<double>()));
+                                   dspec, consistent ? 1 : 0, p->tab64.as<double>()));
     SC_TRY(reserve_power(p));
     HIP_TRY(launch_power_gaussian(st, n_k, p->n_surf, p->d_k.as<double>(), p->pos64.as<double>(),
-                                  p->nrm.as<double>(), p->wgt.as<double>(), beam, w0, pol_angle,
-                                  spectrum ? dspec.as<double>() : nullptr, consistent ? 1 : 0,
-                                  p->d_power.as<double>() + n_k, p->d_power.as<double>()));
+                                  p->nrm.as<double>(), p->wgt.as<double>(), beam, w0, pol_angle, dspec,
+                                  consistent ? 1 : 0, p->d_power.as<double>() + n_k, p->d_power.as<double>()));
     p->has_power = true;
     ev_record(p, EV_PREP1);
     p->ev_prep = p->ctx->profiling;
-    HIP_TRY(hipStreamSynchronize(st));   // dspec is freed on return
     return finish_tables(p);
 }
 
@@ -604,15 +629,17 @@ extern "C" sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs
     p->res_prec = -1;
     SC_TRY(p->obs64.reserve(sizeof(double) * 4 * pad, p->alloc_stream));
     SC_TRY(p->obs32.reserve(sizeof(float) * 4 * pad, p->alloc_stream));
-    DevBuf stage;
     const double *d = xyz;
     if (!on_device) {
-        SC_TRY(stage.reserve(sizeof(double) * 3 * n_obs, p->alloc_stream));
-        HIP_TRY(hipMemcpyAsync(stage.p, xyz, sizeof(double) * 3 * n_obs, hipMemcpyHostToDevice, st));
-        d = stage.as<double>();
+        SC_TRY(staging_wait(p));
+        p->h_stage_obs.assign(xyz, xyz + 3 * (size_t)n_obs);
+        SC_TRY(p->d_obs_in.reserve(sizeof(double) * 3 * n_obs, p->alloc_stream));
+        HIP_TRY(hipMemcpyAsync(p->d_obs_in.p, p->h_stage_obs.data(), sizeof(double) * 3 * n_obs,
+                               hipMemcpyHostToDevice, st));
+        SC_TRY(staging_mark(p));
+        d = p->d_obs_in.as<double>();
     }
     HIP_TRY(launch_obs_prep(st, d, n_obs, pad, p->obs64.as<double>(), p->obs32.as<float>()));
-    if (!on_device) HIP_TRY(hipStreamSynchronize(st));
     p->n_obs = n_obs;
     p->n_obs_pad = pad;
     return SC_OK;

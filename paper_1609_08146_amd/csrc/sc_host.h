@@ -150,6 +150,12 @@ struct sc_prob {
     sc::DevBuf partial;
     // time transform
     sc::DevBuf d_t, tw, timeE, timeB;
+    // host staging of small uploads (rule, spectrum, points), reused across calls so that set-up calls
+    // need not wait for their copies; stage_ev marks the last upload from them
+    std::vector<double> h_stage_rule, h_stage_spec, h_stage_obs;
+    sc::DevBuf d_spec, d_obs_in;
+    hipEvent_t stage_ev = nullptr;
+    bool stage_pending = false;
     // launch override
     bool has_launch = false;
     sc_launch launch{};

@@ -239,8 +239,7 @@ static sc_status setup_request(sc_server *s, Req *r)
     HIP_TRY(hipEventCreateWithFlags(&r->fin_ev, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(r->ready_ev, s->prep->stream));
-    // the time samples were copied from pageable memory
-    HIP_TRY(hipStreamSynchronize(s->prep->stream));
+    // the time samples are copied from r->t, which lives as long as the request
     r->evals = (int64_t)r->n_obs * n_k * p->n_surf;
     return SC_OK;
 }
@@ -407,6 +406,8 @@ static void prep_main(sc_server *s)
         const sc_status st = setup_request(s, r);
         const double prep_ms = ms_between(t0, Clock::now());
         const std::string err = st == SC_OK ? std::string() : std::string(sc_last_error());
+        // a failed request may still have copies from its host arrays in flight
+        if (st != SC_OK) (void)hipStreamSynchronize(s->prep->stream);
         lk.lock();
         s->stats.prep_ms += prep_ms;
         s->preparing--;
