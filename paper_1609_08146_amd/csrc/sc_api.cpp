@@ -630,7 +630,13 @@ extern "C" sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs
     SC_TRY(p->obs64.reserve(sizeof(double) * 4 * pad, p->alloc_stream));
     SC_TRY(p->obs32.reserve(sizeof(float) * 4 * pad, p->alloc_stream));
     const double *d = xyz;
+    p->obs_r2max = -1.0;
+    double r2max = -1.0;
     if (!on_device) {
+        for (int o = 0; o < n_obs; ++o) {
+            const double *q = xyz + 3 * (size_t)o;
+            r2max = std::max(r2max, q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        }
         SC_TRY(staging_wait(p));
         p->h_stage_obs.assign(xyz, xyz + 3 * (size_t)n_obs);
         SC_TRY(p->d_obs_in.reserve(sizeof(double) * 3 * n_obs, p->alloc_stream));
@@ -640,6 +646,7 @@ extern "C" sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs
         d = p->d_obs_in.as<double>();
     }
     HIP_TRY(launch_obs_prep(st, d, n_obs, pad, p->obs64.as<double>(), p->obs32.as<float>()));
+    p->obs_r2max = r2max;
     p->n_obs = n_obs;
     p->n_obs_pad = pad;
     return SC_OK;
@@ -771,6 +778,13 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
     job.tab = tab;
     job.pos = prec == SC_FP64 ? p->pos64.p : (fact ? p->posf.p : p->pos32.p);
     job.factored = fact ? 1 : 0;
+    // |delta| = ||R| - |r_s|| <= |r'|, so the split phase k delta stays below k_max |r'|_max; the
+    // hardware sin / cos take up to 256 turns directly (kept below 250 for the FP32 rounding of k delta)
+    {
+        const double kmax = *std::max_element(p->k.begin(), p->k.end());
+        const double tmax = p->obs_r2max >= 0.0 ? kmax / (2.0 * M_PI) * std::sqrt(p->obs_r2max) : 1e300;
+        job.raw_phase = prec == SC_FP32_SPLIT && tmax < 250.0 ? 1 : 0;
+    }
     job.obs = prec == SC_FP64 ? p->obs64.p : p->obs32.p;
     job.k = p->d_k.as<double>();
     job.partial = p->partial.p;

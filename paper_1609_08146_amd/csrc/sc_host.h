@@ -141,8 +141,9 @@ struct sc_prob {
     // incident power per frequency through the aperture: [n_k] then the reduction scratch
     bool has_power = false;
     sc::DevBuf d_power;
-    // observation points
+    // observation points; obs_r2max = max |r'|^2 when they came from host memory, else -1
     int n_obs = 0, n_obs_pad = 0;
+    double obs_r2max = -1.0;
     sc::DevBuf obs64, obs32;
     // result of the last evaluate
     int res_prec = -1;

@@ -28,11 +28,14 @@ typedef __attribute__((address_space(4))) const v4f cv4f;
 typedef __attribute__((address_space(4))) const double cdouble;
 typedef __attribute__((address_space(4))) const QuadJob cjob;
 
-// sin and cos of theta = 2 pi * t, t in turns: hardware v_sin / v_cos on the
-// fractional part (the exact reduction modulo one turn, in [0, 1)).
+// sin and cos of theta = 2 pi * t, t in turns, with the hardware v_sin / v_cos.
+// They accept |t| <= 256 turns directly, as accurately as the fractional part
+// (1.2e-7 absolute either way); RAW = false first reduces to the fractional
+// part (exact, in [0, 1)), which any t allows.
+template <bool RAW>
 __device__ __forceinline__ void sincos_turns(float t, float &s, float &c)
 {
-    const float r = __builtin_amdgcn_fractf(t);
+    const float r = RAW ? t : __builtin_amdgcn_fractf(t);
     s = __builtin_amdgcn_sinf(r);
     c = __builtin_amdgcn_cosf(r);
 }
@@ -104,10 +107,11 @@ __device__ __forceinline__ void accumulate_f32(float dx, float dy, float dz, flo
 }
 
 // Split form, one frequency: phase k delta (kt = k / 2 pi, in turns).
+template <bool RAW>
 __device__ __forceinline__ void freq_split(const GeomF &g, const v4f t0, const v4f t1, float k, float kt, float *acc)
 {
     float s, c;
-    sincos_turns(kt * g.delta, s, c);
+    sincos_turns<RAW>(kt * g.delta, s, c);
     accumulate_f32(g.dx, g.dy, g.dz, g.rinv, c, s, t0, t1, k, acc);
 }
 
@@ -116,11 +120,12 @@ __device__ __forceinline__ void freq_split(const GeomF &g, const v4f t0, const v
 //   J~ gt = u (s gt),   (J~ ht) x R = (s ht) (u x R),
 // and w = u x R is shared by the frequencies of a lane.  t = (s, rho_t) as
 // (re, im) pairs; u = (ux, uy, uz, 0).  acc as in accumulate_f32.
+template <bool RAW>
 __device__ __forceinline__ void freq_factored(const GeomF &g, float wx, float wy, float wz, const v4f u, const v4f t,
                                               float k, float kt, float *acc)
 {
     float s, c;
-    sincos_turns(kt * g.delta, s, c);
+    sincos_turns<RAW>(kt * g.delta, s, c);
     const float rinv = g.rinv;
     const float gr = c * rinv, gi = s * rinv;
     const float a = -(rinv * rinv), b = k * rinv;
@@ -289,7 +294,9 @@ constexpr int KAHAN_BLOCK = 32;   // nodes summed plainly before each compensate
 // frequencies.  FACT selects the factored layout: node records of two v4f
 // (x, y, z, |r_s|), (u, 0) and one v4f (s, rho_t) per table record, instead of
 // one v4f node record and two v4f (Jt.x, Jt.y), (Jt.z, rho_t) per table record.
-template <int MODE, int OPL, int FPB, bool FACT>
+// RAW passes the split phase k delta / 2 pi to the hardware sin / cos without
+// taking its fractional part (the job guarantees it stays below 250 turns).
+template <int MODE, int OPL, int FPB, bool FACT, bool RAW>
 __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
                                          const double *k64, int n_valid)
 {
@@ -359,11 +366,11 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
                 const float wy = __fmaf_rn(un.z, g.dx, -(un.x * g.dz));
                 const float wz = __fmaf_rn(un.x, g.dy, -(un.y * g.dx));
 #pragma unroll
-                for (int f = 0; f < FPB; ++f) freq_factored(g, wx, wy, wz, un, t0[f], k[f], kt[f], blk[s][f]);
+                for (int f = 0; f < FPB; ++f) freq_factored<RAW>(g, wx, wy, wz, un, t0[f], k[f], kt[f], blk[s][f]);
             } else if constexpr (MODE == MODE_SPLIT) {
                 const GeomF g = geom_split(pn, o[s]);
 #pragma unroll
-                for (int f = 0; f < FPB; ++f) freq_split(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
+                for (int f = 0; f < FPB; ++f) freq_split<RAW>(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
             } else {
                 GeomF g;
                 float R;
@@ -505,12 +512,17 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
                     for (int c = 0; c < 12; ++c) part[(size_t)c * n_obs_pad + obase + 64 * s] = acc[s][f][c];
             }
         } else if constexpr (MODE == MODE_SPLIT) {
-            if (jobs[j].factored)
-                tile_f32<MODE, OPL, FPB, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
-            else
-                tile_f32<MODE, OPL, FPB, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+            // per job (not per tile), so the bits of a point do not depend on the launch shape
+            const bool raw = jobs[j].raw_phase != 0;
+            if (jobs[j].factored) {
+                if (raw) tile_f32<MODE, OPL, FPB, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                else tile_f32<MODE, OPL, FPB, true, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+            } else {
+                if (raw) tile_f32<MODE, OPL, FPB, false, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                else tile_f32<MODE, OPL, FPB, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+            }
         } else {
-            tile_f32<MODE, OPL, FPB, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+            tile_f32<MODE, OPL, FPB, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
         }
     }
 }
