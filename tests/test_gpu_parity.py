@@ -367,3 +367,35 @@ def test_fp32_only_table_storage(ctx):
     N2, _ = q.evaluate("fp32")          # naive tables derived from the FP32 split tables
     assert rel_l2(N2, N0) < 1e-6
     q.close()
+
+
+def test_phase_with_and_without_the_fractional_turn(ctx, orc):
+    """The split phase goes to the hardware sin/cos as is when every point of a problem keeps
+    |k delta| / 2 pi below 250 turns, else through its fractional part.  Points near the focus alone
+    take the first path; the same points with one far point (|r'| = 300 wavelengths) take the
+    second.  Both match the oracle, and each other to FP32 rounding."""
+    from paper_1609_08146_amd import Problem
+    f, a, nr, nphi = 20.0, 40.0, 48, 32
+    near = workloads.random_points(150, 2.5, seed=21)
+    far = np.array([[0.0, 0.0, 300.0]])
+    m = orc.mirror(f, a, nr, nphi)
+    Ei, Bi = workloads.random_incident_tables(1, m.n_tot, seed=4)
+    res = {}
+    for name, pts in (("near", near), ("near+far", np.concatenate([near, far]))):
+        p = Problem(ctx)
+        p.set_mirror(f, a, nr, nphi)
+        p.set_frequencies([K])
+        p.set_incident(Ei, Bi)
+        p.set_observation(pts)
+        res[name] = p.evaluate("fp32_split")
+        p.close()
+    Eo, Bo = orc.reflected_field(m, np.array([K]), Ei, Bi, near)
+    En, Bn = res["near"]
+    Ef, Bf = res["near+far"]
+    Ef, Bf = Ef[:, : len(near)], Bf[:, : len(near)]
+    errs = dict(raw=max(rel_l2(En, Eo), rel_l2(Bn, Bo)), fract=max(rel_l2(Ef, Eo), rel_l2(Bf, Bo)),
+                between=max(rel_l2(En, Ef), rel_l2(Bn, Bf)))
+    print({k: f"{v:.2e}" for k, v in errs.items()})
+    assert errs["raw"] < 1e-5 and errs["fract"] < 1e-5
+    assert errs["between"] < 2e-6
+    assert not np.array_equal(En, Ef)          # the two paths really differ in rounding
