@@ -119,6 +119,9 @@ def parse():
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM admission budget")
     ap.add_argument("--quantum-ms", type=float, default=20.0, help="serve: device time per scheduling quantum")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="step: seconds of the request stream timed after the steps for the latency figures (0: none)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="step: arrivals per second of that stream")
     return ap.parse_args()
 
 
@@ -221,6 +224,11 @@ def bench_batch(args):
 
 
 def bench_serve(args):
+    """--mode serve: one JSON line for a serving run (see serve_run)."""
+    print(json.dumps(serve_run(args.rate, args.duration, args.budget_gb, args.quantum_ms)), flush=True)
+
+
+def serve_run(rate: float, duration: float, budget_gb: float = 200.0, quantum_ms: float = 20.0) -> dict:
     """Poisson stream of sweep-like requests through the serving loop; p50/p99 latency and throughput.
 
     One thread submits at the drawn arrival times, another collects results in submission order as
@@ -232,9 +240,9 @@ def bench_serve(args):
     from paper_1609_08146_amd import Context, ScError, Server
     from paper_1609_08146_amd._abi import SC_E_TIMEOUT
     torch.cuda.init()
-    times, draw = workloads.serving_arrivals(args.rate, args.duration)
+    times, draw = workloads.serving_arrivals(rate, duration)
     ctx = Context(0, use_torch_stream=False)
-    srv = Server(ctx, hbm_budget=int(args.budget_gb * 1e9), max_running=64, quantum_ms=args.quantum_ms)
+    srv = Server(ctx, hbm_budget=int(budget_gb * 1e9), max_running=64, quantum_ms=quantum_ms)
     tickets = []
     lock = threading.Lock()
     submitted_all = threading.Event()
@@ -294,16 +302,16 @@ def bench_serve(args):
     th_s.start()
     th_c.start()
     th_s.join()
-    drain_deadline.append(time.perf_counter() + max(10.0, 0.25 * args.duration))
+    drain_deadline.append(time.perf_counter() + max(10.0, 0.25 * duration))
     th_c.join()
     elapsed = time.perf_counter() - start
     s = srv.stats()
     srv.close()
     ctx.close()
     lat = np.array(lat) if lat else np.array([np.nan])
-    print(json.dumps({
+    return {
         "metric": "serving: p50/p99 request latency and integrand evals/s",
-        "rate_hz": args.rate, "duration_s": args.duration, "arrivals": len(times),
+        "rate_hz": rate, "duration_s": duration, "arrivals": len(times),
         "completed": int(s["completed"]), "cancelled": int(s["cancelled"]), "rejected": int(s["rejected"]),
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "evals_per_s": s["evals_done"] / elapsed, "elapsed_s": elapsed, "launches": int(s["launches"]),
@@ -311,54 +319,7 @@ def bench_serve(args):
         "quanta_evals_per_device_s": s["evals_launched"] / max(s["quad_ms"] * 1e-3, 1e-9),
         "device_busy_frac": s["quad_ms"] * 1e-3 / elapsed,
         "prep_ms_per_request": s["prep_ms"] / max(1, int(s["admitted"])),
-        "hbm_budget_gb": args.budget_gb, "quantum_ms": args.quantum_ms}), flush=True)
-
-
-C_LIGHT = 299792458.0   # m/s
-
-
-def _fwhm(cut: np.ndarray, i: int, dx: float):
-    """Full width at half maximum of a sampled profile around its sample i (linear interpolation of
-    the two half-maximum crossings); None if the profile does not fall to half within the samples."""
-    half = 0.5 * cut[i]
-    edges = []
-    for step in (-1, 1):
-        j = i
-        while 0 <= j + step < len(cut) and cut[j + step] >= half:
-            j += step
-        if not 0 <= j + step < len(cut):
-            return None
-        a, b = cut[j], cut[j + step]
-        edges.append((j + step * (a - half) / (a - b)) * dx)
-    return float(edges[1] - edges[0])
-
-
-def focal_spot(Et: np.ndarray, Bt: np.ndarray, n: int, half_width: float):
-    """Peak electric intensity I_E = (1/2) c E^2 of Sec. IV-B and the shape of the focal spot.
-
-    Et, Bt: time samples [n_t][n_points][3] of the analytic field on an n x n focal-plane grid over
-    +-half_width (x fastest; the physical field is 2 Re).  The field is in Lorentz-Heaviside units
-    (sqrt(J/m^3), lengths in m), so c E^2 / 2 is W/m^2.  At the time sample and point of the largest
-    intensity: the intensity, the FWHM of the intensity along x and y through that point, the
-    eccentricity sqrt(1 - (minor/major)^2) of those widths; and the largest longitudinal components
-    relative to the largest E_x over all samples (max |E_z| / max |E_x|, max |B_z| / max |E_x|)."""
-    E = 2.0 * np.real(Et[:, : n * n])
-    B = 2.0 * np.real(Bt[:, : n * n])
-    inten = 0.5 * C_LIGHT * np.sum(E * E, axis=-1)
-    ti, oi = np.unravel_index(int(np.argmax(inten)), inten.shape)
-    grid = inten[ti].reshape(n, n)          # [y][x]
-    iy, ix = divmod(int(oi), n)
-    dx = 2.0 * half_width / (n - 1)
-    fx, fy = _fwhm(grid[iy, :], ix, dx), _fwhm(grid[:, ix], iy, dx)
-    ecc = None
-    if fx and fy:
-        lo, hi = min(fx, fy), max(fx, fy)
-        ecc = float(np.sqrt(1.0 - (lo / hi) ** 2))
-    return {"peak_intensity_W_cm2": float(inten[ti, oi]) * 1e-4, "time_index": int(ti),
-            "peak_x_m": (ix - (n - 1) / 2) * dx, "peak_y_m": (iy - (n - 1) / 2) * dx,
-            "fwhm_x_m": fx, "fwhm_y_m": fy, "eccentricity": ecc,
-            "max_Ez_over_max_Ex": float(np.max(np.abs(E[..., 2])) / np.max(np.abs(E[..., 0]))),
-            "max_Bz_over_max_Ex": float(np.max(np.abs(B[..., 2])) / np.max(np.abs(E[..., 0])))}
+        "hbm_budget_gb": budget_gb, "quantum_ms": quantum_ms}
 
 
 def bench_table1(args):
@@ -548,12 +509,14 @@ def main():
         run_step(p, w, args.precision)
     torch.cuda.synchronize()
 
-    quad_ms = []
+    quad_ms, step_ms = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         run_step(p, w, args.precision)
         torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
         tm = p.timing()
         quad_ms.append(tm["quad_ms"])
         last_timing = tm
@@ -608,6 +571,10 @@ def main():
             "quad_launches": len(quad_ms),
         },
         "phases_ms": {k: last_timing[k] for k in ("prep_ms", "quad_ms", "reduce_ms", "time_ms")},
+        # one step is one complete solve of the workload (set-up to time samples on the device);
+        # the latency of requests of mixed sizes under load is `python bench.py --mode serve`
+        "solve_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                             "max": float(np.max(step_ms))},
     }
 
     if not args.no_fp64_form and args.precision != "fp64":
@@ -658,10 +625,18 @@ def main():
                 "quad_evals_per_s": rg, "quad_ms": min(qg), "tflops": fpg * rg / 1e12,
                 "frac_fp32_peak": fpg * rg / 1e12 / PEAK_FP32}
 
+    ctx.close()
+    if args.serve_seconds > 0 and args.shard == 1:
+        # p50 / p99 solve latency of a request stream of mixed sizes (about 0.8 of capacity by default)
+        sv = serve_run(args.serve_rate, args.serve_seconds)
+        out["serving"] = {k: sv[k] for k in ("rate_hz", "duration_s", "arrivals", "completed", "p50_ms", "p99_ms",
+                                             "evals_per_s", "device_busy_frac")}
+        out["serving"]["workload"] = ("seeded Poisson stream of sweep-like requests (mean 3.6e10 evaluations), "
+                                      "FP32-split with time transform; longer runs: --mode serve")
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
 
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 
