@@ -322,6 +322,53 @@ def serve_run(rate: float, duration: float, budget_gb: float = 200.0, quantum_ms
         "hbm_budget_gb": budget_gb, "quantum_ms": quantum_ms}
 
 
+C_LIGHT = 299792458.0   # m/s
+
+
+def _fwhm(cut: np.ndarray, i: int, dx: float):
+    """Full width at half maximum of a sampled profile around its sample i (linear interpolation of
+    the two half-maximum crossings); None if the profile does not fall to half within the samples."""
+    half = 0.5 * cut[i]
+    edges = []
+    for step in (-1, 1):
+        j = i
+        while 0 <= j + step < len(cut) and cut[j + step] >= half:
+            j += step
+        if not 0 <= j + step < len(cut):
+            return None
+        a, b = cut[j], cut[j + step]
+        edges.append((j + step * (a - half) / (a - b)) * dx)
+    return float(edges[1] - edges[0])
+
+
+def focal_spot(Et: np.ndarray, Bt: np.ndarray, n: int, half_width: float):
+    """Peak electric intensity I_E = (1/2) c E^2 of Sec. IV-B and the shape of the focal spot.
+
+    Et, Bt: time samples [n_t][n_points][3] of the analytic field on an n x n focal-plane grid over
+    +-half_width (x fastest; the physical field is 2 Re).  The field is in Lorentz-Heaviside units
+    (sqrt(J/m^3), lengths in m), so c E^2 / 2 is W/m^2.  At the time sample and point of the largest
+    intensity: the intensity, the FWHM of the intensity along x and y through that point, the
+    eccentricity sqrt(1 - (minor/major)^2) of those widths; and the largest longitudinal components
+    relative to the largest E_x over all samples (max |E_z| / max |E_x|, max |B_z| / max |E_x|)."""
+    E = 2.0 * np.real(Et[:, : n * n])
+    B = 2.0 * np.real(Bt[:, : n * n])
+    inten = 0.5 * C_LIGHT * np.sum(E * E, axis=-1)
+    ti, oi = np.unravel_index(int(np.argmax(inten)), inten.shape)
+    grid = inten[ti].reshape(n, n)          # [y][x]
+    iy, ix = divmod(int(oi), n)
+    dx = 2.0 * half_width / (n - 1)
+    fx, fy = _fwhm(grid[iy, :], ix, dx), _fwhm(grid[:, ix], iy, dx)
+    ecc = None
+    if fx and fy:
+        lo, hi = min(fx, fy), max(fx, fy)
+        ecc = float(np.sqrt(1.0 - (lo / hi) ** 2))
+    return {"peak_intensity_W_cm2": float(inten[ti, oi]) * 1e-4, "time_index": int(ti),
+            "peak_x_m": (ix - (n - 1) / 2) * dx, "peak_y_m": (iy - (n - 1) / 2) * dx,
+            "fwhm_x_m": fx, "fwhm_y_m": fy, "eccentricity": ecc,
+            "max_Ez_over_max_Ex": float(np.max(np.abs(E[..., 2])) / np.max(np.abs(E[..., 0]))),
+            "max_Bz_over_max_Ex": float(np.max(np.abs(B[..., 2])) / np.max(np.abs(E[..., 0])))}
+
+
 def bench_table1(args):
     """The Table I workload end to end with the diagnostics of Sec. IV-A: energy-normalised
     super-Gaussian spectrum (100 samples, 150 J), 400 x 400 nodes, focal plane + axis, time
