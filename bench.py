@@ -567,10 +567,10 @@ def main():
         tm = p.timing()
         quad_ms.append(tm["quad_ms"])
         last_timing = tm
-    factored = args.precision == "fp32_split" and p.factored
-    p.close()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    factored = args.precision == "fp32_split" and p.factored
+    p.close()
 
     evals = w.evals
     ms_per_step = elapsed * 1e3 / args.steps
