@@ -122,18 +122,23 @@ def test_factored_launch_shapes_and_batch_bitwise(ctx):
     from paper_1609_08146_amd import problem_from_workload
     w = workloads.broadband(n_k=5, n_nodes=64)
     p = problem_from_workload(ctx, w)
-    for fact in (True, False):
-        p.set_factoring(fact)
-        assert p.factored is fact
-        ref = None
-        for opl, fpb in [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4)]:
-            for wpb in (1, 4):
-                p.set_launch(obs_per_lane=opl, freq_per_lane=fpb, waves_per_block=wpb, chunk=1024)
-                E, B = p.evaluate("fp32_split")
-                if ref is None:
-                    ref = (E, B)
-                else:
-                    assert np.array_equal(E, ref[0]) and np.array_equal(B, ref[1]), (fact, opl, fpb, wpb)
+    # with one point 400 wavelengths out, the phase takes the fractional-turn path
+    far = np.concatenate([w.obs, [[0.0, 0.0, 400 * workloads.LAMBDA0]]])
+    for obs in (w.obs, far):
+        p.set_observation(obs)
+        for fact in (True, False):
+            p.set_factoring(fact)
+            assert p.factored is fact
+            ref = None
+            for opl, fpb in [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4)]:
+                for wpb in (1, 4):
+                    p.set_launch(obs_per_lane=opl, freq_per_lane=fpb, waves_per_block=wpb, chunk=1024)
+                    E, B = p.evaluate("fp32_split")
+                    if ref is None:
+                        ref = (E, B)
+                    else:
+                        assert np.array_equal(E, ref[0]) and np.array_equal(B, ref[1]), \
+                            (len(obs), fact, opl, fpb, wpb)
     p.close()
     ws = workloads.sweep(6)
     ws = [w.with_nodes(min(w.n_r, 80), min(w.n_phi, 48)).subset(k_idx=np.arange(min(w.n_k, 3))) for w in ws]
