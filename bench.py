@@ -40,14 +40,15 @@ import workloads  # noqa: E402
 #                                 E += Jt g 24, rho_t h 6, E += .. R 12,
 #                                 Jt h 18, B += (Jt h) x R 24              96
 # Factored current Jt = u s (a real direction u per node):
-#   per (node, point):            geometry 18, w = u x R 9                 27
-#   per (node, point, frequency): phase 2, g 2, (ik - 1/R)/R 2, h 6,
-#                                 s g 6, E += u (s g) 12, rho_t h 6,
-#                                 E += .. R 12, s h 6, B += (s h) w 12     66
+#   per (node, point):            geometry 18, 1/R^2 1, v = u/R 3,
+#                                 e = R/R^2 3, w = u x e 9                 34
+#   per (node, point, frequency): phase 2, A = s Z 6, C = rho_t Z 6,
+#                                 A m, C m (m = ik - 1/R) 12, E += v A 12,
+#                                 E += (C m) e 12, B += (A m) w 12         62
 # The kernel shares the per-(node, point) work among the FREQ_PER_LANE
 # frequencies of a lane.
 FLOPS_GEOM, FLOPS_FREQ = 18, 96
-FLOPS_GEOM_FACTORED, FLOPS_FREQ_FACTORED = 27, 66
+FLOPS_GEOM_FACTORED, FLOPS_FREQ_FACTORED = 34, 62
 FREQ_PER_LANE = 2
 
 
