@@ -106,7 +106,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--general-tables", action="store_true",
-                    help="step: never use the factored current (time the general-table layout)")
+                    help="step, batch: never use the factored current (time the general-table layout)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mode", default="step",
                     choices=["step", "batch", "serve", "copy", "table1", "valu", "convergence"],
@@ -195,6 +195,8 @@ def bench_batch(args):
     for w in ws:
         p = Problem(ctx)
         p.set_table_storage(False)
+        if args.general_tables:
+            p.set_factoring(False)
         p.set_launch(chunk=16384)
         p.set_mirror(w.f, w.a, w.n_r, w.n_phi)
         p.set_frequencies(w.k)
@@ -217,7 +219,8 @@ def bench_batch(args):
            "factored_instances": sum(1 for p in probs if p.factored),
            "tflops": flops / (quad_ms * 1e-3) / 1e12,
            "frac_fp32_peak": flops / (quad_ms * 1e-3) / 1e12 / PEAK_FP32,
-           "precision": "fp32_split", "chunk": 16384}
+           "precision": "fp32_split", "chunk": 16384,
+           "tables": "general" if args.general_tables else "factored where the current allows"}
     for p in probs:
         p.close()
     ctx.close()
