@@ -573,7 +573,7 @@ def main():
         last_timing = tm
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    factored = args.precision == "fp32_split" and p.factored
+    factored = p.factored_for(args.precision)
     p.close()
 
     evals = w.evals
@@ -610,7 +610,8 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_quad (split-form surface quadrature" + (", factored current)" if factored else ")"),
+            "kernel": ("k_quad (split-form surface quadrature" + (" in FP64" if args.precision == "fp64" else "")
+                       + (", factored current)" if factored else ")")),
             "achieved": achieved,
             "peak": peak,
             "unit": "TFLOP/s",
@@ -639,6 +640,7 @@ def main():
         p.evaluate("fp64", keep_on_device=True)
         torch.cuda.synchronize()
         q64 = p.timing()["quad_ms"]
+        fact64 = p.factored_for("fp64")
         # error of every output component of the chosen form against the FP64 form (itself held to the
         # oracle at 1e-12 by the tests) over the whole grid: max |F_c - F_c,64| / max |F_c,64| (the
         # paper's e_rel, Sec. IV-A) and the same maximum over the peak |F| of the field
@@ -655,9 +657,11 @@ def main():
         r64 = w64.evals / (q64 * 1e-3)
         rq = evals / (quad_avg * 1e-3)
         fpg = flops_per_eval(False)
+        f64 = flops_per_eval(fact64)
         out["forms"] = {
             "fp64": {"quad_evals_per_s": r64, "quad_ms": q64, "n_freq": w64.n_k,
-                     "tflops": fpg * r64 / 1e12, "frac_fp64_peak": fpg * r64 / 1e12 / PEAK_FP64},
+                     "current": "factored" if fact64 else "general tables", "flops_per_eval": f64,
+                     "tflops": f64 * r64 / 1e12, "frac_fp64_peak": f64 * r64 / 1e12 / PEAK_FP64},
             args.precision: {"quad_evals_per_s": rq, "per_component_vs_fp64": per_comp},
             "speedup_vs_fp64": rq / r64,
         }
@@ -675,6 +679,22 @@ def main():
             out["forms"]["fp32_split_general_tables"] = {
                 "quad_evals_per_s": rg, "quad_ms": min(qg), "tflops": fpg * rg / 1e12,
                 "frac_fp32_peak": fpg * rg / 1e12 / PEAK_FP32}
+        if fact64:
+            # the FP64 form on the general tables
+            p = Problem(ctx)
+            p.set_factoring(False)
+            p.set_mirror(w64.f, w64.a, w64.n_r, w64.n_phi)
+            p.set_frequencies(w64.k)
+            p.set_incident_gaussian(w64.w0, 0.0, w64.spectrum, False)
+            p.set_observation(w64.obs)
+            p.evaluate("fp64", keep_on_device=True)
+            torch.cuda.synchronize()
+            qg64 = p.timing()["quad_ms"]
+            p.close()
+            rg64 = w64.evals / (qg64 * 1e-3)
+            out["forms"]["fp64_general_tables"] = {
+                "quad_evals_per_s": rg64, "quad_ms": qg64, "tflops": fpg * rg64 / 1e12,
+                "frac_fp64_peak": fpg * rg64 / 1e12 / PEAK_FP64}
 
     ctx.close()
     if args.serve_seconds > 0 and args.shard == 1:

@@ -244,7 +244,7 @@ sc_status sc_normalize_energy(sc_prob *p, const double *eps, double e_tot, doubl
  * SC_E_STATE until the incident field is set again with keep_fp64 = 1.     */
 sc_status sc_set_table_storage(sc_prob *p, int keep_fp64);
 
-/* Factored current for SC_FP32_SPLIT.  The surface current of the integrand
+/* Factored current for SC_FP32_SPLIT and SC_FP64.  The surface current of the integrand
  * (Sec. II: J = n x B_inc, with the quadrature weight and the node phase
  * folded in) often has one real direction per node at every frequency:
  * J~[k][q] = u_q s[k][q] (the literal linearly polarised, the radially and
@@ -253,21 +253,27 @@ sc_status sc_set_table_storage(sc_prob *p, int keep_fp64);
  * n x B with k).  Then
  *   J~ g = u (s g)   and   (J~ h) x R = (s h)(u x R),
  * with u x R shared by the frequencies, so each (point, frequency, node)
- * term needs about a quarter fewer operations.  The library tests every
- * node of the FP64 tables (|J~ - u (u.J~)| <= 1e-10 max_k |J~| with u the
- * unit direction of the largest J~ of the node) and, when all pass, builds
- * FP32 tables of (s, rho~) per (k, node) (16 B) and node records of
- * (x, y, z, |r_s|, u) (32 B); otherwise the general tables are used.  The
- * sums are the same up to FP32 rounding (the same tolerance against the
- * oracle applies); results are reproducible and independent of the launch
- * shape either way, and a batch may mix factored and general problems.
+ * term needs about a third fewer operations.  The library tests every node
+ * of the FP64 tables once per table set (residual |J~ - u (u.J~)| against
+ * max_k |J~|, u the unit direction of the largest J~ of the node).  When
+ * every residual is below 1e-10, SC_FP32_SPLIT uses FP32 tables of
+ * (s, rho~) per (k, node) (16 B) and node records of (x, y, z, |r_s|, u)
+ * (32 B); when below 1e-14 (the built-in beams that factor do so to
+ * rounding), SC_FP64 uses the same records in FP64 (32 B and 64 B, built
+ * at the first FP64 evaluation); otherwise the general tables.  The sums
+ * are the same up to rounding (the same tolerances against the oracle
+ * apply); results are reproducible and independent of the launch shape
+ * either way, and a batch may mix factored and general problems.
  * enable = 1 (default) uses the factored tables whenever the test passes,
  * 0 never.  The test needs the FP64 tables: with keep_fp64 = 0 it runs when
  * the incident field is set, so enabling afterwards has no effect until the
  * field is set again.                                                      */
 sc_status sc_set_factoring(sc_prob *p, int enable);
-/* *active = 1 if SC_FP32_SPLIT evaluation of p uses the factored tables (runs
- * the test if it has not run yet).  SC_E_STATE without an incident field.  */
+/* *active = 1 if evaluation of p in precision prec uses the factored tables
+ * (runs the test if it has not run yet; always 0 for SC_FP32).  SC_E_STATE
+ * without an incident field, SC_E_INVAL for an unknown precision.         */
+sc_status sc_get_factoring_for(sc_prob *p, sc_precision prec, int *active);
+/* sc_get_factoring_for(p, SC_FP32_SPLIT, active).                          */
 sc_status sc_get_factoring(sc_prob *p, int *active);
 
 /* Observation points, [n_obs][3] doubles, n_obs >= 1.                       */

@@ -89,6 +89,7 @@ SIGNATURES = {
     "sc_set_table_storage": [V, I],
     "sc_set_factoring": [V, I],
     "sc_get_factoring": [V, ctypes.POINTER(I)],
+    "sc_get_factoring_for": [V, I, ctypes.POINTER(I)],
     "sc_set_observation": [V, P, I, I],
     "sc_evaluate": [V, I, P, P, I],
     "sc_get_result": [V, P, P, I],

@@ -272,7 +272,8 @@ class Problem:
         call("sc_set_table_storage", self.h, int(bool(keep_fp64)))
 
     def set_factoring(self, enable: bool):
-        """Use the factored current J~ = u s for "fp32_split" when the tables allow it (sc_set_factoring)."""
+        """Use the factored current J~ = u s for "fp32_split" and "fp64" when the tables allow it
+        (sc_set_factoring)."""
         call("sc_set_factoring", self.h, int(bool(enable)))
 
     @property
@@ -280,6 +281,12 @@ class Problem:
         """True if "fp32_split" evaluation uses the factored tables (sc_get_factoring)."""
         v = ctypes.c_int(0)
         call("sc_get_factoring", self.h, ctypes.byref(v))
+        return bool(v.value)
+
+    def factored_for(self, precision="fp32_split") -> bool:
+        """True if evaluation in `precision` uses the factored tables (sc_get_factoring_for)."""
+        v = ctypes.c_int(0)
+        call("sc_get_factoring_for", self.h, _prec(precision), ctypes.byref(v))
         return bool(v.value)
 
     def set_observation(self, xyz):

@@ -202,37 +202,64 @@ static void gauss_rule_cached(sc_ctx *c, int n, const std::vector<double> *out[2
 static void invalidate_tables(sc_prob *p)
 {
     p->has_tab = p->tab32_ok = p->tab32n_ok = p->has_tab64 = p->has_power = false;
-    p->fact_checked = p->fact_ok = false;
+    p->fact_checked = p->fact_ok = p->fact64_ok = p->fact32_built = p->fact64_built = false;
     p->res_prec = -1;
 }
 
-// Relative tolerance of the factoring test: the built-in beams whose current keeps one real
-// direction factor to rounding (~1e-16); the longitudinal magnetic term of the curl-consistent
-// linear beam turns the current by O(1/(k w0)) and is rejected.
+// Relative tolerances of the factoring test (residual of the current off its direction u, over the
+// node's largest |Jt|): the built-in beams whose current keeps one real direction factor to rounding
+// (~1e-16); the longitudinal magnetic term of the curl-consistent linear beam turns the current by
+// O(1/(k w0)) and is rejected.  FP64 evaluation, accurate to ~1e-13, takes the factored tables only
+// when the residual is below 1e-14.
 constexpr double FACTOR_TOL = 1e-10;
+constexpr double FACTOR_TOL_FP64 = 1e-14;
 
-// Build the factored FP32 split tables from the FP64 tables once per table set, if the current of
-// every node keeps one real direction over the frequencies (otherwise the general tables are used).
-static sc_status ensure_factored(sc_prob *p)
+// Factored tables from the FP64 tables: the test runs once per table set (one flag read back); the
+// FP32 split (need32) and FP64 (need64) tables are built when asked for and the test passed at that
+// precision's tolerance (otherwise the general tables are used).
+static sc_status ensure_factored(sc_prob *p, bool need32, bool need64)
 {
-    if (p->fact_checked || !p->allow_fact || !p->has_tab64) return SC_OK;
+    if (!p->allow_fact || !p->has_tab64) return SC_OK;
+    if (p->fact_checked) {
+        need32 = need32 && p->fact_ok && !p->fact32_built;
+        need64 = need64 && p->fact64_ok && !p->fact64_built;
+        if (!need32 && !need64) return SC_OK;
+    }
     hipStream_t st = p->ctx->stream;
     const int n_k = (int)p->k.size();
     const size_t nrec = (size_t)n_k * p->n_tot;
-    SC_TRY(p->tabf.reserve(sizeof(float) * 4 * nrec, p->alloc_stream));
-    SC_TRY(p->posf.reserve(sizeof(float) * 8 * (size_t)p->n_tot, p->alloc_stream));
+    if (need32) {
+        SC_TRY(p->tabf.reserve(sizeof(float) * 4 * nrec, p->alloc_stream));
+        SC_TRY(p->posf.reserve(sizeof(float) * 8 * (size_t)p->n_tot, p->alloc_stream));
+    }
+    if (need64) {
+        SC_TRY(p->tabf64.reserve(sizeof(double) * 4 * nrec, p->alloc_stream));
+        SC_TRY(p->posf64.reserve(sizeof(double) * 8 * (size_t)p->n_tot, p->alloc_stream));
+    }
     SC_TRY(p->fact_flag.reserve(sizeof(unsigned int), p->alloc_stream));
     HIP_TRY(launch_fill_u32(st, p->fact_flag.as<unsigned int>(), 0u, 1));
-    HIP_TRY(launch_tables_factor(st, n_k, p->n_tot, p->tab64.as<double>(), p->pos32.as<float>(), FACTOR_TOL,
-                                 p->tabf.as<float>(), p->posf.as<float>(), p->fact_flag.as<unsigned int>()));
-    unsigned int bad = 1;
-    HIP_TRY(hipMemcpyAsync(&bad, p->fact_flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    p->fact_checked = true;
-    p->fact_ok = bad == 0;
+    HIP_TRY(launch_tables_factor(st, n_k, p->n_tot, p->tab64.as<double>(), p->pos32.as<float>(),
+                                 p->pos64.as<double>(), FACTOR_TOL, FACTOR_TOL_FP64,
+                                 need32 ? p->tabf.as<float>() : nullptr, need32 ? p->posf.as<float>() : nullptr,
+                                 need64 ? p->tabf64.as<double>() : nullptr,
+                                 need64 ? p->posf64.as<double>() : nullptr, p->fact_flag.as<unsigned int>()));
+    if (!p->fact_checked) {
+        unsigned int bad = 3;
+        HIP_TRY(hipMemcpyAsync(&bad, p->fact_flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        p->fact_checked = true;
+        p->fact_ok = (bad & 1u) == 0;
+        p->fact64_ok = p->fact_ok && (bad & 2u) == 0;
+    }
+    p->fact32_built = p->fact32_built || (need32 && p->fact_ok);
+    p->fact64_built = p->fact64_built || (need64 && p->fact64_ok);
     if (!p->fact_ok) {
         p->tabf.release();
         p->posf.release();
+    }
+    if (!p->fact64_ok) {
+        p->tabf64.release();
+        p->posf64.release();
     }
     return SC_OK;
 }
@@ -249,7 +276,7 @@ static sc_status finish_tables(sc_prob *p)
     p->has_tab = true;
     p->has_tab64 = true;
     if (p->keep_fp64) return SC_OK;
-    SC_TRY(ensure_factored(p));   // needs the FP64 tables
+    SC_TRY(ensure_factored(p, true, false));   // needs the FP64 tables
     const size_t nrec = p->k.size() * (size_t)p->n_tot;
     SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
     HIP_TRY(launch_tables_cast(p->ctx->stream, (int)p->k.size(), p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
@@ -278,14 +305,23 @@ extern "C" sc_status sc_set_factoring(sc_prob *p, int enable)
     return SC_OK;
 }
 
-extern "C" sc_status sc_get_factoring(sc_prob *p, int *active)
+extern "C" sc_status sc_get_factoring_for(sc_prob *p, sc_precision prec, int *active)
 {
     if (!p || !active) return fail(SC_E_INVAL, "sc_get_factoring: NULL argument");
+    if (prec != SC_FP64 && prec != SC_FP32_SPLIT && prec != SC_FP32)
+        return fail(SC_E_INVAL, "sc_get_factoring: unknown precision %d", (int)prec);
     if (!p->has_tab) return fail(SC_E_STATE, "sc_get_factoring: no incident field set");
     DeviceGuard g(p->ctx->device);
-    SC_TRY(ensure_factored(p));
-    *active = p->allow_fact && p->fact_ok ? 1 : 0;
+    SC_TRY(ensure_factored(p, false, false));   // runs the test if it has not run yet
+    if (prec == SC_FP32_SPLIT) *active = p->allow_fact && p->fact_ok ? 1 : 0;
+    else if (prec == SC_FP64) *active = p->allow_fact && p->fact64_ok && p->has_tab64 ? 1 : 0;
+    else *active = 0;
     return SC_OK;
+}
+
+extern "C" sc_status sc_get_factoring(sc_prob *p, int *active)
+{
+    return sc_get_factoring_for(p, SC_FP32_SPLIT, active);
 }
 
 extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, int n_phi)
@@ -554,11 +590,11 @@ static sc_status scale_tables(sc_prob *p, const std::vector<double> &fac)
     if (p->has_tab64) {
         HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, 4, dfac.as<double>(), p->tab64.as<double>(), nullptr));
         p->tab32_ok = false;   // rebuilt from the scaled FP64 tables when needed
-        p->fact_checked = p->fact_ok = false;
+        p->fact_checked = p->fact_ok = p->fact64_ok = p->fact32_built = p->fact64_built = false;
     } else {
         if (p->tab32_ok)
             HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, 4, dfac.as<double>(), nullptr, p->tab32.as<float>()));
-        if (p->fact_ok)   // a factor per frequency keeps the direction: scale s and rho_t
+        if (p->fact32_built)   // a factor per frequency keeps the direction: scale s and rho_t
             HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, 2, dfac.as<double>(), nullptr, p->tabf.as<float>()));
     }
     p->tab32n_ok = false;
@@ -747,11 +783,14 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
         return fail(SC_E_STATE, "evaluate: no tables to build the FP32 tables from");
     bool fact = false;
     if (prec == SC_FP32_SPLIT && p->allow_fact) {
-        SC_TRY(ensure_factored(p));
-        fact = p->fact_ok;
+        SC_TRY(ensure_factored(p, true, false));
+        fact = p->fact32_built;
+    } else if (prec == SC_FP64 && p->allow_fact) {
+        SC_TRY(ensure_factored(p, false, true));
+        fact = p->fact64_built;
     }
     if (fact) {
-        tab = p->tabf.p;
+        tab = prec == SC_FP64 ? p->tabf64.p : p->tabf.p;
     } else if (prec == SC_FP32_SPLIT) {
         if (!p->tab32_ok) {
             SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
@@ -776,7 +815,7 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
     SC_TRY(p->resE.reserve(rs * 6 * (size_t)n_k * p->n_obs, p->alloc_stream));
     SC_TRY(p->resB.reserve(rs * 6 * (size_t)n_k * p->n_obs, p->alloc_stream));
     job.tab = tab;
-    job.pos = prec == SC_FP64 ? p->pos64.p : (fact ? p->posf.p : p->pos32.p);
+    job.pos = prec == SC_FP64 ? (fact ? p->posf64.p : p->pos64.p) : (fact ? p->posf.p : p->pos32.p);
     job.factored = fact ? 1 : 0;
     // |delta| = ||R| - |r_s|| <= |r'|, so the split phase k delta stays below k_max |r'|_max; the
     // hardware sin / cos take up to 256 turns directly (kept below 250 for the FP32 rounding of k delta)
@@ -816,6 +855,7 @@ size_t sc::footprint_bytes(int n_r, int n_phi, int n_k, int n_obs, int n_t, sc_p
     if (prec != SC_FP64) b += (size_t)n_k * n_tot * sizeof(float) * 8;                      // FP32 tables
     if (prec == SC_FP32_SPLIT)                                                               // factored tables
         b += (size_t)n_k * n_tot * sizeof(float) * 4 + n_tot * sizeof(float) * 8;
+    if (prec == SC_FP64) b += (size_t)n_k * n_tot * sizeof(double) * 4 + n_tot * sizeof(double) * 8;
     b += pad * (sizeof(double) + sizeof(float)) * 4;                                        // observation records
     b += rs * 12 * (size_t)n_k * n_obs;                                                      // results E, B
     b += rs * 12 * n_chunks * (size_t)n_k * pad;                                             // split-K partials
@@ -1113,7 +1153,7 @@ extern "C" sc_status sc_prob_device_bytes(const sc_prob *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(SC_E_INVAL, "sc_prob_device_bytes: NULL argument");
     const DevBuf *bufs[] = {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->nrm, &p->wgt,
-                            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->tabf, &p->posf,
+                            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->tabf, &p->posf, &p->tabf64, &p->posf64,
                             &p->fact_flag, &p->d_power, &p->obs64, &p->obs32, &p->resE, &p->resB, &p->partial,
                             &p->d_t, &p->tw, &p->timeE, &p->timeB};
     size_t s = 0;

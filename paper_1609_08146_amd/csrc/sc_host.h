@@ -135,9 +135,12 @@ struct sc_prob {
     bool has_tab = false, tab32_ok = false, tab32n_ok = false;
     bool keep_fp64 = true, has_tab64 = false;
     sc::DevBuf tab64, tab32, tab32n;
-    // factored FP32 split tables (current Jt = u s with a real direction u per node), built from tab64
-    bool allow_fact = true, fact_checked = false, fact_ok = false;
-    sc::DevBuf tabf, posf, fact_flag;
+    // factored tables (current Jt = u s with a real direction u per node), built from tab64: the
+    // test runs once per table set (fact_ok: FP32 split tolerance, fact64_ok: FP64 tolerance), the
+    // FP32 (tabf, posf) and FP64 (tabf64, posf64) tables are built when first needed
+    bool allow_fact = true, fact_checked = false, fact_ok = false, fact64_ok = false;
+    bool fact32_built = false, fact64_built = false;
+    sc::DevBuf tabf, posf, tabf64, posf64, fact_flag;
     // incident power per frequency through the aperture: [n_k] then the reduction scratch
     bool has_power = false;
     sc::DevBuf d_power;

@@ -43,11 +43,13 @@ int power_partial_count(int n_k);
 // 2 factored); exactly one of tab64, tab32 non-null
 hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, int n_cplx, const double *fac, double *tab64,
                                float *tab32);
-// Factored FP32 tables (Jt = u s per node): tabf [n_k][n_tot][4] = (s, rho_t), posf [n_tot][8] =
-// (x, y, z, |r_s|, u, 0); *bad (zeroed by the caller) is set when some node's current has no single
-// real direction within tol (relative to its largest |Jt| over k).
+// Factored tables (Jt = u s per node): tabf [n_k][n_tot][4] = (s, rho_t), posf [n_tot][8] =
+// (x, y, z, |r_s|, u, 0) in FP32, tabf64 / posf64 the same in FP64 (each output may be NULL);
+// *bad (zeroed by the caller) gets bit 0 when some node's current has no single real direction
+// within tol32 (relative to its largest |Jt| over k), bit 1 for tol64.
 hipError_t launch_tables_factor(hipStream_t st, int n_k, int n_tot, const double *tab64, const float *pos32,
-                                double tol, float *tabf, float *posf, unsigned int *bad);
+                                const double *pos64, double tol32, double tol64, float *tabf, float *posf,
+                                double *tabf64, double *posf64, unsigned int *bad);
 // Maxwell-residual diagnostics (sc_diag.hip).  Stencil results [rows][13 n_pts][3] complex (double
 // if is_f64, else float); work holds diag_slots() doubles per (row, point), mx 4 per row, out 1 per
 // (row, point).  The time form reads [n_t * 5][13 n_pts][3] (times t_m + (j - 2) dt).

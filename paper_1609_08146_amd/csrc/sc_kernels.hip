@@ -6,7 +6,7 @@
 //  k_tables_gaussian     same for the built-in collimated beams: linearly, radially or
 //                        azimuthally polarised Gaussian (Sec. III-A, IV-A)
 //  k_tables_cast         FP64 tables -> FP32 (split: as is; naive: node phase removed)
-//  k_tables_factor       FP64 tables -> factored FP32 tables J~ = u s, when the current
+//  k_tables_factor       FP64 tables -> factored FP32 / FP64 tables J~ = u s, when the current
 //                        of every node keeps one real direction over the frequencies
 //  k_power_*             incident power per frequency through the aperture (Sec. III-B)
 //  k_tables_scale        spectral amplitude / phase applied to the tables (Sec. III-B)
@@ -438,13 +438,16 @@ __global__ void k_tables_cast(int n_k, int n_tot, const double *__restrict__ kv,
 // spectrum, or a radially or azimuthally polarised beam): then
 // Jt[k][q] = u_q s[k][q] and the quadrature can use u_q and s.  One thread per
 // node q: u_q is the unit vector along the longer of Re Jt, Im Jt at the
-// frequency where |Jt[k][q]| is largest (u_q = 0 if Jt vanishes), s = u_q . Jt;
-// if |Jt[k][q] - u_q s[k][q]| > tol max_k |Jt[k][q]| for any k, *bad is set and
-// the tables must not be used.  Outputs (FP32): tabf[k][q] = (s, rho_t) and
-// posf[q] = (x, y, z, |r_s|, u_q, 0).
+// frequency where |Jt[k][q]| is largest (u_q = 0 if Jt vanishes), s = u_q . Jt.
+// Bit 0 of *bad is set if |Jt[k][q] - u_q s[k][q]| > tol32 max_k |Jt[k][q]|
+// for any node and k, bit 1 if it exceeds tol64; the tables of a precision
+// must not be used when its bit is set.  Outputs, each optional (NULL skips
+// it): FP32 tabf[k][q] = (s, rho_t) and posf[q] = (x, y, z, |r_s|, u_q, 0);
+// FP64 tabf64[k][q] and posf64[q], the same records in double.
 __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ tab64, const float *__restrict__ pos32,
-                                double tol, float *__restrict__ tabf, float *__restrict__ posf,
-                                unsigned int *__restrict__ bad)
+                                const double *__restrict__ pos64, double tol32, double tol64,
+                                float *__restrict__ tabf, float *__restrict__ posf, double *__restrict__ tabf64,
+                                double *__restrict__ posf64, unsigned int *__restrict__ bad)
 {
     const int64_t gq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gq >= n_tot) return;
@@ -468,8 +471,8 @@ __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ t
         const double inv = 1.0 / sqrt(part ? im2 : re2);
         for (int c = 0; c < 3; ++c) u[c] = v[2 * c + part] * inv;
     }
-    const double lim = tol * tol * best;
-    bool ok = true;
+    const double lim32 = tol32 * tol32 * best, lim64 = tol64 * tol64 * best;
+    unsigned int flags = 0;
     for (int kk = 0; kk < n_k; ++kk) {
         const int64_t rec = (int64_t)kk * n_tot + gq;
         const double *v = tab64 + rec * 8;
@@ -480,18 +483,36 @@ __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ t
             const double dr = v[2 * c] - u[c] * sr, di = v[2 * c + 1] - u[c] * si;
             r2 += dr * dr + di * di;
         }
-        if (!(r2 <= lim)) ok = false;
-        float *t = tabf + rec * 4;
-        t[0] = (float)sr;
-        t[1] = (float)si;
-        t[2] = (float)v[6];
-        t[3] = (float)v[7];
+        if (!(r2 <= lim32)) flags |= 1u;
+        if (!(r2 <= lim64)) flags |= 2u;
+        if (tabf) {
+            float *t = tabf + rec * 4;
+            t[0] = (float)sr;
+            t[1] = (float)si;
+            t[2] = (float)v[6];
+            t[3] = (float)v[7];
+        }
+        if (tabf64) {
+            double *t = tabf64 + rec * 4;
+            t[0] = sr;
+            t[1] = si;
+            t[2] = v[6];
+            t[3] = v[7];
+        }
     }
-    float *pr = posf + gq * 8;
-    for (int c = 0; c < 4; ++c) pr[c] = pos32[gq * 4 + c];
-    for (int c = 0; c < 3; ++c) pr[4 + c] = (float)u[c];
-    pr[7] = 0.0f;
-    if (!ok) atomicOr(bad, 1u);
+    if (posf) {
+        float *pr = posf + gq * 8;
+        for (int c = 0; c < 4; ++c) pr[c] = pos32[gq * 4 + c];
+        for (int c = 0; c < 3; ++c) pr[4 + c] = (float)u[c];
+        pr[7] = 0.0f;
+    }
+    if (posf64) {
+        double *pr = posf64 + gq * 8;
+        for (int c = 0; c < 4; ++c) pr[c] = pos64[gq * 4 + c];
+        for (int c = 0; c < 3; ++c) pr[4 + c] = u[c];
+        pr[7] = 0.0;
+    }
+    if (flags) atomicOr(bad, flags);
 }
 
 // Split-K reduction: E[k][o][c] = sum over chunks (in FP64, fixed order); B gets the 1/(ik) factor.
@@ -655,10 +676,11 @@ hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, int n_cplx, c
 }
 
 hipError_t launch_tables_factor(hipStream_t st, int n_k, int n_tot, const double *tab64, const float *pos32,
-                                double tol, float *tabf, float *posf, unsigned int *bad)
+                                const double *pos64, double tol32, double tol64, float *tabf, float *posf,
+                                double *tabf64, double *posf64, unsigned int *bad)
 {
-    hipLaunchKernelGGL(k_tables_factor, dim3(nblocks(n_tot, 256)), dim3(256), 0, st, n_k, n_tot, tab64, pos32, tol,
-                       tabf, posf, bad);
+    hipLaunchKernelGGL(k_tables_factor, dim3(nblocks(n_tot, 256)), dim3(256), 0, st, n_k, n_tot, tab64, pos32, pos64,
+                       tol32, tol64, tabf, posf, tabf64, posf64, bad);
     return hipGetLastError();
 }
 

@@ -275,6 +275,97 @@ __device__ __forceinline__ void freq_f64(const GeomD &g, const double *t, double
     acc[11] = __fma_rn(qxi, dy, __fma_rn(-qyi, dx, acc[11]));
 }
 
+// Factored current in FP64, one frequency: the algebra of freq_factored
+// (A = s Z, C = rho_t Z, m = ik - 1/R; E += v A + (C m) e, B += (A m) w) with
+// t = (s, rho_t) as (re, im) pairs.
+__device__ __forceinline__ void freq_f64_factored(double rinv, double delta, const double *v, const double *e,
+                                                  const double *w, const double *t, double k, double kt,
+                                                  double *acc)
+{
+    double sn, c;
+    sincos_turns_f64(kt * delta, sn, c);
+    const double ar = __fma_rn(t[0], c, -(t[1] * sn)), ai = __fma_rn(t[0], sn, t[1] * c);
+    const double cr = __fma_rn(t[2], c, -(t[3] * sn)), ci = __fma_rn(t[2], sn, t[3] * c);
+    const double amr = __fma_rn(-rinv, ar, -(k * ai)), ami = __fma_rn(-rinv, ai, k * ar);
+    const double cmr = __fma_rn(-rinv, cr, -(k * ci)), cmi = __fma_rn(-rinv, ci, k * cr);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        acc[2 * d] = __fma_rn(cmr, e[d], __fma_rn(v[d], ar, acc[2 * d]));
+        acc[2 * d + 1] = __fma_rn(cmi, e[d], __fma_rn(v[d], ai, acc[2 * d + 1]));
+        acc[6 + 2 * d] = __fma_rn(w[d], amr, acc[6 + 2 * d]);
+        acc[7 + 2 * d] = __fma_rn(w[d], ami, acc[7 + 2 * d]);
+    }
+}
+
+// One tile of the FP64 form: nodes [n0, n1) of a chunk, 64*OPL points, FPB
+// frequencies.  General layout: node records (x, y, z, |r_s|) and table
+// records (Jt.x, Jt.y, Jt.z, rho_t) as (re, im) pairs, 4 and 8 doubles;
+// factored (FACT): node records (x, y, z, |r_s|, u, 0) and table records
+// (s, rho_t), 8 and 4 doubles.  Plain FP64 sums.
+template <int OPL, int FPB, bool FACT>
+__device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
+                                         const double *k64, int n_valid)
+{
+    constexpr int PS = FACT ? 8 : 4;   // doubles per node record
+    constexpr int TS = FACT ? 4 : 8;   // doubles per table record
+    const int n_tot = job->n_tot, n_k = job->n_k, n_obs_pad = job->n_obs_pad;
+    cdouble *pos = (cdouble *)job->pos;
+    cdouble *tab[FPB];
+    double kt64[FPB];   // wavenumbers in turns per unit length
+#pragma unroll
+    for (int f = 0; f < FPB; ++f) {
+        tab[f] = (cdouble *)job->tab + (size_t)kidx[f] * n_tot * TS;
+        kt64[f] = k64[f] * INV_TWO_PI;
+    }
+    const double4 *obs = (const double4 *)job->obs;
+    double4 o[OPL];
+    double acc[OPL][FPB][12];
+#pragma unroll
+    for (int s = 0; s < OPL; ++s) {
+        o[s] = obs[obase + 64 * s];
+#pragma unroll
+        for (int f = 0; f < FPB; ++f)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[s][f][c] = 0.0;
+    }
+    for (int n = n0; n < n1; ++n) {
+        double pn[PS], tn[FPB][TS];
+#pragma unroll
+        for (int c = 0; c < PS; ++c) pn[c] = pos[PS * (size_t)n + c];
+#pragma unroll
+        for (int f = 0; f < FPB; ++f)
+#pragma unroll
+            for (int c = 0; c < TS; ++c) tn[f][c] = tab[f][TS * (size_t)n + c];
+#pragma unroll
+        for (int s = 0; s < OPL; ++s) {
+            const GeomD g = geom_f64(pn, o[s]);
+            if constexpr (FACT) {
+                // v = u / R, e = R / R^2, w = u x e, shared by the frequencies
+                const double r2 = g.rinv * g.rinv;
+                const double v[3] = {pn[4] * g.rinv, pn[5] * g.rinv, pn[6] * g.rinv};
+                const double e[3] = {g.dx * r2, g.dy * r2, g.dz * r2};
+                const double w[3] = {__fma_rn(pn[5], e[2], -(pn[6] * e[1])), __fma_rn(pn[6], e[0], -(pn[4] * e[2])),
+                                     __fma_rn(pn[4], e[1], -(pn[5] * e[0]))};
+#pragma unroll
+                for (int f = 0; f < FPB; ++f)
+                    freq_f64_factored(g.rinv, g.delta, v, e, w, tn[f], k64[f], kt64[f], acc[s][f]);
+            } else {
+#pragma unroll
+                for (int f = 0; f < FPB; ++f) freq_f64(g, tn[f], k64[f], kt64[f], acc[s][f]);
+            }
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < FPB; ++f) {
+        if (f >= n_valid) break;
+        double *part = (double *)job->partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
+#pragma unroll
+        for (int s = 0; s < OPL; ++s)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) part[(size_t)c * n_obs_pad + obase + 64 * s] = acc[s][f][c];
+    }
+}
+
 // Map a global tile index to its job (binary search over tile0; uniform).
 __device__ __forceinline__ int find_job(cjob *jobs, int n_jobs, int64_t t)
 {
@@ -463,7 +554,7 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
         const int64_t rest = local / obs_blocks;
         const int chunk = (int)(rest % n_chunks);
         const int kb = (int)(rest / n_chunks);
-        const int n_tot = jobs[j].n_tot, n_k = jobs[j].n_k, n_obs_pad = jobs[j].n_obs_pad;
+        const int n_tot = jobs[j].n_tot, n_k = jobs[j].n_k;
         const int n0 = chunk * jobs[j].chunk;
         const int n1 = min(n0 + jobs[j].chunk, n_tot);
         const int obase = ob * 64 * OPL + lane;
@@ -478,48 +569,8 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
         const int n_valid = min(FPB, n_k - kb * FPB);
 
         if constexpr (MODE == MODE_FP64) {
-            cdouble *pos = (cdouble *)jobs[j].pos;
-            cdouble *tab[FPB];
-#pragma unroll
-            for (int f = 0; f < FPB; ++f) tab[f] = (cdouble *)jobs[j].tab + (size_t)kidx[f] * n_tot * 8;
-            const double4 *obs = (const double4 *)jobs[j].obs;
-            double kt64[FPB];   // wavenumbers in turns per unit length
-#pragma unroll
-            for (int f = 0; f < FPB; ++f) kt64[f] = k64[f] * INV_TWO_PI;
-            double4 o[OPL];
-            double acc[OPL][FPB][12];
-#pragma unroll
-            for (int s = 0; s < OPL; ++s) {
-                o[s] = obs[obase + 64 * s];
-#pragma unroll
-                for (int f = 0; f < FPB; ++f)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) acc[s][f][c] = 0.0;
-            }
-            for (int n = n0; n < n1; ++n) {
-                double pn[4], tn[FPB][8];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) pn[c] = pos[4 * (size_t)n + c];
-#pragma unroll
-                for (int f = 0; f < FPB; ++f)
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) tn[f][c] = tab[f][8 * (size_t)n + c];
-#pragma unroll
-                for (int s = 0; s < OPL; ++s) {
-                    const GeomD g = geom_f64(pn, o[s]);
-#pragma unroll
-                    for (int f = 0; f < FPB; ++f) freq_f64(g, tn[f], k64[f], kt64[f], acc[s][f]);
-                }
-            }
-#pragma unroll
-            for (int f = 0; f < FPB; ++f) {
-                if (f >= n_valid) break;
-                double *part = (double *)jobs[j].partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
-#pragma unroll
-                for (int s = 0; s < OPL; ++s)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) part[(size_t)c * n_obs_pad + obase + 64 * s] = acc[s][f][c];
-            }
+            if (jobs[j].factored) tile_f64<OPL, FPB, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+            else tile_f64<OPL, FPB, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
         } else if constexpr (MODE == MODE_SPLIT) {
             // per job (not per tile), so the bits of a point do not depend on the launch shape
             const bool raw = jobs[j].raw_phase != 0;

@@ -55,8 +55,10 @@ def test_which_fields_factor(ctx, beam, consistent, w0, expect):
     p.set_incident_beam(beam, w0, 0.3 if beam == 0 else 0.0, spec, bool(consistent))
     p.set_observation(np.zeros((1, 3)))
     assert p.factored is expect
+    # the beams that factor at all do so to rounding, below the FP64 form's tolerance too
+    assert p.factored_for("fp64") is expect and p.factored_for("fp32") is False
     p.set_factoring(False)
-    assert p.factored is False
+    assert p.factored is False and p.factored_for("fp64") is False
     p.set_factoring(True)
     assert p.factored is expect
     p.close()
@@ -69,7 +71,7 @@ def test_random_tables_do_not_factor(ctx):
     p.set_frequencies([6.0, 7.0])
     Ei, Bi = workloads.random_incident_tables(2, 13 * 8, seed=3)
     p.set_incident(Ei, Bi)
-    assert p.factored is False
+    assert p.factored is False and p.factored_for("fp64") is False
     p.close()
 
 
@@ -173,4 +175,76 @@ def test_spectrum_scaling_on_fp32_only_factored_tables(ctx, orc):
     err = max(rel_l2(E1, Eo), rel_l2(B1, Bo))
     print(f"scaled factored FP32-only tables vs oracle: {err:.2e}")
     assert err < 1e-5
+    q.close()
+
+
+@pytest.mark.parametrize("name", ["broadband", "stress"])
+def test_fp64_factored_and_general_match_the_oracle(ctx, orc, name):
+    """The FP64 form on the factored tables: the oracle's tolerance for FP64 (1e-12 relative L2
+    per field), and within 1e-13 of the FP64 form on the general tables."""
+    from paper_1609_08146_amd import problem_from_workload
+    if name == "broadband":
+        w = workloads.broadband(n_k=128, n_nodes=120)
+        sub = w.subset(obs_idx=np.arange(0, w.n_obs, 29), k_idx=np.arange(0, 128, 21))
+    else:                                   # kR up to 1.6e6 rad
+        w = workloads.stress(n_k=64, n_nodes=200)
+        sub = w.subset(obs_idx=np.arange(0, w.n_obs, 1023), k_idx=[0, 31, 63])
+    Eo, Bo = orc.solve(sub)
+    p = problem_from_workload(ctx, sub)
+    assert p.factored_for("fp64")
+    Ef, Bf = p.evaluate("fp64")
+    p.set_factoring(False)
+    assert not p.factored_for("fp64")
+    Eg, Bg = p.evaluate("fp64")
+    errs = dict(factored=max(rel_l2(Ef, Eo), rel_l2(Bf, Bo)), general=max(rel_l2(Eg, Eo), rel_l2(Bg, Bo)),
+                between=max(rel_l2(Ef, Eg), rel_l2(Bf, Bg)))
+    print(name, {k: f"{v:.2e}" for k, v in errs.items()})
+    assert errs["factored"] < 1e-12 and errs["general"] < 1e-12
+    assert errs["between"] < 1e-13
+    p.close()
+
+
+def test_fp64_factored_launch_shapes_batch_and_rescaling(ctx, orc):
+    """FP64 on the factored tables: launch shapes keep the bits, a batch mixing factored and
+    general FP64 problems keeps each problem's bits, and a spectral factor applied after the
+    factored FP64 tables were built rebuilds them (the field equals the oracle's for the scaled
+    spectrum)."""
+    from paper_1609_08146_amd import problem_from_workload
+    w = workloads.broadband(n_k=5, n_nodes=64)
+    p = problem_from_workload(ctx, w)
+    assert p.factored_for("fp64")
+    ref = None
+    for opl, fpb in [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4)]:
+        p.set_launch(obs_per_lane=opl, freq_per_lane=fpb, waves_per_block=2, chunk=1024)
+        E, B = p.evaluate("fp64")
+        if ref is None:
+            ref = (E, B)
+        else:
+            assert np.array_equal(E, ref[0]) and np.array_equal(B, ref[1]), (opl, fpb)
+    p.close()
+
+    ws = workloads.sweep(4)
+    ws = [w.with_nodes(min(w.n_r, 60), min(w.n_phi, 40)).subset(k_idx=np.arange(min(w.n_k, 2))) for w in ws]
+    ws[1] = replace(ws[1], consistent=1)          # does not factor
+    probs = [problem_from_workload(ctx, w) for w in ws]
+    assert [q.factored_for("fp64") for q in probs] == [True, False, True, True]
+    alone = [q.evaluate("fp64") for q in probs]
+    ctx.evaluate_batch(probs, "fp64")
+    for q, (E, B) in zip(probs, alone):
+        Eb, Bb = q.result()
+        assert np.array_equal(E, Eb) and np.array_equal(B, Bb)
+    for q in probs:
+        q.close()
+
+    w = workloads.broadband(n_k=6, n_nodes=70).subset(obs_idx=np.arange(0, 4160, 53))
+    fac = 0.7 * np.exp(1j * np.linspace(0.0, 3.0, w.n_k))
+    q = problem_from_workload(ctx, w)
+    q.evaluate("fp64")                            # builds the factored FP64 tables
+    q.scale_spectrum(fac)
+    assert q.factored_for("fp64")
+    E1, B1 = q.evaluate("fp64")
+    Eo, Bo = orc.solve(replace(w, spectrum=w.spectrum * fac))
+    err = max(rel_l2(E1, Eo), rel_l2(B1, Bo))
+    print(f"rescaled factored FP64 tables vs oracle: {err:.2e}")
+    assert err < 1e-12
     q.close()
