@@ -6,7 +6,7 @@
 //               per job either general tables or the factored current
 //               J~ = u s (a real direction u per node, a complex s per
 //               frequency and node), which needs fewer operations per pair
-//   MODE_FP64   the same split form in FP64
+//   MODE_FP64   the same split form in FP64, on either table layout
 //   MODE_NAIVE  the whole phase k|R| per pair in FP32 (the precision ablation)
 //
 // All floating-point expressions are written with explicit fma/mul/add and

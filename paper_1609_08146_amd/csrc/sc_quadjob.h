@@ -11,8 +11,8 @@ namespace sc {
 //   local = (k * n_chunks + chunk) * obs_blocks + obs_block
 // so that waves running side by side share (k, chunk) table data.
 struct QuadJob {
-    const void *tab;      // [n_k][n_tot][8] real (float or double); factored: [n_k][n_tot][4] float
-    const void *pos;      // [n_tot][4] real; factored: [n_tot][8] float
+    const void *tab;      // [n_k][n_tot][8] real (float or double); factored: [n_k][n_tot][4] real
+    const void *pos;      // [n_tot][4] real; factored: [n_tot][8] real
     const void *obs;      // [n_obs_pad][4] real
     const double *k;      // [n_k]
     void *partial;        // [n_chunks][n_k][12][n_obs_pad] real
@@ -22,7 +22,7 @@ struct QuadJob {
     int chunk;            // nodes per split-K chunk
     int n_chunks;
     int obs_blocks;       // n_obs_pad / (64 * obs_per_lane)
-    int factored;         // FP32 split form with the current factored as J~ = u s (u real, per node)
+    int factored;         // split form (FP32 or FP64) with the current factored as J~ = u s (u real, per node)
     int raw_phase;        // FP32 split form: |k delta| / 2 pi < 250 turns for every pair of the job
     int64_t tile0;        // first global tile of this job in the launch
     int64_t tile_offset;  // first job-local tile covered (a launch may cover a sub-range)
