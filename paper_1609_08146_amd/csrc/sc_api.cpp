@@ -286,6 +286,10 @@ static sc_status finish_tables(sc_prob *p)
     if (!p->tab64.stream) HIP_TRY(hipStreamSynchronize(p->ctx->stream));
     p->tab64.release();
     p->has_tab64 = false;
+    // without the FP64 tables there is no FP64 evaluation, so its factored tables go too
+    p->tabf64.release();
+    p->posf64.release();
+    p->fact64_built = false;
     return SC_OK;
 }
 
@@ -857,6 +861,7 @@ size_t sc::footprint_bytes(int n_r, int n_phi, int n_k, int n_obs, int n_t, sc_p
         b += (size_t)n_k * n_tot * sizeof(float) * 4 + n_tot * sizeof(float) * 8;
     if (prec == SC_FP64) b += (size_t)n_k * n_tot * sizeof(double) * 4 + n_tot * sizeof(double) * 8;
     b += pad * (sizeof(double) + sizeof(float)) * 4;                                        // observation records
+    b += sizeof(double) * (2 * (size_t)n_k + 3 * (size_t)n_obs);                             // upload staging
     b += rs * 12 * (size_t)n_k * n_obs;                                                      // results E, B
     b += rs * 12 * n_chunks * (size_t)n_k * pad;                                             // split-K partials
     if (n_t > 0) b += sizeof(double) * ((size_t)n_t + 2 * (size_t)n_t * n_k) + rs * 12 * (size_t)n_t * n_obs;
@@ -1155,7 +1160,7 @@ extern "C" sc_status sc_prob_device_bytes(const sc_prob *p, size_t *bytes)
     const DevBuf *bufs[] = {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->nrm, &p->wgt,
                             &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->tabf, &p->posf, &p->tabf64, &p->posf64,
                             &p->fact_flag, &p->d_power, &p->obs64, &p->obs32, &p->resE, &p->resB, &p->partial,
-                            &p->d_t, &p->tw, &p->timeE, &p->timeB};
+                            &p->d_t, &p->tw, &p->timeE, &p->timeB, &p->d_spec, &p->d_obs_in};
     size_t s = 0;
     for (const DevBuf *b : bufs) s += b->bytes;
     *bytes = s;

@@ -248,3 +248,26 @@ def test_fp64_factored_launch_shapes_batch_and_rescaling(ctx, orc):
     print(f"rescaled factored FP64 tables vs oracle: {err:.2e}")
     assert err < 1e-12
     q.close()
+
+
+def test_releasing_the_fp64_tables_releases_their_factored_copy(ctx):
+    """Dropping the FP64 tables (sc_set_table_storage(p, 0)) after an FP64 evaluation built the
+    factored FP64 records frees those too: FP64 evaluation is refused, the split form still runs
+    on its factored FP32 tables, and the device footprint shrinks by both FP64 layouts less the
+    FP32 general tables the release casts (64 + 32 - 32 B per (k, node), 64 B per node)."""
+    from paper_1609_08146_amd import problem_from_workload, ScError
+    w = workloads.broadband(n_k=6, n_nodes=60).subset(obs_idx=np.arange(0, 4160, 97))
+    p = problem_from_workload(ctx, w)
+    E32, B32 = p.evaluate("fp32_split")
+    p.evaluate("fp64")
+    before = p.device_bytes()
+    n_tot = (w.n_r + 1) * w.n_phi
+    p.set_table_storage(False)
+    after = p.device_bytes()
+    assert before - after >= w.n_k * n_tot * 64 + n_tot * 64   # 32 B per (k, node) less if kept
+    assert not p.factored_for("fp64") and p.factored
+    with pytest.raises(ScError):
+        p.evaluate("fp64")
+    E, B = p.evaluate("fp32_split")
+    assert np.array_equal(E, E32) and np.array_equal(B, B32)
+    p.close()
