@@ -161,26 +161,46 @@ def _time_out(w, precision):
     return _TIME_BUF[key]
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, target_s):
     import oracle
     oracle.build()
     threads = oracle.max_threads()
     # calibrate on a small sample (long enough that thread start-up does not dominate), then size
-    # the sample to ~target_s of work
+    # the sample to ~target_s of work; thread counts are passed explicitly (the setting persists)
     n_probe = max(threads, 16)
     probe = w.subset(obs_idx=np.linspace(0, w.n_obs - 1, n_probe).astype(int), k_idx=np.arange(min(4, w.n_k)))
     t0 = time.perf_counter()
-    oracle.solve(probe)
+    oracle.solve(probe, threads=threads)
     rate = probe.evals / (time.perf_counter() - t0)
     n_obs = int(max(threads, min(w.n_obs, target_s * rate / (w.n_k * w.n_nodes))))
     idx = np.linspace(0, w.n_obs - 1, n_obs).astype(int)
     sample = w.subset(obs_idx=idx)
     t0 = time.perf_counter()
-    oracle.solve(sample)
+    oracle.solve(sample, threads=threads)
     dt = time.perf_counter() - t0
+    # one thread, for comparison with the paper's per-core rate (Sec. III-C-3): 2 points x 4 frequencies
+    one = w.subset(obs_idx=np.linspace(0, w.n_obs - 1, 2).astype(int), k_idx=np.arange(min(4, w.n_k)))
+    t0 = time.perf_counter()
+    oracle.solve(one, threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": sample.evals / dt, "unit": "integrand evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_obs} evenly spaced observation points x all {w.n_k} shard frequencies x "
-                      f"{w.n_nodes} surface nodes (+ rim), FP64 with long-double phase, {dt:.1f} s"}
+                      f"{w.n_nodes} surface nodes (+ rim), FP64 with long-double phase, {dt:.1f} s",
+            "cpu_model": _cpu_model(),
+            "single_thread_value": one.evals / dt1,
+            "single_thread_sample": f"2 observation points x {one.n_k} frequencies x {w.n_nodes} surface nodes, "
+                                    f"one thread, {dt1:.1f} s"}
 
 
 def bench_batch(args):
