@@ -271,3 +271,33 @@ def test_releasing_the_fp64_tables_releases_their_factored_copy(ctx):
     E, B = p.evaluate("fp32_split")
     assert np.array_equal(E, E32) and np.array_equal(B, B32)
     p.close()
+
+
+def test_current_that_factors_only_at_the_split_tolerance(ctx, orc):
+    """Tables whose current turns by ~3e-12 of its size from node direction u (a Gaussian beam's
+    B plus a small random field, set through sc_set_incident) pass the split form's factoring
+    test (1e-10) but not the FP64 form's (1e-14): FP32-split takes the factored tables, FP64 the
+    general ones, and each stays within its tolerance of the oracle on the same tables."""
+    from paper_1609_08146_amd import Problem
+    f, a, nr, nphi = 20.0, 40.0, 40, 24
+    ks = np.array([2 * np.pi, 2.3 * np.pi])
+    m = orc.mirror(f, a, nr, nphi)
+    Ei, Bi = orc.incident_tables(m, ks, orc.GAUSSIAN, 20.0)
+    rng = np.random.default_rng(21)
+    noise = rng.normal(size=Bi.shape) + 1j * rng.normal(size=Bi.shape)
+    Bi = Bi + 3e-12 * np.abs(Bi).max(axis=-1, keepdims=True) * noise
+    obs = workloads.random_points(64, 2.0, seed=4)
+    Eo, Bo = orc.reflected_field(m, ks, Ei, Bi, obs)
+    p = Problem(ctx)
+    p.set_mirror(f, a, nr, nphi)
+    p.set_frequencies(ks)
+    p.set_incident(Ei, Bi)
+    p.set_observation(obs)
+    assert p.factored and not p.factored_for("fp64")
+    E32, B32 = p.evaluate("fp32_split")
+    E64, B64 = p.evaluate("fp64")
+    e32 = max(rel_l2(E32, Eo), rel_l2(B32, Bo))
+    e64 = max(rel_l2(E64, Eo), rel_l2(B64, Bo))
+    print(f"split (factored) {e32:.2e}, fp64 (general) {e64:.2e}")
+    assert e32 < 1e-5 and e64 < 1e-12
+    p.close()
