@@ -46,7 +46,10 @@ import workloads  # noqa: E402
 #                                 A m, C m (m = ik - 1/R) 12, E += v A 12,
 #                                 E += (C m) e 12, B += (A m) w 12         62
 # The kernel shares the per-(node, point) work among the FREQ_PER_LANE
-# frequencies of a lane.
+# frequencies of a lane.  Where the observation points lie within 4e-4 |r_s|
+# of the focus, the factored kernel forms delta by a short series instead of a
+# reciprocal (4 more flops per (node, point), not counted: the constant stays
+# the formula's).
 FLOPS_GEOM, FLOPS_FREQ = 18, 96
 FLOPS_GEOM_FACTORED, FLOPS_FREQ_FACTORED = 34, 62
 FREQ_PER_LANE = 2

@@ -377,6 +377,7 @@ extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, 
                                p->pos32.as<float>(), p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>()));
     p->f = f;
     p->a = r_max;
+    p->rs_min = f;   // |r_s| = r^2 / 4f + f on the paraboloid (distance to the focus)
     p->n_r = n_r;
     p->n_phi = n_phi;
     p->n_surf = n_r * n_phi;
@@ -430,6 +431,13 @@ extern "C" sc_status sc_set_surface(sc_prob *p, int n_surf, const double *xyz, c
                                    d_rn.as<double>(), d_rdl.as<double>(), p->pos64.as<double>(), p->pos32.as<float>(),
                                    p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>()));
     HIP_TRY(hipStreamSynchronize(st));   // staging buffers are freed on return
+    double rs2 = INFINITY;
+    for (int i = 0; i < n_surf; ++i)
+        rs2 = std::min(rs2, xyz[3 * i] * xyz[3 * i] + xyz[3 * i + 1] * xyz[3 * i + 1] + xyz[3 * i + 2] * xyz[3 * i + 2]);
+    for (int j = 0; j < n_rim; ++j)
+        rs2 = std::min(rs2, rim_xyz[3 * j] * rim_xyz[3 * j] + rim_xyz[3 * j + 1] * rim_xyz[3 * j + 1] +
+                                rim_xyz[3 * j + 2] * rim_xyz[3 * j + 2]);
+    p->rs_min = std::sqrt(rs2);
     p->f = p->a = 0.0;
     p->n_r = p->n_phi = 0;
     p->n_surf = n_surf;
@@ -828,6 +836,13 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
         const double tmax = p->obs_r2max >= 0.0 ? kmax / (2.0 * M_PI) * std::sqrt(p->obs_r2max) : 1e300;
         job.raw_phase = prec == SC_FP32_SPLIT && tmax < 250.0 ? 1 : 0;
     }
+    // delta = (|r'|^2 - 2 r_s.r') / (|R| + |r_s|) by its series in x = delta_1 / (2|r_s|), where
+    // |x| <= |r'| / (2|r_s|) <= 2e-4 keeps the truncation (5 x^3, relative) far below FP32 rounding
+    // (the factored node records carry 1 / (2|r_s|)); per job, like the phase path
+    job.series_delta = prec == SC_FP32_SPLIT && fact && p->rs_min > 0.0 && p->obs_r2max >= 0.0 &&
+                               std::sqrt(p->obs_r2max) <= 4e-4 * p->rs_min
+                           ? 1
+                           : 0;
     job.obs = prec == SC_FP64 ? p->obs64.p : p->obs32.p;
     job.k = p->d_k.as<double>();
     job.partial = p->partial.p;

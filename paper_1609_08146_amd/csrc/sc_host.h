@@ -144,6 +144,8 @@ struct sc_prob {
     // incident power per frequency through the aperture: [n_k] then the reduction scratch
     bool has_power = false;
     sc::DevBuf d_power;
+    // lower bound of |r_s| over the nodes (the paraboloid: f), -1 if unknown
+    double rs_min = -1.0;
     // observation points; obs_r2max = max |r'|^2 when they came from host memory, else -1
     int n_obs = 0, n_obs_pad = 0;
     double obs_r2max = -1.0;

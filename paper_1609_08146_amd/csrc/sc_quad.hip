@@ -67,6 +67,28 @@ __device__ __forceinline__ GeomF geom_split(const v4f p, const v4f o)
     return g;
 }
 
+// The same geometry with delta from its series: delta (2|r_s| + delta) = num,
+// so with h = 1 / (2|r_s|), delta_1 = num h and x = delta_1 h,
+//   delta = delta_1 (1 - x + 2 x^2 - 5 x^3 + ...)   (Catalan numbers).
+// The caller guarantees |x| <= |r'| / (2|r_s|) <= 2e-4, where the omitted
+// terms (5 |x|^3 relative) are far below the FP32 rounding of delta.  No
+// reciprocal and no |R| on the way to the phase.
+__device__ __forceinline__ GeomF geom_series(const v4f p, const v4f o, float h)
+{
+    GeomF g;
+    g.dx = p.x - o.x;
+    g.dy = p.y - o.y;
+    g.dz = p.z - o.z;
+    const float R2 = __fmaf_rn(g.dx, g.dx, __fmaf_rn(g.dy, g.dy, g.dz * g.dz));
+    g.rinv = __builtin_amdgcn_rsqf(R2);
+    const float dot = __fmaf_rn(p.x, o.x, __fmaf_rn(p.y, o.y, p.z * o.z));
+    const float num = __fmaf_rn(-2.0f, dot, o.w);
+    const float d1 = num * h;
+    const float x = d1 * h;
+    g.delta = d1 * __fmaf_rn(x, __fmaf_rn(2.0f, x, -1.0f), 1.0f);
+    return g;
+}
+
 // Accumulate one (node, point, frequency) term given e^{i theta} = (c, s):
 //   gt = e^{i theta} / R,  ht = (ik - 1/R) gt / R,
 //   acc[0..5] += Jt gt + rho_t ht R   (E),   acc[6..11] += (Jt ht) x R   (B before 1/ik).
@@ -387,11 +409,13 @@ constexpr int KAHAN_BLOCK = 128;
 
 // One tile of the FP32 forms: nodes [n0, n1) of a chunk, 64*OPL points, FPB
 // frequencies.  FACT selects the factored layout: node records of two v4f
-// (x, y, z, |r_s|), (u, 0) and one v4f (s, rho_t) per table record, instead of
+// (x, y, z, |r_s|), (u, 1 / (2|r_s|)) and one v4f (s, rho_t) per table record, instead of
 // one v4f node record and two v4f (Jt.x, Jt.y), (Jt.z, rho_t) per table record.
 // RAW passes the split phase k delta / 2 pi to the hardware sin / cos without
 // taking its fractional part (the job guarantees it stays below 250 turns).
-template <int MODE, int OPL, int FPB, bool FACT, bool RAW>
+// SER (factored layout only) forms delta by its series (geom_series) from
+// h = 1 / (2|r_s|) in the node record (the job guarantees |r'| <= 4e-4 |r_s|).
+template <int MODE, int OPL, int FPB, bool FACT, bool RAW, bool SER = false>
 __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
                                          const double *k64, int n_valid)
 {
@@ -455,7 +479,7 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
 #pragma unroll
         for (int s = 0; s < OPL; ++s) {
             if constexpr (MODE == MODE_SPLIT && FACT) {
-                const GeomF g = geom_split(pn, o[s]);
+                const GeomF g = SER ? geom_series(pn, o[s], un.w) : geom_split(pn, o[s]);
                 // v = u / R, e = R / R^2, w = u x e, shared by the frequencies
                 const float r2 = g.rinv * g.rinv;
                 const float vx = un.x * g.rinv, vy = un.y * g.rinv, vz = un.z * g.rinv;
@@ -575,8 +599,16 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
             // per job (not per tile), so the bits of a point do not depend on the launch shape
             const bool raw = jobs[j].raw_phase != 0;
             if (jobs[j].factored) {
-                if (raw) tile_f32<MODE, OPL, FPB, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
-                else tile_f32<MODE, OPL, FPB, true, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                const bool ser = jobs[j].series_delta != 0;
+                if (raw && ser)
+                    tile_f32<MODE, OPL, FPB, true, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                else if (raw)
+                    tile_f32<MODE, OPL, FPB, true, true, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                else if (ser)
+                    tile_f32<MODE, OPL, FPB, true, false, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                else
+                    tile_f32<MODE, OPL, FPB, true, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64,
+                                                                 n_valid);
             } else {
                 if (raw) tile_f32<MODE, OPL, FPB, false, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
                 else tile_f32<MODE, OPL, FPB, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
