@@ -26,6 +26,7 @@ namespace sc {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(4))) const v4f cv4f;
 typedef __attribute__((address_space(4))) const double cdouble;
+typedef __attribute__((address_space(4))) const float cfloat;
 typedef __attribute__((address_space(4))) const QuadJob cjob;
 
 // sin and cos of theta = 2 pi * t, t in turns, with the hardware v_sin / v_cos.
@@ -413,8 +414,9 @@ constexpr int KAHAN_BLOCK = 128;
 // one v4f node record and two v4f (Jt.x, Jt.y), (Jt.z, rho_t) per table record.
 // RAW passes the split phase k delta / 2 pi to the hardware sin / cos without
 // taking its fractional part (the job guarantees it stays below 250 turns).
-// SER (factored layout only) forms delta by its series (geom_series) from
-// h = 1 / (2|r_s|) in the node record (the job guarantees |r'| <= 4e-4 |r_s|).
+// SER forms delta by its series (geom_series) from h = 1 / (2|r_s|), in the
+// node record of the factored layout or the job's per-node array otherwise
+// (the job guarantees |r'| <= 4e-4 |r_s|).
 template <int MODE, int OPL, int FPB, bool FACT, bool RAW, bool SER = false>
 __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
                                          const double *k64, int n_valid)
@@ -457,8 +459,12 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
 #pragma unroll
             for (int c = 0; c < 12; ++c) blk[s][f][c] = 0.0f;
     // node data of node n+1 is loaded while node n is computed
+    constexpr bool HV = SER && !FACT;   // h from the per-node array
+    cfloat *hv = (cfloat *)job->hinv;
     v4f pn = pos[PS * n0], un = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (FACT) un = pos[PS * n0 + 1];
+    float hn = 0.0f;
+    if constexpr (HV) hn = hv[n0];
     v4f t0[FPB], t1[FPB];
 #pragma unroll
     for (int f = 0; f < FPB; ++f) {
@@ -470,6 +476,8 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
         const v4f pnx = pos[PS * nx];
         v4f unx = un;
         if constexpr (FACT) unx = pos[PS * nx + 1];
+        float hnx = hn;
+        if constexpr (HV) hnx = hv[nx];
         v4f t0x[FPB], t1x[FPB];
 #pragma unroll
         for (int f = 0; f < FPB; ++f) {
@@ -492,7 +500,7 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
                     freq_factored<RAW>(g.rinv, g.delta, vx, vy, vz, ex, ey, ez, wx, wy, wz, t0[f], k[f], kt[f],
                                        blk[s][f]);
             } else if constexpr (MODE == MODE_SPLIT) {
-                const GeomF g = geom_split(pn, o[s]);
+                const GeomF g = SER ? geom_series(pn, o[s], hn) : geom_split(pn, o[s]);
 #pragma unroll
                 for (int f = 0; f < FPB; ++f) freq_split<RAW>(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
             } else {
@@ -521,6 +529,7 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
         }
         pn = pnx;
         un = unx;
+        hn = hnx;
 #pragma unroll
         for (int f = 0; f < FPB; ++f) {
             t0[f] = t0x[f];
@@ -610,8 +619,18 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
                     tile_f32<MODE, OPL, FPB, true, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64,
                                                                  n_valid);
             } else {
-                if (raw) tile_f32<MODE, OPL, FPB, false, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
-                else tile_f32<MODE, OPL, FPB, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                const bool ser = jobs[j].series_delta != 0;
+                if (raw && ser)
+                    tile_f32<MODE, OPL, FPB, false, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                else if (raw)
+                    tile_f32<MODE, OPL, FPB, false, true, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64,
+                                                                 n_valid);
+                else if (ser)
+                    tile_f32<MODE, OPL, FPB, false, false, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64,
+                                                                 n_valid);
+                else
+                    tile_f32<MODE, OPL, FPB, false, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64,
+                                                                  n_valid);
             }
         } else {
             tile_f32<MODE, OPL, FPB, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
