@@ -276,7 +276,13 @@ sc_status sc_get_factoring_for(sc_prob *p, sc_precision prec, int *active);
 /* sc_get_factoring_for(p, SC_FP32_SPLIT, active).                          */
 sc_status sc_get_factoring(sc_prob *p, int *active);
 
-/* Observation points, [n_obs][3] doubles, n_obs >= 1.                       */
+/* Observation points, [n_obs][3] doubles, n_obs >= 1 (host or device per
+ * on_device).  From host points the library also takes max |r'|, which lets
+ * SC_FP32_SPLIT skip the fractional-turn reduction of the per-pair phase
+ * (k_max |r'| / 2pi < 250 turns) and form delta = |r_s - r'| - |r_s| by a
+ * short series (|r'| <= 4e-4 |r_s| on every node); the choice is per problem
+ * and changes the rounding, not the tolerance.  Device points always take
+ * the general forms.                                                        */
 sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs, int on_device);
 
 /* Evaluate the reflected spectral field at every (observation point, k).
