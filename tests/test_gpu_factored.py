@@ -301,3 +301,32 @@ def test_current_that_factors_only_at_the_split_tolerance(ctx, orc):
     print(f"split (factored) {e32:.2e}, fp64 (general) {e64:.2e}")
     assert e32 < 1e-5 and e64 < 1e-12
     p.close()
+
+
+@pytest.mark.parametrize("factored", [True, False])
+def test_delta_by_series_and_by_division(ctx, orc, factored):
+    """delta = |r_s - r'| - |r_s| comes from its series when every point lies within 4e-4 |r_s|
+    (here f = 0.1 m, points within 4 wavelengths), else from the division.  One point 100
+    wavelengths out switches the series off while the phase still skips the fractional turn
+    (121 turns), so the two problems differ in delta alone.  Both match the oracle on the near
+    points, and each other to FP32 rounding, on either table layout."""
+    from paper_1609_08146_amd import problem_from_workload
+    w = workloads.broadband(n_k=6, n_nodes=60)
+    near = w.obs[::41]
+    far = np.array([[0.0, 0.0, 100 * workloads.LAMBDA0]])
+    sub = replace(w, obs=near)
+    Eo, Bo = orc.solve(sub)
+    p = problem_from_workload(ctx, sub)
+    p.set_factoring(factored)
+    assert p.factored is factored
+    Es, Bs = p.evaluate("fp32_split")
+    p.set_observation(np.concatenate([near, far]))
+    Ed, Bd = p.evaluate("fp32_split")
+    Ed, Bd = Ed[:, : len(near)], Bd[:, : len(near)]
+    errs = dict(series=max(rel_l2(Es, Eo), rel_l2(Bs, Bo)), division=max(rel_l2(Ed, Eo), rel_l2(Bd, Bo)),
+                between=max(rel_l2(Es, Ed), rel_l2(Bs, Bd)))
+    print("factored" if factored else "general", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert errs["series"] < 1e-5 and errs["division"] < 1e-5
+    assert errs["between"] < 2e-6
+    assert not np.array_equal(Es, Ed)          # the two paths really differ in rounding
+    p.close()
