@@ -47,9 +47,9 @@ import workloads  # noqa: E402
 #                                 E += (C m) e 12, B += (A m) w 12         62
 # The kernel shares the per-(node, point) work among the FREQ_PER_LANE
 # frequencies of a lane.  Where the observation points lie within 4e-4 |r_s|
-# of the focus, the factored kernel forms delta by a short series instead of a
-# reciprocal (4 more flops per (node, point), not counted: the constant stays
-# the formula's).
+# of the focus, the kernel forms delta and 1/|R| by short series instead of a
+# reciprocal and a square root (5 more flops per (node, point), not counted:
+# the constant stays the formula's).
 FLOPS_GEOM, FLOPS_FREQ = 18, 96
 FLOPS_GEOM_FACTORED, FLOPS_FREQ_FACTORED = 34, 62
 FREQ_PER_LANE = 2

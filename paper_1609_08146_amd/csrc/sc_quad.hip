@@ -68,25 +68,28 @@ __device__ __forceinline__ GeomF geom_split(const v4f p, const v4f o)
     return g;
 }
 
-// The same geometry with delta from its series: delta (2|r_s| + delta) = num,
+// The same geometry by series, near the focus.  delta (2|r_s| + delta) = num,
 // so with h = 1 / (2|r_s|), delta_1 = num h and x = delta_1 h,
-//   delta = delta_1 (1 - x + 2 x^2 - 5 x^3 + ...)   (Catalan numbers).
-// The caller guarantees |x| <= |r'| / (2|r_s|) <= 2e-4, where the omitted
-// terms (5 |x|^3 relative) are far below the FP32 rounding of delta.  No
-// reciprocal and no |R| on the way to the phase.
+//   delta = delta_1 (1 - x + 2 x^2 - 5 x^3 + ...)   (Catalan numbers),
+// and |R| = |r_s| + delta gives, with y = 2 h delta = delta / |r_s|,
+//   1 / |R| = 2h (1 - y + y^2 - y^3 + ...).
+// The caller guarantees |r'| <= 4e-4 |r_s|, so |x| <= 2e-4 and |y| <= 4e-4:
+// the omitted terms (5 |x|^3 and |y|^3 relative, below 1e-10) are far below
+// the FP32 rounding.  Neither a reciprocal nor a square root.
 __device__ __forceinline__ GeomF geom_series(const v4f p, const v4f o, float h)
 {
     GeomF g;
     g.dx = p.x - o.x;
     g.dy = p.y - o.y;
     g.dz = p.z - o.z;
-    const float R2 = __fmaf_rn(g.dx, g.dx, __fmaf_rn(g.dy, g.dy, g.dz * g.dz));
-    g.rinv = __builtin_amdgcn_rsqf(R2);
     const float dot = __fmaf_rn(p.x, o.x, __fmaf_rn(p.y, o.y, p.z * o.z));
     const float num = __fmaf_rn(-2.0f, dot, o.w);
     const float d1 = num * h;
     const float x = d1 * h;
     g.delta = d1 * __fmaf_rn(x, __fmaf_rn(2.0f, x, -1.0f), 1.0f);
+    const float h2 = h + h;
+    const float y = g.delta * h2;
+    g.rinv = h2 * __fmaf_rn(y, y - 1.0f, 1.0f);
     return g;
 }
 
