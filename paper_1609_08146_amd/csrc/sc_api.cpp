@@ -844,7 +844,8 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
     // |x| <= |r'| / (2|r_s|) <= 2e-4 keeps the truncation (5 x^3, relative) far below FP32 rounding
     // (1 / (2|r_s|) rides in the factored node records, or in hinv32); per job, like the phase path
     job.hinv = p->hinv32.as<float>();
-    job.series_delta = prec == SC_FP32_SPLIT && p->rs_min > 0.0 && p->obs_r2max >= 0.0 &&
+    job.series_delta = (prec == SC_FP32_SPLIT || (prec == SC_FP64 && fact)) && p->rs_min > 0.0 &&
+                               p->obs_r2max >= 0.0 &&
                                std::sqrt(p->obs_r2max) <= 4e-4 * p->rs_min
                            ? 1
                            : 0;

@@ -46,8 +46,8 @@ int power_partial_count(int n_k);
 hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, int n_cplx, const double *fac, double *tab64,
                                float *tab32);
 // Factored tables (Jt = u s per node): tabf [n_k][n_tot][4] = (s, rho_t), posf [n_tot][8] =
-// (x, y, z, |r_s|, u, 1 / (2|r_s|)) in FP32, tabf64 / posf64 = (s, rho_t), (x, y, z, |r_s|, u, 0)
-// in FP64 (each output may be NULL);
+// (x, y, z, |r_s|, u, 1 / (2|r_s|)) in FP32, tabf64 / posf64 the same in FP64 (each output may be
+// NULL);
 // *bad (zeroed by the caller) gets bit 0 when some node's current has no single real direction
 // within tol32 (relative to its largest |Jt| over k), bit 1 for tol64.
 hipError_t launch_tables_factor(hipStream_t st, int n_k, int n_tot, const double *tab64, const float *pos32,

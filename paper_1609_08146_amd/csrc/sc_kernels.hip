@@ -453,7 +453,7 @@ __global__ void k_tables_cast(int n_k, int n_tot, const double *__restrict__ kv,
 // for any node and k, bit 1 if it exceeds tol64; the tables of a precision
 // must not be used when its bit is set.  Outputs, each optional (NULL skips
 // it): FP32 tabf[k][q] = (s, rho_t) and posf[q] = (x, y, z, |r_s|, u_q, 1 / (2|r_s|));
-// FP64 tabf64[k][q] and posf64[q] = (x, y, z, |r_s|, u_q, 0) in double.
+// FP64 tabf64[k][q] and posf64[q], the same records in double.
 __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ tab64, const float *__restrict__ pos32,
                                 const double *__restrict__ pos64, double tol32, double tol64,
                                 float *__restrict__ tabf, float *__restrict__ posf, double *__restrict__ tabf64,
@@ -520,7 +520,7 @@ __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ t
         double *pr = posf64 + gq * 8;
         for (int c = 0; c < 4; ++c) pr[c] = pos64[gq * 4 + c];
         for (int c = 0; c < 3; ++c) pr[4 + c] = u[c];
-        pr[7] = 0.0;
+        pr[7] = pos64[gq * 4 + 3] > 0.0 ? 0.5 / pos64[gq * 4 + 3] : 0.0;   // 1 / (2 |r_s|)
     }
     if (flags) atomicOr(bad, flags);
 }

@@ -246,6 +246,33 @@ __device__ __forceinline__ void sincos_turns_f64(double t, double &s, double &c)
     c = (qi == 1 || qi == 2) ? -ca : ca;      // quadrants 1, 2
 }
 
+// The FP64 geometry by series near the focus (see geom_series): with
+// |x| <= 2e-4 and |y| <= 4e-4 the terms through x^4 and y^4 leave omitted
+// terms below 2e-17 relative.  h = 1 / (2|r_s|) from the factored node record.
+__device__ __forceinline__ GeomD geom_f64_series(const double *p, const double4 o, double h)
+{
+    GeomD g;
+    g.dx = p[0] - o.x;
+    g.dy = p[1] - o.y;
+    g.dz = p[2] - o.z;
+    const double dot = __fma_rn(p[0], o.x, __fma_rn(p[1], o.y, p[2] * o.z));
+    const double num = __fma_rn(-2.0, dot, o.w);
+    const double d1 = num * h;
+    const double x = d1 * h;
+    // 1 - x + 2x^2 - 5x^3 + 14x^4
+    double q = __fma_rn(14.0, x, -5.0);
+    q = __fma_rn(q, x, 2.0);
+    q = __fma_rn(q, x, -1.0);
+    g.delta = d1 * __fma_rn(q, x, 1.0);
+    const double h2 = h + h;
+    const double y = g.delta * h2;
+    // 1 - y + y^2 - y^3 + y^4
+    double r = __fma_rn(y - 1.0, y, 1.0);
+    r = __fma_rn(r, y, -1.0);
+    g.rinv = h2 * __fma_rn(r, y, 1.0);
+    return g;
+}
+
 __device__ __forceinline__ GeomD geom_f64(const double *p, const double4 o)
 {
     GeomD g;
@@ -328,7 +355,7 @@ __device__ __forceinline__ void freq_f64_factored(double rinv, double delta, con
 // records (Jt.x, Jt.y, Jt.z, rho_t) as (re, im) pairs, 4 and 8 doubles;
 // factored (FACT): node records (x, y, z, |r_s|, u, 0) and table records
 // (s, rho_t), 8 and 4 doubles.  Plain FP64 sums.
-template <int OPL, int FPB, bool FACT>
+template <int OPL, int FPB, bool FACT, bool SER = false>
 __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
                                          const double *k64, int n_valid)
 {
@@ -364,7 +391,9 @@ __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0,
             for (int c = 0; c < TS; ++c) tn[f][c] = tab[f][TS * (size_t)n + c];
 #pragma unroll
         for (int s = 0; s < OPL; ++s) {
-            const GeomD g = geom_f64(pn, o[s]);
+            GeomD g;
+            if constexpr (SER) g = geom_f64_series(pn, o[s], pn[PS - 1]);
+            else g = geom_f64(pn, o[s]);
             if constexpr (FACT) {
                 // v = u / R, e = R / R^2, w = u x e, shared by the frequencies
                 const double r2 = g.rinv * g.rinv;
@@ -605,8 +634,12 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
         const int n_valid = min(FPB, n_k - kb * FPB);
 
         if constexpr (MODE == MODE_FP64) {
-            if (jobs[j].factored) tile_f64<OPL, FPB, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
-            else tile_f64<OPL, FPB, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+            if (jobs[j].factored && jobs[j].series_delta)
+                tile_f64<OPL, FPB, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+            else if (jobs[j].factored)
+                tile_f64<OPL, FPB, true, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+            else
+                tile_f64<OPL, FPB, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
         } else if constexpr (MODE == MODE_SPLIT) {
             // per job (not per tile), so the bits of a point do not depend on the launch shape
             const bool raw = jobs[j].raw_phase != 0;

@@ -25,7 +25,7 @@ struct QuadJob {
     int obs_blocks;       // n_obs_pad / (64 * obs_per_lane)
     int factored;         // split form (FP32 or FP64) with the current factored as J~ = u s (u real, per node)
     int raw_phase;        // FP32 split form: |k delta| / 2 pi < 250 turns for every pair of the job
-    int series_delta;     // FP32 split form: |r'| <= 4e-4 |r_s| for every pair (delta by its series)
+    int series_delta;     // split forms (FP64: factored only): |r'| <= 4e-4 |r_s| for every pair (series)
     int64_t tile0;        // first global tile of this job in the launch
     int64_t tile_offset;  // first job-local tile covered (a launch may cover a sub-range)
     int64_t n_tiles;      // tiles covered by this launch
