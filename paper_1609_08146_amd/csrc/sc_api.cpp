@@ -375,8 +375,10 @@ extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, 
     HIP_TRY(launch_node_tables(st, n_r, n_phi, f, p->d_r.as<double>(), p->d_wr.as<double>(), p->d_c.as<double>(),
                                p->d_s.as<double>(), 2.0 * M_PI / (double)n_phi, p->pos64.as<double>(),
                                p->pos32.as<float>(), p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>()));
+    SC_TRY(p->hinv64.reserve(sizeof(double) * n_tot, p->alloc_stream));
     SC_TRY(p->hinv32.reserve(sizeof(float) * n_tot, p->alloc_stream));
-    HIP_TRY(launch_node_half_inverse(st, n_tot, p->pos64.as<double>(), p->hinv32.as<float>()));
+    HIP_TRY(launch_node_half_inverse(st, n_tot, p->pos64.as<double>(), p->hinv64.as<double>(),
+                                     p->hinv32.as<float>()));
     p->f = f;
     p->a = r_max;
     p->rs_min = f;   // |r_s| = r^2 / 4f + f on the paraboloid (distance to the focus)
@@ -432,8 +434,10 @@ extern "C" sc_status sc_set_surface(sc_prob *p, int n_surf, const double *xyz, c
     HIP_TRY(launch_surface_records(st, n_surf, n_rim, d_xyz.as<double>(), d_nds.as<double>(), d_rx.as<double>(),
                                    d_rn.as<double>(), d_rdl.as<double>(), p->pos64.as<double>(), p->pos32.as<float>(),
                                    p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>()));
+    SC_TRY(p->hinv64.reserve(sizeof(double) * n_tot, p->alloc_stream));
     SC_TRY(p->hinv32.reserve(sizeof(float) * n_tot, p->alloc_stream));
-    HIP_TRY(launch_node_half_inverse(st, n_tot, p->pos64.as<double>(), p->hinv32.as<float>()));
+    HIP_TRY(launch_node_half_inverse(st, n_tot, p->pos64.as<double>(), p->hinv64.as<double>(),
+                                     p->hinv32.as<float>()));
     HIP_TRY(hipStreamSynchronize(st));   // staging buffers are freed on return
     double rs2 = INFINITY;
     for (int i = 0; i < n_surf; ++i)
@@ -843,9 +847,8 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
     // delta = (|r'|^2 - 2 r_s.r') / (|R| + |r_s|) by its series in x = delta_1 / (2|r_s|), where
     // |x| <= |r'| / (2|r_s|) <= 2e-4 keeps the truncation (5 x^3, relative) far below FP32 rounding
     // (1 / (2|r_s|) rides in the factored node records, or in hinv32); per job, like the phase path
-    job.hinv = p->hinv32.as<float>();
-    job.series_delta = (prec == SC_FP32_SPLIT || (prec == SC_FP64 && fact)) && p->rs_min > 0.0 &&
-                               p->obs_r2max >= 0.0 &&
+    job.hinv = prec == SC_FP64 ? p->hinv64.p : p->hinv32.p;
+    job.series_delta = (prec == SC_FP32_SPLIT || prec == SC_FP64) && p->rs_min > 0.0 && p->obs_r2max >= 0.0 &&
                                std::sqrt(p->obs_r2max) <= 4e-4 * p->rs_min
                            ? 1
                            : 0;
@@ -872,7 +875,7 @@ size_t sc::footprint_bytes(int n_r, int n_phi, int n_k, int n_obs, int n_t, sc_p
     const size_t n_chunks = (n_tot + chunk - 1) / chunk;
     size_t b = 0;
     b += sizeof(double) * (2 * (size_t)n_r + 1 + 2 * (size_t)n_phi + 3 * (size_t)n_phi);   // 1-D rule, rim tangents
-    b += n_tot * (sizeof(double) * (4 + 3 + 1) + sizeof(float) * 5);                        // node records
+    b += n_tot * (sizeof(double) * (4 + 3 + 1 + 1) + sizeof(float) * 5);                    // node records
     b += sizeof(double) * n_k;
     b += sizeof(double) * (size_t)n_k * (1 + (size_t)power_partial_count(1));                // incident power
     // FP64 tables (kept for SC_FP64; for the FP32 forms they exist only while the FP32 tables are cast)
@@ -1178,7 +1181,7 @@ extern "C" sc_status sc_get_timing(const sc_prob *p, sc_timing *out)
 extern "C" sc_status sc_prob_device_bytes(const sc_prob *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(SC_E_INVAL, "sc_prob_device_bytes: NULL argument");
-    const DevBuf *bufs[] = {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->hinv32, &p->nrm, &p->wgt,
+    const DevBuf *bufs[] = {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->hinv64, &p->hinv32, &p->nrm, &p->wgt,
                             &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->tabf, &p->posf, &p->tabf64, &p->posf64,
                             &p->fact_flag, &p->d_power, &p->obs64, &p->obs32, &p->resE, &p->resB, &p->partial,
                             &p->d_t, &p->tw, &p->timeE, &p->timeB, &p->d_spec, &p->d_obs_in};

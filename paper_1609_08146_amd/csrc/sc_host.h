@@ -128,7 +128,7 @@ struct sc_prob {
     int n_r = 0, n_phi = 0, n_surf = 0, n_rim = 0, n_tot = 0;
     sc::DevBuf d_r, d_wr, d_c, d_s;          // 1-D rule (device copies)
     sc::DevBuf pos64, pos32, nrm, wgt, tan;  // node records
-    sc::DevBuf hinv32;                         // [n_tot] 1 / (2|r_s|), FP32
+    sc::DevBuf hinv64, hinv32;                 // [n_tot] 1 / (2|r_s|), FP64 and FP32
     // frequencies
     std::vector<double> k;
     sc::DevBuf d_k;

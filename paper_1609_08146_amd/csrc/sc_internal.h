@@ -17,8 +17,8 @@ hipError_t launch_node_tables(hipStream_t st, int n_r, int n_phi, double f, cons
 hipError_t launch_surface_records(hipStream_t st, int n_surf, int n_rim, const double *xyz, const double *ndS,
                                   const double *rim_xyz, const double *rim_n, const double *rim_dl, double *pos64,
                                   float *pos32, double *nrm, double *wgt, double *tan);
-// hinv32[q] = 1 / (2 |r_s|) from the FP64 node records (0 where |r_s| = 0).
-hipError_t launch_node_half_inverse(hipStream_t st, int n_tot, const double *pos64, float *hinv32);
+// hinv64[q], hinv32[q] = 1 / (2 |r_s|) from the FP64 node records (0 where |r_s| = 0).
+hipError_t launch_node_half_inverse(hipStream_t st, int n_tot, const double *pos64, double *hinv64, float *hinv32);
 hipError_t launch_obs_prep(hipStream_t st, const double *xyz, int n_obs, int n_obs_pad, double *obs64,
                            float *obs32);
 hipError_t launch_tables_from_fields(hipStream_t st, int n_k, int n_surf, int n_tot, const double *k,

@@ -98,14 +98,18 @@ __global__ void k_surface_records(int n_surf, int n_rim, const double *__restric
         for (int c = 0; c < 3; ++c) tan[3 * j + c] = rim_dl[3 * j + c];
 }
 
-// 1 / (2|r_s|) per node in FP32, for the series form of delta in the split
-// quadrature (0 for a node at the origin, where the series is never used).
-__global__ void k_node_half_inverse(int n_tot, const double *__restrict__ pos64, float *__restrict__ hinv32)
+// 1 / (2|r_s|) per node in FP64 and FP32, for the series forms of delta and
+// 1/|R| in the split quadrature (0 for a node at the origin, where the series
+// is never used).
+__global__ void k_node_half_inverse(int n_tot, const double *__restrict__ pos64, double *__restrict__ hinv64,
+                                    float *__restrict__ hinv32)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n_tot) return;
     const double rs = pos64[4 * q + 3];
-    hinv32[q] = rs > 0.0 ? (float)(0.5 / rs) : 0.0f;
+    const double h = rs > 0.0 ? 0.5 / rs : 0.0;
+    hinv64[q] = h;
+    hinv32[q] = (float)h;
 }
 
 __global__ void k_obs_prep(const double *__restrict__ xyz, int n_obs, int n_obs_pad, double *__restrict__ obs64,
@@ -621,9 +625,10 @@ hipError_t launch_node_tables(hipStream_t st, int n_r, int n_phi, double f, cons
     return hipGetLastError();
 }
 
-hipError_t launch_node_half_inverse(hipStream_t st, int n_tot, const double *pos64, float *hinv32)
+hipError_t launch_node_half_inverse(hipStream_t st, int n_tot, const double *pos64, double *hinv64, float *hinv32)
 {
-    hipLaunchKernelGGL(k_node_half_inverse, dim3(nblocks(n_tot, 256)), dim3(256), 0, st, n_tot, pos64, hinv32);
+    hipLaunchKernelGGL(k_node_half_inverse, dim3(nblocks(n_tot, 256)), dim3(256), 0, st, n_tot, pos64, hinv64,
+                       hinv32);
     return hipGetLastError();
 }
 

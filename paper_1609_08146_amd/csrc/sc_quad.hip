@@ -248,7 +248,8 @@ __device__ __forceinline__ void sincos_turns_f64(double t, double &s, double &c)
 
 // The FP64 geometry by series near the focus (see geom_series): with
 // |x| <= 2e-4 and |y| <= 4e-4 the terms through x^4 and y^4 leave omitted
-// terms below 2e-17 relative.  h = 1 / (2|r_s|) from the factored node record.
+// terms below 2e-17 relative.  h = 1 / (2|r_s|) from the factored node record
+// or the job's per-node array.
 __device__ __forceinline__ GeomD geom_f64_series(const double *p, const double4 o, double h)
 {
     GeomD g;
@@ -385,6 +386,10 @@ __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0,
         double pn[PS], tn[FPB][TS];
 #pragma unroll
         for (int c = 0; c < PS; ++c) pn[c] = pos[PS * (size_t)n + c];
+        // h = 1 / (2|r_s|): last entry of the factored node record, else the per-node array
+        double hn = 0.0;
+        if constexpr (SER && FACT) hn = pn[PS - 1];
+        else if constexpr (SER) hn = ((cdouble *)job->hinv)[n];
 #pragma unroll
         for (int f = 0; f < FPB; ++f)
 #pragma unroll
@@ -392,7 +397,7 @@ __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0,
 #pragma unroll
         for (int s = 0; s < OPL; ++s) {
             GeomD g;
-            if constexpr (SER) g = geom_f64_series(pn, o[s], pn[PS - 1]);
+            if constexpr (SER) g = geom_f64_series(pn, o[s], hn);
             else g = geom_f64(pn, o[s]);
             if constexpr (FACT) {
                 // v = u / R, e = R / R^2, w = u x e, shared by the frequencies
@@ -634,10 +639,13 @@ __global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_,
         const int n_valid = min(FPB, n_k - kb * FPB);
 
         if constexpr (MODE == MODE_FP64) {
-            if (jobs[j].factored && jobs[j].series_delta)
+            const bool ser = jobs[j].series_delta != 0;
+            if (jobs[j].factored && ser)
                 tile_f64<OPL, FPB, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
             else if (jobs[j].factored)
                 tile_f64<OPL, FPB, true, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+            else if (ser)
+                tile_f64<OPL, FPB, false, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
             else
                 tile_f64<OPL, FPB, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
         } else if constexpr (MODE == MODE_SPLIT) {

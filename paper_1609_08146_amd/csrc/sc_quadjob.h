@@ -14,7 +14,7 @@ struct QuadJob {
     const void *tab;      // [n_k][n_tot][8] real (float or double); factored: [n_k][n_tot][4] real
     const void *pos;      // [n_tot][4] real; factored: [n_tot][8] real
     const void *obs;      // [n_obs_pad][4] real
-    const float *hinv;    // [n_tot] 1 / (2|r_s|) (FP32 split form, general layout, series_delta)
+    const void *hinv;     // [n_tot] 1 / (2|r_s|) real (general layout, series_delta)
     const double *k;      // [n_k]
     void *partial;        // [n_chunks][n_k][12][n_obs_pad] real
     int n_tot;            // surface + rim nodes
@@ -25,7 +25,7 @@ struct QuadJob {
     int obs_blocks;       // n_obs_pad / (64 * obs_per_lane)
     int factored;         // split form (FP32 or FP64) with the current factored as J~ = u s (u real, per node)
     int raw_phase;        // FP32 split form: |k delta| / 2 pi < 250 turns for every pair of the job
-    int series_delta;     // split forms (FP64: factored only): |r'| <= 4e-4 |r_s| for every pair (series)
+    int series_delta;     // split forms: |r'| <= 4e-4 |r_s| for every pair (delta and 1/|R| by series)
     int64_t tile0;        // first global tile of this job in the launch
     int64_t tile_offset;  // first job-local tile covered (a launch may cover a sub-range)
     int64_t n_tiles;      // tiles covered by this launch
