@@ -212,15 +212,17 @@ def test_fp64_factored_launch_shapes_batch_and_rescaling(ctx, orc):
     from paper_1609_08146_amd import problem_from_workload
     w = workloads.broadband(n_k=5, n_nodes=64)
     p = problem_from_workload(ctx, w)
-    assert p.factored_for("fp64")
-    ref = None
-    for opl, fpb in [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4)]:
-        p.set_launch(obs_per_lane=opl, freq_per_lane=fpb, waves_per_block=2, chunk=1024)
-        E, B = p.evaluate("fp64")
-        if ref is None:
-            ref = (E, B)
-        else:
-            assert np.array_equal(E, ref[0]) and np.array_equal(B, ref[1]), (opl, fpb)
+    for fact in (True, False):                    # both layouts take the near-focus series here
+        p.set_factoring(fact)
+        assert p.factored_for("fp64") is fact
+        ref = None
+        for opl, fpb in [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4)]:
+            p.set_launch(obs_per_lane=opl, freq_per_lane=fpb, waves_per_block=2, chunk=1024)
+            E, B = p.evaluate("fp64")
+            if ref is None:
+                ref = (E, B)
+            else:
+                assert np.array_equal(E, ref[0]) and np.array_equal(B, ref[1]), (fact, opl, fpb)
     p.close()
 
     ws = workloads.sweep(4)
