@@ -45,17 +45,17 @@ import workloads  # noqa: E402
 #   per (node, point, frequency): phase 2, A = s Z 6, C = rho_t Z 6,
 #                                 A m, C m (m = ik - 1/R) 12, E += v A 12,
 #                                 E += (C m) e 12, B += (A m) w 12         62
-# The kernel shares the per-(node, point) work among the FREQ_PER_LANE
-# frequencies of a lane.  Where the observation points lie within 4e-4 |r_s|
+# The kernel shares the per-(node, point) work among the frequencies of a
+# lane (freq_per_lane of the launch, read back from the library for every
+# figure below).  Where the observation points lie within 4e-4 |r_s|
 # of the focus, the kernel forms delta and 1/|R| by short series instead of a
 # reciprocal and a square root (5 more flops per (node, point), not counted:
 # the constant stays the formula's).
 FLOPS_GEOM, FLOPS_FREQ = 18, 96
 FLOPS_GEOM_FACTORED, FLOPS_FREQ_FACTORED = 34, 62
-FREQ_PER_LANE = 2
 
 
-def flops_per_eval(factored: bool = False, freq_per_lane: int = FREQ_PER_LANE) -> float:
+def flops_per_eval(factored: bool, freq_per_lane: int) -> float:
     if factored:
         return FLOPS_FREQ_FACTORED + FLOPS_GEOM_FACTORED / freq_per_lane
     return FLOPS_FREQ + FLOPS_GEOM / freq_per_lane
@@ -235,7 +235,8 @@ def bench_batch(args):
     dt = time.perf_counter() - t0
     quad_ms = probs[0].timing()["quad_ms"]
     fact_evals = sum(w.evals for w, p in zip(ws, probs) if p.factored)
-    flops = flops_per_eval(True) * fact_evals + flops_per_eval(False) * (evals - fact_evals)
+    fpl = probs[0].launch("fp32_split")["freq_per_lane"]   # one kernel shape per launch: the first problem's
+    flops = flops_per_eval(True, fpl) * fact_evals + flops_per_eval(False, fpl) * (evals - fact_evals)
     out = {"metric": "integrand evals/s, seeded sweep of uneven instances in one persistent launch",
            "value": evals / dt, "unit": "integrand evals/s", "n_gpus": 1, "instances": len(ws),
            "evals": evals, "seconds": dt, "quad_ms": quad_ms, "setup_s": setup,
@@ -525,12 +526,18 @@ def bench_convergence(args):
 
 
 def bench_valu(args):
-    """Issue cost of the vector instructions of the quadrature kernel (the built microbenchmark)."""
+    """Issue cost of the vector instructions of the quadrature kernel: a separate microbenchmark
+    (not part of the library), compiled here on demand for gfx950 and run once."""
     import subprocess
-    exe = os.path.join(ROOT, "paper_1609_08146_amd", "lib", "valu_rates")
-    if not os.path.exists(exe):
-        raise SystemExit(f"{exe} is not built (python -m paper_1609_08146_amd.build)")
-    res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    import tempfile
+    from paper_1609_08146_amd import build as b
+    src = os.path.join(ROOT, "paper_1609_08146_amd", "csrc", "valu_rates.hip")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "valu_rates")
+        res = subprocess.run([b.hipcc(), *b.HIP_FLAGS, src, "-o", exe], capture_output=True, text=True)
+        if res.returncode != 0:
+            raise SystemExit(f"hipcc failed on valu_rates.hip: {res.stderr}")
+        res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     if res.returncode != 0:
         raise SystemExit(f"valu_rates failed ({res.returncode}): {res.stderr}")
     out = json.loads(res.stdout)
@@ -597,6 +604,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     factored = p.factored_for(args.precision)
+    launch = p.launch(args.precision)
     # the same step with its results handed back in host memory: spectral E, B and the time
     # samples copied to (pageable) numpy arrays through the C ABI's host-output path
     host_ms = []
@@ -615,7 +623,7 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = evals * args.steps / elapsed
     quad_avg = float(np.mean(quad_ms))
-    fpe = flops_per_eval(factored)
+    fpe = flops_per_eval(factored, launch["freq_per_lane"])
     achieved = fpe * evals / (quad_avg * 1e-3) / 1e12
     peak = PEAK_FP64 if args.precision == "fp64" else PEAK_FP32
     # the counters were taken on the full FP32-split workload with the default launch
@@ -637,7 +645,8 @@ def main():
             "workload": f"broadband pulse, 800 nm carrier, 10 fs FWHM, f=0.1 m, aperture radius 0.075 m, "
                         f"w0=0.05 m, 400x400 GL x trapezoid nodes, 64x64 focal plane +-4 lambda0 + 64 axial, "
                         f"256 time samples; {shard_desc}",
-            "precision": args.precision, "launch": "obs_per_lane=1, freq_per_lane=2, 4 waves/block, chunk 4096",
+            "precision": args.precision, "launch": (f"obs_per_lane={launch['obs_per_lane']}, freq_per_lane={launch['freq_per_lane']}, "
+                                                 f"{launch['waves_per_block']} waves/block, chunk {launch['chunk']}"),
             "current": "factored (Jt = u s: the current n x B keeps one real direction per node)" if factored
                        else "general tables",
             "n_obs": w.n_obs, "n_freq": w.n_k, "n_nodes": w.n_nodes, "n_time": len(w.t),
@@ -680,6 +689,7 @@ def main():
         torch.cuda.synchronize()
         q64 = p.timing()["quad_ms"]
         fact64 = p.factored_for("fp64")
+        fpl64 = p.launch("fp64")["freq_per_lane"]
         # error of every output component of the chosen form against the FP64 form (itself held to the
         # oracle at 1e-12 by the tests) over the whole grid: max |F_c - F_c,64| / max |F_c,64| (the
         # paper's e_rel, Sec. IV-A) and the same maximum over the peak |F| of the field
@@ -695,8 +705,9 @@ def main():
                                            "max_err_over_field_peak": err / peak}
         r64 = w64.evals / (q64 * 1e-3)
         rq = evals / (quad_avg * 1e-3)
-        fpg = flops_per_eval(False)
-        f64 = flops_per_eval(fact64)
+        fpg = flops_per_eval(False, launch["freq_per_lane"])
+        fpg64 = flops_per_eval(False, fpl64)
+        f64 = flops_per_eval(fact64, fpl64)
         out["forms"] = {
             "fp64": {"quad_evals_per_s": r64, "quad_ms": q64, "n_freq": w64.n_k,
                      "current": "factored" if fact64 else "general tables", "flops_per_eval": f64,
@@ -732,8 +743,8 @@ def main():
             p.close()
             rg64 = w64.evals / (qg64 * 1e-3)
             out["forms"]["fp64_general_tables"] = {
-                "quad_evals_per_s": rg64, "quad_ms": qg64, "tflops": fpg * rg64 / 1e12,
-                "frac_fp64_peak": fpg * rg64 / 1e12 / PEAK_FP64}
+                "quad_evals_per_s": rg64, "quad_ms": qg64, "tflops": fpg64 * rg64 / 1e12,
+                "frac_fp64_peak": fpg64 * rg64 / 1e12 / PEAK_FP64}
 
     ctx.close()
     if args.serve_seconds > 0 and args.shard == 1:

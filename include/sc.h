@@ -124,6 +124,11 @@ typedef struct {
 } sc_launch;
 /* Fix the launch shape for a problem (overrides the context's tuned value). */
 sc_status sc_set_launch(sc_prob *p, const sc_launch *launch);
+/* The launch shape an evaluation of `p` in precision `prec` uses now (the
+ * problem's override, else the context's tuned entry for its size bucket,
+ * else the library default), every field filled in.  `out` is host memory.
+ * SC_E_INVAL for NULL arguments or an unknown precision.                   */
+sc_status sc_get_launch(const sc_prob *p, sc_precision prec, sc_launch *out);
 /* Time candidate launch shapes on problem `p` and store the fastest in the
  * context's cache, keyed by (precision, size bucket of n_obs, n_k, nodes).
  * `budget_ms` bounds the total time spent (0 = default).                    */
@@ -279,10 +284,16 @@ sc_status sc_get_factoring(sc_prob *p, int *active);
 /* Observation points, [n_obs][3] doubles, n_obs >= 1 (host or device per
  * on_device).  From host points the library also takes max |r'|, which lets
  * SC_FP32_SPLIT skip the fractional-turn reduction of the per-pair phase
- * (k_max |r'| / 2pi < 250 turns) and form delta = |r_s - r'| - |r_s| by a
- * short series (|r'| <= 4e-4 |r_s| on every node); the choice is per problem
+ * (k_max |r'| / 2pi < 250 turns), and lets both split forms (SC_FP32_SPLIT
+ * and SC_FP64) form delta = |r_s - r'| - |r_s| and 1/|r_s - r'| by short
+ * series (when |r'| <= 4e-4 |r_s| on every node); the choice is per problem
  * and changes the rounding, not the tolerance.  Device points always take
- * the general forms.                                                        */
+ * the general forms.
+ * Accuracy away from the focus: SC_FP32_SPLIT rounds the per-pair phase
+ * k delta (|k delta| <= k |r'|) to FP32, an error of about k |r'| 2^-24 rad
+ * per term (1e-4 rad at |r'| = 300 wavelengths), so its relative error grows
+ * linearly with the distance of the points from the focus; SC_FP64 holds
+ * about k |r'| 2^-53 rad.                                                   */
 sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs, int on_device);
 
 /* Evaluate the reflected spectral field at every (observation point, k).

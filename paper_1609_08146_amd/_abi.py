@@ -70,6 +70,7 @@ SIGNATURES = {
     "sc_ctx_set_profiling": [V, I],
     "sc_get_timing": [V, ctypes.POINTER(sc_timing)],
     "sc_set_launch": [V, ctypes.POINTER(sc_launch)],
+    "sc_get_launch": [V, I, ctypes.POINTER(sc_launch)],
     "sc_autotune": [V, I, D, ctypes.POINTER(sc_launch)],
     "sc_autotune_load": [V, ctypes.c_char_p],
     "sc_autotune_save": [V, ctypes.c_char_p],

@@ -309,6 +309,12 @@ class Problem:
         l = _abi.sc_launch(obs_per_lane, waves_per_block, chunk, blocks_per_cu, freq_per_lane)
         call("sc_set_launch", self.h, ctypes.byref(l))
 
+    def launch(self, precision="fp32_split") -> dict:
+        """The launch shape an evaluation in `precision` uses now (sc_get_launch)."""
+        l = _abi.sc_launch()
+        call("sc_get_launch", self.h, _prec(precision), ctypes.byref(l))
+        return {f: getattr(l, f) for f, _ in l._fields_}
+
     def autotune(self, precision="fp32_split", budget_ms: float = 0.0):
         l = _abi.sc_launch()
         call("sc_autotune", self.h, _prec(precision), float(budget_ms), ctypes.byref(l))

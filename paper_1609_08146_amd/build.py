@@ -69,16 +69,6 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("link of libsc.so failed")
     os.replace(tmp, LIB)
-    # the instruction-cost microbenchmark behind the roofline notes (a separate executable)
-    exe = os.path.join(LIBDIR, "valu_rates")
-    cmd = [cc, *HIP_FLAGS, os.path.join(CSRC, "valu_rates.hip"), "-o", exe + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed on valu_rates.hip")
-    os.replace(exe + ".tmp", exe)
     return LIB
 
 

@@ -777,6 +777,15 @@ extern "C" sc_status sc_set_launch(sc_prob *p, const sc_launch *l)
     return SC_OK;
 }
 
+extern "C" sc_status sc_get_launch(const sc_prob *p, sc_precision prec, sc_launch *out)
+{
+    if (!p || !out) return fail(SC_E_INVAL, "sc_get_launch: NULL argument");
+    if (prec != SC_FP64 && prec != SC_FP32_SPLIT && prec != SC_FP32)
+        return fail(SC_E_INVAL, "sc_get_launch: unknown precision %d", (int)prec);
+    *out = resolve_launch(p, prec);
+    return SC_OK;
+}
+
 // ====================================================================== evaluate
 
 int sc::mode_of(sc_precision prec)

@@ -354,8 +354,8 @@ __device__ __forceinline__ void freq_f64_factored(double rinv, double delta, con
 // One tile of the FP64 form: nodes [n0, n1) of a chunk, 64*OPL points, FPB
 // frequencies.  General layout: node records (x, y, z, |r_s|) and table
 // records (Jt.x, Jt.y, Jt.z, rho_t) as (re, im) pairs, 4 and 8 doubles;
-// factored (FACT): node records (x, y, z, |r_s|, u, 0) and table records
-// (s, rho_t), 8 and 4 doubles.  Plain FP64 sums.
+// factored (FACT): node records (x, y, z, |r_s|, u, 1 / (2|r_s|)) and table
+// records (s, rho_t), 8 and 4 doubles.  Plain FP64 sums.
 template <int OPL, int FPB, bool FACT, bool SER = false>
 __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
                                          const double *k64, int n_valid)

@@ -28,6 +28,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -192,6 +193,23 @@ static void release_prob(Req *r)
     }
 }
 
+// Test hook: SC_DEBUG_FAIL_QUANTUM=<n> makes the job-buffer reservation of the
+// n-th scheduling quantum of the process report SC_E_NOMEM (before anything of
+// that quantum is enqueued), so the failure path can be exercised from the host.
+static bool debug_fail_this_quantum()
+{
+    static std::mutex mu;
+    static long count = 0;
+    static long fail_at = -2;
+    std::lock_guard<std::mutex> lk(mu);
+    if (fail_at == -2) {
+        const char *e = getenv("SC_DEBUG_FAIL_QUANTUM");
+        fail_at = e ? atol(e) : -1;
+    }
+    ++count;
+    return fail_at > 0 && count == fail_at;
+}
+
 // One kernel shape per precision, so that requests of a precision share launches.
 static int server_opl(sc_precision) { return 1; }
 static int server_fpb(sc_precision) { return 2; }
@@ -331,6 +349,7 @@ static sc_status launch_quantum(sc_server *s)
         HIP_TRY(hipHostMalloc((void **)&s->hjobs[slot], sizeof(QuadJob) * cap, hipHostMallocDefault));
         s->hjobs_cap[slot] = cap;
     }
+    if (debug_fail_this_quantum()) return fail(SC_E_NOMEM, "injected job-buffer allocation failure");
     SC_TRY(s->jobbuf[slot].reserve(sizeof(QuadJob) * s->hjobs_cap[slot]));
     memcpy(s->hjobs[slot], jobs.data(), sizeof(QuadJob) * jobs.size());
     for (Req *r : group) HIP_TRY(hipStreamWaitEvent(st, r->ready_ev, 0));
@@ -467,9 +486,25 @@ static void worker_main(sc_server *s)
         if (more && s->inflight.size() < 2) {
             sc_status st = launch_quantum(s);
             if (st != SC_OK) {
-                // a device error poisons every running request
+                // The quanta already queued still read and write the running requests' buffers, and
+                // finished requests may still be copying to their pinned blocks: completing a request
+                // releases both, so wait for the compute and copy streams first.
                 std::string err = sc_last_error();
-                for (Req *r : s->active) complete_request(s, r, R_FAILED, st, err);
+                (void)hipStreamSynchronize(s->ctx->stream);
+                (void)hipStreamSynchronize(s->copy_stream);
+                while (!s->inflight.empty()) {
+                    s->slot_busy[s->inflight.front().slot] = false;
+                    s->inflight.pop_front();
+                }
+                // Requests whose results reached the host complete normally; the others have lost
+                // tiles (or share a failing device) and fail with the quantum's status.
+                for (Req *r : s->active) {
+                    if (r->state == R_FINISHING && hipEventQuery(r->done_ev) == hipSuccess)
+                        complete_request(s, r, R_DONE, SC_OK, "");
+                    else
+                        complete_request(s, r, R_FAILED, st, err);
+                }
+                (void)hipGetLastError();
                 s->active.clear();
                 s->worker_error = err;
             }

@@ -179,3 +179,42 @@ srv.close(); ctx.close()
     assert "fail:-2" in line            # SC_E_NOMEM for the request that hit the failure
     assert line.count("'ok'") == 2
     assert line.rstrip().endswith(" 0")  # nothing left charged
+
+
+def test_failed_quantum_waits_for_queued_work_and_later_requests_match():
+    """A quantum whose job-buffer reservation fails fails its running requests with SC_E_NOMEM only after
+    the work already queued for them has drained; requests submitted afterwards give their alone results
+    bitwise (their tables must not reuse memory that earlier kernels were still writing)."""
+    code = r'''
+import sys
+sys.path.insert(0, %r)
+import numpy as np, workloads
+from paper_1609_08146_amd import Context, Server, ScError, problem_from_workload
+ctx = Context(0)
+big = workloads.broadband(n_k=6, n_nodes=200)
+later = [workloads.mono().with_nodes(60 + 10 * i, 40).subset(obs_idx=np.arange(0, 1024, 5 + i)) for i in range(3)]
+ref = []
+for w in later:
+    p = problem_from_workload(ctx, w); ref.append(p.evaluate("fp32_split")); p.close()
+srv = Server(ctx, hbm_budget=int(8e9), max_running=2, quantum_ms=0.5)
+t_big = srv.submit(big, "fp32_split")
+try:
+    srv.wait(t_big); print("BIG ok")
+except ScError as e:
+    print("BIG fail:%%d" %% e.status)
+tk = [srv.submit(w, "fp32_split") for w in later]
+same = []
+for t, (E0, B0) in zip(tk, ref):
+    E, B, _, _, _ = srv.wait(t)
+    same.append(bool(np.array_equal(E, E0) and np.array_equal(B, B0)))
+s = srv.stats()
+print("LATER", same, s["completed"], s["hbm_in_use"])
+srv.close(); ctx.close()
+''' % ROOT
+    env = dict(os.environ, SC_DEBUG_FAIL_QUANTUM="2")
+    out = subprocess.run([sys.executable, "-u", "-c", code], env=env, capture_output=True, text=True, timeout=180)
+    print(out.stdout[-2000:], out.stderr[-2000:])
+    assert out.returncode == 0
+    assert "BIG fail:-2" in out.stdout          # SC_E_NOMEM for the request whose tiles were in that quantum
+    line = [l for l in out.stdout.splitlines() if l.startswith("LATER")][0]
+    assert line == "LATER [True, True, True] 3 0"
