@@ -8,6 +8,7 @@ arrays.  Every function follows the paper directly:
 * ``gauss_legendre``          -- quadrature rule of Sec. III-C (Gauss-Legendre in r)
 * ``mirror``                  -- paraboloid z = r^2/4f - f, cylindrical nodes (Sec. III-A/C)
 * ``incident``/``incident_tables`` -- collimated beam along -z on the mirror (Sec. III-A)
+* ``incident_lg``/``incident_lg_tables`` -- Laguerre-Gauss mode sets, the expansion basis of Sec. III-A
 * ``reflected_field``         -- Stokes-converted POA integrals (Sec. II, eq. stratton-chu-poa-og)
 * ``reflected_field_dgrad``   -- double-gradient POA form (Sec. II, eq. stratton-chu-poa), cross-check
 * ``time_transform``          -- semi-discrete Fourier sum (Sec. III-B, eq. impl.semiDiscreteFFT)
@@ -58,6 +59,7 @@ def open_library(path: str):
     lib.orc_gauss_legendre.argtypes = [I, P, P]
     lib.orc_mirror.argtypes = [I, D, D, I, I, P, P, P, P]
     lib.orc_incident.argtypes = [I, I, P, D, D, D, D, D, P, P]
+    lib.orc_incident_lg.argtypes = [I, ctypes.POINTER(ctypes.c_int), P, D, I, P, D, D, D, P, P]
     lib.orc_reflected_field.argtypes = [I, I, P, P, P, P, I, P, P, P, I, P, P, P, I, I]
     lib.orc_reflected_field_dgrad.argtypes = [I, P, P, P, I, I, P, P, I, P, P, I]
     lib.orc_time_transform.argtypes = [I, P, D, I, P, ctypes.c_long, P, P, I]
@@ -198,6 +200,31 @@ def incident_tables(m: Mirror, k, kind: int, w0: float = np.inf, pol: float = 0.
     B = np.empty_like(E)
     for i, kk in enumerate(k):
         E[i], B[i] = incident(kind, m.pos, kk, w0, pol, spectrum[i])
+    return E, B
+
+
+def incident_lg(modes, pts, k: float, w0: float, amp: complex = 1.0):
+    """Incident E, B (complex [n, 3]) of a Laguerre-Gauss mode set (Sec. III-A): modes is a list of
+    (p, l, ex, ey) with complex amplitudes ex, ey of the x- and y-polarised parts."""
+    pts = _f64(pts).reshape(-1, 3)
+    n = pts.shape[0]
+    pl = np.ascontiguousarray(np.array([[int(m[0]), int(m[1])] for m in modes], dtype=np.int32).reshape(-1, 2))
+    exy = _f64([[np.real(m[2]), np.imag(m[2]), np.real(m[3]), np.imag(m[3])] for m in modes]).reshape(-1, 4)
+    E = np.empty((n, 3), np.complex128)
+    B = np.empty((n, 3), np.complex128)
+    _load().orc_incident_lg(len(modes), pl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(exy), float(w0), n,
+                            _p(pts), float(k), float(np.real(amp)), float(np.imag(amp)), _p(E), _p(B))
+    return E, B
+
+
+def incident_lg_tables(m: Mirror, k, modes, w0: float, spectrum=None):
+    """E_inc, B_inc tables [n_k, n_tot, 3] of a Laguerre-Gauss mode set on the mirror nodes."""
+    k = _f64(k).ravel()
+    spectrum = np.ones(k.shape[0], np.complex128) if spectrum is None else _c128(spectrum)
+    E = np.empty((k.shape[0], m.n_tot, 3), np.complex128)
+    B = np.empty_like(E)
+    for i, kk in enumerate(k):
+        E[i], B[i] = incident_lg(modes, m.pos, kk, w0, spectrum[i])
     return E, B
 
 

@@ -269,6 +269,70 @@ int orc_incident(int kind, int n_pts, const double *pts, double k, double w0, do
 }
 
 /* ------------------------------------------------------------------------ */
+/* Laguerre-Gauss modes of the paraxial wave equation, the expansion basis of */
+/* the incident beams (Sec. III-A), taken in their waist cross-section and    */
+/* carried along -z without diffraction (a collimated beam, like the         */
+/* Gaussians above):                                                         */
+/*   u_{p,l}(r, phi) = C_{p,l} (sqrt(2) r / w0)^|l| L_p^|l|(2 r^2 / w0^2)     */
+/*                     exp(-r^2 / w0^2) e^{i l phi},                         */
+/*   C_{p,l} = sqrt(2 p! / (pi (p + |l|)!)) / w0,                            */
+/* so that the integral of |u|^2 over the plane is 1.  L_p^a is the           */
+/* generalized Laguerre polynomial, here from its explicit finite sum         */
+/*   L_p^a(x) = sum_{j=0..p} (-1)^j binom(p + a, p - j) x^j / j!.            */
+/* A beam is a set of modes m with indices (p_m, l_m) and complex amplitudes  */
+/* ex_m, ey_m of its x- and y-polarised parts:                               */
+/*   E = amp e^{-ikz} sum_m (ex_m x^ + ey_m y^) u_m,                          */
+/*   B = (-z^) x E = amp e^{-ikz} sum_m (ey_m x^ - ex_m y^) u_m.              */
+/* pl: [n_modes][2] ints (p, l); exy: [n_modes][4] doubles (ex re, im, ey re, im). */
+/* ------------------------------------------------------------------------ */
+static ld laguerre_sum(int p, int a, ld x)
+{
+    ld s = 0.0L;
+    for (int j = 0; j <= p; ++j) {
+        /* binom(p + a, p - j) = (p + a)! / ((p - j)! (a + j)!) */
+        ld b = expl(lgammal((ld)(p + a + 1)) - lgammal((ld)(p - j + 1)) - lgammal((ld)(a + j + 1)));
+        ld term = b * powl(x, (ld)j) / expl(lgammal((ld)(j + 1)));
+        s += (j % 2) ? -term : term;
+    }
+    return s;
+}
+
+int orc_incident_lg(int n_modes, const int *pl, const double *exy, double w0, int n_pts, const double *pts,
+                    double k, double amp_re, double amp_im, double *E, double *B)
+{
+    for (int q = 0; q < n_pts; ++q) {
+        ld X = pts[3 * q], Y = pts[3 * q + 1], Z = pts[3 * q + 2];
+        ld r = sqrtl(X * X + Y * Y), phi = atan2l(Y, X);
+        ld ex_re = 0, ex_im = 0, ey_re = 0, ey_im = 0;   /* sum over modes of (ex, ey) u */
+        for (int m = 0; m < n_modes; ++m) {
+            int p = pl[2 * m], l = pl[2 * m + 1], al = l < 0 ? -l : l;
+            ld C = sqrtl(2.0L * expl(lgammal((ld)(p + 1)) - lgammal((ld)(p + al + 1))) / PI_L) / (ld)w0;
+            ld rho = sqrtl(2.0L) * r / (ld)w0;
+            ld u = C * powl(rho, (ld)al) * laguerre_sum(p, al, rho * rho) * expl(-r * r / ((ld)w0 * (ld)w0));
+            ld ur = u * cosl((ld)l * phi), ui = u * sinl((ld)l * phi);
+            const double *c = exy + 4 * m;
+            ex_re += c[0] * ur - c[1] * ui;
+            ex_im += c[0] * ui + c[1] * ur;
+            ey_re += c[2] * ur - c[3] * ui;
+            ey_im += c[2] * ui + c[3] * ur;
+        }
+        /* times amp e^{-ikz} */
+        ld sl, cl;
+        sincosl(-(ld)k * Z, &sl, &cl);
+        ld fr = cl * amp_re - sl * amp_im, fi = cl * amp_im + sl * amp_re;
+        ld Exr = ex_re * fr - ex_im * fi, Exi = ex_re * fi + ex_im * fr;
+        ld Eyr = ey_re * fr - ey_im * fi, Eyi = ey_re * fi + ey_im * fr;
+        E[6 * q + 0] = (double)Exr; E[6 * q + 1] = (double)Exi;
+        E[6 * q + 2] = (double)Eyr; E[6 * q + 3] = (double)Eyi;
+        E[6 * q + 4] = 0.0;         E[6 * q + 5] = 0.0;
+        B[6 * q + 0] = (double)Eyr;  B[6 * q + 1] = (double)Eyi;
+        B[6 * q + 2] = -(double)Exr; B[6 * q + 3] = -(double)Exi;
+        B[6 * q + 4] = 0.0;          B[6 * q + 5] = 0.0;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Small complex helpers in long double.                                     */
 /* ------------------------------------------------------------------------ */
 typedef struct { ld re, im; } cld;

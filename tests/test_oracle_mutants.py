@@ -84,6 +84,15 @@ MUTANTS = [
     ("cyl_azimuthal_E", [("E[0] = -Y * gr; E[1] = -Y * gi;", "E[0] = Y * gr; E[1] = Y * gi;", 1)]),
     ("power_with_rim", [("for (int q = 0; q < n_surf; ++q) {\n            const double *e = E + 6",
                          "for (int q = 0; q < n_tot; ++q) {\n            const double *e = E + 6", 1)]),
+    ("lg_laguerre_sign", [("s += (j % 2) ? -term : term;", "s += term;", 1)]),
+    ("lg_normalisation", [("ld C = sqrtl(2.0L * expl(", "ld C = sqrtl(1.0L * expl(", 1)]),
+    ("lg_phase_sign", [("ui = u * sinl((ld)l * phi);", "ui = -u * sinl((ld)l * phi);", 1)]),
+    ("lg_B_sign", [("B[6 * q + 2] = -(double)Exr; B[6 * q + 3] = -(double)Exi;",
+                    "B[6 * q + 2] = (double)Exr; B[6 * q + 3] = (double)Exi;", 1)]),
+    ("lg_width", [("expl(-r * r / ((ld)w0 * (ld)w0))", "expl(-r * r / (2.0L * (ld)w0 * (ld)w0))", 1)]),
+    ("lg_radial_power", [("powl(rho, (ld)al)", "powl(rho, (ld)(al + 1))", 1)]),
+    ("lg_binomial", [("lgammal((ld)(p - j + 1)) - lgammal((ld)(a + j + 1))",
+                      "lgammal((ld)(p - j + 1)) - lgammal((ld)(j + 1))", 1)]),
 ]
 
 
@@ -290,8 +299,35 @@ def pin_cylindrical(orc):
     return np.abs(_curl(_fd_jac(E, h)) - 1j * K * B[0]).max() / s < 1e-9
 
 
+def pin_lg(orc):
+    # Laguerre-Gauss modes: LG_00 is the normalised Gaussian, aperture powers match the closed form
+    # (scipy's Laguerre polynomials and incomplete gamma), modes of the same l and different p are
+    # orthogonal on the plane, and LG_{0,+-1} make the radial beam
+    from test_oracle_lg import aperture_power_closed_form
+    w0 = 4.0
+    pts = np.array([[0.5, -1.2, 0.3], [2.0, 1.0, -0.4], [-3.0, 0.5, 0.9]])
+    E, B = orc.incident_lg([(0, 0, 1.0, 0.0)], pts, K, w0)
+    Eg, Bg = orc.incident(orc.GAUSSIAN, pts, K, w0)
+    c = math.sqrt(2 / math.pi) / w0
+    if np.abs(E - c * Eg).max() > 1e-14 * np.abs(Eg).max() or np.abs(B - c * Bg).max() > 1e-14 * np.abs(Bg).max():
+        return False
+    m = orc.mirror(20.0, 6.0, 80, 32)
+    for p, l in ((0, 1), (2, 1), (1, -2)):
+        P = orc.incident_power(m, *orc.incident_lg_tables(m, [K], [(p, l, 1.0, 0.0)], w0))[0]
+        if abs(P / aperture_power_closed_form(p, l, w0, 6.0) - 1) > 1e-11:
+            return False
+    m = orc.mirror(20.0, 7 * w0, 160, 32)
+    P = orc.incident_power(m, *orc.incident_lg_tables(m, [K], [(0, 1, 1.0, 0.0), (2, 1, 1.0, 0.0)], w0))[0]
+    if abs(P / (8 * math.pi) - 1) > 1e-11:
+        return False
+    al = 1 / (2 * math.sqrt(2) * c)
+    E, B = orc.incident_lg([(0, 1, al, -1j * al), (0, -1, al, 1j * al)], pts, K, w0)
+    Er, Br = orc.incident(orc.RADIAL, pts, K, w0)
+    return np.abs(E - Er).max() < 1e-13 * np.abs(Er).max() and np.abs(B - Br).max() < 1e-13 * np.abs(Br).max()
+
+
 BATTERY = [pin_p1, pin_p2, pin_forms, pin_maxwell, pin_symmetry, pin_paraxial, pin_flux, pin_rules, pin_time,
-           pin_power, pin_cylindrical]
+           pin_power, pin_cylindrical, pin_lg]
 
 
 def run_battery(orc):
