@@ -112,20 +112,25 @@ def parse():
                     help="step, batch: never use the factored current (time the general-table layout)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mode", default="step",
-                    choices=["step", "batch", "serve", "copy", "table1", "valu", "convergence"],
+                    choices=["step", "batch", "serve", "copy", "table1", "valu", "convergence", "refine"],
                     help="step: the hot path on the broadband workload (default); batch: the seeded sweep of "
                          "uneven instances in one persistent launch; serve: a Poisson request stream; "
                          "table1: the Table I workload with energy normalisation and diagnostics; "
                          "valu: issue cost of the kernel's vector instructions; "
-                         "convergence: e_rel per component under mesh refinement (Sec. IV-A)")
+                         "convergence: e_rel per component under mesh refinement (Sec. IV-A); "
+                         "refine: e_rel under refinement on the paraboloid and an ellipsoidal cap (Sec. III-C-1)")
     ap.add_argument("--instances", type=int, default=256, help="batch: instances of the sweep")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM admission budget")
     ap.add_argument("--quantum-ms", type=float, default=20.0, help="serve: device time per scheduling quantum")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="step: seconds of the request stream timed after the steps for the latency figures (0: none)")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="step: arrivals per second of that stream")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="step: arrivals per second of that stream")
+    ap.add_argument("--serve-seconds-low", type=float, default=20.0,
+                    help="step: seconds of a second stream at a sustainable rate (0: none)")
+    ap.add_argument("--serve-rate-low", type=float, default=20.0, help="step: arrivals per second of that stream")
+    ap.add_argument("--no-batch", action="store_true", help="step: skip the 256-instance batch")
     return ap.parse_args()
 
 
@@ -147,7 +152,7 @@ def run_step(p, w, precision):
     p.set_incident_gaussian(w.w0, w.pol, w.spectrum, False)
     p.set_observation(w.obs)
     p.evaluate(precision, keep_on_device=True)
-    p.to_time(w.dk, w.t, out=_time_out(w, precision))
+    p.to_time_at(w.dk, w.t, out=_time_out(w, precision))
     return p
 
 
@@ -206,11 +211,13 @@ def cpu_baseline(w, target_s):
                                     f"one thread, {dt1:.1f} s"}
 
 
-def bench_batch(args):
-    """All instances of the seeded sweep in ONE persistent launch (FP32 split, FP32-only tables)."""
+def batch_run(n_instances: int = 256, general: bool = False, tune: bool = True, tune_budget_ms: float = 20000.0):
+    """All instances of the seeded sweep in ONE persistent launch (FP32 split, FP32-only tables),
+    timed with the library's batch launch and, when `tune`, again after sc_autotune_batch has tuned
+    the launch on every 16th instance.  Returns a dict of both runs."""
     import torch
     from paper_1609_08146_amd import Context, Problem
-    ws = workloads.sweep(args.instances)
+    ws = workloads.sweep(n_instances)
     ctx = Context(0)
     ctx.set_profiling(True)
     t0 = time.perf_counter()
@@ -218,9 +225,8 @@ def bench_batch(args):
     for w in ws:
         p = Problem(ctx)
         p.set_table_storage(False)
-        if args.general_tables:
+        if general:
             p.set_factoring(False)
-        p.set_launch(chunk=16384)
         p.set_mirror(w.f, w.a, w.n_r, w.n_phi)
         p.set_frequencies(w.k)
         p.set_incident_gaussian(w.w0, w.pol, w.spectrum, False)
@@ -229,26 +235,59 @@ def bench_batch(args):
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     evals = sum(w.evals for w in ws)
-    t0 = time.perf_counter()
-    ctx.evaluate_batch(probs, "fp32_split")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    quad_ms = probs[0].timing()["quad_ms"]
     fact_evals = sum(w.evals for w, p in zip(ws, probs) if p.factored)
-    fpl = probs[0].launch("fp32_split")["freq_per_lane"]   # one kernel shape per launch: the first problem's
-    flops = flops_per_eval(True, fpl) * fact_evals + flops_per_eval(False, fpl) * (evals - fact_evals)
-    out = {"metric": "integrand evals/s, seeded sweep of uneven instances in one persistent launch",
-           "value": evals / dt, "unit": "integrand evals/s", "n_gpus": 1, "instances": len(ws),
-           "evals": evals, "seconds": dt, "quad_ms": quad_ms, "setup_s": setup,
-           "factored_instances": sum(1 for p in probs if p.factored),
-           "tflops": flops / (quad_ms * 1e-3) / 1e12,
-           "frac_fp32_peak": flops / (quad_ms * 1e-3) / 1e12 / PEAK_FP32,
-           "precision": "fp32_split", "chunk": 16384,
-           "tables": "general" if args.general_tables else "factored where the current allows"}
+
+    def partial_bytes(chunk_of):
+        # split-K partials: 12 reals per (chunk, frequency, padded point)
+        return sum(4 * 12 * -(-(w.n_r + 1) * w.n_phi // chunk_of(p)) * w.n_k * (-(-w.n_obs // 128) * 128)
+                   for w, p in zip(ws, probs))
+
+    def timed(label, launch):
+        ctx.evaluate_batch(probs, "fp32_split")          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.evaluate_batch(probs, "fp32_split")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        quad_ms = probs[0].timing()["quad_ms"]
+        fpl = launch["freq_per_lane"]
+        flops = flops_per_eval(True, fpl) * fact_evals + flops_per_eval(False, fpl) * (evals - fact_evals)
+        chunk = launch["chunk"]
+        return {"label": label, "value": evals / dt, "seconds": dt, "quad_ms": quad_ms,
+                "quad_evals_per_s": evals / (quad_ms * 1e-3), "launch": launch,
+                "tflops": flops / (quad_ms * 1e-3) / 1e12,
+                "frac_fp32_peak": flops / (quad_ms * 1e-3) / 1e12 / PEAK_FP32,
+                "partial_bytes": partial_bytes(lambda p: chunk if chunk else p.launch("fp32_split")["chunk"])}
+
+    # the library's batch launch: the shape of the layout carrying most evaluations, each problem's chunk
+    fact_major = 2 * fact_evals > evals
+    lib = {"obs_per_lane": 1, "freq_per_lane": 4 if fact_major else 2, "waves_per_block": 4, "chunk": 0,
+           "blocks_per_cu": 0}
+    runs = [timed("library launch", lib)]
+    if tune:
+        t0 = time.perf_counter()
+        best = ctx.autotune_batch(probs[::16], "fp32_split", budget_ms=tune_budget_ms)
+        tune_s = time.perf_counter() - t0
+        r = timed("tuned launch", best)
+        r["tune_seconds"] = tune_s
+        r["tuned_on"] = f"every 16th instance ({len(probs[::16])} of {len(probs)})"
+        runs.append(r)
+        ctx.set_batch_launch("fp32_split", reset=True)
+    out = {"instances": len(ws), "evals": evals, "setup_s": setup,
+           "factored_instances": sum(1 for p in probs if p.factored), "precision": "fp32_split",
+           "tables": "general" if general else "factored where the current allows", "runs": runs}
     for p in probs:
         p.close()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def bench_batch(args):
+    """--mode batch: the 256-instance sweep in one persistent launch, library and tuned launch."""
+    out = batch_run(args.instances, args.general_tables)
+    best = max(out["runs"], key=lambda r: r["value"])
+    print(json.dumps({"metric": "integrand evals/s, seeded sweep of uneven instances in one persistent launch",
+                      "value": best["value"], "unit": "integrand evals/s", "n_gpus": 1, **out}), flush=True)
 
 
 def bench_serve(args):
@@ -419,7 +458,7 @@ def bench_table1(args):
         p.normalize_energy(w.meta["eps"], w.meta["e_tot"], w.dk)
         p.evaluate(prec, keep_on_device=True)
         Et, Bt = _time_out(w, prec)
-        p.to_time(w.dk, w.t, out=(Et, Bt))
+        p.to_time_at(w.dk, w.t, out=(Et, Bt))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         tm = p.timing()
@@ -427,7 +466,7 @@ def bench_table1(args):
             # the 256-sample window resolves the envelope, not the carrier: for the instantaneous
             # intensity, sample +-4 periods about the focal arrival 2f every lambda_c / 32
             t_fine = 2 * w.f + np.arange(-128, 129) * (lam / 32)
-            Ef, Bf = p.to_time(w.dk, t_fine)
+            Ef, Bf = p.to_time_at(w.dk, t_fine)
         p.close()
     out["path"] = {"evals": w.evals, "seconds": dt, "evals_per_s": w.evals / dt,
                    "phases_ms": {k: tm[k] for k in ("prep_ms", "quad_ms", "reduce_ms", "time_ms")}}
@@ -525,6 +564,53 @@ def bench_convergence(args):
           flush=True)
 
 
+def bench_refine(args):
+    """Mesh refinement on a non-parabolic mirror (Sec. III-C-1): the paraboloid of focal length f
+    and the ellipsoidal cap of the same aperture whose vertex curvature matches it
+    (workloads.ellipsoid_cap), lit by the same literal Gaussian, wavelength 1, N x N nodes for
+    growing N.  Per surface and form, e_rel = max |F_N - F_ref| / max |F_ref| over the focal-plane
+    and axial points and the six components, against the FP64 field at the finest N.  The folded
+    tables of the paraboloid are smooth (k(|r_s| - z) = 2kf); the cap's turn through some fifty
+    periods, which the radial rule must resolve."""
+    import torch
+    from paper_1609_08146_amd import Context, Problem
+    torch.cuda.init()
+    f, c, rm, w0 = 200.0, 600.0, 300.0, 150.0
+    k = np.array([2 * np.pi])
+    g = np.linspace(-2.0, 2.0, 16)
+    obs = np.concatenate([workloads.focal_plane(2.0, 16), np.stack([0 * g, 0 * g, g], axis=-1)])
+    ctx = Context(0)
+
+    def field(surface, n, prec):
+        p = Problem(ctx)
+        if surface == "paraboloid":
+            p.set_mirror(f, rm, n, n)
+        else:
+            p.set_surface(*workloads.ellipsoid_cap(f, c, rm, n, n))
+        p.set_frequencies(k)
+        p.set_incident_beam("linear", w0, 0.0, None, False)
+        p.set_observation(obs)
+        E, B = p.evaluate(prec)
+        p.close()
+        return np.concatenate([E[0], B[0]], axis=-1).astype(np.complex128)
+
+    ns = [8, 12, 16, 24, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 512]
+    rows = {}
+    for surface in ("paraboloid", "ellipsoid"):
+        ref = field(surface, 1024, "fp64")
+        peak = np.abs(ref).max()
+        rows[surface] = [{"n": n, **{prec: float(np.abs(field(surface, n, prec) - ref).max() / peak)
+                                     for prec in ("fp64", "fp32_split")}} for n in ns]
+    first = {s: next((r["n"] for r in rows[s] if r["fp64"] < 1e-6), None) for s in rows}
+    xyz = workloads.ellipsoid_cap(f, c, rm, 512, 4)[0]
+    ph = 2 * np.pi * (np.linalg.norm(xyz, axis=1) - xyz[:, 2])
+    ctx.close()
+    print(json.dumps({"metric": "e_rel under mesh refinement, paraboloid vs ellipsoidal cap (Sec. III-C-1)",
+                      "geometry": {"f": f, "c": c, "r_max": rm, "w0": w0, "wavelength": 1.0,
+                                   "ellipsoid_table_phase_span_rad": float(ph.max() - ph.min())},
+                      "reference_n": 1024, "rows": rows, "first_n_below_1e-6_fp64": first}), flush=True)
+
+
 def bench_valu(args):
     """Issue cost of the vector instructions of the quadrature kernel: a separate microbenchmark
     (not part of the library), compiled here on demand for gfx950 and run once."""
@@ -572,6 +658,8 @@ def main():
         return bench_valu(args)
     if args.mode == "convergence":
         return bench_convergence(args)
+    if args.mode == "refine":
+        return bench_refine(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the frequency-sharded multi-GPU "
                                    "design is described but not built, so --gpus must be 1"}))
@@ -615,7 +703,7 @@ def main():
         p.set_incident_gaussian(w.w0, w.pol, w.spectrum, False)
         p.set_observation(w.obs)
         p.evaluate(args.precision)
-        p.to_time(w.dk, w.t)
+        p.to_time_at(w.dk, w.t)
         host_ms.append((time.perf_counter() - ts) * 1e3)
     p.close()
 
@@ -716,18 +804,26 @@ def main():
             "speedup_vs_fp64": rq / r64,
         }
         if factored:
-            # the same split form on the general tables (what an arbitrary incident field costs)
-            qg = []
+            # the same split form on the general tables (what an arbitrary incident field costs): the
+            # whole step, timed like the headline over a few steps, and its quadrature
+            qg, sg = [], []
             p = Problem(ctx)
             p.set_factoring(False)
-            for _ in range(3):
+            run_step(p, w, args.precision)
+            torch.cuda.synchronize()
+            for _ in range(4):
+                ts = time.perf_counter()
                 run_step(p, w, args.precision)
                 torch.cuda.synchronize()
+                sg.append(time.perf_counter() - ts)
                 qg.append(p.timing()["quad_ms"])
+            fpg = flops_per_eval(False, p.launch(args.precision)["freq_per_lane"])
             p.close()
             rg = evals / (min(qg) * 1e-3)
+            out["value_general_tables"] = evals / float(np.mean(sg))
             out["forms"]["fp32_split_general_tables"] = {
-                "quad_evals_per_s": rg, "quad_ms": min(qg), "tflops": fpg * rg / 1e12,
+                "step_evals_per_s": evals / float(np.mean(sg)), "ms_per_step": 1e3 * float(np.mean(sg)),
+                "quad_evals_per_s": rg, "quad_ms": min(qg), "flops_per_eval": fpg, "tflops": fpg * rg / 1e12,
                 "frac_fp32_peak": fpg * rg / 1e12 / PEAK_FP32}
         if fact64:
             # the FP64 form on the general tables
@@ -747,13 +843,28 @@ def main():
                 "frac_fp64_peak": fpg64 * rg64 / 1e12 / PEAK_FP64}
 
     ctx.close()
+    if not args.no_batch and args.shard == 1:
+        # the 256-instance sweep in one persistent launch, library and tuned batch launch
+        b = batch_run(256, tune=True, tune_budget_ms=20000.0)
+        out["batch"] = {"workload": "seeded sweep of 256 uneven instances (f 2-20 cm, 1-256 frequencies, "
+                                    "100^2-600^2 nodes, 16^2-128^2 + 16-128 axial points) in one persistent launch, "
+                                    "FP32-split, FP32-only tables",
+                        "instances": b["instances"], "evals": b["evals"], "setup_s": b["setup_s"],
+                        "runs": [{k: r[k] for k in ("label", "quad_evals_per_s", "quad_ms", "seconds", "launch",
+                                                      "frac_fp32_peak", "partial_bytes", "tune_seconds", "tuned_on")
+                                  if k in r} for r in b["runs"]]}
     if args.serve_seconds > 0 and args.shard == 1:
-        # p50 / p99 solve latency of a request stream of mixed sizes (about 0.8 of capacity by default)
-        sv = serve_run(args.serve_rate, args.serve_seconds)
-        out["serving"] = {k: sv[k] for k in ("rate_hz", "duration_s", "arrivals", "completed", "p50_ms", "p99_ms",
-                                             "evals_per_s", "device_busy_frac")}
-        out["serving"]["workload"] = ("seeded Poisson stream of sweep-like requests (mean 3.6e10 evaluations), "
-                                      "FP32-split with time transform; longer runs: --mode serve")
+        # the request stream as specified (200 per second for 60 s: an overload) and one sustainable rate
+        out["serving"] = []
+        for rate, secs in ((args.serve_rate, args.serve_seconds), (args.serve_rate_low, args.serve_seconds_low)):
+            if secs <= 0:
+                continue
+            sv = serve_run(rate, secs)
+            row = {k: sv[k] for k in ("rate_hz", "duration_s", "arrivals", "completed", "cancelled", "rejected",
+                                      "p50_ms", "p99_ms", "evals_per_s", "device_busy_frac")}
+            row["workload"] = ("seeded Poisson stream of sweep-like requests (mean 3.6e10 evaluations), FP32-split "
+                               "with time transform, 200 GB admission budget")
+            out["serving"].append(row)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -112,8 +112,11 @@ typedef struct {
 sc_status sc_get_timing(const sc_prob *p, sc_timing *out);
 
 /* Quadrature launch shape.  Only `chunk` changes the floating-point
- * summation order (and therefore the last bits of FP32 results); the other
- * fields change speed only.  Zero fields mean "library default".            */
+ * summation order (and therefore the last bits of results); the other
+ * fields change speed only.  Zero fields mean "library default": 1 point per
+ * lane, 4 waves per workgroup, chunks of 2048 nodes, the resident limit of
+ * workgroups, and frequencies per lane by table layout (4 with the factored
+ * current in the FP32 forms, else 2).                                       */
 typedef struct {
     int obs_per_lane;    /* 1 or 2 observation points per lane                    */
     int waves_per_block; /* 1, 2 or 4 waves of 64 lanes per workgroup             */
@@ -129,10 +132,30 @@ sc_status sc_set_launch(sc_prob *p, const sc_launch *launch);
  * else the library default), every field filled in.  `out` is host memory.
  * SC_E_INVAL for NULL arguments or an unknown precision.                   */
 sc_status sc_get_launch(const sc_prob *p, sc_precision prec, sc_launch *out);
-/* Time candidate launch shapes on problem `p` and store the fastest in the
- * context's cache, keyed by (precision, size bucket of n_obs, n_k, nodes).
- * `budget_ms` bounds the total time spent (0 = default).                    */
+/* Time candidate launches on problem `p` (quadrature plus reduction, best of
+ * two runs each) and store the fastest in the context's cache, keyed by
+ * (precision, table layout, size buckets of n_obs, n_k and nodes): first the
+ * kernel shape and waves per workgroup at the library's chunk, then the chunk
+ * (512 ... 16384 nodes) and workgroups per CU.  A tuned chunk sets the
+ * summation order, so every problem of the bucket then gets that chunk's bits
+ * (alone and in batches alike).  `budget_ms` bounds the time spent (0 = 20 s);
+ * *best (may be NULL) receives the winner.                                  */
 sc_status sc_autotune(sc_prob *p, sc_precision prec, double budget_ms, sc_launch *best);
+/* The launch of sc_evaluate_batch in precision `prec`: the kernel shape,
+ * waves per workgroup and workgroups per CU of the one persistent launch, and
+ * `chunk` = 0 (each problem keeps its own) or a chunk for every problem of the
+ * batch that does not fix one with sc_set_launch.  NULL clears it, and the
+ * batch then takes the library's shape for the table layout that carries most
+ * of its evaluations.                                                        */
+sc_status sc_set_batch_launch(sc_ctx *ctx, sc_precision prec, const sc_launch *launch);
+/* Time candidate batch launches on the batch `probs[0..n)` (pass a
+ * representative part of a large batch: every candidate evaluates all of
+ * them) and keep the fastest as the context's batch launch for `prec`: first
+ * the kernel shape and waves per workgroup, then one chunk for the batch (or
+ * each problem's own) and workgroups per CU.  A problem evaluated in a batch
+ * with a tuned chunk gives its alone result at that chunk (sc_set_launch).  */
+sc_status sc_autotune_batch(sc_ctx *ctx, sc_prob *const *probs, int n, sc_precision prec, double budget_ms,
+                            sc_launch *best);
 /* Load / save the context's tuning cache (plain text).                     */
 sc_status sc_autotune_load(sc_ctx *ctx, const char *path);
 sc_status sc_autotune_save(sc_ctx *ctx, const char *path);
@@ -171,18 +194,29 @@ sc_status sc_set_surface(sc_prob *p, int n_surf, const double *xyz, const double
                          const double *rim_xyz, const double *rim_n, const double *rim_dl);
 /* Number of surface nodes (n_r*n_phi) and rim nodes (n_phi).                */
 sc_status sc_get_num_nodes(const sc_prob *p, int *n_surface, int *n_rim);
-/* Copy node data to host arrays (any may be NULL):
+/* The mirror's quadrature (Sec. III-C-1: the tensor-product rule over the
+ * mirror's cylindrical parametrisation), copied to host arrays so that a
+ * caller can tabulate its incident field on the nodes (sc_set_incident); any
+ * pointer may be NULL:
  *   xyz    [(n_r+1)*n_phi][3] positions (surface nodes, then rim),
- *   normal [(n_r+1)*n_phi][3] unnormalised normals n~,
- *   weight [(n_r+1)*n_phi]    surface weights w_r(i) r_i 2pi/n_phi, then 2pi/n_phi. */
+ *   normal [(n_r+1)*n_phi][3] unnormalised normals n~ (n dS = n~ weight),
+ *   weight [(n_r+1)*n_phi]    surface weights w_r(i) r_i 2pi/n_phi, then the rim
+ *                             weights 2pi/n_phi (the rim tangent is dr_s/dphi).
+ * For a general surface (sc_set_surface): the caller's nodes, its n dS as the
+ * normal with weight 1, and the boundary's normals with weight 1.
+ * SC_E_STATE without a mirror.                                              */
 sc_status sc_get_nodes(const sc_prob *p, double *xyz, double *normal, double *weight);
 
 /* Size limits (grid dimensions of the per-frequency and time kernels).      */
 #define SC_MAX_FREQUENCIES 65535
 #define SC_MAX_TIMES 524280
 
-/* Wavenumbers k_n > 0 (c = 1), 1 <= n_k <= SC_MAX_FREQUENCIES.  Invalidates
- * incident tables.                                                          */
+/* The frequency samples of the spectral field (Sec. III-B: the pulse is
+ * handled as a sum over frequency components, each evaluated on its own):
+ * wavenumbers k_n = omega_n > 0 (c = 1), 1 <= n_k <= SC_MAX_FREQUENCIES, in
+ * any order and spacing (sc_to_time needs a uniform grid, sc_to_time_at does
+ * not).  k: host [n_k].  SC_E_INVAL for non-positive or non-finite values.
+ * Invalidates the incident tables and results.                              */
 sc_status sc_set_frequencies(sc_prob *p, const double *k, int n_k);
 
 /* Incident field on the mirror nodes (Sec. III-A): E and B are complex128
@@ -212,6 +246,38 @@ sc_status sc_set_incident(sc_prob *p, const double *E, const double *B, int on_d
 typedef enum { SC_BEAM_LINEAR = 0, SC_BEAM_RADIAL = 1, SC_BEAM_AZIMUTHAL = 2 } sc_beam;
 sc_status sc_set_incident_beam(sc_prob *p, int beam, double w0, double pol_angle,
                                const double *spectrum, int consistent);
+/* Laguerre-Gauss mode sets (Sec. III-A: the Laguerre-Gauss modes of the
+ * paraxial wave equation are the expansion basis of the incident linearly and
+ * radially polarised beams).  Each mode is taken in its waist cross-section
+ * and carried along -z without diffraction (a collimated beam, as the
+ * Gaussians above; the divergence is neglected, as Sec. III-A argues):
+ *   u_{p,l}(r, phi) = C_{p,l} (sqrt(2) r / w0)^|l| L_p^|l|(2 r^2 / w0^2)
+ *                     exp(-r^2 / w0^2) e^{i l phi},
+ *   C_{p,l} = sqrt(2 p! / (pi (p + |l|)!)) / w0  (unit integral of |u|^2 over
+ * the plane), L_p^a the generalized Laguerre polynomial.  A mode carries
+ * complex amplitudes ex, ey of its x- and y-polarised parts, and
+ *   E = amp_n e^{-ikz} sum_m (ex_m x + ey_m y) u_m,
+ *   B = (-z) x E = amp_n e^{-ikz} sum_m (ey_m x - ex_m y) u_m
+ * (transverse fields; amp_n from `spectrum`, complex128 [n_k], NULL = 1).
+ * LG_{0,0} with ex = 1 is sqrt(2/pi)/w0 times the literal Gaussian, and
+ * (LG_{0,1} + LG_{0,-1}) / (2 sqrt 2 C_{0,1}) in x plus
+ * (LG_{0,1} - LG_{0,-1}) / (2i sqrt 2 C_{0,1}) in y is the radially polarised
+ * beam above.  Whether the tables factor (sc_set_factoring) is decided from
+ * the tables as for any field: a linear polarisation common to all modes
+ * does, circular or mixed polarisations do not.
+ * 1 <= n_modes <= SC_MAX_LG_MODES, 0 <= p <= SC_MAX_LG_INDEX,
+ * |l| <= SC_MAX_LG_INDEX, finite amplitudes, 0 < w0 < inf (SC_E_INVAL);
+ * needs mirror and frequencies (SC_E_STATE).  `modes` is host memory.      */
+#define SC_MAX_LG_MODES 64
+#define SC_MAX_LG_INDEX 64
+typedef struct {
+    int p;          /* radial index                                  */
+    int l;          /* azimuthal index (either sign)                 */
+    double ex[2];   /* complex amplitude (re, im) of the x part      */
+    double ey[2];   /* complex amplitude (re, im) of the y part      */
+} sc_lg_mode;
+sc_status sc_set_incident_lg(sc_prob *p, const sc_lg_mode *modes, int n_modes, double w0,
+                             const double *spectrum);
 /* The linearly polarised Gaussian: sc_set_incident_beam(p, SC_BEAM_LINEAR, ...). */
 sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_angle,
                                    const double *spectrum, int consistent);
@@ -281,8 +347,11 @@ sc_status sc_get_factoring_for(sc_prob *p, sc_precision prec, int *active);
 /* sc_get_factoring_for(p, SC_FP32_SPLIT, active).                          */
 sc_status sc_get_factoring(sc_prob *p, int *active);
 
-/* Observation points, [n_obs][3] doubles, n_obs >= 1 (host or device per
- * on_device).  From host points the library also takes max |r'|, which lets
+/* The observation points r' where the reflected field is evaluated (Sec.
+ * III-C: the focal region, discretised separately from the mirror; the
+ * paper's domain decomposition splits these points across processes, here
+ * they are the tiles of one launch), [n_obs][3] doubles, n_obs >= 1 (host or
+ * device per on_device); SC_E_INVAL for non-finite host points.  From host points the library also takes max |r'|, which lets
  * SC_FP32_SPLIT skip the fractional-turn reduction of the per-pair phase
  * (k_max |r'| / 2pi < 250 turns), and lets both split forms (SC_FP32_SPLIT
  * and SC_FP64) form delta = |r_s - r'| - |r_s| and 1/|r_s - r'| by short
@@ -296,20 +365,32 @@ sc_status sc_get_factoring(sc_prob *p, int *active);
  * about k |r'| 2^-53 rad.                                                   */
 sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs, int on_device);
 
-/* Evaluate the reflected spectral field at every (observation point, k).
+/* Evaluate the reflected spectral field at every (observation point, k): the
+ * Stokes-converted physical-optics integrals of Sec. II (eq.
+ * stratton-chu-poa-og, with the rim line integral) by the mirror's quadrature,
+ * in the arithmetic `prec` (see sc_precision).
  * E, B: [n_k][n_obs][3] complex128 (SC_FP64) or complex64 (FP32 forms),
  * host or device per on_device; either may be NULL to keep the result only
- * on the device (for sc_to_time / sc_get_result).  Needs mirror, frequencies,
+ * on the device (for sc_to_time / sc_to_time_at / sc_get_result).  Needs mirror, frequencies,
  * incident field and observation points (SC_E_STATE).                      */
 sc_status sc_evaluate(sc_prob *p, sc_precision prec, void *E, void *B, int on_device);
 /* Copy the last result (same layout and type as sc_evaluate).              */
 sc_status sc_get_result(const sc_prob *p, void *E, void *B, int on_device);
 
-/* Semi-discrete transform of the last result to n_t <= SC_MAX_TIMES times t[] (host array):
- *   F(t_m) = dk * sum_n F_n e^{-i k_n t_m}    (complex; the physical field is
- * 2 Re F(t) when the samples cover positive frequencies only).
- * Et, Bt: [n_t][n_obs][3], same complex type as the result.                 */
-sc_status sc_to_time(sc_prob *p, double dk, const double *t, int n_t, void *Et, void *Bt, int on_device);
+/* Semi-discrete transform of the last result to time (Sec. III-B,
+ * eq. impl.semiDiscreteFFT, the sum over the positive-frequency samples):
+ *   F(t_m) = dk * sum_n F_n e^{-i k_n t_m}
+ * (complex; the physical field is 2 Re F(t)), at the n_t <= SC_MAX_TIMES
+ * uniform times t_m = t0 + m dt, with dk the step of the problem's uniformly
+ * spaced frequencies (at least two, spaced to 1e-12 relative; SC_E_INVAL
+ * otherwise).  Et, Bt: [n_t][n_obs][3], the complex type of the result, host
+ * or device per on_device (either may be NULL to keep them on the device).
+ * SC_E_STATE without a result.                                              */
+sc_status sc_to_time(sc_prob *p, double t0, double dt, int n_t, void *Et, void *Bt, int on_device);
+/* The same sum at arbitrary times t[n_t] (host array) with the weight dk given
+ * (any frequency grid, e.g. the trapezoid or quadrature weight of a
+ * non-uniform one).                                                         */
+sc_status sc_to_time_at(sc_prob *p, double dk, const double *t, int n_t, void *Et, void *Bt, int on_device);
 
 /* ------------------------------------------------------------ diagnostics */
 /* Verification of the reflected field as in Sec. IV-A: Maxwell residuals in
@@ -345,8 +426,10 @@ sc_status sc_field_energy(sc_prob *p, const double *t, int n_t, double dk, doubl
 
 /* Evaluate several problems in ONE persistent launch (tiles of all problems
  * share the device), then reduce each; results are kept per problem (read
- * with sc_get_result).  Each problem's result is bitwise identical to what
- * sc_evaluate gives it alone with the same launch chunk.                    */
+ * with sc_get_result).  The launch shape is the context's batch launch
+ * (sc_set_batch_launch, sc_autotune_batch) or the library's.  Each problem's
+ * result is bitwise identical to what sc_evaluate gives it alone with the same
+ * chunk.                                                                    */
 sc_status sc_evaluate_batch(sc_ctx *ctx, sc_prob *const *probs, int n, sc_precision prec);
 
 /* Device bytes held by the problem (tables, observation data, results).    */

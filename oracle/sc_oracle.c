@@ -9,7 +9,8 @@
  * It is deliberately plain and slow: one loop per sum, FP64 everywhere, and
  * the large phase k*R (up to ~1e6 rad) plus the accumulations in x87
  * long double (64-bit mantissa), with glibc's sincosl for the exponentials;
- * the quadrature roots are refined in quad precision (__float128).
+ * the quadrature roots are refined and the phases k t of the time transform
+ * formed in quad precision (__float128).
  *
  * What it computes (units c = 1, Lorentz-Heaviside, time factor e^{-ikt}):
  *
@@ -53,6 +54,8 @@
 
 typedef long double ld;
 typedef __float128 qd;
+#include <quadmath.h>
+#define TWO_PI_Q (2.0Q * M_PIq)
 
 static const ld PI_L = 3.141592653589793238462643383279502884L;
 
@@ -512,8 +515,14 @@ int orc_time_transform(int n_k, const double *kv, double dk, int n_t, const doub
         for (long x = 0; x < n_x; ++x) {
             cld acc = { 0.0L, 0.0L };
             for (int n = 0; n < n_k; ++n) {
+                /* the phase -k t formed in quad precision (the product of two doubles is exact
+                   there) and reduced by 2 pi in quad precision, then the long-double sincos:
+                   k t reaches ~1e6 rad, where a long-double product would already be off by
+                   ~1e-13 rad */
+                qd ph = -(qd)kv[n] * (qd)t[m];
+                qd red = ph - TWO_PI_Q * rintq(ph / TWO_PI_Q);
                 ld s, c;
-                sincosl(-(ld)kv[n] * (ld)t[m], &s, &c);
+                sincosl((ld)red, &s, &c);
                 cld tw = { c, s };
                 acc = cadd(acc, cmul(cget(F + 2 * ((size_t)n * n_x + x)), tw));
             }

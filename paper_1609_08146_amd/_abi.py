@@ -36,6 +36,10 @@ class sc_launch(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int), ("freq_per_lane", ctypes.c_int)]
 
 
+class sc_lg_mode(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("l", ctypes.c_int), ("ex", ctypes.c_double * 2), ("ey", ctypes.c_double * 2)]
+
+
 class sc_request(ctypes.Structure):
     _fields_ = [("f", ctypes.c_double), ("r_max", ctypes.c_double), ("n_r", ctypes.c_int), ("n_phi", ctypes.c_int),
                 ("n_k", ctypes.c_int), ("k", ctypes.c_void_p), ("spectrum", ctypes.c_void_p),
@@ -72,6 +76,8 @@ SIGNATURES = {
     "sc_set_launch": [V, ctypes.POINTER(sc_launch)],
     "sc_get_launch": [V, I, ctypes.POINTER(sc_launch)],
     "sc_autotune": [V, I, D, ctypes.POINTER(sc_launch)],
+    "sc_set_batch_launch": [V, I, ctypes.POINTER(sc_launch)],
+    "sc_autotune_batch": [V, PP, I, I, D, ctypes.POINTER(sc_launch)],
     "sc_autotune_load": [V, ctypes.c_char_p],
     "sc_autotune_save": [V, ctypes.c_char_p],
     "sc_prob_create": [V, PP],
@@ -84,6 +90,7 @@ SIGNATURES = {
     "sc_set_incident": [V, P, P, I],
     "sc_set_incident_gaussian": [V, D, D, P, I],
     "sc_set_incident_beam": [V, I, D, D, P, I],
+    "sc_set_incident_lg": [V, ctypes.POINTER(sc_lg_mode), I, D, P],
     "sc_get_incident_power": [V, P],
     "sc_scale_spectrum": [V, P],
     "sc_normalize_energy": [V, P, D, D],
@@ -94,7 +101,8 @@ SIGNATURES = {
     "sc_set_observation": [V, P, I, I],
     "sc_evaluate": [V, I, P, P, I],
     "sc_get_result": [V, P, P, I],
-    "sc_to_time": [V, D, P, I, P, P, I],
+    "sc_to_time": [V, D, D, I, P, P, I],
+    "sc_to_time_at": [V, D, P, I, P, P, I],
     "sc_stencil_points": [P, I, D, P],
     "sc_maxwell_residual_freq": [V, I, D, P],
     "sc_maxwell_residual_time": [V, I, D, P, I, D, D, P],

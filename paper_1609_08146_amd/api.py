@@ -134,6 +134,22 @@ class Context:
         for p in probs:
             p._res_prec = _prec(precision)
 
+    def set_batch_launch(self, precision="fp32_split", obs_per_lane=0, waves_per_block=0, chunk=0, blocks_per_cu=0,
+                         freq_per_lane=0, reset=False):
+        """Launch of evaluate_batch in `precision` (sc_set_batch_launch); reset=True clears it."""
+        if reset:
+            call("sc_set_batch_launch", self.h, _prec(precision), None)
+            return
+        l = _abi.sc_launch(obs_per_lane, waves_per_block, chunk, blocks_per_cu, freq_per_lane)
+        call("sc_set_batch_launch", self.h, _prec(precision), ctypes.byref(l))
+
+    def autotune_batch(self, probs: Sequence["Problem"], precision="fp32_split", budget_ms: float = 0.0) -> dict:
+        """Tune the batched launch on `probs` (sc_autotune_batch); returns the winner."""
+        arr = (ctypes.c_void_p * len(probs))(*[p.h for p in probs])
+        l = _abi.sc_launch()
+        call("sc_autotune_batch", self.h, arr, len(probs), _prec(precision), float(budget_ms), ctypes.byref(l))
+        return {f: getattr(l, f) for f, _ in l._fields_}
+
     def autotune_save(self, path: str):
         call("sc_autotune_save", self.h, path.encode())
 
@@ -225,6 +241,17 @@ class Problem:
         """beam: 0/'linear', 1/'radial', 2/'azimuthal' (sc_set_incident_beam)."""
         sp = None if spectrum is None else _host_c128(spectrum).ravel()
         call("sc_set_incident_beam", self.h, _beam(beam), float(w0), float(pol), _ptr(sp), int(bool(consistent)))
+
+    def set_incident_lg(self, modes, w0: float, spectrum=None):
+        """Laguerre-Gauss mode set (sc_set_incident_lg): modes is a sequence of (p, l, ex, ey) with
+        complex amplitudes ex, ey of the x- and y-polarised parts."""
+        arr = (_abi.sc_lg_mode * len(modes))()
+        for i, (pp, ll, ex, ey) in enumerate(modes):
+            arr[i].p, arr[i].l = int(pp), int(ll)
+            arr[i].ex[0], arr[i].ex[1] = float(np.real(ex)), float(np.imag(ex))
+            arr[i].ey[0], arr[i].ey[1] = float(np.real(ey)), float(np.imag(ey))
+        sp = None if spectrum is None else _host_c128(spectrum).ravel()
+        call("sc_set_incident_lg", self.h, arr, len(modes), float(w0), _ptr(sp))
 
     def incident_power(self):
         """Power of each frequency component through the aperture, [n_k] (sc_get_incident_power)."""
@@ -349,17 +376,27 @@ class Problem:
         call("sc_get_result", self.h, _ptr(E), _ptr(B), 0)
         return E, B
 
-    def to_time(self, dk: float, t, out=None):
-        t = _host_f64(t).ravel()
+    def _time_out(self, n_t, out, name):
         if out is not None:
             Et, Bt = out
             dt = "complex128" if self._res_prec == SC_FP64 else "complex64"
-            for a, name in ((Et, "to_time Et"), (Bt, "to_time Bt")):
-                _check_device(a, dt, t.shape[0] * self.n_obs * 3, name)
-            call("sc_to_time", self.h, float(dk), _ptr(t), int(t.shape[0]), _ptr(Et), _ptr(Bt), 1)
-            return out
-        Et, Bt = self._out_host(self._res_prec, t.shape[0]), self._out_host(self._res_prec, t.shape[0])
-        call("sc_to_time", self.h, float(dk), _ptr(t), int(t.shape[0]), _ptr(Et), _ptr(Bt), 0)
+            for a, nm in ((Et, f"{name} Et"), (Bt, f"{name} Bt")):
+                _check_device(a, dt, n_t * self.n_obs * 3, nm)
+            return Et, Bt, 1
+        return self._out_host(self._res_prec, n_t), self._out_host(self._res_prec, n_t), 0
+
+    def to_time(self, t0: float, dt: float, n_t: int, out=None):
+        """sc_to_time: the last result at times t0 + m dt, m < n_t, with dk the step of the uniform
+        frequency grid; host arrays [n_t][n_obs][3], or fills `out`=(Et, Bt) device tensors."""
+        Et, Bt, dev = self._time_out(int(n_t), out, "to_time")
+        call("sc_to_time", self.h, float(t0), float(dt), int(n_t), _ptr(Et), _ptr(Bt), dev)
+        return Et, Bt
+
+    def to_time_at(self, dk: float, t, out=None):
+        """sc_to_time_at: the last result at the times t[] with the frequency weight dk."""
+        t = _host_f64(t).ravel()
+        Et, Bt, dev = self._time_out(t.shape[0], out, "to_time_at")
+        call("sc_to_time_at", self.h, float(dk), _ptr(t), int(t.shape[0]), _ptr(Et), _ptr(Bt), dev)
         return Et, Bt
 
     def timing(self) -> dict:

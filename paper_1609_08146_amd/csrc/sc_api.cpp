@@ -275,8 +275,10 @@ static sc_status finish_tables(sc_prob *p)
 {
     p->has_tab = true;
     p->has_tab64 = true;
+    // the factoring test (and the factored FP32 tables) now, so that the table layout, and with it
+    // the launch shape, is known before the first evaluation; it needs the FP64 tables
+    SC_TRY(ensure_factored(p, true, false));
     if (p->keep_fp64) return SC_OK;
-    SC_TRY(ensure_factored(p, true, false));   // needs the FP64 tables
     const size_t nrec = p->k.size() * (size_t)p->n_tot;
     SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
     HIP_TRY(launch_tables_cast(p->ctx->stream, (int)p->k.size(), p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
@@ -538,23 +540,14 @@ extern "C" sc_status sc_set_incident(sc_prob *p, const double *E, const double *
     return finish_tables(p);
 }
 
-extern "C" sc_status sc_set_incident_beam(sc_prob *p, int beam, double w0, double pol_angle, const double *spectrum,
-                                          int consistent)
+// Tables and aperture power of a built-in beam (beam 3: the Laguerre-Gauss modes already in d_modes).
+static sc_status set_incident_builtin(sc_prob *p, int beam, double w0, double pol_angle, const double *spectrum,
+                                      int consistent, int n_modes, const char *who)
 {
-    if (!p) return fail(SC_E_INVAL, "sc_set_incident_beam: prob is NULL");
-    if (beam != SC_BEAM_LINEAR && beam != SC_BEAM_RADIAL && beam != SC_BEAM_AZIMUTHAL)
-        return fail(SC_E_INVAL, "sc_set_incident_beam: unknown beam %d", beam);
-    if (!(w0 > 0.0)) return fail(SC_E_INVAL, "sc_set_incident_beam: w0 must be > 0");
-    if (beam != SC_BEAM_LINEAR && !std::isfinite(w0))
-        return fail(SC_E_INVAL, "sc_set_incident_beam: a radially or azimuthally polarised beam needs a finite w0");
-    if (!std::isfinite(pol_angle)) return fail(SC_E_INVAL, "sc_set_incident_beam: bad polarisation angle");
-    if (!p->has_mirror || p->k.empty())
-        return fail(SC_E_STATE, "sc_set_incident_beam: set mirror and frequencies first");
+    if (!p->has_mirror || p->k.empty()) return fail(SC_E_STATE, "%s: set mirror and frequencies first", who);
     if (spectrum)
         for (size_t i = 0; i < 2 * p->k.size(); ++i)
-            if (!std::isfinite(spectrum[i]))
-                return fail(SC_E_INVAL, "sc_set_incident_beam: spectrum[%zu] is not finite", i / 2);
-    DeviceGuard g(p->ctx->device);
+            if (!std::isfinite(spectrum[i])) return fail(SC_E_INVAL, "%s: spectrum[%zu] is not finite", who, i / 2);
     hipStream_t st = p->ctx->stream;
     const int n_k = (int)p->k.size();
     invalidate_tables(p);
@@ -569,18 +562,70 @@ extern "C" sc_status sc_set_incident_beam(sc_prob *p, int beam, double w0, doubl
         SC_TRY(staging_mark(p));
         dspec = p->d_spec.as<double>();
     }
+    const double *modes = beam == 3 ? p->d_modes.as<double>() : nullptr;
     ev_record(p, EV_PREP0);
     HIP_TRY(launch_tables_gaussian(st, n_k, p->n_surf, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
                                    p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>(), beam, w0, pol_angle,
-                                   dspec, consistent ? 1 : 0, p->tab64.as<double>()));
+                                   dspec, consistent ? 1 : 0, modes, n_modes, p->tab64.as<double>()));
     SC_TRY(reserve_power(p));
     HIP_TRY(launch_power_gaussian(st, n_k, p->n_surf, p->d_k.as<double>(), p->pos64.as<double>(),
                                   p->nrm.as<double>(), p->wgt.as<double>(), beam, w0, pol_angle, dspec,
-                                  consistent ? 1 : 0, p->d_power.as<double>() + n_k, p->d_power.as<double>()));
+                                  consistent ? 1 : 0, modes, n_modes, p->d_power.as<double>() + n_k,
+                                  p->d_power.as<double>()));
     p->has_power = true;
     ev_record(p, EV_PREP1);
     p->ev_prep = p->ctx->profiling;
     return finish_tables(p);
+}
+
+extern "C" sc_status sc_set_incident_beam(sc_prob *p, int beam, double w0, double pol_angle, const double *spectrum,
+                                          int consistent)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_set_incident_beam: prob is NULL");
+    if (beam != SC_BEAM_LINEAR && beam != SC_BEAM_RADIAL && beam != SC_BEAM_AZIMUTHAL)
+        return fail(SC_E_INVAL, "sc_set_incident_beam: unknown beam %d", beam);
+    if (!(w0 > 0.0)) return fail(SC_E_INVAL, "sc_set_incident_beam: w0 must be > 0");
+    if (beam != SC_BEAM_LINEAR && !std::isfinite(w0))
+        return fail(SC_E_INVAL, "sc_set_incident_beam: a radially or azimuthally polarised beam needs a finite w0");
+    if (!std::isfinite(pol_angle)) return fail(SC_E_INVAL, "sc_set_incident_beam: bad polarisation angle");
+    DeviceGuard g(p->ctx->device);
+    return set_incident_builtin(p, beam, w0, pol_angle, spectrum, consistent, 0, "sc_set_incident_beam");
+}
+
+extern "C" sc_status sc_set_incident_lg(sc_prob *p, const sc_lg_mode *modes, int n_modes, double w0,
+                                        const double *spectrum)
+{
+    if (!p || !modes) return fail(SC_E_INVAL, "sc_set_incident_lg: NULL argument");
+    if (n_modes < 1 || n_modes > SC_MAX_LG_MODES)
+        return fail(SC_E_INVAL, "sc_set_incident_lg: need 1 <= n_modes <= %d", SC_MAX_LG_MODES);
+    if (!(w0 > 0.0) || !std::isfinite(w0)) return fail(SC_E_INVAL, "sc_set_incident_lg: w0 must be finite and > 0");
+    for (int m = 0; m < n_modes; ++m) {
+        const sc_lg_mode &md = modes[m];
+        if (md.p < 0 || md.p > SC_MAX_LG_INDEX || md.l < -SC_MAX_LG_INDEX || md.l > SC_MAX_LG_INDEX)
+            return fail(SC_E_INVAL, "sc_set_incident_lg: mode %d: need 0 <= p <= %d and |l| <= %d", m,
+                        SC_MAX_LG_INDEX, SC_MAX_LG_INDEX);
+        if (!std::isfinite(md.ex[0]) || !std::isfinite(md.ex[1]) || !std::isfinite(md.ey[0]) ||
+            !std::isfinite(md.ey[1]))
+            return fail(SC_E_INVAL, "sc_set_incident_lg: mode %d: amplitudes must be finite", m);
+    }
+    if (!p->has_mirror || p->k.empty()) return fail(SC_E_STATE, "sc_set_incident_lg: set mirror and frequencies first");
+    DeviceGuard g(p->ctx->device);
+    SC_TRY(staging_wait(p));
+    p->h_stage_modes.resize(6 * (size_t)n_modes);
+    for (int m = 0; m < n_modes; ++m) {
+        double *d = p->h_stage_modes.data() + 6 * m;
+        d[0] = modes[m].p;
+        d[1] = modes[m].l;
+        d[2] = modes[m].ex[0];
+        d[3] = modes[m].ex[1];
+        d[4] = modes[m].ey[0];
+        d[5] = modes[m].ey[1];
+    }
+    SC_TRY(p->d_modes.reserve(sizeof(double) * 6 * (size_t)n_modes, p->alloc_stream));
+    HIP_TRY(hipMemcpyAsync(p->d_modes.p, p->h_stage_modes.data(), sizeof(double) * 6 * (size_t)n_modes,
+                           hipMemcpyHostToDevice, p->ctx->stream));
+    SC_TRY(staging_mark(p));
+    return set_incident_builtin(p, 3, w0, 0.0, spectrum, 0, n_modes, "sc_set_incident_lg");
 }
 
 extern "C" sc_status sc_set_incident_gaussian(sc_prob *p, double w0, double pol_angle, const double *spectrum,
@@ -710,23 +755,39 @@ extern "C" sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs
 
 // ============================================================ launch shapes
 
+// The library's launch: one point per lane, frequencies per lane by table layout (0 here, settled in
+// resolve_launch), 4 waves per workgroup, node chunks of 2048, as many workgroups as fit.
 static sc_launch default_launch(sc_precision prec)
 {
-    // measured fastest on MI355X for the broadband workload, both precisions:
-    // one point x two frequencies per lane (the geometry is shared by the two)
     (void)prec;
     sc_launch l{};
     l.obs_per_lane = 1;
-    l.freq_per_lane = 2;
+    l.freq_per_lane = 0;
     l.waves_per_block = 4;
-    l.chunk = 4096;
+    l.chunk = 2048;
     l.blocks_per_cu = 0;   // 0 = occupancy limit
     return l;
 }
 
+// Whether an evaluation of p in prec reads the factored tables, as far as the problem knows now
+// (the factoring test runs when the incident field is set).
+static bool uses_factored(const sc_prob *p, sc_precision prec)
+{
+    if (!p->allow_fact || !p->fact_checked) return false;
+    if (prec == SC_FP32_SPLIT) return p->fact_ok;
+    if (prec == SC_FP64) return p->fact64_ok;
+    return false;
+}
+
+// Frequencies per lane by table layout: with the factored current a frequency costs 37 vector
+// instructions against the 30 of the geometry it shares, so four per lane (at five waves per SIMD)
+// beat two; the general tables' longer per-frequency work does not pay for the registers.
+static int auto_freq_per_lane(sc_precision prec, bool fact) { return prec != SC_FP64 && fact ? 4 : 2; }
+
 static TuneKey tune_key(const sc_prob *p, sc_precision prec)
 {
-    return {(int)prec, log2_bucket(p->n_obs), log2_bucket((int64_t)p->k.size()), log2_bucket(p->n_tot)};
+    return {(int)prec, uses_factored(p, prec) ? 1 : 0, log2_bucket(p->n_obs), log2_bucket((int64_t)p->k.size()),
+            log2_bucket(p->n_tot)};
 }
 
 sc_status sc::check_launch(const sc_launch &l)
@@ -755,6 +816,9 @@ sc_launch sc::resolve_launch(const sc_prob *p, sc_precision prec)
         if (p->launch.blocks_per_cu) l.blocks_per_cu = p->launch.blocks_per_cu;
         if (p->launch.freq_per_lane) l.freq_per_lane = p->launch.freq_per_lane;
     }
+    if (l.freq_per_lane == 0) l.freq_per_lane = auto_freq_per_lane(prec, uses_factored(p, prec));
+    if (l.obs_per_lane * l.freq_per_lane > 4 || (l.obs_per_lane == 2 && l.freq_per_lane == 4))
+        l.freq_per_lane = 4 / (2 * l.obs_per_lane);   // 2 points per lane: at most 2 frequencies
     return l;
 }
 
@@ -766,6 +830,7 @@ extern "C" sc_status sc_set_launch(sc_prob *p, const sc_launch *l)
         return SC_OK;
     }
     sc_launch full = default_launch(SC_FP32_SPLIT);
+    full.freq_per_lane = 1;   // a shape left to the library is always valid: check the rest with 1
     if (l->obs_per_lane) full.obs_per_lane = l->obs_per_lane;
     if (l->waves_per_block) full.waves_per_block = l->waves_per_block;
     if (l->chunk) full.chunk = l->chunk;
@@ -795,54 +860,68 @@ int sc::mode_of(sc_precision prec)
 
 size_t sc::real_size(sc_precision prec) { return prec == SC_FP64 ? sizeof(double) : sizeof(float); }
 
-// Make sure the tables of precision `prec` exist; size the partial and result buffers.
-sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob &job)
+// The tables an evaluation in `prec` reads: with `build`, built first where missing (which may
+// allocate); without, SC_E_STATE if they are not there yet.  *fact: the factored layout.
+static sc_status select_tables(sc_prob *p, sc_precision prec, bool build, const void **tab, bool *fact)
 {
     if (prec != SC_FP64 && prec != SC_FP32_SPLIT && prec != SC_FP32)
         return fail(SC_E_INVAL, "evaluate: unknown precision %d", (int)prec);
     if (!p->has_mirror || p->k.empty() || !p->has_tab || p->n_obs < 1)
         return fail(SC_E_STATE, "evaluate: mirror, frequencies, incident field and observation points are required");
-    hipStream_t st = p->ctx->stream;
-    const int n_k = (int)p->k.size();
-    const size_t nrec = (size_t)n_k * p->n_tot;
-    const void *tab = p->tab64.p;
     if (prec == SC_FP64 && !p->has_tab64)
         return fail(SC_E_STATE, "evaluate: FP64 tables were not kept (sc_set_table_storage(p, 0))");
     if (prec != SC_FP64 && !p->tab32_ok && !p->has_tab64)
         return fail(SC_E_STATE, "evaluate: no tables to build the FP32 tables from");
-    bool fact = false;
-    if (prec == SC_FP32_SPLIT && p->allow_fact) {
-        SC_TRY(ensure_factored(p, true, false));
-        fact = p->fact32_built;
-    } else if (prec == SC_FP64 && p->allow_fact) {
-        SC_TRY(ensure_factored(p, false, true));
-        fact = p->fact64_built;
+    static const char *not_built = "evaluate: the tables of this precision are not built yet "
+                                   "(evaluate the problem once with sc_evaluate first)";
+    hipStream_t st = p->ctx->stream;
+    const int n_k = (int)p->k.size();
+    const size_t nrec = (size_t)n_k * p->n_tot;
+    *fact = false;
+    if ((prec == SC_FP32_SPLIT || prec == SC_FP64) && p->allow_fact) {
+        const bool is64 = prec == SC_FP64;
+        if (build) {
+            SC_TRY(ensure_factored(p, !is64, is64));
+        } else if (p->has_tab64 && !(p->fact_checked && (is64 ? (!p->fact64_ok || p->fact64_built)
+                                                              : (!p->fact_ok || p->fact32_built)))) {
+            return fail(SC_E_STATE, "%s", not_built);
+        }
+        *fact = is64 ? p->fact64_built : p->fact32_built;
     }
-    if (fact) {
-        tab = prec == SC_FP64 ? p->tabf64.p : p->tabf.p;
+    if (*fact) {
+        *tab = prec == SC_FP64 ? p->tabf64.p : p->tabf.p;
     } else if (prec == SC_FP32_SPLIT) {
         if (!p->tab32_ok) {
+            if (!build) return fail(SC_E_STATE, "%s", not_built);
             SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
             HIP_TRY(launch_tables_cast(st, n_k, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
                                        p->tab64.as<double>(), nullptr, p->tab32.as<float>(), 0));
             p->tab32_ok = true;
         }
-        tab = p->tab32.p;
+        *tab = p->tab32.p;
     } else if (prec == SC_FP32) {
         if (!p->tab32n_ok) {
+            if (!build) return fail(SC_E_STATE, "%s", not_built);
             SC_TRY(p->tab32n.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
             HIP_TRY(launch_tables_cast(st, n_k, p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
                                        p->has_tab64 ? p->tab64.as<double>() : nullptr, p->tab32.as<float>(),
                                        p->tab32n.as<float>(), 1));
             p->tab32n_ok = true;
         }
-        tab = p->tab32n.p;
+        *tab = p->tab32n.p;
+    } else {
+        *tab = p->tab64.p;
     }
+    return SC_OK;
+}
+
+// The quadrature job of one problem (no allocation): tables `tab` of the chosen layout, split-K
+// partials in `partial` ([n_chunks][n_k][12][n_obs_pad] reals of the precision).
+static void fill_job(const sc_prob *p, sc_precision prec, const sc_launch &l, const void *tab, bool fact,
+                     void *partial, QuadJob &job)
+{
+    const int n_k = (int)p->k.size();
     const int n_chunks = (p->n_tot + l.chunk - 1) / l.chunk;
-    const size_t rs = real_size(prec);
-    SC_TRY(p->partial.reserve(rs * 12 * (size_t)n_chunks * n_k * p->n_obs_pad, p->alloc_stream));
-    SC_TRY(p->resE.reserve(rs * 6 * (size_t)n_k * p->n_obs, p->alloc_stream));
-    SC_TRY(p->resB.reserve(rs * 6 * (size_t)n_k * p->n_obs, p->alloc_stream));
     job.tab = tab;
     job.pos = prec == SC_FP64 ? (fact ? p->posf64.p : p->pos64.p) : (fact ? p->posf.p : p->pos32.p);
     job.factored = fact ? 1 : 0;
@@ -863,7 +942,7 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
                            : 0;
     job.obs = prec == SC_FP64 ? p->obs64.p : p->obs32.p;
     job.k = p->d_k.as<double>();
-    job.partial = p->partial.p;
+    job.partial = partial;
     job.n_tot = p->n_tot;
     job.n_obs_pad = p->n_obs_pad;
     job.n_k = n_k;
@@ -873,6 +952,27 @@ sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob
     job.tile0 = 0;
     job.tile_offset = 0;
     job.n_tiles = (int64_t)job.obs_blocks * n_chunks * ((n_k + l.freq_per_lane - 1) / l.freq_per_lane);
+}
+
+// Bytes of the split-K partials of an evaluation of p with launch l.
+static size_t partial_bytes(const sc_prob *p, sc_precision prec, const sc_launch &l)
+{
+    const size_t n_chunks = ((size_t)p->n_tot + l.chunk - 1) / l.chunk;
+    return real_size(prec) * 12 * n_chunks * p->k.size() * (size_t)p->n_obs_pad;
+}
+
+// Make sure the tables of precision `prec` exist; size the partial and result buffers.
+sc_status sc::prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob &job)
+{
+    const void *tab = nullptr;
+    bool fact = false;
+    SC_TRY(select_tables(p, prec, true, &tab, &fact));
+    const size_t rs = real_size(prec);
+    const int n_k = (int)p->k.size();
+    SC_TRY(p->partial.reserve(partial_bytes(p, prec, l), p->alloc_stream));
+    SC_TRY(p->resE.reserve(rs * 6 * (size_t)n_k * p->n_obs, p->alloc_stream));
+    SC_TRY(p->resB.reserve(rs * 6 * (size_t)n_k * p->n_obs, p->alloc_stream));
+    fill_job(p, prec, l, tab, fact, p->partial.p, job);
     return SC_OK;
 }
 
@@ -901,6 +1001,19 @@ size_t sc::footprint_bytes(int n_r, int n_phi, int n_k, int n_obs, int n_t, sc_p
     return b;
 }
 
+// Workgroups of a persistent quadrature launch: the resident limit (or the launch's blocks per CU)
+// on every CU, but no more than the tiles need (one wave per tile).
+static int quad_grid(const sc_ctx *c, sc_precision prec, const sc_launch &l, int64_t n_tiles)
+{
+    int bpc = l.blocks_per_cu;
+    const int occ = quad_max_blocks_per_cu(mode_of(prec), l.obs_per_lane, l.freq_per_lane, l.waves_per_block);
+    if (bpc <= 0 || bpc > occ) bpc = occ;
+    int64_t grid = (int64_t)bpc * c->n_cu;
+    const int64_t blocks_needed = (n_tiles + l.waves_per_block - 1) / l.waves_per_block;
+    if (grid > blocks_needed) grid = blocks_needed;
+    return (int)std::max<int64_t>(grid, 1);
+}
+
 // Upload jobs and run one persistent quadrature launch over all their tiles.
 sc_status sc::run_quad(sc_ctx *c, std::vector<QuadJob> &jobs, sc_precision prec, const sc_launch &l,
                           sc_prob *timed)
@@ -921,17 +1034,9 @@ sc_status sc::run_quad(sc_ctx *c, std::vector<QuadJob> &jobs, sc_precision prec,
                            st));
     HIP_TRY(hipEventRecord(c->upload_done, st));
     HIP_TRY(launch_fill_u32(st, c->counter.as<unsigned int>(), 0u, QUAD_SEGMENTS));
-    const int mode = mode_of(prec);
-    int bpc = l.blocks_per_cu;
-    const int occ = quad_max_blocks_per_cu(mode, l.obs_per_lane, l.freq_per_lane, l.waves_per_block);
-    if (bpc <= 0 || bpc > occ) bpc = occ;
-    int64_t grid = (int64_t)bpc * c->n_cu;
-    const int64_t waves_needed = (n_tiles + 0);
-    const int64_t blocks_needed = (waves_needed + l.waves_per_block - 1) / l.waves_per_block;
-    if (grid > blocks_needed) grid = blocks_needed;
-    if (grid < 1) grid = 1;
+    const int grid = quad_grid(c, prec, l, n_tiles);
     if (timed) ev_record(timed, EV_Q0);
-    HIP_TRY(launch_quad(st, mode, l.obs_per_lane, l.freq_per_lane, l.waves_per_block, (int)grid,
+    HIP_TRY(launch_quad(st, mode_of(prec), l.obs_per_lane, l.freq_per_lane, l.waves_per_block, grid,
                         c->jobs.as<QuadJob>(), (int)jobs.size(), n_tiles, c->counter.as<unsigned int>()));
     if (timed) ev_record(timed, EV_Q1);
     return SC_OK;
@@ -977,6 +1082,41 @@ extern "C" sc_status sc_get_result(const sc_prob *p, void *E, void *B, int on_de
                     real_size((sc_precision)p->res_prec) * 6 * p->k.size() * (size_t)p->n_obs);
 }
 
+// The kernel shape (and, from the tuner, possibly a chunk) of one batched launch: the context's
+// batch launch for the precision if one is set, else the library's shape for the table layout that
+// carries most of the batch's evaluations (chunk 0: each problem's own).
+static sc_launch batch_launch(const sc_ctx *c, sc_prob *const *probs, int n, sc_precision prec)
+{
+    auto it = c->batch_tune.find((int)prec);
+    if (it != c->batch_tune.end()) return it->second;
+    double fact_evals = 0.0, all_evals = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double e = (double)probs[i]->n_obs * (double)probs[i]->k.size() * (double)probs[i]->n_tot;
+        all_evals += e;
+        if (uses_factored(probs[i], prec)) fact_evals += e;
+    }
+    sc_launch l = default_launch(prec);
+    l.freq_per_lane = auto_freq_per_lane(prec, 2.0 * fact_evals > all_evals);
+    l.chunk = 0;
+    return l;
+}
+
+extern "C" sc_status sc_set_batch_launch(sc_ctx *c, sc_precision prec, const sc_launch *l)
+{
+    if (!c) return fail(SC_E_INVAL, "sc_set_batch_launch: ctx is NULL");
+    if (prec != SC_FP64 && prec != SC_FP32_SPLIT && prec != SC_FP32)
+        return fail(SC_E_INVAL, "sc_set_batch_launch: unknown precision %d", (int)prec);
+    if (!l) {
+        c->batch_tune.erase((int)prec);
+        return SC_OK;
+    }
+    sc_launch full = *l;
+    if (full.chunk == 0) full.chunk = 64;   // 0 = each problem's own chunk: check the rest
+    SC_TRY(check_launch(full));
+    c->batch_tune[(int)prec] = *l;
+    return SC_OK;
+}
+
 extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, sc_precision prec)
 {
     if (!c || (!probs && n > 0) || n < 0) return fail(SC_E_INVAL, "sc_evaluate_batch: bad arguments");
@@ -991,14 +1131,21 @@ extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, 
         if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
             return fail(SC_E_INVAL, "sc_evaluate_batch: a problem appears twice");
     }
-    sc_launch l0 = resolve_launch(probs[0], prec);
-    SC_TRY(check_launch(l0));
+    const sc_launch l0 = batch_launch(c, probs, n, prec);
+    {
+        sc_launch shape = l0;
+        if (shape.chunk == 0) shape.chunk = 64;   // 0 = each problem's own chunk
+        SC_TRY(check_launch(shape));
+    }
     std::vector<QuadJob> jobs(n);
     std::vector<sc_launch> ls(n);
     for (int i = 0; i < n; ++i) {
+        // one kernel shape per launch; the chunk stays per problem (it alone fixes the summation
+        // order), unless the context's tuned batch launch sets one for problems that fix none
         ls[i] = resolve_launch(probs[i], prec);
-        ls[i].obs_per_lane = l0.obs_per_lane;   // one kernel shape per launch; the chunk stays per problem
-        ls[i].freq_per_lane = l0.freq_per_lane; // (only the chunk fixes the summation order)
+        ls[i].obs_per_lane = l0.obs_per_lane;
+        ls[i].freq_per_lane = l0.freq_per_lane;
+        if (l0.chunk && !(probs[i]->has_launch && probs[i]->launch.chunk)) ls[i].chunk = l0.chunk;
         SC_TRY(check_launch(ls[i]));
         SC_TRY(prepare(probs[i], prec, ls[i], jobs[i]));
         probs[i]->res_prec = -1;
@@ -1017,12 +1164,12 @@ extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, 
     return SC_OK;
 }
 
-extern "C" sc_status sc_to_time(sc_prob *p, double dk, const double *t, int n_t, void *Et, void *Bt, int on_device)
+extern "C" sc_status sc_to_time_at(sc_prob *p, double dk, const double *t, int n_t, void *Et, void *Bt, int on_device)
 {
-    if (!p || !t) return fail(SC_E_INVAL, "sc_to_time: NULL argument");
-    if (n_t < 1 || n_t > SC_MAX_TIMES) return fail(SC_E_INVAL, "sc_to_time: need 1 <= n_t <= %d", SC_MAX_TIMES);
-    if (!std::isfinite(dk)) return fail(SC_E_INVAL, "sc_to_time: dk must be finite");
-    if (p->res_prec < 0) return fail(SC_E_STATE, "sc_to_time: no spectral result (evaluate first)");
+    if (!p || !t) return fail(SC_E_INVAL, "sc_to_time_at: NULL argument");
+    if (n_t < 1 || n_t > SC_MAX_TIMES) return fail(SC_E_INVAL, "sc_to_time_at: need 1 <= n_t <= %d", SC_MAX_TIMES);
+    if (!std::isfinite(dk)) return fail(SC_E_INVAL, "sc_to_time_at: dk must be finite");
+    if (p->res_prec < 0) return fail(SC_E_STATE, "sc_to_time_at: no spectral result (evaluate first)");
     DeviceGuard g(p->ctx->device);
     hipStream_t st = p->ctx->stream;
     const int n_k = (int)p->k.size();
@@ -1047,6 +1194,24 @@ extern "C" sc_status sc_to_time(sc_prob *p, double dk, const double *t, int n_t,
     // t was copied from pageable host memory; complete before returning
     HIP_TRY(hipStreamSynchronize(st));
     return SC_OK;
+}
+
+extern "C" sc_status sc_to_time(sc_prob *p, double t0, double dt, int n_t, void *Et, void *Bt, int on_device)
+{
+    if (!p) return fail(SC_E_INVAL, "sc_to_time: prob is NULL");
+    if (n_t < 1 || n_t > SC_MAX_TIMES) return fail(SC_E_INVAL, "sc_to_time: need 1 <= n_t <= %d", SC_MAX_TIMES);
+    if (!std::isfinite(t0) || !std::isfinite(dt)) return fail(SC_E_INVAL, "sc_to_time: t0 and dt must be finite");
+    const size_t n_k = p->k.size();
+    if (n_k < 2) return fail(SC_E_INVAL, "sc_to_time: needs at least two frequencies (else use sc_to_time_at)");
+    // the frequency step of a uniform grid; any other grid needs sc_to_time_at with its own weights
+    const double dk = (p->k[n_k - 1] - p->k[0]) / (double)(n_k - 1);
+    const double kmax = std::max(std::fabs(p->k[0]), std::fabs(p->k[n_k - 1]));
+    for (size_t n = 0; n < n_k; ++n)
+        if (std::fabs(p->k[n] - (p->k[0] + (double)n * dk)) > 1e-12 * kmax || !(dk > 0.0))
+            return fail(SC_E_INVAL, "sc_to_time: the frequencies are not uniformly spaced (use sc_to_time_at)");
+    std::vector<double> t((size_t)n_t);
+    for (int m = 0; m < n_t; ++m) t[m] = t0 + (double)m * dt;
+    return sc_to_time_at(p, dk, t.data(), n_t, Et, Bt, on_device);
 }
 
 // ================================================================ diagnostics
@@ -1193,7 +1358,7 @@ extern "C" sc_status sc_prob_device_bytes(const sc_prob *p, size_t *bytes)
     const DevBuf *bufs[] = {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->hinv64, &p->hinv32, &p->nrm, &p->wgt,
                             &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->tabf, &p->posf, &p->tabf64, &p->posf64,
                             &p->fact_flag, &p->d_power, &p->obs64, &p->obs32, &p->resE, &p->resB, &p->partial,
-                            &p->d_t, &p->tw, &p->timeE, &p->timeB, &p->d_spec, &p->d_obs_in};
+                            &p->d_t, &p->tw, &p->timeE, &p->timeB, &p->d_spec, &p->d_obs_in, &p->d_modes};
     size_t s = 0;
     for (const DevBuf *b : bufs) s += b->bytes;
     *bytes = s;
@@ -1201,6 +1366,44 @@ extern "C" sc_status sc_prob_device_bytes(const sc_prob *p, size_t *bytes)
 }
 
 // ================================================================== autotuner
+
+// Candidate kernel shapes (points x frequencies per lane) of the tuner.
+static const int TUNE_SHAPES[5][2] = {{1, 4}, {1, 2}, {2, 2}, {1, 1}, {2, 1}};
+
+// Device time of the quadrature and its reduction in the last evaluation timed on p (ms).
+static double timed_ms(const sc_prob *p)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev[EV_Q0], p->ev[EV_R1]) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1e300;
+    }
+    return ms;
+}
+
+// Time `run` (best of two) for each candidate in order until the budget is spent; returns the
+// index of the fastest.
+template <typename Run>
+static sc_status tune_loop(const std::vector<sc_launch> &cands, double budget_ms,
+                           std::chrono::steady_clock::time_point t_start, Run run, int *best_i, double *best_ms)
+{
+    for (size_t i = 0; i < cands.size(); ++i) {
+        double tmin = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            double ms = 0.0;
+            SC_TRY(run(cands[i], &ms));
+            tmin = std::min(tmin, ms);
+        }
+        if (tmin < *best_ms) {
+            *best_ms = tmin;
+            *best_i = (int)i;
+        }
+        const double spent =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        if (spent > budget_ms) break;
+    }
+    return SC_OK;
+}
 
 extern "C" sc_status sc_autotune(sc_prob *p, sc_precision prec, double budget_ms, sc_launch *best)
 {
@@ -1212,45 +1415,47 @@ extern "C" sc_status sc_autotune(sc_prob *p, sc_precision prec, double budget_ms
     const bool saved_has = p->has_launch;
     const sc_launch saved = p->launch;
     c->profiling = 1;
-    std::vector<sc_launch> cands;
-    const int chunk0 = default_launch(prec).chunk;
-    const int shapes[5][2] = {{1, 1}, {2, 1}, {1, 2}, {2, 2}, {1, 4}};
-    for (auto &sh : shapes)
-        for (int wpb : {1, 2, 4})
-            for (int bpc : {0, 2, 1}) {
-                sc_launch l{};
-                l.obs_per_lane = sh[0];
-                l.freq_per_lane = sh[1];
-                l.waves_per_block = wpb;
-                l.chunk = chunk0;
-                l.blocks_per_cu = bpc;
-                cands.push_back(l);
-            }
-    auto t_start = std::chrono::steady_clock::now();
-    double best_ms = 1e300;
-    sc_launch best_l = default_launch(prec);
-    sc_status st = SC_OK;
-    for (const sc_launch &l : cands) {
+    auto run = [&](const sc_launch &l, double *ms) -> sc_status {
         p->launch = l;
         p->has_launch = true;
-        double tmin = 1e300;
-        for (int rep = 0; rep < 2 && st == SC_OK; ++rep) {
-            st = sc_evaluate(p, prec, nullptr, nullptr, 1);
-            if (st != SC_OK) break;
-            if (hipStreamSynchronize(c->stream) != hipSuccess) {
-                st = fail(SC_E_DEVICE, "sc_autotune: stream failed");
-                break;
+        SC_TRY(sc_evaluate(p, prec, nullptr, nullptr, 1));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        *ms = timed_ms(p);
+        return SC_OK;
+    };
+    // stage 1: kernel shape and waves per workgroup at the library's chunk; stage 2: the chunk (it
+    // sets the split-K partials' size and the summation order) and workgroups per CU for that shape
+    const sc_launch lib = resolve_launch(p, prec);
+    std::vector<sc_launch> cands;
+    for (auto &sh : TUNE_SHAPES)
+        for (int wpb : {4, 2, 1}) {
+            sc_launch l = lib;
+            l.obs_per_lane = sh[0];
+            l.freq_per_lane = sh[1];
+            l.waves_per_block = wpb;
+            l.blocks_per_cu = 0;
+            cands.push_back(l);
+        }
+    const auto t_start = std::chrono::steady_clock::now();
+    double best_ms = 1e300;
+    int bi = -1;
+    sc_status st = tune_loop(cands, 0.6 * budget_ms, t_start, run, &bi, &best_ms);
+    sc_launch best_l = bi >= 0 ? cands[bi] : lib;
+    if (st == SC_OK && bi >= 0) {
+        std::vector<sc_launch> c2;
+        for (int chunk = 512; chunk <= 16384; chunk *= 2) {
+            if (chunk > 2 * p->n_tot && chunk != best_l.chunk) continue;
+            for (int bpc : {0, 2, 1}) {
+                if (chunk == best_l.chunk && bpc == 0) continue;   // timed in stage 1
+                sc_launch l = best_l;
+                l.chunk = chunk;
+                l.blocks_per_cu = bpc;
+                c2.push_back(l);
             }
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, p->ev[EV_Q0], p->ev[EV_Q1]) == hipSuccess) tmin = std::min(tmin, (double)ms);
         }
-        if (st != SC_OK) break;
-        if (tmin < best_ms) {
-            best_ms = tmin;
-            best_l = l;
-        }
-        double spent = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-        if (spent > budget_ms) break;
+        int bi2 = -1;
+        st = tune_loop(c2, budget_ms, t_start, run, &bi2, &best_ms);
+        if (bi2 >= 0) best_l = c2[bi2];
     }
     c->profiling = saved_prof;
     p->launch = saved;
@@ -1261,16 +1466,79 @@ extern "C" sc_status sc_autotune(sc_prob *p, sc_precision prec, double budget_ms
     return SC_OK;
 }
 
+extern "C" sc_status sc_autotune_batch(sc_ctx *c, sc_prob *const *probs, int n, sc_precision prec, double budget_ms,
+                                       sc_launch *best)
+{
+    if (!c || !probs || n < 1) return fail(SC_E_INVAL, "sc_autotune_batch: bad arguments");
+    if (prec != SC_FP64 && prec != SC_FP32_SPLIT && prec != SC_FP32)
+        return fail(SC_E_INVAL, "sc_autotune_batch: unknown precision %d", (int)prec);
+    DeviceGuard g(c->device);
+    if (budget_ms <= 0) budget_ms = 20000.0;
+    const int saved_prof = c->profiling;
+    auto it = c->batch_tune.find((int)prec);
+    const bool had = it != c->batch_tune.end();
+    const sc_launch saved = had ? it->second : sc_launch{};
+    c->profiling = 1;
+    auto run = [&](const sc_launch &l, double *ms) -> sc_status {
+        c->batch_tune[(int)prec] = l;
+        SC_TRY(sc_evaluate_batch(c, probs, n, prec));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        *ms = timed_ms(probs[0]);
+        return SC_OK;
+    };
+    c->batch_tune.erase((int)prec);
+    const sc_launch lib = batch_launch(c, probs, n, prec);
+    std::vector<sc_launch> cands;
+    for (auto &sh : TUNE_SHAPES)
+        for (int wpb : {4, 2}) {
+            sc_launch l = lib;
+            l.obs_per_lane = sh[0];
+            l.freq_per_lane = sh[1];
+            l.waves_per_block = wpb;
+            cands.push_back(l);
+        }
+    const auto t_start = std::chrono::steady_clock::now();
+    double best_ms = 1e300;
+    int bi = -1;
+    sc_status st = tune_loop(cands, 0.6 * budget_ms, t_start, run, &bi, &best_ms);
+    sc_launch best_l = bi >= 0 ? cands[bi] : lib;
+    if (st == SC_OK && bi >= 0) {
+        // one chunk for the whole batch (0: each problem's own), and workgroups per CU
+        std::vector<sc_launch> c2;
+        for (int chunk : {0, 1024, 2048, 4096, 8192, 16384})
+            for (int bpc : {0, 2}) {
+                if (chunk == best_l.chunk && bpc == best_l.blocks_per_cu) continue;
+                sc_launch l = best_l;
+                l.chunk = chunk;
+                l.blocks_per_cu = bpc;
+                c2.push_back(l);
+            }
+        int bi2 = -1;
+        st = tune_loop(c2, budget_ms, t_start, run, &bi2, &best_ms);
+        if (bi2 >= 0) best_l = c2[bi2];
+    }
+    c->profiling = saved_prof;
+    if (st != SC_OK) {
+        if (had) c->batch_tune[(int)prec] = saved;
+        else c->batch_tune.erase((int)prec);
+        return st;
+    }
+    c->batch_tune[(int)prec] = best_l;
+    if (best) *best = best_l;
+    return SC_OK;
+}
+
 extern "C" sc_status sc_autotune_save(sc_ctx *c, const char *path)
 {
     if (!c || !path) return fail(SC_E_INVAL, "sc_autotune_save: NULL argument");
     std::ofstream f(path);
     if (!f) return fail(SC_E_INVAL, "sc_autotune_save: cannot open %s", path);
-    f << "# prec log2_obs log2_k log2_nodes obs_per_lane waves_per_block chunk blocks_per_cu freq_per_lane\n";
+    f << "# prec factored log2_obs log2_k log2_nodes obs_per_lane waves_per_block chunk blocks_per_cu "
+         "freq_per_lane\n";
     for (auto &kv : c->tune)
-        f << kv.first.prec << ' ' << kv.first.b_obs << ' ' << kv.first.b_k << ' ' << kv.first.b_nodes << ' '
-          << kv.second.obs_per_lane << ' ' << kv.second.waves_per_block << ' ' << kv.second.chunk << ' '
-          << kv.second.blocks_per_cu << ' ' << kv.second.freq_per_lane << '\n';
+        f << kv.first.prec << ' ' << kv.first.fact << ' ' << kv.first.b_obs << ' ' << kv.first.b_k << ' '
+          << kv.first.b_nodes << ' ' << kv.second.obs_per_lane << ' ' << kv.second.waves_per_block << ' '
+          << kv.second.chunk << ' ' << kv.second.blocks_per_cu << ' ' << kv.second.freq_per_lane << '\n';
     return f ? SC_OK : fail(SC_E_INVAL, "sc_autotune_save: write failed");
 }
 
@@ -1286,8 +1554,8 @@ extern "C" sc_status sc_autotune_load(sc_ctx *c, const char *path)
         std::istringstream is(line);
         TuneKey k{};
         sc_launch l{};
-        if (!(is >> k.prec >> k.b_obs >> k.b_k >> k.b_nodes >> l.obs_per_lane >> l.waves_per_block >> l.chunk >>
-              l.blocks_per_cu >> l.freq_per_lane))
+        if (!(is >> k.prec >> k.fact >> k.b_obs >> k.b_k >> k.b_nodes >> l.obs_per_lane >> l.waves_per_block >>
+              l.chunk >> l.blocks_per_cu >> l.freq_per_lane))
             return fail(SC_E_INVAL, "sc_autotune_load: malformed line '%s'", line.c_str());
         if (check_launch(l) != SC_OK) return fail(SC_E_INVAL, "sc_autotune_load: invalid launch in '%s'", line.c_str());
         m[k] = l;

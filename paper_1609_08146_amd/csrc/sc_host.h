@@ -92,11 +92,13 @@ struct DeviceGuard {
     }
 };
 
+// Autotuner cache key: precision, table layout (1 factored current, 0 general tables) and the log2
+// size buckets of points, frequencies and nodes.
 struct TuneKey {
-    int prec, b_obs, b_k, b_nodes;
+    int prec, fact, b_obs, b_k, b_nodes;
     bool operator<(const TuneKey &o) const
     {
-        return std::tie(prec, b_obs, b_k, b_nodes) < std::tie(o.prec, o.b_obs, o.b_k, o.b_nodes);
+        return std::tie(prec, fact, b_obs, b_k, b_nodes) < std::tie(o.prec, o.fact, o.b_obs, o.b_k, o.b_nodes);
     }
 };
 
@@ -115,6 +117,7 @@ struct sc_ctx {
     std::vector<sc::QuadJob> host_jobs;
     hipEvent_t upload_done = nullptr;
     std::map<sc::TuneKey, sc_launch> tune;
+    std::map<int, sc_launch> batch_tune;   // batched-launch shape per precision (chunk 0: per problem)
     std::map<int, std::pair<std::vector<double>, std::vector<double>>> gauss;   // Gauss-Legendre rules by order
     std::atomic<int> n_probs{0};   // live problems and servers (a context outlives them)
 };
@@ -159,8 +162,8 @@ struct sc_prob {
     sc::DevBuf d_t, tw, timeE, timeB;
     // host staging of small uploads (rule, spectrum, points), reused across calls so that set-up calls
     // need not wait for their copies; stage_ev marks the last upload from them
-    std::vector<double> h_stage_rule, h_stage_spec, h_stage_obs;
-    sc::DevBuf d_spec, d_obs_in;
+    std::vector<double> h_stage_rule, h_stage_spec, h_stage_obs, h_stage_modes;
+    sc::DevBuf d_spec, d_obs_in, d_modes;
     hipEvent_t stage_ev = nullptr;
     bool stage_pending = false;
     // launch override

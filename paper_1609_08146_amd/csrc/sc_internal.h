@@ -24,11 +24,12 @@ hipError_t launch_obs_prep(hipStream_t st, const double *xyz, int n_obs, int n_o
 hipError_t launch_tables_from_fields(hipStream_t st, int n_k, int n_surf, int n_tot, const double *k,
                                      const double *pos64, const double *nrm, const double *wgt,
                                      const double *tan, const double *E, const double *B, double *tab64);
-// beam: 0 linear Gaussian, 1 radially, 2 azimuthally polarised
+// beam: 0 linear Gaussian, 1 radially, 2 azimuthally polarised, 3 Laguerre-Gauss mode set
+// (modes: device [n_modes][6] = p, l, ex re, ex im, ey re, ey im; unused otherwise)
 hipError_t launch_tables_gaussian(hipStream_t st, int n_k, int n_surf, int n_tot, const double *k,
                                   const double *pos64, const double *nrm, const double *wgt,
                                   const double *tan, int beam, double w0, double pol, const double *spectrum,
-                                  int consistent, double *tab64);
+                                  int consistent, const double *modes, int n_modes, double *tab64);
 // FP32 tables from the FP64 ones (tab64), or from FP32 split tables (src32, when tab64 is null)
 hipError_t launch_tables_cast(hipStream_t st, int n_k, int n_tot, const double *k, const double *pos64,
                               const double *tab64, const float *src32, float *tab32, int naive);
@@ -39,7 +40,8 @@ hipError_t launch_power_fields(hipStream_t st, int n_k, int n_surf, int n_tot, c
                                const double *E, const double *B, double *part, double *P);
 hipError_t launch_power_gaussian(hipStream_t st, int n_k, int n_surf, const double *k, const double *pos64,
                                  const double *nrm, const double *wgt, int beam, double w0, double pol,
-                                 const double *spectrum, int consistent, double *part, double *P);
+                                 const double *spectrum, int consistent, const double *modes, int n_modes,
+                                 double *part, double *P);
 int power_partial_count(int n_k);
 // tab[k][node] *= fac[k] (complex128 [n_k]) for the n_cplx complex numbers of each record (4 general,
 // 2 factored); exactly one of tab64, tab32 non-null

@@ -219,10 +219,62 @@ __global__ void k_tables_from_fields(int n_k, int n_surf, int n_tot, const doubl
 //   beam 2, azimuthally polarised: E = (-y, x, 0) g, B = (x, y, c) g;
 //   with c = (2i/k)(r^2/w0^2 - 1) for the curl-consistent variants (E = (i/k) curl B,
 //   resp. B = (-i/k) curl E) and c = 0 for the literal ones (B = -z x E).  The
-//   cylindrical beams are axisymmetric, so `pol` does not enter.
-__device__ __forceinline__ void beam_fields(int beam, double k, double X, double Y, double w0, double pol, c64 amp,
-                                            int consistent, c64 *E, c64 *B)
+//   cylindrical beams are axisymmetric, so `pol` does not enter;
+//   beam 3, a Laguerre-Gauss mode set (lg_fields), literal.
+// Laguerre-Gauss mode set (Sec. III-A: the Laguerre-Gauss modes of the paraxial wave equation are
+// the expansion basis of the incident beams), each mode in its waist cross-section carried along -z:
+//   u_{p,l} = C_{p,l} ((X + i sgn(l) Y) sqrt(2) / w0)^|l| L_p^|l|(2 r^2 / w0^2) exp(-r^2 / w0^2),
+//   C_{p,l} = sqrt(2 p! / (pi (p + |l|)!)) / w0   (unit power over the plane),
+// that is (sqrt(2) r / w0)^|l| e^{i l phi} times the radial factor, with L_p^a by its three-term
+// recurrence.  modes: [n_modes][6] = (p, l, ex re, ex im, ey re, ey im);
+//   E = sum_m (ex_m x + ey_m y) u_m amp,   B = (-z) x E = sum_m (ey_m x - ex_m y) u_m amp.
+__device__ __forceinline__ void lg_fields(const double *__restrict__ modes, int n_modes, double X, double Y,
+                                          double w0, c64 amp, c64 *E, c64 *B)
 {
+    const double s2w = 1.4142135623730951 / w0;
+    const double t = 2.0 * (X * X + Y * Y) / (w0 * w0);
+    const double gauss = exp(-0.5 * t);
+    c64 ex = {0.0, 0.0}, ey = {0.0, 0.0};
+    for (int m = 0; m < n_modes; ++m) {
+        const double *md = modes + 6 * m;
+        const int p = (int)md[0], l = (int)md[1], al = l < 0 ? -l : l;
+        // L_p^al(t): L_0 = 1, L_1 = 1 + al - t, (n + 1) L_{n+1} = (2n + 1 + al - t) L_n - (n + al) L_{n-1}
+        double l0 = 1.0, l1 = 1.0 + al - t;
+        const double lag = p == 0 ? 1.0 : l1;
+        for (int n = 1; n < p; ++n) {
+            const double l2 = ((2.0 * n + 1.0 + al - t) * l1 - (n + al) * l0) / (n + 1.0);
+            l0 = l1;
+            l1 = l2;
+        }
+        const double L = p <= 1 ? lag : l1;
+        // ((X +- iY) sqrt(2) / w0)^|l|
+        const c64 z1 = {X * s2w, (l < 0 ? -Y : Y) * s2w};
+        c64 zp = {1.0, 0.0};
+        for (int j = 0; j < al; ++j) zp = cmul(zp, z1);
+        const double C = sqrt(2.0 * exp(lgamma(p + 1.0) - lgamma(p + al + 1.0)) / M_PI) / w0;
+        const double radial = C * L * gauss;
+        const c64 u = {radial * zp.re, radial * zp.im};
+        const c64 cx = cmul(u, {md[2], md[3]}), cy = cmul(u, {md[4], md[5]});
+        ex = {ex.re + cx.re, ex.im + cx.im};
+        ey = {ey.re + cy.re, ey.im + cy.im};
+    }
+    ex = cmul(ex, amp);
+    ey = cmul(ey, amp);
+    E[0] = ex;
+    E[1] = ey;
+    E[2] = {0.0, 0.0};
+    B[0] = ey;
+    B[1] = {-ex.re, -ex.im};
+    B[2] = {0.0, 0.0};
+}
+
+__device__ __forceinline__ void beam_fields(int beam, double k, double X, double Y, double w0, double pol, c64 amp,
+                                            int consistent, const double *modes, int n_modes, c64 *E, c64 *B)
+{
+    if (beam == 3) {
+        lg_fields(modes, n_modes, X, Y, w0, amp, E, B);
+        return;
+    }
     if (beam != 0) {
         const double r2 = X * X + Y * Y;
         const double G = exp(-r2 / (w0 * w0)) / w0;
@@ -288,7 +340,7 @@ __global__ void k_tables_gaussian(int n_k, int n_surf, int n_tot, const double *
                                   const double *__restrict__ pos64, const double *__restrict__ nrm,
                                   const double *__restrict__ wgt, const double *__restrict__ tan, int beam, double w0,
                                   double pol, const double *__restrict__ spectrum, int consistent,
-                                  double *__restrict__ tab64)
+                                  const double *__restrict__ modes, int n_modes, double *__restrict__ tab64)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n_k * n_tot) return;
@@ -299,7 +351,7 @@ __global__ void k_tables_gaussian(int n_k, int n_surf, int n_tot, const double *
     const double X = p[0], Y = p[1], Z = p[2];
     const c64 amp = spectrum ? c64{spectrum[2 * kk], spectrum[2 * kk + 1]} : c64{1.0, 0.0};
     c64 E[3], B[3];
-    beam_fields(beam, k, X, Y, w0, pol, amp, consistent, E, B);
+    beam_fields(beam, k, X, Y, w0, pol, amp, consistent, modes, n_modes, E, B);
     // propagation phase e^{-ikz} fused with the node phase e^{ik|r_s|}: e^{ik(|r_s| - z)},
     // formed in double-double so that no ~1e6 rad phase is ever rounded to double
     const dd rs = dd_norm3(X, Y, Z);
@@ -368,6 +420,7 @@ __global__ void __launch_bounds__(256) k_power_gaussian(int n_surf, const double
                                                         const double *__restrict__ wgt, int beam, double w0,
                                                         double pol,
                                                         const double *__restrict__ spectrum, int consistent,
+                                                        const double *__restrict__ modes, int n_modes,
                                                         double *__restrict__ part)
 {
     const int kk = blockIdx.y;
@@ -378,7 +431,7 @@ __global__ void __launch_bounds__(256) k_power_gaussian(int n_surf, const double
     double acc = 0.0;
     for (int q = q0 + (int)threadIdx.x; q < q1; q += 256) {
         c64 E[3], B[3];
-        beam_fields(beam, k, pos64[4 * q], pos64[4 * q + 1], w0, pol, amp, consistent, E, B);
+        beam_fields(beam, k, pos64[4 * q], pos64[4 * q + 1], w0, pol, amp, consistent, modes, n_modes, E, B);
         acc += (nrm[3 * q + 2] * wgt[q]) * flux_minus_z(E, B);
     }
     block_sum_256(acc, part + (size_t)kk * POWER_BLOCKS + blockIdx.x);
@@ -541,8 +594,9 @@ __global__ void k_reduce(const PT *__restrict__ partial, int n_chunks, int n_k, 
     double acc[12];
     for (int c = 0; c < 12; ++c) acc[c] = 0.0;
     for (int ch = 0; ch < n_chunks; ++ch) {
-        const PT *p = partial + ((size_t)ch * n_k + kk) * 12 * (size_t)n_obs_pad + o;
-        for (int c = 0; c < 12; ++c) acc[c] += (double)p[(size_t)c * n_obs_pad];
+        // partials [chunk][k][point / 64][12][64]
+        const PT *p = partial + ((size_t)ch * n_k + kk) * 12 * (size_t)n_obs_pad + (size_t)(o >> 6) * 768 + (o & 63);
+        for (int c = 0; c < 12; ++c) acc[c] += (double)p[c * 64];
     }
     const double ik_inv = 1.0 / kv[kk];   // 1/(ik) = -i/k
     OT *e = E + idx * 6, *b = B + idx * 6;
@@ -660,10 +714,10 @@ hipError_t launch_tables_from_fields(hipStream_t st, int n_k, int n_surf, int n_
 hipError_t launch_tables_gaussian(hipStream_t st, int n_k, int n_surf, int n_tot, const double *k,
                                   const double *pos64, const double *nrm, const double *wgt, const double *tan,
                                   int beam, double w0, double pol, const double *spectrum, int consistent,
-                                  double *tab64)
+                                  const double *modes, int n_modes, double *tab64)
 {
     hipLaunchKernelGGL(k_tables_gaussian, dim3(nblocks((int64_t)n_k * n_tot, 256)), dim3(256), 0, st, n_k, n_surf,
-                       n_tot, k, pos64, nrm, wgt, tan, beam, w0, pol, spectrum, consistent, tab64);
+                       n_tot, k, pos64, nrm, wgt, tan, beam, w0, pol, spectrum, consistent, modes, n_modes, tab64);
     return hipGetLastError();
 }
 
@@ -678,10 +732,11 @@ hipError_t launch_power_fields(hipStream_t st, int n_k, int n_surf, int n_tot, c
 
 hipError_t launch_power_gaussian(hipStream_t st, int n_k, int n_surf, const double *k, const double *pos64,
                                  const double *nrm, const double *wgt, int beam, double w0, double pol,
-                                 const double *spectrum, int consistent, double *part, double *P)
+                                 const double *spectrum, int consistent, const double *modes, int n_modes,
+                                 double *part, double *P)
 {
     hipLaunchKernelGGL(k_power_gaussian, dim3(POWER_BLOCKS, n_k), dim3(256), 0, st, n_surf, k, pos64, nrm, wgt, beam,
-                       w0, pol, spectrum, consistent, part);
+                       w0, pol, spectrum, consistent, modes, n_modes, part);
     hipLaunchKernelGGL(k_power_finish, dim3(nblocks(n_k, 256)), dim3(256), 0, st, n_k, part, P);
     return hipGetLastError();
 }

@@ -418,11 +418,13 @@ __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0,
 #pragma unroll
     for (int f = 0; f < FPB; ++f) {
         if (f >= n_valid) break;
-        double *part = (double *)job->partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
+        // partials [chunk][k][point / 64][12][64]
+        double *part = (double *)job->partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad +
+                       (size_t)((obase - lane) >> 6) * 768;
 #pragma unroll
         for (int s = 0; s < OPL; ++s)
 #pragma unroll
-            for (int c = 0; c < 12; ++c) part[(size_t)c * n_obs_pad + obase + 64 * s] = acc[s][f][c];
+            for (int c = 0; c < 12; ++c) part[s * 768 + c * 64 + lane] = acc[s][f][c];
     }
 }
 
@@ -438,12 +440,12 @@ __device__ __forceinline__ int find_job(cjob *jobs, int n_jobs, int64_t t)
     return lo;
 }
 
-// Nodes summed plainly (FP32) before each compensated add into the running
-// sum.  The compensation is kept in LDS, and its LDS traffic waits on the
-// same counter as the scalar loads of the next node's data, so the blocks are
-// long.  A plain FP32 sum of 128 terms errs by at most 127 u (7.6e-6) of the
-// sum of their magnitudes, and typically by about sqrt(128) u (7e-7).
-constexpr int KAHAN_BLOCK = 128;
+// Nodes summed plainly in FP32 registers before each block sum is added into
+// the chunk's running sum.  A plain FP32 sum of 512 terms errs by at most
+// 511 u (3e-5) of the sum of their magnitudes and typically by about
+// sqrt(512) u (1.3e-6); the running sum over the blocks of a chunk adds at most
+// chunk / 512 - 1 further roundings.
+constexpr int SUM_BLOCK = 512;
 
 // One tile of the FP32 forms: nodes [n0, n1) of a chunk, 64*OPL points, FPB
 // frequencies.  FACT selects the factored layout: node records of two v4f
@@ -454,6 +456,13 @@ constexpr int KAHAN_BLOCK = 128;
 // SER forms delta by its series (geom_series) from h = 1 / (2|r_s|), in the
 // node record of the factored layout or the job's per-node array otherwise
 // (the job guarantees |r'| <= 4e-4 |r_s|).
+// The sums: each block of SUM_BLOCK nodes (counted from the chunk start) is
+// summed plainly in registers, and the block sums are added in order into the
+// tile's own slice of the partials in device memory, which is the chunk's
+// running sum (the first block stores, the later ones load, add and store:
+// every address belongs to one lane of one tile).  No LDS, and no second set of
+// 12 accumulators per (point, frequency) in registers, so a lane can hold four
+// frequencies at five waves per SIMD.
 template <int MODE, int OPL, int FPB, bool FACT, bool RAW, bool SER = false>
 __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
                                          const double *k64, int n_valid)
@@ -464,124 +473,85 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
     cv4f *pos = (cv4f *)job->pos;
     cv4f *tab[FPB];
     float k[FPB], kt[FPB];
+    float *part[FPB];
+    const int ob64 = (obase - lane) >> 6;   // the tile's first block of 64 points
 #pragma unroll
     for (int f = 0; f < FPB; ++f) {
         tab[f] = (cv4f *)job->tab + (size_t)kidx[f] * n_tot * TS;
         k[f] = (float)k64[f];
         kt[f] = (float)(k64[f] * INV_TWO_PI);
+        // partials [chunk][k][point / 64][12][64]: the tile's [12][64 * OPL] slice is contiguous
+        part[f] = (float *)job->partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad +
+                  (size_t)ob64 * 768;
     }
     const v4f *obs = (const v4f *)job->obs;
     v4f o[OPL];
-    // Running sums stay in registers; their Kahan compensations live in LDS
-    // (touched once per KAHAN_BLOCK nodes), which frees VGPRs for occupancy.
-    // dynamic LDS: [waves per block][OPL * FPB * 12][64] floats
-    extern __shared__ float lds_dyn[];
-    float(*cmp)[64] = (float(*)[64])(lds_dyn + (size_t)(threadIdx.x >> 6) * (OPL * FPB * 12 * 64));
-    float sum[OPL][FPB][12];
 #pragma unroll
-    for (int s = 0; s < OPL; ++s) {
-        o[s] = obs[obase + 64 * s];
-#pragma unroll
-        for (int f = 0; f < FPB; ++f)
-#pragma unroll
-            for (int c = 0; c < 12; ++c) sum[s][f][c] = 0.0f;
-    }
-#pragma unroll
-    for (int a = 0; a < OPL * FPB * 12; ++a) cmp[a][lane] = 0.0f;
-    float blk[OPL][FPB][12];
-#pragma unroll
-    for (int s = 0; s < OPL; ++s)
-#pragma unroll
-        for (int f = 0; f < FPB; ++f)
-#pragma unroll
-            for (int c = 0; c < 12; ++c) blk[s][f][c] = 0.0f;
-    // node data of node n+1 is loaded while node n is computed
+    for (int s = 0; s < OPL; ++s) o[s] = obs[obase + 64 * s];
     constexpr bool HV = SER && !FACT;   // h from the per-node array
     cfloat *hv = (cfloat *)job->hinv;
-    v4f pn = pos[PS * n0], un = {0.0f, 0.0f, 0.0f, 0.0f};
-    if constexpr (FACT) un = pos[PS * n0 + 1];
-    float hn = 0.0f;
-    if constexpr (HV) hn = hv[n0];
-    v4f t0[FPB], t1[FPB];
-#pragma unroll
-    for (int f = 0; f < FPB; ++f) {
-        t0[f] = tab[f][TS * n0];
-        if constexpr (!FACT) t1[f] = tab[f][TS * n0 + 1];
-    }
-    for (int n = n0; n < n1; ++n) {
-        const int nx = min(n + 1, n1 - 1);
-        const v4f pnx = pos[PS * nx];
-        v4f unx = un;
-        if constexpr (FACT) unx = pos[PS * nx + 1];
-        float hnx = hn;
-        if constexpr (HV) hnx = hv[nx];
-        v4f t0x[FPB], t1x[FPB];
-#pragma unroll
-        for (int f = 0; f < FPB; ++f) {
-            t0x[f] = tab[f][TS * nx];
-            if constexpr (!FACT) t1x[f] = tab[f][TS * nx + 1];
-        }
-#pragma unroll
-        for (int s = 0; s < OPL; ++s) {
-            if constexpr (MODE == MODE_SPLIT && FACT) {
-                const GeomF g = SER ? geom_series(pn, o[s], un.w) : geom_split(pn, o[s]);
-                // v = u / R, e = R / R^2, w = u x e, shared by the frequencies
-                const float r2 = g.rinv * g.rinv;
-                const float vx = un.x * g.rinv, vy = un.y * g.rinv, vz = un.z * g.rinv;
-                const float ex = g.dx * r2, ey = g.dy * r2, ez = g.dz * r2;
-                const float wx = __fmaf_rn(un.y, ez, -(un.z * ey));
-                const float wy = __fmaf_rn(un.z, ex, -(un.x * ez));
-                const float wz = __fmaf_rn(un.x, ey, -(un.y * ex));
-#pragma unroll
-                for (int f = 0; f < FPB; ++f)
-                    freq_factored<RAW>(g.rinv, g.delta, vx, vy, vz, ex, ey, ez, wx, wy, wz, t0[f], k[f], kt[f],
-                                       blk[s][f]);
-            } else if constexpr (MODE == MODE_SPLIT) {
-                const GeomF g = SER ? geom_series(pn, o[s], hn) : geom_split(pn, o[s]);
-#pragma unroll
-                for (int f = 0; f < FPB; ++f) freq_split<RAW>(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
-            } else {
-                GeomF g;
-                float R;
-                geom_naive(pn, o[s], g, R);
-#pragma unroll
-                for (int f = 0; f < FPB; ++f) freq_naive(g, R, t0[f], t1[f], k[f], blk[s][f]);
-            }
-        }
-        // every KAHAN_BLOCK nodes (counted from the chunk start), a compensated add
-        if ((n - n0) % KAHAN_BLOCK == KAHAN_BLOCK - 1 || n == n1 - 1) {
-#pragma unroll
-            for (int s = 0; s < OPL; ++s)
-#pragma unroll
-                for (int f = 0; f < FPB; ++f)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) {
-                        const int a = (s * FPB + f) * 12 + c;
-                        const float y = blk[s][f][c] - cmp[a][lane];
-                        const float tsum = sum[s][f][c] + y;
-                        cmp[a][lane] = (tsum - sum[s][f][c]) - y;
-                        sum[s][f][c] = tsum;
-                        blk[s][f][c] = 0.0f;
-                    }
-        }
-        pn = pnx;
-        un = unx;
-        hn = hnx;
-#pragma unroll
-        for (int f = 0; f < FPB; ++f) {
-            t0[f] = t0x[f];
-            if constexpr (!FACT) t1[f] = t1x[f];
-        }
-    }
-#pragma unroll
-    for (int f = 0; f < FPB; ++f) {
-        if (f >= n_valid) break;
-        float *part = (float *)job->partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad;
+    for (int b0 = n0; b0 < n1; b0 += SUM_BLOCK) {
+        const int b1 = min(b0 + SUM_BLOCK, n1);
+        float blk[OPL][FPB][12];
 #pragma unroll
         for (int s = 0; s < OPL; ++s)
 #pragma unroll
-            for (int c = 0; c < 12; ++c)
-                part[(size_t)c * n_obs_pad + obase + 64 * s] = sum[s][f][c] - cmp[(s * FPB + f) * 12 + c][lane];
+            for (int f = 0; f < FPB; ++f)
+#pragma unroll
+                for (int c = 0; c < 12; ++c) blk[s][f][c] = 0.0f;
+        for (int n = b0; n < b1; ++n) {
+            const v4f pn = pos[PS * n];
+            v4f un = {0.0f, 0.0f, 0.0f, 0.0f};
+            if constexpr (FACT) un = pos[PS * n + 1];
+            float hn = 0.0f;
+            if constexpr (HV) hn = hv[n];
+            v4f t0[FPB], t1[FPB];
+#pragma unroll
+            for (int f = 0; f < FPB; ++f) {
+                t0[f] = tab[f][TS * n];
+                if constexpr (!FACT) t1[f] = tab[f][TS * n + 1];
+            }
+#pragma unroll
+            for (int s = 0; s < OPL; ++s) {
+                if constexpr (MODE == MODE_SPLIT && FACT) {
+                    const GeomF g = SER ? geom_series(pn, o[s], un.w) : geom_split(pn, o[s]);
+                    // v = u / R, e = R / R^2, w = u x e, shared by the frequencies
+                    const float r2 = g.rinv * g.rinv;
+                    const float vx = un.x * g.rinv, vy = un.y * g.rinv, vz = un.z * g.rinv;
+                    const float ex = g.dx * r2, ey = g.dy * r2, ez = g.dz * r2;
+                    const float wx = __fmaf_rn(un.y, ez, -(un.z * ey));
+                    const float wy = __fmaf_rn(un.z, ex, -(un.x * ez));
+                    const float wz = __fmaf_rn(un.x, ey, -(un.y * ex));
+#pragma unroll
+                    for (int f = 0; f < FPB; ++f)
+                        freq_factored<RAW>(g.rinv, g.delta, vx, vy, vz, ex, ey, ez, wx, wy, wz, t0[f], k[f], kt[f],
+                                           blk[s][f]);
+                } else if constexpr (MODE == MODE_SPLIT) {
+                    const GeomF g = SER ? geom_series(pn, o[s], hn) : geom_split(pn, o[s]);
+#pragma unroll
+                    for (int f = 0; f < FPB; ++f) freq_split<RAW>(g, t0[f], t1[f], k[f], kt[f], blk[s][f]);
+                } else {
+                    GeomF g;
+                    float R;
+                    geom_naive(pn, o[s], g, R);
+#pragma unroll
+                    for (int f = 0; f < FPB; ++f) freq_naive(g, R, t0[f], t1[f], k[f], blk[s][f]);
+                }
+            }
+        }
+        // the block sum into the chunk's running sum (a frequency past the last one is not stored)
+        const bool first = b0 == n0;
+#pragma unroll
+        for (int f = 0; f < FPB; ++f) {
+            if (f >= n_valid) break;
+#pragma unroll
+            for (int s = 0; s < OPL; ++s)
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    float *q = part[f] + s * 768 + c * 64 + lane;
+                    *q = first ? blk[s][f][c] : *q + blk[s][f][c];
+                }
+        }
     }
 }
 
@@ -591,8 +561,19 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
 // Node and table data are wave-uniform (scalar loads); each lane owns OPL
 // points x FPB frequencies x 12 accumulators.  Every wave exits once all
 // segments are exhausted.
+// Resident waves per SIMD the register allocation plans for.  One point x four frequencies per
+// lane in FP32 holds 48 accumulators; unconstrained, the compiler interleaves the four
+// frequencies' chains with up to ~116 VGPRs (4 waves); at 5 waves (<= 102 VGPRs) it keeps most of
+// that overlap without spilling, which measured fastest.  Other shapes: no constraint.
 template <int MODE, int OPL, int FPB>
-__global__ void __launch_bounds__(256) k_quad(const QuadJob *__restrict__ jobs_, int n_jobs, int64_t n_tiles,
+constexpr int quad_waves_per_eu()
+{
+    return MODE != MODE_FP64 && OPL == 1 && FPB == 4 ? 5 : 1;
+}
+
+template <int MODE, int OPL, int FPB>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(quad_waves_per_eu<MODE, OPL, FPB>())))
+k_quad(const QuadJob *__restrict__ jobs_, int n_jobs, int64_t n_tiles,
                                               unsigned int *__restrict__ counter)
 {
     cjob *jobs = (cjob *)jobs_;
@@ -701,19 +682,11 @@ static const void *quad_fn_dyn(int mode, int opl, int fpb)
     return nullptr;
 }
 
-// Dynamic LDS of one quadrature block: the FP32 forms keep their Kahan compensations there.
-static size_t quad_lds_bytes(int mode, int opl, int fpb, int waves_per_block)
-{
-    return mode == MODE_FP64 ? 0 : sizeof(float) * 64 * 12 * (size_t)opl * fpb * waves_per_block;
-}
-
 int quad_max_blocks_per_cu(int mode, int opl, int fpb, int waves_per_block)
 {
     const void *fn = quad_fn_dyn(mode, opl, fpb);
     int nb = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * waves_per_block,
-                                                            quad_lds_bytes(mode, opl, fpb, waves_per_block)) !=
-                   hipSuccess)
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * waves_per_block, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
@@ -723,10 +696,9 @@ hipError_t launch_quad(hipStream_t st, int mode, int opl, int fpb, int waves_per
 {
     if (!shape_ok(opl, fpb)) return hipErrorInvalidValue;
     dim3 g(grid), b(64 * waves_per_block);
-    const size_t lds = quad_lds_bytes(mode, opl, fpb, waves_per_block);
 #define SC_QUAD_LAUNCH(M, O, F)                                                                          \
     if (mode == M && opl == O && fpb == F) {                                                            \
-        hipLaunchKernelGGL((k_quad<M, O, F>), g, b, lds, st, jobs, n_jobs, n_tiles, counter);           \
+        hipLaunchKernelGGL((k_quad<M, O, F>), g, b, 0, st, jobs, n_jobs, n_tiles, counter);           \
         return hipGetLastError();                                                                       \
     }
     SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_FP64)

@@ -16,7 +16,7 @@ struct QuadJob {
     const void *obs;      // [n_obs_pad][4] real
     const void *hinv;     // [n_tot] 1 / (2|r_s|) real (general layout, series_delta)
     const double *k;      // [n_k]
-    void *partial;        // [n_chunks][n_k][12][n_obs_pad] real
+    void *partial;        // [n_chunks][n_k][n_obs_pad / 64][12][64] real
     int n_tot;            // surface + rim nodes
     int n_obs_pad;        // observation points, padded to the obs block
     int n_k;

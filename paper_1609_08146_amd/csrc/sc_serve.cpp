@@ -210,9 +210,10 @@ static bool debug_fail_this_quantum()
     return fail_at > 0 && count == fail_at;
 }
 
-// One kernel shape per precision, so that requests of a precision share launches.
+// One kernel shape per precision, so that requests of a precision share launches: the FP32 forms
+// take four frequencies per lane (the built-in beams of the requests factor), FP64 two.
 static int server_opl(sc_precision) { return 1; }
-static int server_fpb(sc_precision) { return 2; }
+static int server_fpb(sc_precision prec) { return prec == SC_FP64 ? 2 : 4; }
 
 // Build the request's device state on the preparation stream.
 static sc_status setup_request(sc_server *s, Req *r)

@@ -10,7 +10,7 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: longer CPU test")
+    config.addinivalue_line("markers", "slow: longer test (selected by -m gpu as well when it needs the GPU)")
 
 
 def gpu_available() -> bool:

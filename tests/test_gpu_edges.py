@@ -130,8 +130,8 @@ def test_rejected_sizes_and_empty_inputs(ctx):
     p = _problem(ctx, 20.0, 40.0, 4, 4, [K], 20.0, np.zeros((1, 3)))
     p.evaluate("fp64")
     with pytest.raises(ScError) as e:
-        p.to_time(1.0, np.zeros(524281))                                          # more than SC_MAX_TIMES
+        p.to_time_at(1.0, np.zeros(524281))                                          # more than SC_MAX_TIMES
     assert e.value.status == SC_E_INVAL
-    Et, _ = p.to_time(1.0, np.zeros(524280))
+    Et, _ = p.to_time_at(1.0, np.zeros(524280))
     assert Et.shape == (524280, 1, 3)
     p.close()

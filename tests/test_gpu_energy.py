@@ -152,7 +152,7 @@ def test_table1_focal_spot_matches_the_paper(ctx):
     p.normalize_energy(w.meta["eps"], w.meta["e_tot"], w.dk)
     p.evaluate("fp32_split", keep_on_device=True)
     t = 2 * w.f + np.arange(-128, 129) * (lam / 32)
-    Et, Bt = p.to_time(w.dk, t)
+    Et, Bt = p.to_time_at(w.dk, t)
     p.close()
     r = bench.focal_spot(Et, Bt, 64, 2.0 * lam)
     print({k: r[k] for k in ("peak_intensity_W_cm2", "eccentricity", "max_Bz_over_max_Ex", "fwhm_x_m",

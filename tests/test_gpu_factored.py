@@ -332,3 +332,30 @@ def test_delta_by_series_and_by_division(ctx, orc, factored):
     assert errs["between"] < 2e-6
     assert not np.array_equal(Es, Ed)          # the two paths really differ in rounding
     p.close()
+
+
+@pytest.mark.parametrize("factored", [True, False])
+def test_fp64_delta_by_series_and_by_division(ctx, orc, factored):
+    """The FP64 form near the focus: delta and 1/|R| by their series (host points within 4e-4 |r_s|)
+    against the division and the square root (the same points handed over in device memory take
+    the general forms), on either table layout.  Both within 1e-12 of the oracle and within 1e-13 of
+    each other."""
+    import torch
+    from paper_1609_08146_amd import problem_from_workload
+    w = workloads.broadband(n_k=6, n_nodes=60)
+    near = w.obs[::41]
+    sub = replace(w, obs=near)
+    Eo, Bo = orc.solve(sub)
+    p = problem_from_workload(ctx, sub)
+    p.set_factoring(factored)
+    assert p.factored_for("fp64") is factored
+    Es, Bs = p.evaluate("fp64")
+    p.set_observation(torch.tensor(near, dtype=torch.float64, device="cuda"))
+    Ed, Bd = p.evaluate("fp64")
+    errs = dict(series=max(rel_l2(Es, Eo), rel_l2(Bs, Bo)), division=max(rel_l2(Ed, Eo), rel_l2(Bd, Bo)),
+                between=max(rel_l2(Es, Ed), rel_l2(Bs, Bd)))
+    print("factored" if factored else "general", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert errs["series"] < 1e-12 and errs["division"] < 1e-12
+    assert errs["between"] < 1e-13
+    assert not np.array_equal(Es, Ed)          # the two paths really differ in rounding
+    p.close()

@@ -49,7 +49,7 @@ def alone(ctx, w, prec, t=None, dk=1.0):
     E, B = p.evaluate(prec)
     Et = Bt = None
     if t is not None:
-        Et, Bt = p.to_time(dk, t)
+        Et, Bt = p.to_time_at(dk, t)
     p.close()
     return E, B, Et, Bt
 

@@ -116,3 +116,42 @@ def test_time_gaussian_pulse(orc):
     expect = math.sqrt(2 * math.pi) * sigma * np.exp(-1j * kc * t) * np.exp(-(sigma * t) ** 2 / 2)
     # truncation at 6 sigma and the (exponentially small) aliasing are < 1e-7 relative
     assert np.abs(Ft - expect).max() / abs(expect).max() < 1e-7
+
+
+def test_time_large_phase_is_exact(orc):
+    """k t up to 2e7 rad: one sample at k = 2 pi (as a double, 2 pi + eps with eps = sin(k)) gives
+    F(t) = e^{-i k t} = e^{-i (eps t + 2 pi t)}; for t an integer plus a quarter that is
+    -i e^{-i eps t} exactly.  A phase rounded to a 64-bit mantissa would be off by ~5e-13 rad here."""
+    k = K
+    eps = math.sin(k)                    # k - 2 pi, to ~1e-48
+    t = np.array([1e5, 1e6 + 0.25, 3e6 + 0.5, 3e6 + 0.75])
+    F = orc.time_transform([k], 1.0, t, np.ones((1, 1), complex))[:, 0]
+    turn = np.array([1.0, -1j, -1.0, 1j])   # e^{-2 pi i t} for the fractional parts 0, 1/4, 1/2, 3/4
+    ref = turn * np.exp(-1j * eps * t)
+    assert np.abs(F - ref).max() < 1e-15, np.abs(F - ref)
+
+
+def test_time_focus_closed_form_pulse(orc):
+    """The focus closed form of a plane wave (P1) under a Gaussian spectral amplitude A(k),
+    transformed to time by the oracle's chain (reflected field, then the semi-discrete sum), equals
+    the direct sum of the closed form: E_x(t) = dk sum_n E_ref(k_n) A(k_n) e^{-i k_n t}."""
+    f, a = 20.0, 25.0
+    U = a * a / (4 * f)
+    ks = K * (1 + 0.05 * np.linspace(-3, 3, 25))
+    dk = ks[1] - ks[0]
+    A = np.exp(-((ks - K) / (0.05 * K)) ** 2 / 2)
+    m = orc.mirror(f, a, 80, 32)
+    Ei, Bi = orc.incident_tables(m, ks, orc.PLANE, spectrum=A)
+    E, B = orc.reflected_field(m, ks, Ei, Bi, np.zeros((1, 3)))
+    t = 2 * f + np.linspace(-30, 30, 13)
+    Et = orc.time_transform(ks, dk, t, E)[:, 0]
+    Bt = orc.time_transform(ks, dk, t, B)[:, 0]
+    ph = np.exp(2j * ks * f)
+    ex = ph * (2j * ks * f * U / (f + U) + U * (U - 2 * f) / (f + U) ** 2 - 2j * f * U / (ks * (f + U) ** 3))
+    by = ph * (2j * ks * f * U / (f + U) - U * (U + 2 * f) / (f + U) ** 2)
+    tw = np.exp(-1j * np.outer(t, ks)) * dk
+    ref_x, ref_y = tw @ (ex * A), tw @ (by * A)
+    scale = np.abs(ref_x).max()
+    assert np.abs(Et[:, 0] - ref_x).max() < 1e-12 * scale
+    assert np.abs(Bt[:, 1] - ref_y).max() < 1e-12 * scale
+    assert np.abs(Et[:, 1:]).max() < 1e-12 * scale

@@ -72,7 +72,8 @@ MUTANTS = [
                         "qd p2 = ((2.0Q * m + 1.0Q) * x * p1 - (qd)m * p0) / (qd)(m + 2);", 1)]),
     ("output_transpose", [("size_t off = ((size_t)ik * n_obs + o) * 6;", "size_t off = ((size_t)o * n_k + ik) * 6;", -2)]),
     ("dgrad_sign", [("cld c1 = { -1.0L / (R * R), k / R };", "cld c1 = { 1.0L / (R * R), k / R };", 1)]),
-    ("time_sign", [("sincosl(-(ld)kv[n] * (ld)t[m], &s, &c);", "sincosl((ld)kv[n] * (ld)t[m], &s, &c);", 1)]),
+    ("time_sign", [("qd ph = -(qd)kv[n] * (qd)t[m];", "qd ph = (qd)kv[n] * (qd)t[m];", 1)]),
+    ("time_reduction", [("qd red = ph - TWO_PI_Q * rintq(ph / TWO_PI_Q);", "qd red = ph - M_PIq * rintq(ph / M_PIq);", 1)]),
     ("time_dk", [("(double)(acc.re * (ld)dk)", "(double)(acc.re)", 1), ("(double)(acc.im * (ld)dk)", "(double)(acc.im)", 1)]),
     ("power_sign", [("acc += (ld)wgt[q] * (ld)nrm[3 * q + 2] * (-sz);", "acc += (ld)wgt[q] * (ld)nrm[3 * q + 2] * sz;", 1)]),
     ("power_drop_EyBx", [("- ((ld)e[2] * b[0] + (ld)e[3] * b[1])", "", 1)]),

@@ -262,7 +262,8 @@ def serving_arrivals(rate_hz: float, duration_s: float, seed: int = SERVING_SEED
 # A general surface is handed to the method as its quadrature: nodes, area-weighted
 # normals n dS (pointing toward the incoming beam), and the boundary as nodes with the
 # surface normal and oriented line elements dl.  These build such data for pieces of
-# the paraboloid z = (x^2 + y^2)/4f - f: off-axis segments and annuli.
+# the paraboloid z = (x^2 + y^2)/4f - f (off-axis segments and annuli) and for an ellipsoidal
+# cap, the non-parabolic surface Sec. III-C-1 discusses.
 
 def _paraboloid_piece(f, cx, rho_lo, rho_hi, n_rho, n_psi):
     """Polar tensor grid (Gauss-Legendre in rho, trapezoid in psi) of the projected region
@@ -310,6 +311,40 @@ def paraboloid_annulus(f: float, a_in: float, a_out: float, n_rho: int, n_psi: i
     o = _paraboloid_circle(f, 0.0, a_out, n_psi, outer=True)
     i = _paraboloid_circle(f, 0.0, a_in, n_psi, outer=False)
     return (xyz, ndS) + tuple(np.concatenate([u, v]) for u, v in zip(o, i))
+
+
+def ellipsoid_cap(f: float, c: float, r_max: float, n_r: int, n_phi: int):
+    """Lower cap of the ellipsoid z^2/c^2 + (x^2 + y^2)/a^2 = 1 with a^2 = 2 f c (the ellipsoid
+    whose vertex curvature is that of the paraboloid of focal length f, reached as c -> inf),
+    shifted up by e = sqrt(c^2 - a^2) so that its lower focus lies at the origin:
+        z = e - c sqrt(1 - r^2/a^2),  0 <= r <= r_max < a.
+    Gauss-Legendre in r x trapezoid in phi like the built-in paraboloid, with n dS = n~ r dr dphi,
+    n~ = (-z' cos phi, -z' sin phi, 1), and the rim r = r_max with dl counter-clockwise seen from
+    +z.  Returns (xyz, ndS, rim_xyz, rim_n, rim_dl).  Needs c > 2f (a prolate ellipsoid)."""
+    a2 = 2.0 * f * c
+    if not (c * c > a2 and r_max * r_max < a2):
+        raise ValueError("ellipsoid_cap needs c > 2f and r_max < sqrt(2 f c)")
+    e = math.sqrt(c * c - a2)
+    xg, wg = np.polynomial.legendre.leggauss(n_r)
+    r = r_max * (xg + 1.0) / 2.0
+    wr = r_max * wg / 2.0
+    phi = 2.0 * math.pi * np.arange(n_phi) / n_phi
+    dphi = 2.0 * math.pi / n_phi
+    R, P = np.meshgrid(r, phi, indexing="ij")
+    root = np.sqrt(1.0 - R * R / a2)
+    z = e - c * root
+    dz = c * R / (a2 * root)
+    x, y = R * np.cos(P), R * np.sin(P)
+    xyz = np.stack([x, y, z], axis=-1).reshape(-1, 3)
+    n = np.stack([-dz * np.cos(P), -dz * np.sin(P), np.ones_like(R)], axis=-1).reshape(-1, 3)
+    ndS = n * (wr[:, None] * R * dphi).reshape(-1, 1)
+    cp, sp = np.cos(phi), np.sin(phi)
+    root_m = math.sqrt(1.0 - r_max * r_max / a2)
+    z_m, dz_m = e - c * root_m, c * r_max / (a2 * root_m)
+    rim_xyz = np.stack([r_max * cp, r_max * sp, np.full(n_phi, z_m)], axis=-1)
+    rim_n = np.stack([-dz_m * cp, -dz_m * sp, np.ones(n_phi)], axis=-1)
+    rim_dl = np.stack([-r_max * sp, r_max * cp, np.zeros(n_phi)], axis=-1) * dphi
+    return xyz, ndS, rim_xyz, rim_n, rim_dl
 
 
 def shifted_gaussian_fields(pts, k, w0: float, cx: float, spectrum=None):
