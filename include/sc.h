@@ -374,6 +374,29 @@ sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs, int on_de
  * on the device (for sc_to_time / sc_to_time_at / sc_get_result).  Needs mirror, frequencies,
  * incident field and observation points (SC_E_STATE).                      */
 sc_status sc_evaluate(sc_prob *p, sc_precision prec, void *E, void *B, int on_device);
+/* sc_evaluate for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the call allocates
+ * nothing, device or host.  Its scratch memory (work counters, the job
+ * record, the split-K partials) is a static device array of
+ * SC_NOALLOC_SCRATCH_BYTES on each GPU, which the library holds until the
+ * process ends.
+ * E, B: DEVICE arrays [n_k][n_obs][3] of complex128 (SC_FP64) or complex64
+ * (the FP32 forms), written by the stream work enqueued here.  Requires the
+ * problem's tables of `prec` to be built (SC_E_STATE otherwise): one
+ * sc_evaluate of the problem in that precision since its mirror, frequencies
+ * or incident field last changed builds them (the FP32-split tables of a
+ * field whose current factors are built when the field is set).  Its split-K
+ * partials, 12 x
+ * ceil(nodes / chunk) x n_k x n_obs (padded to 128) reals of the precision,
+ * must fit in SC_NOALLOC_SCRATCH_BYTES - 1024 bytes (SC_E_INVAL otherwise).
+ * The results equal sc_evaluate's bit for bit with the same launch shape; the
+ * problem's stored result (sc_get_result, sc_to_time*) is left as it was.
+ * Every call on a GPU shares that GPU's array and leaves its contents there
+ * (each call clears the counters it needs): calls that overlap on one GPU,
+ * from other streams, contexts or threads, race and give wrong results.     */
+#define SC_NOALLOC_SCRATCH_BYTES (64u << 20)
+sc_status sc_evaluate_noalloc(sc_prob *p, sc_precision prec, void *E, void *B);
+
 /* Copy the last result (same layout and type as sc_evaluate).              */
 sc_status sc_get_result(const sc_prob *p, void *E, void *B, int on_device);
 

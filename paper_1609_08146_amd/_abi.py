@@ -15,6 +15,7 @@ SC_OK, SC_E_INVAL, SC_E_NOMEM, SC_E_DEVICE, SC_E_STATE, SC_E_UNSUPPORTED = 0, -1
 SC_E_TIMEOUT, SC_E_CANCELLED, SC_E_REJECTED = -6, -7, -8
 SC_FP64, SC_FP32_SPLIT, SC_FP32 = 0, 1, 2
 SC_BEAM_LINEAR, SC_BEAM_RADIAL, SC_BEAM_AZIMUTHAL = 0, 1, 2
+SC_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 STATUS_NAMES = {0: "SC_OK", -1: "SC_E_INVAL", -2: "SC_E_NOMEM", -3: "SC_E_DEVICE", -4: "SC_E_STATE",
                 -5: "SC_E_UNSUPPORTED", -6: "SC_E_TIMEOUT", -7: "SC_E_CANCELLED", -8: "SC_E_REJECTED"}
@@ -100,6 +101,7 @@ SIGNATURES = {
     "sc_get_factoring_for": [V, I, ctypes.POINTER(I)],
     "sc_set_observation": [V, P, I, I],
     "sc_evaluate": [V, I, P, P, I],
+    "sc_evaluate_noalloc": [V, I, P, P],
     "sc_get_result": [V, P, P, I],
     "sc_to_time": [V, D, D, I, P, P, I],
     "sc_to_time_at": [V, D, P, I, P, P, I],

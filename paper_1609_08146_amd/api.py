@@ -371,6 +371,17 @@ class Problem:
         call("sc_evaluate", self.h, prec, _ptr(E), _ptr(B), 0)
         return E, B
 
+    def evaluate_noalloc(self, out, precision="fp32_split"):
+        """sc_evaluate_noalloc: evaluate into device tensors out=(E, B) without any allocation (the
+        problem must have been evaluated once in this precision; the stored result is unchanged)."""
+        prec = _prec(precision)
+        E, B = out
+        dt = "complex128" if prec == SC_FP64 else "complex64"
+        for t, name in ((E, "evaluate_noalloc E"), (B, "evaluate_noalloc B")):
+            _check_device(t, dt, self.n_k * self.n_obs * 3, name)
+        call("sc_evaluate_noalloc", self.h, prec, _ptr(E), _ptr(B))
+        return out
+
     def result(self):
         E, B = self._out_host(self._res_prec, self.n_k), self._out_host(self._res_prec, self.n_k)
         call("sc_get_result", self.h, _ptr(E), _ptr(B), 0)

@@ -54,6 +54,8 @@ bool sc::debug_fail_this_alloc()
     return fail_at > 0 && count == fail_at;
 }
 
+static sc_status scratch_init(int device);
+
 extern "C" sc_status sc_ctx_create(int device, void *stream, sc_ctx **out)
 {
     if (!out) return fail(SC_E_INVAL, "sc_ctx_create: out is NULL");
@@ -78,7 +80,8 @@ extern "C" sc_status sc_ctx_create(int device, void *stream, sc_ctx **out)
         c->own_stream = true;
     }
     static_assert(QUAD_SEGMENTS * sizeof(unsigned int) <= 256, "work counters must fit the counter buffer");
-    sc_status st = c->counter.reserve(256);
+    sc_status st = scratch_init(device);
+    if (st == SC_OK) st = c->counter.reserve(256);
     if (st == SC_OK && hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess)
         st = fail(SC_E_DEVICE, "sc_ctx_create: hipEventCreate failed");
     if (st != SC_OK) {
@@ -872,7 +875,7 @@ static sc_status select_tables(sc_prob *p, sc_precision prec, bool build, const 
         return fail(SC_E_STATE, "evaluate: FP64 tables were not kept (sc_set_table_storage(p, 0))");
     if (prec != SC_FP64 && !p->tab32_ok && !p->has_tab64)
         return fail(SC_E_STATE, "evaluate: no tables to build the FP32 tables from");
-    static const char *not_built = "evaluate: the tables of this precision are not built yet "
+    static const char *not_built = "evaluate without allocation: the tables of this precision are not built yet "
                                    "(evaluate the problem once with sc_evaluate first)";
     hipStream_t st = p->ctx->stream;
     const int n_k = (int)p->k.size();
@@ -1071,6 +1074,77 @@ extern "C" sc_status sc_evaluate(sc_prob *p, sc_precision prec, void *E, void *B
     p->last_evals = (int64_t)p->n_obs * job.n_k * p->n_surf;
     p->last_tiles = job.n_tiles;
     return copy_out(p, E, B, on_device, real_size(prec) * 6 * (size_t)job.n_k * p->n_obs);
+}
+
+// ------------------------------------------------------- evaluation without allocation
+// A statically allocated device array serves sc_evaluate_noalloc as its scratch memory: the work
+// counters, the job record and the split-K partials.  The array's name is a host-side stand-in;
+// its device address (one copy per GPU) is looked up once per device with hipGetSymbolAddress
+// when a context is created there, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[SC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+constexpr size_t SCRATCH_COUNTERS = 0;        // QUAD_SEGMENTS work counters
+constexpr size_t SCRATCH_JOB = 256;           // one QuadJob
+constexpr size_t SCRATCH_PARTIAL = 1024;      // split-K partials from here on
+std::mutex scratch_mu;
+void *scratch_dev[MAX_DEVICES] = {};
+}  // namespace
+
+static_assert(QUAD_SEGMENTS * sizeof(unsigned int) <= SCRATCH_JOB, "work counters overlap the job record");
+static_assert(SCRATCH_JOB + sizeof(QuadJob) <= SCRATCH_PARTIAL, "job record overlaps the partials");
+
+// Called with the device current (sc_ctx_create).
+static sc_status scratch_init(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return SC_OK;   // sc_evaluate_noalloc reports it
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (scratch_dev[device]) return SC_OK;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(SC_E_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", device, hipGetErrorString(e));
+    scratch_dev[device] = ptr;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_evaluate_noalloc(sc_prob *p, sc_precision prec, void *E, void *B)
+{
+    if (!p || !E || !B) return fail(SC_E_INVAL, "sc_evaluate_noalloc: NULL argument");
+    const int dev = p->ctx->device;
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(scratch_mu);
+        if (dev >= 0 && dev < MAX_DEVICES) base = scratch_dev[dev];
+    }
+    if (!base) return fail(SC_E_STATE, "sc_evaluate_noalloc: no scratch memory on device %d", dev);
+    DeviceGuard g(dev);
+    const sc_launch l = resolve_launch(p, prec);
+    SC_TRY(check_launch(l));
+    const void *tab = nullptr;
+    bool fact = false;
+    SC_TRY(select_tables(p, prec, false, &tab, &fact));
+    const size_t need = partial_bytes(p, prec, l);
+    if (need > SC_NOALLOC_SCRATCH_BYTES - SCRATCH_PARTIAL)
+        return fail(SC_E_INVAL,
+                    "sc_evaluate_noalloc: the split-K partials need %zu bytes (12 x %d node chunks x %zu frequencies x "
+                    "%d padded points), the scratch holds %zu",
+                    need, (p->n_tot + l.chunk - 1) / l.chunk, p->k.size(), p->n_obs_pad,
+                    (size_t)SC_NOALLOC_SCRATCH_BYTES - SCRATCH_PARTIAL);
+    char *b = (char *)base;
+    unsigned int *counter = (unsigned int *)(b + SCRATCH_COUNTERS);
+    QuadJob *djob = (QuadJob *)(b + SCRATCH_JOB);
+    QuadJob job{};
+    fill_job(p, prec, l, tab, fact, b + SCRATCH_PARTIAL, job);
+    hipStream_t st = p->ctx->stream;
+    HIP_TRY(launch_store_job(st, job, djob));
+    HIP_TRY(launch_fill_u32(st, counter, 0u, QUAD_SEGMENTS));
+    HIP_TRY(launch_quad(st, mode_of(prec), l.obs_per_lane, l.freq_per_lane, l.waves_per_block,
+                        quad_grid(p->ctx, prec, l, job.n_tiles), djob, 1, job.n_tiles, counter));
+    HIP_TRY(launch_reduce(st, mode_of(prec), b + SCRATCH_PARTIAL, job.n_chunks, job.n_k, p->n_obs, p->n_obs_pad,
+                          p->d_k.as<double>(), E, B));
+    return SC_OK;
 }
 
 extern "C" sc_status sc_get_result(const sc_prob *p, void *E, void *B, int on_device)

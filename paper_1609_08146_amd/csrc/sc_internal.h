@@ -76,6 +76,8 @@ hipError_t launch_twiddles(hipStream_t st, int n_k, const double *k, int n_t, co
 hipError_t launch_time(hipStream_t st, int is_f64, int n_k, int n_t, int64_t n_x, const double *tw,
                        const void *F, void *Ft);
 hipError_t launch_fill_u32(hipStream_t st, unsigned int *p, unsigned int v, int n);
+// *dst = job on the device (the job travels as a kernel argument)
+hipError_t launch_store_job(hipStream_t st, const QuadJob &job, QuadJob *dst);
 
 // Occupancy helper: max resident workgroups per CU for a quadrature variant.
 int quad_max_blocks_per_cu(int mode, int obs_per_lane, int freq_per_lane, int waves_per_block);

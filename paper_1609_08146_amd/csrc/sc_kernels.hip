@@ -665,6 +665,12 @@ __global__ void k_fill_u32(unsigned int *p, unsigned int v, int n)
     if (i < n) p[i] = v;
 }
 
+// One quadrature job written to device memory from a kernel argument (no host buffer to keep alive).
+__global__ void k_store_job(QuadJob job, QuadJob *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = job;
+}
+
 // ================================================================== launchers
 
 static inline unsigned int nblocks(int64_t n, int bs) { return (unsigned int)((n + bs - 1) / bs); }
@@ -802,6 +808,12 @@ hipError_t launch_time(hipStream_t st, int is_f64, int n_k, int n_t, int64_t n_x
 hipError_t launch_fill_u32(hipStream_t st, unsigned int *p, unsigned int v, int n)
 {
     hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(n, 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_job(hipStream_t st, const QuadJob &job, QuadJob *dst)
+{
+    hipLaunchKernelGGL(k_store_job, dim3(1), dim3(64), 0, st, job, dst);
     return hipGetLastError();
 }
 
