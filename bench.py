@@ -237,9 +237,9 @@ def batch_run(n_instances: int = 256, general: bool = False, tune: bool = True, 
     evals = sum(w.evals for w in ws)
     fact_evals = sum(w.evals for w, p in zip(ws, probs) if p.factored)
 
-    def partial_bytes(chunk_of):
-        # split-K partials: 12 reals per (chunk, frequency, padded point)
-        return sum(4 * 12 * -(-(w.n_r + 1) * w.n_phi // chunk_of(p)) * w.n_k * (-(-w.n_obs // 128) * 128)
+    def partial_bytes():
+        # split-K partials: 12 reals per (chunk, frequency, padded point), at the chunk each problem used
+        return sum(4 * 12 * -(-(w.n_r + 1) * w.n_phi // p.timing()["chunk"]) * w.n_k * (-(-w.n_obs // 128) * 128)
                    for w, p in zip(ws, probs))
 
     def timed(label, launch):
@@ -252,12 +252,12 @@ def batch_run(n_instances: int = 256, general: bool = False, tune: bool = True, 
         quad_ms = probs[0].timing()["quad_ms"]
         fpl = launch["freq_per_lane"]
         flops = flops_per_eval(True, fpl) * fact_evals + flops_per_eval(False, fpl) * (evals - fact_evals)
-        chunk = launch["chunk"]
         return {"label": label, "value": evals / dt, "seconds": dt, "quad_ms": quad_ms,
                 "quad_evals_per_s": evals / (quad_ms * 1e-3), "launch": launch,
                 "tflops": flops / (quad_ms * 1e-3) / 1e12,
                 "frac_fp32_peak": flops / (quad_ms * 1e-3) / 1e12 / PEAK_FP32,
-                "partial_bytes": partial_bytes(lambda p: chunk if chunk else p.launch("fp32_split")["chunk"])}
+                "chunks_used": sorted({p.timing()["chunk"] for p in probs}),
+                "partial_bytes": partial_bytes()}
 
     # the library's batch launch: the shape of the layout carrying most evaluations, each problem's chunk
     fact_major = 2 * fact_evals > evals
@@ -856,12 +856,15 @@ def main():
     if args.serve_seconds > 0 and args.shard == 1:
         # the request stream as specified (200 per second for 60 s: an overload) and one sustainable rate
         out["serving"] = []
-        for rate, secs in ((args.serve_rate, args.serve_seconds), (args.serve_rate_low, args.serve_seconds_low)):
+        # the sustainable rate first: a server started in a process right after an overload prepares
+        # requests more slowly for a while
+        for rate, secs in ((args.serve_rate_low, args.serve_seconds_low), (args.serve_rate, args.serve_seconds)):
             if secs <= 0:
                 continue
             sv = serve_run(rate, secs)
             row = {k: sv[k] for k in ("rate_hz", "duration_s", "arrivals", "completed", "cancelled", "rejected",
-                                      "p50_ms", "p99_ms", "evals_per_s", "device_busy_frac")}
+                                      "p50_ms", "p99_ms", "evals_per_s", "device_busy_frac",
+                                      "quanta_evals_per_device_s", "prep_ms_per_request")}
             row["workload"] = ("seeded Poisson stream of sweep-like requests (mean 3.6e10 evaluations), FP32-split "
                                "with time transform, 200 GB admission budget")
             out["serving"].append(row)

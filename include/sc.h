@@ -75,8 +75,9 @@ typedef enum {
  *  SC_FP32_SPLIT the large phase k|r_s| (up to ~1e6 rad) is folded into the
  *                per-(k,node) tables in double-double/FP64 and reduced mod 2pi;
  *                the per-pair remainder k(|r_s - r'| - |r_s|) is formed without
- *                cancellation and evaluated in FP32, with blocked compensated
- *                (Kahan) node sums.  Output complex64.
+ *                cancellation and evaluated in FP32; FP32 sums over blocks of
+ *                512 nodes, added into per-chunk running sums, and the chunk
+ *                sums added in FP64.  Output complex64.
  *  SC_FP32       naive FP32: per-pair phase k|r_s - r'| in FP32 (an ablation;
  *                loses accuracy once k|r_s| >> 1e3).  Output complex64.
  */
@@ -108,6 +109,7 @@ typedef struct {
     double time_ms;      /* the semi-discrete time transform                      */
     int64_t evals;       /* obs x freq x surface nodes of the last evaluate       */
     int64_t tiles;       /* quadrature tiles of the last evaluate                 */
+    int32_t chunk;       /* node chunk of the last evaluate (fixes its bits)      */
 } sc_timing;
 sc_status sc_get_timing(const sc_prob *p, sc_timing *out);
 
@@ -189,7 +191,13 @@ sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, int n_phi);
  * n_rim = 0 drops the line integral (a surface without boundary).  Replaces
  * the mirror and invalidates the tables.  The split form is accurate when the
  * observation points lie near the origin (|r'| << |r_s|); the node phase is
- * folded as for the paraboloid.  SC_E_INVAL for bad sizes or non-finite data. */
+ * folded as for the paraboloid.  Where the folded integrand oscillates over
+ * the surface (any shape but the paraboloid), its terms cancel in the sum, and
+ * per-term rounding of the FP32-split form weighs by the ratio
+ * sum |term| / |sum of terms| (about 70 at the focus of an ellipsoidal cap
+ * whose folded phase spans 330 rad, where FP32-split measured 2e-5 to 6e-5
+ * of the field peak against 1e-6 on the paraboloid): use SC_FP64 there.
+ * SC_E_INVAL for bad sizes or non-finite data.                               */
 sc_status sc_set_surface(sc_prob *p, int n_surf, const double *xyz, const double *ndS, int n_rim,
                          const double *rim_xyz, const double *rim_n, const double *rim_dl);
 /* Number of surface nodes (n_r*n_phi) and rim nodes (n_phi).                */
@@ -263,8 +271,9 @@ sc_status sc_set_incident_beam(sc_prob *p, int beam, double w0, double pol_angle
  * (LG_{0,1} + LG_{0,-1}) / (2 sqrt 2 C_{0,1}) in x plus
  * (LG_{0,1} - LG_{0,-1}) / (2i sqrt 2 C_{0,1}) in y is the radially polarised
  * beam above.  Whether the tables factor (sc_set_factoring) is decided from
- * the tables as for any field: a linear polarisation common to all modes
- * does, circular or mixed polarisations do not.
+ * the tables as for any field: modes sharing one linear polarisation, and
+ * the radial combination above, keep one real current direction per node and
+ * factor; a circularly polarised part generally does not.
  * 1 <= n_modes <= SC_MAX_LG_MODES, 0 <= p <= SC_MAX_LG_INDEX,
  * |l| <= SC_MAX_LG_INDEX, finite amplitudes, 0 < w0 < inf (SC_E_INVAL);
  * needs mirror and frequencies (SC_E_STATE).  `modes` is host memory.      */
@@ -450,9 +459,14 @@ sc_status sc_field_energy(sc_prob *p, const double *t, int n_t, double dk, doubl
 /* Evaluate several problems in ONE persistent launch (tiles of all problems
  * share the device), then reduce each; results are kept per problem (read
  * with sc_get_result).  The launch shape is the context's batch launch
- * (sc_set_batch_launch, sc_autotune_batch) or the library's.  Each problem's
- * result is bitwise identical to what sc_evaluate gives it alone with the same
- * chunk.                                                                    */
+ * (sc_set_batch_launch, sc_autotune_batch) or the library's.  The split-K
+ * partials of the batch (12 reals per chunk, frequency and point of each
+ * problem) are kept within max(2 x 16 B x sum of frequencies x nodes, 8 GiB),
+ * doubled for SC_FP64: if the chunks so far exceed that, the problems that fix
+ * no chunk with sc_set_launch take the smallest power-of-two chunk from 2048
+ * up that fits (sc_get_timing reports each problem's chunk).  Each problem's
+ * result is bitwise identical to what sc_evaluate gives it alone with the
+ * same chunk.                                                               */
 sc_status sc_evaluate_batch(sc_ctx *ctx, sc_prob *const *probs, int n, sc_precision prec);
 
 /* Device bytes held by the problem (tables, observation data, results).    */

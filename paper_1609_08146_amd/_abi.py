@@ -29,7 +29,8 @@ class ScError(RuntimeError):
 
 class sc_timing(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_double), ("quad_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double),
-                ("time_ms", ctypes.c_double), ("evals", ctypes.c_int64), ("tiles", ctypes.c_int64)]
+                ("time_ms", ctypes.c_double), ("evals", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("chunk", ctypes.c_int32)]
 
 
 class sc_launch(ctypes.Structure):

@@ -1073,6 +1073,7 @@ extern "C" sc_status sc_evaluate(sc_prob *p, sc_precision prec, void *E, void *B
     p->res_prec = (int)prec;
     p->last_evals = (int64_t)p->n_obs * job.n_k * p->n_surf;
     p->last_tiles = job.n_tiles;
+    p->last_chunk = l.chunk;
     return copy_out(p, E, B, on_device, real_size(prec) * 6 * (size_t)job.n_k * p->n_obs);
 }
 
@@ -1175,6 +1176,33 @@ static sc_launch batch_launch(const sc_ctx *c, sc_prob *const *probs, int n, sc_
     return l;
 }
 
+// A batch keeps its split-K partials within max(2 x the bytes of its tables read per (frequency,
+// node) at 16 B, 8 GiB): the partials of one problem are 12 reals per (chunk, frequency, point),
+// so many problems with many points at a small chunk would hold several times their tables.  If
+// the chunks chosen so far exceed that, the problems that fix no chunk of their own take the
+// smallest power-of-two chunk from 2048 up (never below their own) that fits; the result of each
+// problem is then its result alone at that chunk.  Deterministic in the batch's sizes.
+static void batch_fit_partials(sc_prob *const *probs, int n, sc_precision prec, std::vector<sc_launch> &ls)
+{
+    double table_ref = 0.0;
+    for (int i = 0; i < n; ++i) table_ref += 16.0 * (double)probs[i]->k.size() * (double)probs[i]->n_tot;
+    const double cap = std::max(2.0 * table_ref * (prec == SC_FP64 ? 2.0 : 1.0), 8.0 * 1073741824.0);
+    auto total = [&](int floor_chunk) {
+        double b = 0.0;
+        for (int i = 0; i < n; ++i) {
+            sc_launch l = ls[i];
+            if (!(probs[i]->has_launch && probs[i]->launch.chunk)) l.chunk = std::max(l.chunk, floor_chunk);
+            b += (double)partial_bytes(probs[i], prec, l);
+        }
+        return b;
+    };
+    if (total(0) <= cap) return;
+    int floor_chunk = 2048;
+    while (floor_chunk < (1 << 20) && total(floor_chunk) > cap) floor_chunk *= 2;
+    for (int i = 0; i < n; ++i)
+        if (!(probs[i]->has_launch && probs[i]->launch.chunk)) ls[i].chunk = std::max(ls[i].chunk, floor_chunk);
+}
+
 extern "C" sc_status sc_set_batch_launch(sc_ctx *c, sc_precision prec, const sc_launch *l)
 {
     if (!c) return fail(SC_E_INVAL, "sc_set_batch_launch: ctx is NULL");
@@ -1221,6 +1249,9 @@ extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, 
         ls[i].freq_per_lane = l0.freq_per_lane;
         if (l0.chunk && !(probs[i]->has_launch && probs[i]->launch.chunk)) ls[i].chunk = l0.chunk;
         SC_TRY(check_launch(ls[i]));
+    }
+    batch_fit_partials(probs, n, prec, ls);
+    for (int i = 0; i < n; ++i) {
         SC_TRY(prepare(probs[i], prec, ls[i], jobs[i]));
         probs[i]->res_prec = -1;
     }
@@ -1232,6 +1263,7 @@ extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, 
         p->res_prec = (int)prec;
         p->last_evals = (int64_t)p->n_obs * jobs[i].n_k * p->n_surf;
         p->last_tiles = jobs[i].n_tiles;
+        p->last_chunk = ls[i].chunk;
     }
     ev_record(probs[0], EV_R1);
     probs[0]->ev_quad = c->profiling;
@@ -1423,6 +1455,7 @@ extern "C" sc_status sc_get_timing(const sc_prob *p, sc_timing *out)
     (void)hipGetLastError();
     out->evals = p->last_evals;
     out->tiles = p->last_tiles;
+    out->chunk = p->last_chunk;
     return SC_OK;
 }
 

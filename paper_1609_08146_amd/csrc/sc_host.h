@@ -173,6 +173,7 @@ struct sc_prob {
     hipEvent_t ev[sc::EV_N] = {};
     bool ev_prep = false, ev_quad = false, ev_time = false;
     int64_t last_evals = 0, last_tiles = 0;
+    int last_chunk = 0;   // node chunk of the last evaluation
 };
 
 namespace sc {

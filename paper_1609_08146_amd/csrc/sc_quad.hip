@@ -210,36 +210,36 @@ struct GeomD {
 };
 
 // sin and cos of 2 pi t in FP64.  The fractional turn r = t - rint(t) is
-// exact, so is y = r - q/4 with the quadrant q = rint(4 r), |y| <= 1/8; sin
-// and cos of x = 2 pi y (|x| <= pi/4) are their Taylor series through x^17
-// and x^18 (the first omitted terms are below 1e-19 of the result), and the
-// quadrant turns the pair by q pi/2.
+// exact, so is y = r - q/4 with the quadrant q = rint(4 r), |y| <= 1/8; with
+// x = 2 pi y (|x| <= pi/4) and u = x^2, sin x = x + x^3 S(u) and
+// cos x = 1 - u/2 + u^2 C(u), where S and C are degree-5 Chebyshev fits of
+// (sin x - x)/x^3 and (cos x - 1 + x^2/2)/x^4 on u in [0, (pi/4)^2] (fit errors
+// 2e-17 and 1.3e-18; sincos_f64_fit.py beside this file derives them).  In
+// FP64 arithmetic the results stay within 1e-16 of sin and cos (the Taylor
+// series through x^17 and x^18 that they replace did the same with four more
+// FMAs); the quadrant turns the pair by q pi/2.
 __device__ __forceinline__ void sincos_turns_f64(double t, double &s, double &c)
 {
     const double r = t - rint(t);
     const double q = rint(4.0 * r);
     const double y = __fma_rn(-0.25, q, r);
     const double x = y * TWO_PI_1;
-    const double x2 = x * x;
-    double ps = 1.0 / 355687428096000.0;   // 1/17!
-    ps = __fma_rn(ps, x2, -1.0 / 1307674368000.0);
-    ps = __fma_rn(ps, x2, 1.0 / 6227020800.0);
-    ps = __fma_rn(ps, x2, -1.0 / 39916800.0);
-    ps = __fma_rn(ps, x2, 1.0 / 362880.0);
-    ps = __fma_rn(ps, x2, -1.0 / 5040.0);
-    ps = __fma_rn(ps, x2, 1.0 / 120.0);
-    ps = __fma_rn(ps, x2, -1.0 / 6.0);
-    const double s0 = __fma_rn(x * x2, ps, x);
-    double pc = -1.0 / 6402373705728000.0;   // -1/18!
-    pc = __fma_rn(pc, x2, 1.0 / 20922789888000.0);
-    pc = __fma_rn(pc, x2, -1.0 / 87178291200.0);
-    pc = __fma_rn(pc, x2, 1.0 / 479001600.0);
-    pc = __fma_rn(pc, x2, -1.0 / 3628800.0);
-    pc = __fma_rn(pc, x2, 1.0 / 40320.0);
-    pc = __fma_rn(pc, x2, -1.0 / 720.0);
-    pc = __fma_rn(pc, x2, 1.0 / 24.0);
-    pc = __fma_rn(pc, x2, -0.5);
-    const double c0 = __fma_rn(x2, pc, 1.0);
+    const double u = x * x;
+    double ps = 1.5918129294866608e-10;
+    ps = __fma_rn(ps, u, -2.5051131845003624e-08);
+    ps = __fma_rn(ps, u, 2.755731610255244e-06);
+    ps = __fma_rn(ps, u, -0.00019841269836758574);
+    ps = __fma_rn(ps, u, 0.008333333333330948);
+    ps = __fma_rn(ps, u, -0.16666666666666666);
+    const double s0 = __fma_rn(x * u, ps, x);
+    double pc = -1.1382632425521717e-11;
+    pc = __fma_rn(pc, u, 2.08761462684032e-09);
+    pc = __fma_rn(pc, u, -2.7557317271729793e-07);
+    pc = __fma_rn(pc, u, 2.480158729876569e-05);
+    pc = __fma_rn(pc, u, -0.0013888888888887398);
+    pc = __fma_rn(pc, u, 0.041666666666666664);
+    pc = __fma_rn(pc, u, -0.5);
+    const double c0 = __fma_rn(u, pc, 1.0);
     const int qi = (int)q & 3;   // q in {-2, ..., 2}
     const double sa = (qi & 1) ? c0 : s0, ca = (qi & 1) ? s0 : c0;
     s = (qi >= 2) ? -sa : sa;                 // quadrants 2, 3: sin < 0 side
@@ -462,7 +462,9 @@ constexpr int SUM_BLOCK = 512;
 // running sum (the first block stores, the later ones load, add and store:
 // every address belongs to one lane of one tile).  No LDS, and no second set of
 // 12 accumulators per (point, frequency) in registers, so a lane can hold four
-// frequencies at five waves per SIMD.
+// frequencies at five waves per SIMD.  The slices in use (12 KB per wave at
+// four frequencies) outgrow an XCD's L2, so the load-add-store goes to memory:
+// traffic, but no time, since the tile is bound by its VALU issue.
 template <int MODE, int OPL, int FPB, bool FACT, bool RAW, bool SER = false>
 __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
                                          const double *k64, int n_valid)

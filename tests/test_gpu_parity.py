@@ -346,6 +346,37 @@ def test_batch_equals_alone_bitwise(ctx):
         p.close()
 
 
+def test_batch_keeps_partials_within_the_cap(ctx):
+    """A batch whose split-K partials at the default chunk would exceed max(2 x 16 B x frequencies x
+    nodes, 8 GiB) raises the chunk of the problems that fix none (here 10.3 GB at 2048 nodes ->
+    4096); a problem with its own chunk keeps it, and each result equals the alone result at the
+    chunk the batch used."""
+    from paper_1609_08146_amd import Problem
+    big = Problem(ctx)
+    big.set_mirror(20.0, 40.0, 320, 320)                    # 102 720 nodes
+    big.set_frequencies(np.linspace(2 * np.pi, 3 * np.pi, 256))
+    big.set_incident_gaussian(20.0)
+    big.set_observation(workloads.random_points(16384, 2.0, seed=21))
+    small = Problem(ctx)
+    small.set_launch(chunk=1024)
+    small.set_mirror(20.0, 40.0, 40, 32)
+    small.set_frequencies([2 * np.pi])
+    small.set_incident_gaussian(20.0)
+    small.set_observation(workloads.random_points(100, 2.0, seed=22))
+    ctx.evaluate_batch([big, small], "fp32_split")
+    assert big.timing()["chunk"] == 4096 and small.timing()["chunk"] == 1024
+    Eb, Bb = big.result()
+    Es, Bs = small.result()
+    big.set_launch(chunk=4096)
+    E, B = big.evaluate("fp32_split")
+    assert big.timing()["chunk"] == 4096
+    assert np.array_equal(E, Eb) and np.array_equal(B, Bb)
+    E, B = small.evaluate("fp32_split")
+    assert np.array_equal(E, Es) and np.array_equal(B, Bs)
+    big.close()
+    small.close()
+
+
 def test_error_paths(ctx):
     from paper_1609_08146_amd import Problem, ScError
     from paper_1609_08146_amd._abi import SC_E_INVAL, SC_E_STATE
