@@ -98,6 +98,11 @@ def measured_traffic():
         return None
 
 
+def progress(msg: str):
+    """One line per finished phase on stderr (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -691,6 +696,7 @@ def main():
         last_timing = tm
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    progress(f"{args.steps} timed steps, {elapsed * 1e3 / args.steps:.2f} ms per step")
     factored = p.factored_for(args.precision)
     launch = p.launch(args.precision)
     # the same step with its results handed back in host memory: spectral E, B and the time
@@ -791,6 +797,7 @@ def main():
                 err = float(np.max(np.abs(F[..., c] - F64[..., c])))
                 per_comp[f"{lab}_{ax}"] = {"e_rel": err / float(np.max(np.abs(F64[..., c]))),
                                            "max_err_over_field_peak": err / peak}
+        progress(f"FP64 form {q64:.1f} ms")
         r64 = w64.evals / (q64 * 1e-3)
         rq = evals / (quad_avg * 1e-3)
         fpg = flops_per_eval(False, launch["freq_per_lane"])
@@ -843,25 +850,17 @@ def main():
                 "frac_fp64_peak": fpg64 * rg64 / 1e12 / PEAK_FP64}
 
     ctx.close()
-    if not args.no_batch and args.shard == 1:
-        # the 256-instance sweep in one persistent launch, library and tuned batch launch
-        b = batch_run(256, tune=True, tune_budget_ms=20000.0)
-        out["batch"] = {"workload": "seeded sweep of 256 uneven instances (f 2-20 cm, 1-256 frequencies, "
-                                    "100^2-600^2 nodes, 16^2-128^2 + 16-128 axial points) in one persistent launch, "
-                                    "FP32-split, FP32-only tables",
-                        "instances": b["instances"], "evals": b["evals"], "setup_s": b["setup_s"],
-                        "runs": [{k: r[k] for k in ("label", "quad_evals_per_s", "quad_ms", "seconds", "launch",
-                                                      "frac_fp32_peak", "partial_bytes", "tune_seconds", "tuned_on")
-                                  if k in r} for r in b["runs"]]}
     if args.serve_seconds > 0 and args.shard == 1:
         # the request stream as specified (200 per second for 60 s: an overload) and one sustainable rate
         out["serving"] = []
-        # the sustainable rate first: a server started in a process right after an overload prepares
-        # requests more slowly for a while
+        # the sustainable rate first, and both before the batch: for about half a minute after a run
+        # that freed a large part of the device memory (the overload stream's 200 GB, the batch's
+        # 80 GB), a new server's request preparation runs slower
         for rate, secs in ((args.serve_rate_low, args.serve_seconds_low), (args.serve_rate, args.serve_seconds)):
             if secs <= 0:
                 continue
             sv = serve_run(rate, secs)
+            progress(f"serving at {rate:g}/s: p50 {sv['p50_ms']:.0f} ms, p99 {sv['p99_ms']:.0f} ms")
             row = {k: sv[k] for k in ("rate_hz", "duration_s", "arrivals", "completed", "cancelled", "rejected",
                                       "p50_ms", "p99_ms", "evals_per_s", "device_busy_frac",
                                       "quanta_evals_per_device_s", "prep_ms_per_request")}
@@ -869,6 +868,17 @@ def main():
                                "with time transform, 200 GB admission budget")
             out["serving"].append(row)
 
+    if not args.no_batch and args.shard == 1:
+        # the 256-instance sweep in one persistent launch, library and tuned batch launch
+        b = batch_run(256, tune=True, tune_budget_ms=20000.0)
+        progress(f"batch of {b['instances']} instances done")
+        out["batch"] = {"workload": "seeded sweep of 256 uneven instances (f 2-20 cm, 1-256 frequencies, "
+                                    "100^2-600^2 nodes, 16^2-128^2 + 16-128 axial points) in one persistent launch, "
+                                    "FP32-split, FP32-only tables",
+                        "instances": b["instances"], "evals": b["evals"], "setup_s": b["setup_s"],
+                        "runs": [{k: r[k] for k in ("label", "quad_evals_per_s", "quad_ms", "seconds", "launch",
+                                                      "frac_fp32_peak", "partial_bytes", "tune_seconds", "tuned_on")
+                                  if k in r} for r in b["runs"]]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
 

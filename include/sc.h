@@ -507,7 +507,10 @@ typedef struct {
     int64_t evals_done;       /* evaluations of completed requests            */
     int64_t evals_launched;   /* evaluations in the launched quanta           */
     double quad_ms;           /* device time of the completed quanta (events) */
-    double prep_ms;           /* host time spent building requests' tables    */
+    double prep_ms;           /* summed per request: start of its set-up to its
+                                 tables ready (includes waiting for the device) */
+    double prep_host_ms;      /* host time of the preparation thread's set-up
+                                 calls (no waiting)                           */
 } sc_server_stats;
 
 /* Start a serving loop on `ctx`: requests are admitted while their HBM

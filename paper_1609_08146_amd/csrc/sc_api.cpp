@@ -166,6 +166,7 @@ extern "C" sc_status sc_prob_destroy(sc_prob *p)
     for (int i = 0; i < EV_N; ++i)
         if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
     if (p->stage_ev) (void)hipEventDestroy(p->stage_ev);
+    if (p->fact_ev) (void)hipEventDestroy(p->fact_ev);
     p->ctx->n_probs--;
     delete p;   // DevBufs free themselves
     return SC_OK;
@@ -206,6 +207,7 @@ static void invalidate_tables(sc_prob *p)
 {
     p->has_tab = p->tab32_ok = p->tab32n_ok = p->has_tab64 = p->has_power = false;
     p->fact_checked = p->fact_ok = p->fact64_ok = p->fact32_built = p->fact64_built = false;
+    p->fact_pending = false;   // a flag still on its way belongs to the old tables
     p->res_prec = -1;
 }
 
@@ -217,12 +219,56 @@ static void invalidate_tables(sc_prob *p)
 constexpr double FACTOR_TOL = 1e-10;
 constexpr double FACTOR_TOL_FP64 = 1e-14;
 
+// The outcome of the factoring test (bit 0: the FP32 split tolerance failed, bit 1: the FP64
+// one): which factored tables exist now, and the ones that will not be used are released.
+static void apply_factoring_flag(sc_prob *p, unsigned int bad, bool need32, bool need64)
+{
+    p->fact_checked = true;
+    p->fact_ok = (bad & 1u) == 0;
+    p->fact64_ok = p->fact_ok && (bad & 2u) == 0;
+    p->fact32_built = p->fact32_built || (need32 && p->fact_ok);
+    p->fact64_built = p->fact64_built || (need64 && p->fact64_ok);
+    if (!p->fact_ok) {
+        p->tabf.release();
+        p->posf.release();
+    }
+    if (!p->fact64_ok) {
+        p->tabf64.release();
+        p->posf64.release();
+    }
+}
+
+sc_status sc::resolve_factoring(sc_prob *p, bool block, bool *ready)
+{
+    if (ready) *ready = true;
+    if (!p->fact_pending) return SC_OK;
+    if (block) {
+        HIP_TRY(hipEventSynchronize(p->fact_ev));
+    } else {
+        const hipError_t e = hipEventQuery(p->fact_ev);
+        if (e == hipErrorNotReady) {
+            (void)hipGetLastError();
+            if (ready) *ready = false;
+            return SC_OK;
+        }
+        HIP_TRY(e);
+    }
+    p->fact_pending = false;
+    apply_factoring_flag(p, *p->fact_flag_host, p->fact_req32, p->fact_req64);
+    return SC_OK;
+}
+
+// A problem's factoring state is read only after a deferred test has completed.
+static sc_status settle_factoring(sc_prob *p) { return resolve_factoring(p, true, nullptr); }
+
 // Factored tables from the FP64 tables: the test runs once per table set (one flag read back); the
 // FP32 split (need32) and FP64 (need64) tables are built when asked for and the test passed at that
-// precision's tolerance (otherwise the general tables are used).
+// precision's tolerance (otherwise the general tables are used).  With fact_flag_host set, the flag
+// is not waited for: the test completes in resolve_factoring.
 static sc_status ensure_factored(sc_prob *p, bool need32, bool need64)
 {
     if (!p->allow_fact || !p->has_tab64) return SC_OK;
+    SC_TRY(settle_factoring(p));
     if (p->fact_checked) {
         need32 = need32 && p->fact_ok && !p->fact32_built;
         need64 = need64 && p->fact64_ok && !p->fact64_built;
@@ -246,24 +292,24 @@ static sc_status ensure_factored(sc_prob *p, bool need32, bool need64)
                                  need32 ? p->tabf.as<float>() : nullptr, need32 ? p->posf.as<float>() : nullptr,
                                  need64 ? p->tabf64.as<double>() : nullptr,
                                  need64 ? p->posf64.as<double>() : nullptr, p->fact_flag.as<unsigned int>()));
-    if (!p->fact_checked) {
-        unsigned int bad = 3;
-        HIP_TRY(hipMemcpyAsync(&bad, p->fact_flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        p->fact_checked = true;
-        p->fact_ok = (bad & 1u) == 0;
-        p->fact64_ok = p->fact_ok && (bad & 2u) == 0;
+    if (p->fact_checked) {
+        p->fact32_built = p->fact32_built || need32;
+        p->fact64_built = p->fact64_built || need64;
+        return SC_OK;
     }
-    p->fact32_built = p->fact32_built || (need32 && p->fact_ok);
-    p->fact64_built = p->fact64_built || (need64 && p->fact64_ok);
-    if (!p->fact_ok) {
-        p->tabf.release();
-        p->posf.release();
+    if (p->fact_flag_host) {
+        HIP_TRY(hipMemcpyAsync(p->fact_flag_host, p->fact_flag.p, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+        if (!p->fact_ev) HIP_TRY(hipEventCreateWithFlags(&p->fact_ev, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(p->fact_ev, st));
+        p->fact_pending = true;
+        p->fact_req32 = need32;
+        p->fact_req64 = need64;
+        return SC_OK;
     }
-    if (!p->fact64_ok) {
-        p->tabf64.release();
-        p->posf64.release();
-    }
+    unsigned int bad = 3;
+    HIP_TRY(hipMemcpyAsync(&bad, p->fact_flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    apply_factoring_flag(p, bad, need32, need64);
     return SC_OK;
 }
 
@@ -278,9 +324,10 @@ static sc_status finish_tables(sc_prob *p)
 {
     p->has_tab = true;
     p->has_tab64 = true;
-    // the factoring test (and the factored FP32 tables) now, so that the table layout, and with it
-    // the launch shape, is known before the first evaluation; it needs the FP64 tables
-    SC_TRY(ensure_factored(p, true, false));
+    // the factoring test (and the factored tables of the expected precision) now, so that the table
+    // layout, and with it the launch shape, is known before the first evaluation; it needs the FP64
+    // tables
+    SC_TRY(ensure_factored(p, p->eager_prec == SC_FP32_SPLIT, p->eager_prec == SC_FP64 && p->keep_fp64));
     if (p->keep_fp64) return SC_OK;
     const size_t nrec = p->k.size() * (size_t)p->n_tot;
     SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
@@ -614,18 +661,23 @@ extern "C" sc_status sc_set_incident_lg(sc_prob *p, const sc_lg_mode *modes, int
     if (!p->has_mirror || p->k.empty()) return fail(SC_E_STATE, "sc_set_incident_lg: set mirror and frequencies first");
     DeviceGuard g(p->ctx->device);
     SC_TRY(staging_wait(p));
-    p->h_stage_modes.resize(6 * (size_t)n_modes);
+    // per mode: p, l, ex (re, im), ey (re, im) and the normalisation
+    // C = sqrt(2 p! / (pi (p + |l|)!)) / w0, which does not depend on the position
+    p->h_stage_modes.resize(SC_LG_RECORD * (size_t)n_modes);
     for (int m = 0; m < n_modes; ++m) {
-        double *d = p->h_stage_modes.data() + 6 * m;
+        double *d = p->h_stage_modes.data() + SC_LG_RECORD * m;
+        const int al = modes[m].l < 0 ? -modes[m].l : modes[m].l;
         d[0] = modes[m].p;
         d[1] = modes[m].l;
         d[2] = modes[m].ex[0];
         d[3] = modes[m].ex[1];
         d[4] = modes[m].ey[0];
         d[5] = modes[m].ey[1];
+        d[6] = std::sqrt(2.0 * std::exp(std::lgamma(modes[m].p + 1.0) - std::lgamma(modes[m].p + al + 1.0)) / M_PI) / w0;
+        d[7] = 0.0;
     }
-    SC_TRY(p->d_modes.reserve(sizeof(double) * 6 * (size_t)n_modes, p->alloc_stream));
-    HIP_TRY(hipMemcpyAsync(p->d_modes.p, p->h_stage_modes.data(), sizeof(double) * 6 * (size_t)n_modes,
+    SC_TRY(p->d_modes.reserve(sizeof(double) * SC_LG_RECORD * (size_t)n_modes, p->alloc_stream));
+    HIP_TRY(hipMemcpyAsync(p->d_modes.p, p->h_stage_modes.data(), sizeof(double) * SC_LG_RECORD * (size_t)n_modes,
                            hipMemcpyHostToDevice, p->ctx->stream));
     SC_TRY(staging_mark(p));
     return set_incident_builtin(p, 3, w0, 0.0, spectrum, 0, n_modes, "sc_set_incident_lg");
@@ -650,6 +702,7 @@ extern "C" sc_status sc_get_incident_power(const sc_prob *p, double *P)
 // Multiply frequency n of the tables by fac[n] (complex, host) and its power by |fac[n]|^2.
 static sc_status scale_tables(sc_prob *p, const std::vector<double> &fac)
 {
+    SC_TRY(settle_factoring(p));
     hipStream_t st = p->ctx->stream;
     const int n_k = (int)p->k.size();
     DevBuf dfac;
@@ -659,6 +712,7 @@ static sc_status scale_tables(sc_prob *p, const std::vector<double> &fac)
         HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, 4, dfac.as<double>(), p->tab64.as<double>(), nullptr));
         p->tab32_ok = false;   // rebuilt from the scaled FP64 tables when needed
         p->fact_checked = p->fact_ok = p->fact64_ok = p->fact32_built = p->fact64_built = false;
+        p->fact_pending = false;
     } else {
         if (p->tab32_ok)
             HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, 4, dfac.as<double>(), nullptr, p->tab32.as<float>()));
@@ -850,6 +904,10 @@ extern "C" sc_status sc_get_launch(const sc_prob *p, sc_precision prec, sc_launc
     if (!p || !out) return fail(SC_E_INVAL, "sc_get_launch: NULL argument");
     if (prec != SC_FP64 && prec != SC_FP32_SPLIT && prec != SC_FP32)
         return fail(SC_E_INVAL, "sc_get_launch: unknown precision %d", (int)prec);
+    {
+        DeviceGuard g(p->ctx->device);
+        SC_TRY(settle_factoring(const_cast<sc_prob *>(p)));   // the layout decides the default shape
+    }
     *out = resolve_launch(p, prec);
     return SC_OK;
 }
@@ -1059,6 +1117,7 @@ extern "C" sc_status sc_evaluate(sc_prob *p, sc_precision prec, void *E, void *B
 {
     if (!p) return fail(SC_E_INVAL, "sc_evaluate: prob is NULL");
     DeviceGuard g(p->ctx->device);
+    SC_TRY(settle_factoring(p));
     const sc_launch l = resolve_launch(p, prec);
     SC_TRY(check_launch(l));
     QuadJob job{};
@@ -1121,6 +1180,7 @@ extern "C" sc_status sc_evaluate_noalloc(sc_prob *p, sc_precision prec, void *E,
     }
     if (!base) return fail(SC_E_STATE, "sc_evaluate_noalloc: no scratch memory on device %d", dev);
     DeviceGuard g(dev);
+    SC_TRY(settle_factoring(p));   // only a problem of the serving loop can have a test pending
     const sc_launch l = resolve_launch(p, prec);
     SC_TRY(check_launch(l));
     const void *tab = nullptr;
@@ -1233,6 +1293,7 @@ extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, 
         if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
             return fail(SC_E_INVAL, "sc_evaluate_batch: a problem appears twice");
     }
+    for (int i = 0; i < n; ++i) SC_TRY(settle_factoring(probs[i]));
     const sc_launch l0 = batch_launch(c, probs, n, prec);
     {
         sc_launch shape = l0;
@@ -1516,6 +1577,7 @@ extern "C" sc_status sc_autotune(sc_prob *p, sc_precision prec, double budget_ms
 {
     if (!p) return fail(SC_E_INVAL, "sc_autotune: prob is NULL");
     DeviceGuard g(p->ctx->device);
+    SC_TRY(settle_factoring(p));
     if (budget_ms <= 0) budget_ms = 20000.0;
     sc_ctx *c = p->ctx;
     const int saved_prof = c->profiling;

@@ -145,6 +145,14 @@ struct sc_prob {
     bool allow_fact = true, fact_checked = false, fact_ok = false, fact64_ok = false;
     bool fact32_built = false, fact64_built = false;
     sc::DevBuf tabf, posf, tabf64, posf64, fact_flag;
+    // deferred test (set by a caller that must not wait, the serving loop): the flag goes to the
+    // pinned word fact_flag_host, fact_ev marks its arrival, and resolve_factoring completes the test
+    unsigned int *fact_flag_host = nullptr;
+    hipEvent_t fact_ev = nullptr;
+    bool fact_pending = false, fact_req32 = false, fact_req64 = false;
+    // the factored tables built with the test when the incident field is set: FP32 split by
+    // default; a caller that knows its one precision (the serving loop) picks that one's
+    sc_precision eager_prec = SC_FP32_SPLIT;
     // incident power per frequency through the aperture: [n_k] then the reduction scratch
     bool has_power = false;
     sc::DevBuf d_power;
@@ -188,6 +196,9 @@ sc_launch resolve_launch(const sc_prob *p, sc_precision prec);
 sc_status check_launch(const sc_launch &l);
 int mode_of(sc_precision prec);
 size_t real_size(sc_precision prec);
+// Completes a deferred factoring test: with `block`, waits for its flag; without, *ready tells whether
+// the flag had arrived (and the test is complete).  A no-op when no test is pending.
+sc_status resolve_factoring(sc_prob *p, bool block, bool *ready);
 // Tables of the precision, partial and result buffers; fills `job` (tile0 = 0, offset 0, all tiles).
 sc_status prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob &job);
 // Upload `jobs` (tile0 assigned here) and run one persistent quadrature launch on ctx's stream.

@@ -25,7 +25,9 @@ hipError_t launch_tables_from_fields(hipStream_t st, int n_k, int n_surf, int n_
                                      const double *pos64, const double *nrm, const double *wgt,
                                      const double *tan, const double *E, const double *B, double *tab64);
 // beam: 0 linear Gaussian, 1 radially, 2 azimuthally polarised, 3 Laguerre-Gauss mode set
-// (modes: device [n_modes][6] = p, l, ex re, ex im, ey re, ey im; unused otherwise)
+// (modes: device [n_modes][SC_LG_RECORD] = p, l, ex re, ex im, ey re, ey im, the normalisation
+// C_{p,l} (including 1 / w0), unused; unused for the other beams)
+constexpr int SC_LG_RECORD = 8;
 hipError_t launch_tables_gaussian(hipStream_t st, int n_k, int n_surf, int n_tot, const double *k,
                                   const double *pos64, const double *nrm, const double *wgt,
                                   const double *tan, int beam, double w0, double pol, const double *spectrum,

@@ -226,7 +226,9 @@ __global__ void k_tables_from_fields(int n_k, int n_surf, int n_tot, const doubl
 //   u_{p,l} = C_{p,l} ((X + i sgn(l) Y) sqrt(2) / w0)^|l| L_p^|l|(2 r^2 / w0^2) exp(-r^2 / w0^2),
 //   C_{p,l} = sqrt(2 p! / (pi (p + |l|)!)) / w0   (unit power over the plane),
 // that is (sqrt(2) r / w0)^|l| e^{i l phi} times the radial factor, with L_p^a by its three-term
-// recurrence.  modes: [n_modes][6] = (p, l, ex re, ex im, ey re, ey im);
+// recurrence.  modes: [n_modes][SC_LG_RECORD] = (p, l, ex re, ex im, ey re, ey im, C_{p,l}, unused),
+// C from the host (it does not depend on the position; a device lgamma here cost the table
+// kernels 72 VGPRs and 380 bytes of scratch per lane);
 //   E = sum_m (ex_m x + ey_m y) u_m amp,   B = (-z) x E = sum_m (ey_m x - ex_m y) u_m amp.
 __device__ __forceinline__ void lg_fields(const double *__restrict__ modes, int n_modes, double X, double Y,
                                           double w0, c64 amp, c64 *E, c64 *B)
@@ -236,7 +238,7 @@ __device__ __forceinline__ void lg_fields(const double *__restrict__ modes, int 
     const double gauss = exp(-0.5 * t);
     c64 ex = {0.0, 0.0}, ey = {0.0, 0.0};
     for (int m = 0; m < n_modes; ++m) {
-        const double *md = modes + 6 * m;
+        const double *md = modes + SC_LG_RECORD * m;
         const int p = (int)md[0], l = (int)md[1], al = l < 0 ? -l : l;
         // L_p^al(t): L_0 = 1, L_1 = 1 + al - t, (n + 1) L_{n+1} = (2n + 1 + al - t) L_n - (n + al) L_{n-1}
         double l0 = 1.0, l1 = 1.0 + al - t;
@@ -251,8 +253,7 @@ __device__ __forceinline__ void lg_fields(const double *__restrict__ modes, int 
         const c64 z1 = {X * s2w, (l < 0 ? -Y : Y) * s2w};
         c64 zp = {1.0, 0.0};
         for (int j = 0; j < al; ++j) zp = cmul(zp, z1);
-        const double C = sqrt(2.0 * exp(lgamma(p + 1.0) - lgamma(p + al + 1.0)) / M_PI) / w0;
-        const double radial = C * L * gauss;
+        const double radial = md[6] * L * gauss;   // md[6]: the mode's normalisation C_{p,l}
         const c64 u = {radial * zp.re, radial * zp.im};
         const c64 cx = cmul(u, {md[2], md[3]}), cy = cmul(u, {md[4], md[5]});
         ex = {ex.re + cx.re, ex.im + cx.im};

@@ -215,24 +215,39 @@ static bool debug_fail_this_quantum()
 static int server_opl(sc_precision) { return 1; }
 static int server_fpb(sc_precision prec) { return prec == SC_FP64 ? 2 : 4; }
 
-// Build the request's device state on the preparation stream.
-static sc_status setup_request(sc_server *s, Req *r)
+// Build the request's device state on the preparation stream, in two steps so that the
+// preparation thread never waits for the device: setup_begin enqueues the tables and the factoring
+// test, whose flag arrives in the request's pinned block; setup_finish, once it has, sizes the
+// partials and results for the table layout the test chose and fills the request's job.
+static sc_status setup_begin(sc_server *s, Req *r)
 {
     SC_TRY(sc_prob_create(s->prep, &r->prob));
     sc_prob *p = r->prob;
     p->alloc_stream = s->prep->stream;
     p->keep_fp64 = r->prec == SC_FP64;   // FP32 requests keep only their FP32 tables
+    p->eager_prec = r->prec;             // and the factored tables of their own precision only
+    const int n_k = (int)r->k.size();
+    const size_t rs = real_size(r->prec);
+    r->res_bytes = rs * 6 * (size_t)n_k * r->n_obs;
+    r->time_bytes = rs * 6 * (size_t)r->n_t * r->n_obs;
+    {   // one pinned block: E, B, then Et, Bt (each 256-byte aligned), then the factoring flag
+        const size_t re = (r->res_bytes + 255) & ~size_t(255), te = (r->time_bytes + 255) & ~size_t(255);
+        const size_t tb = r->n_t > 0 ? 2 * te : 0;
+        HIP_TRY(s->pinned.get(2 * re + tb + 256, &r->host_block, &r->host_block_bytes));
+        char *b = (char *)r->host_block;
+        r->hE = b;
+        r->hB = b + re;
+        if (r->n_t > 0) {
+            r->hEt = b + 2 * re;
+            r->hBt = b + 2 * re + te;
+        }
+        p->fact_flag_host = (unsigned int *)(b + 2 * re + tb);
+    }
     SC_TRY(sc_set_mirror(p, r->f, r->a, r->n_r, r->n_phi));
-    SC_TRY(sc_set_frequencies(p, r->k.data(), (int)r->k.size()));
+    SC_TRY(sc_set_frequencies(p, r->k.data(), n_k));
     SC_TRY(sc_set_incident_beam(p, r->beam, r->w0, r->pol, r->spec.empty() ? nullptr : r->spec.data(),
                                 r->consistent));
     SC_TRY(sc_set_observation(p, r->obs.data(), r->n_obs, 0));
-    sc_launch l = resolve_launch(p, r->prec);
-    l.obs_per_lane = server_opl(r->prec);
-    l.freq_per_lane = server_fpb(r->prec);
-    SC_TRY(prepare(p, r->prec, l, r->job));
-    const int n_k = (int)r->k.size();
-    const size_t rs = real_size(r->prec);
     if (r->n_t > 0) {
         SC_TRY(p->d_t.reserve(sizeof(double) * r->n_t, p->alloc_stream));
         SC_TRY(p->tw.reserve(sizeof(double) * 2 * (size_t)r->n_t * n_k, p->alloc_stream));
@@ -241,25 +256,25 @@ static sc_status setup_request(sc_server *s, Req *r)
         HIP_TRY(hipMemcpyAsync(p->d_t.p, r->t.data(), sizeof(double) * r->n_t, hipMemcpyHostToDevice,
                                s->prep->stream));
     }
-    r->res_bytes = rs * 6 * (size_t)n_k * r->n_obs;
-    r->time_bytes = rs * 6 * (size_t)r->n_t * r->n_obs;
-    {   // one pinned block: E, B, then Et, Bt (each 256-byte aligned)
-        const size_t re = (r->res_bytes + 255) & ~size_t(255), te = (r->time_bytes + 255) & ~size_t(255);
-        HIP_TRY(s->pinned.get(2 * re + (r->n_t > 0 ? 2 * te : 0), &r->host_block, &r->host_block_bytes));
-        char *b = (char *)r->host_block;
-        r->hE = b;
-        r->hB = b + re;
-        if (r->n_t > 0) {
-            r->hEt = b + 2 * re;
-            r->hBt = b + 2 * re + te;
-        }
-    }
     HIP_TRY(hipEventCreateWithFlags(&r->ready_ev, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&r->fin_ev, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming));
+    return SC_OK;
+}
+
+// *ready = false (and nothing done) while the factoring flag is still on its way.
+static sc_status setup_finish(sc_server *s, Req *r, bool *ready)
+{
+    sc_prob *p = r->prob;
+    SC_TRY(resolve_factoring(p, false, ready));
+    if (!*ready) return SC_OK;
+    sc_launch l = resolve_launch(p, r->prec);
+    l.obs_per_lane = server_opl(r->prec);
+    l.freq_per_lane = server_fpb(r->prec);
+    SC_TRY(prepare(p, r->prec, l, r->job));
     HIP_TRY(hipEventRecord(r->ready_ev, s->prep->stream));
     // the time samples are copied from r->t, which lives as long as the request
-    r->evals = (int64_t)r->n_obs * n_k * p->n_surf;
+    r->evals = (int64_t)r->n_obs * (int64_t)r->k.size() * p->n_surf;
     return SC_OK;
 }
 
@@ -398,14 +413,22 @@ static void complete_request(sc_server *s, Req *r, ReqState state, sc_status st,
     s->cv_done.notify_all();
 }
 
-// Preparation thread: builds the tables of admitted requests on the preparation
-// stream, then hands them to the scheduler.
+// Preparation thread: starts admitted requests' set-up on the preparation stream (up to
+// MAX_STARTED at a time) and completes each once its factoring flag has arrived, then hands it to
+// the scheduler; finished problems are released here too.
 static void prep_main(sc_server *s)
 {
+    constexpr int MAX_STARTED = 8;
     (void)hipSetDevice(s->ctx->device);
+    std::deque<std::pair<Req *, Clock::time_point>> started;   // set-up begun, flag not in yet
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        s->cv_prep.wait(lk, [s] { return s->stop || !s->to_prepare.empty() || !s->to_release.empty(); });
+        auto work = [s, &started] {
+            return (s->stop && started.empty()) || !s->to_release.empty() ||
+                   (!s->to_prepare.empty() && (int)started.size() < MAX_STARTED);
+        };
+        if (started.empty()) s->cv_prep.wait(lk, work);
+        else s->cv_prep.wait_for(lk, std::chrono::microseconds(500), work);   // poll the flags
         if (!s->to_release.empty()) {   // frees first, so the next request's allocations can reuse them
             std::vector<sc_prob *> rel;
             rel.swap(s->to_release);
@@ -414,26 +437,50 @@ static void prep_main(sc_server *s)
             lk.lock();
             continue;
         }
-        if (s->to_prepare.empty()) {
-            if (s->stop) break;
-            continue;
+        // at shutdown the admitted requests still run (the scheduler waits for them), so the started
+        // ones are completed first
+        if (s->stop && s->to_prepare.empty() && started.empty()) break;
+        // complete, in order, the started requests whose flag has arrived
+        while (!started.empty()) {
+            Req *r = started.front().first;
+            lk.unlock();
+            bool ready = false;
+            const Clock::time_point h0 = Clock::now();
+            const sc_status st = setup_finish(s, r, &ready);
+            const double host_ms = ms_between(h0, Clock::now());
+            const std::string err = st == SC_OK ? std::string() : std::string(sc_last_error());
+            if (st != SC_OK) (void)hipStreamSynchronize(s->prep->stream);
+            lk.lock();
+            s->stats.prep_host_ms += host_ms;
+            if (st == SC_OK && !ready) break;
+            s->stats.prep_ms += ms_between(started.front().second, Clock::now());
+            started.pop_front();
+            s->preparing--;
+            if (st == SC_OK) s->active.push_back(r);
+            else complete_request(s, r, R_FAILED, st, err);
+            s->cv_work.notify_one();
         }
+        if (s->to_prepare.empty() || (int)started.size() >= MAX_STARTED) continue;
         Req *r = s->to_prepare.front();
         s->to_prepare.pop_front();
         s->preparing++;
         lk.unlock();
         const Clock::time_point t0 = Clock::now();
-        const sc_status st = setup_request(s, r);
-        const double prep_ms = ms_between(t0, Clock::now());
+        const sc_status st = setup_begin(s, r);
+        const double host_ms = ms_between(t0, Clock::now());
         const std::string err = st == SC_OK ? std::string() : std::string(sc_last_error());
         // a failed request may still have copies from its host arrays in flight
         if (st != SC_OK) (void)hipStreamSynchronize(s->prep->stream);
         lk.lock();
-        s->stats.prep_ms += prep_ms;
-        s->preparing--;
-        if (st == SC_OK) s->active.push_back(r);
-        else complete_request(s, r, R_FAILED, st, err);
-        s->cv_work.notify_one();
+        s->stats.prep_host_ms += host_ms;
+        if (st == SC_OK) {
+            started.emplace_back(r, t0);
+        } else {
+            s->stats.prep_ms += ms_between(t0, Clock::now());
+            s->preparing--;
+            complete_request(s, r, R_FAILED, st, err);
+            s->cv_work.notify_one();
+        }
     }
 }
 

@@ -120,6 +120,21 @@ def test_admission_respects_hbm_budget(ctx):
     srv.close()
 
 
+@pytest.mark.timeout(180)
+def test_close_while_requests_are_being_prepared(ctx):
+    """Closing the server right after a burst of submissions: the requests admitted and still in
+    preparation (tables enqueued, factoring flag not yet read) are completed and run before the
+    scheduler stops, the queued ones are cancelled, and close returns."""
+    from paper_1609_08146_amd import Server
+    ws = small_requests(24, seed=19)
+    srv = Server(ctx, hbm_budget=int(64e9), max_running=16, quantum_ms=2.0)
+    tickets = [srv.submit(w, "fp32_split") for w in ws]
+    assert len(tickets) == 24
+    t0 = time.perf_counter()
+    srv.close()
+    assert time.perf_counter() - t0 < 120.0
+
+
 def test_rejection_cancel_timeout_and_bad_request(ctx):
     from paper_1609_08146_amd import ScError, Server
     from paper_1609_08146_amd._abi import SC_E_CANCELLED, SC_E_INVAL, SC_E_REJECTED, SC_E_TIMEOUT
