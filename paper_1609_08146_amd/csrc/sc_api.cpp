@@ -162,7 +162,9 @@ extern "C" sc_status sc_prob_destroy(sc_prob *p)
 {
     if (!p) return SC_OK;
     DeviceGuard g(p->ctx->device);
-    (void)hipStreamSynchronize(p->ctx->stream);
+    // buffers from the stream-ordered allocator are freed behind the work queued on their stream; the
+    // others need the problem's work finished first
+    if (!p->alloc_stream) (void)hipStreamSynchronize(p->ctx->stream);
     for (int i = 0; i < EV_N; ++i)
         if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
     if (p->stage_ev) (void)hipEventDestroy(p->stage_ev);
@@ -187,6 +189,25 @@ static sc_status staging_mark(sc_prob *p)
     if (!p->stage_ev) HIP_TRY(hipEventCreateWithFlags(&p->stage_ev, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(p->stage_ev, p->ctx->stream));
     p->stage_pending = true;
+    return SC_OK;
+}
+
+// Host memory for an upload of n doubles: a slice of the problem's pinned area when it has one with
+// room left (*in_ext = true), else the staging vector `vec` (after its last upload has run); in that
+// case staging_mark follows the copies.
+static sc_status stage_area(sc_prob *p, std::vector<double> &vec, size_t n, double **out, bool *in_ext)
+{
+    const size_t bytes = (sizeof(double) * n + 63) & ~size_t(63);
+    if (p->stage_ext && p->stage_ext_off + bytes <= p->stage_ext_cap) {
+        *out = (double *)(p->stage_ext + p->stage_ext_off);
+        p->stage_ext_off += bytes;
+        *in_ext = true;
+        return SC_OK;
+    }
+    SC_TRY(staging_wait(p));
+    vec.resize(n);
+    *out = vec.data();
+    *in_ext = false;
     return SC_OK;
 }
 
@@ -393,11 +414,11 @@ extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, 
     const std::vector<double> *xw[2];
     gauss_rule_cached(p->ctx, n_r, xw);
     const std::vector<double> &x = *xw[0], &w = *xw[1];
-    SC_TRY(staging_wait(p));
     // staging layout: r [n_r + 1], w_r [n_r], cos phi [n_phi], sin phi [n_phi]
-    std::vector<double> &stage = p->h_stage_rule;
-    stage.resize((size_t)2 * n_r + 1 + 2 * (size_t)n_phi);
-    double *r = stage.data(), *wr = r + n_r + 1, *c = wr + n_r, *s = c + n_phi;
+    double *r = nullptr;
+    bool ext = false;
+    SC_TRY(stage_area(p, p->h_stage_rule, (size_t)2 * n_r + 1 + 2 * (size_t)n_phi, &r, &ext));
+    double *wr = r + n_r + 1, *c = wr + n_r, *s = c + n_phi;
     for (int i = 0; i < n_r; ++i) {
         r[i] = r_max * (1.0 + x[i]) / 2.0;
         wr[i] = r_max * w[i] / 2.0;
@@ -423,7 +444,7 @@ extern "C" sc_status sc_set_mirror(sc_prob *p, double f, double r_max, int n_r, 
     HIP_TRY(hipMemcpyAsync(p->d_wr.p, wr, sizeof(double) * n_r, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(p->d_c.p, c, sizeof(double) * n_phi, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(p->d_s.p, s, sizeof(double) * n_phi, hipMemcpyHostToDevice, st));
-    SC_TRY(staging_mark(p));
+    if (!ext) SC_TRY(staging_mark(p));
     HIP_TRY(launch_node_tables(st, n_r, n_phi, f, p->d_r.as<double>(), p->d_wr.as<double>(), p->d_c.as<double>(),
                                p->d_s.as<double>(), 2.0 * M_PI / (double)n_phi, p->pos64.as<double>(),
                                p->pos32.as<float>(), p->nrm.as<double>(), p->wgt.as<double>(), p->tan.as<double>()));
@@ -547,6 +568,16 @@ extern "C" sc_status sc_set_frequencies(sc_prob *p, const double *k, int n_k)
     invalidate_tables(p);
     p->k.assign(k, k + n_k);
     SC_TRY(p->d_k.reserve(sizeof(double) * n_k, p->alloc_stream));
+    if (p->stage_ext) {   // p->k is pageable: copy from the pinned area when there is one
+        double *h = nullptr;
+        bool ext = false;
+        SC_TRY(stage_area(p, p->h_stage_spec, (size_t)n_k, &h, &ext));
+        if (ext) {
+            std::copy(k, k + n_k, h);
+            HIP_TRY(hipMemcpyAsync(p->d_k.p, h, sizeof(double) * n_k, hipMemcpyHostToDevice, p->ctx->stream));
+            return SC_OK;
+        }
+    }
     HIP_TRY(hipMemcpyAsync(p->d_k.p, p->k.data(), sizeof(double) * n_k, hipMemcpyHostToDevice, p->ctx->stream));
     return SC_OK;
 }
@@ -604,12 +635,13 @@ static sc_status set_incident_builtin(sc_prob *p, int beam, double w0, double po
     SC_TRY(p->tab64.reserve(sizeof(double) * 8 * (size_t)n_k * p->n_tot, p->alloc_stream));
     const double *dspec = nullptr;
     if (spectrum) {
-        SC_TRY(staging_wait(p));
-        p->h_stage_spec.assign(spectrum, spectrum + 2 * (size_t)n_k);
+        double *h = nullptr;
+        bool ext = false;
+        SC_TRY(stage_area(p, p->h_stage_spec, 2 * (size_t)n_k, &h, &ext));
+        std::copy(spectrum, spectrum + 2 * (size_t)n_k, h);
         SC_TRY(p->d_spec.reserve(sizeof(double) * 2 * n_k, p->alloc_stream));
-        HIP_TRY(hipMemcpyAsync(p->d_spec.p, p->h_stage_spec.data(), sizeof(double) * 2 * n_k, hipMemcpyHostToDevice,
-                               st));
-        SC_TRY(staging_mark(p));
+        HIP_TRY(hipMemcpyAsync(p->d_spec.p, h, sizeof(double) * 2 * n_k, hipMemcpyHostToDevice, st));
+        if (!ext) SC_TRY(staging_mark(p));
         dspec = p->d_spec.as<double>();
     }
     const double *modes = beam == 3 ? p->d_modes.as<double>() : nullptr;
@@ -660,12 +692,13 @@ extern "C" sc_status sc_set_incident_lg(sc_prob *p, const sc_lg_mode *modes, int
     }
     if (!p->has_mirror || p->k.empty()) return fail(SC_E_STATE, "sc_set_incident_lg: set mirror and frequencies first");
     DeviceGuard g(p->ctx->device);
-    SC_TRY(staging_wait(p));
     // per mode: p, l, ex (re, im), ey (re, im) and the normalisation
     // C = sqrt(2 p! / (pi (p + |l|)!)) / w0, which does not depend on the position
-    p->h_stage_modes.resize(SC_LG_RECORD * (size_t)n_modes);
+    double *h = nullptr;
+    bool ext = false;
+    SC_TRY(stage_area(p, p->h_stage_modes, SC_LG_RECORD * (size_t)n_modes, &h, &ext));
     for (int m = 0; m < n_modes; ++m) {
-        double *d = p->h_stage_modes.data() + SC_LG_RECORD * m;
+        double *d = h + SC_LG_RECORD * m;
         const int al = modes[m].l < 0 ? -modes[m].l : modes[m].l;
         d[0] = modes[m].p;
         d[1] = modes[m].l;
@@ -677,9 +710,9 @@ extern "C" sc_status sc_set_incident_lg(sc_prob *p, const sc_lg_mode *modes, int
         d[7] = 0.0;
     }
     SC_TRY(p->d_modes.reserve(sizeof(double) * SC_LG_RECORD * (size_t)n_modes, p->alloc_stream));
-    HIP_TRY(hipMemcpyAsync(p->d_modes.p, p->h_stage_modes.data(), sizeof(double) * SC_LG_RECORD * (size_t)n_modes,
-                           hipMemcpyHostToDevice, p->ctx->stream));
-    SC_TRY(staging_mark(p));
+    HIP_TRY(hipMemcpyAsync(p->d_modes.p, h, sizeof(double) * SC_LG_RECORD * (size_t)n_modes, hipMemcpyHostToDevice,
+                           p->ctx->stream));
+    if (!ext) SC_TRY(staging_mark(p));
     return set_incident_builtin(p, 3, w0, 0.0, spectrum, 0, n_modes, "sc_set_incident_lg");
 }
 
@@ -795,12 +828,13 @@ extern "C" sc_status sc_set_observation(sc_prob *p, const double *xyz, int n_obs
             const double *q = xyz + 3 * (size_t)o;
             r2max = std::max(r2max, q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
         }
-        SC_TRY(staging_wait(p));
-        p->h_stage_obs.assign(xyz, xyz + 3 * (size_t)n_obs);
+        double *h = nullptr;
+        bool ext = false;
+        SC_TRY(stage_area(p, p->h_stage_obs, 3 * (size_t)n_obs, &h, &ext));
+        std::copy(xyz, xyz + 3 * (size_t)n_obs, h);
         SC_TRY(p->d_obs_in.reserve(sizeof(double) * 3 * n_obs, p->alloc_stream));
-        HIP_TRY(hipMemcpyAsync(p->d_obs_in.p, p->h_stage_obs.data(), sizeof(double) * 3 * n_obs,
-                               hipMemcpyHostToDevice, st));
-        SC_TRY(staging_mark(p));
+        HIP_TRY(hipMemcpyAsync(p->d_obs_in.p, h, sizeof(double) * 3 * n_obs, hipMemcpyHostToDevice, st));
+        if (!ext) SC_TRY(staging_mark(p));
         d = p->d_obs_in.as<double>();
     }
     HIP_TRY(launch_obs_prep(st, d, n_obs, pad, p->obs64.as<double>(), p->obs32.as<float>()));
@@ -1520,15 +1554,26 @@ extern "C" sc_status sc_get_timing(const sc_prob *p, sc_timing *out)
     return SC_OK;
 }
 
+// Every device buffer a problem owns.
+static std::vector<DevBuf *> prob_buffers(sc_prob *p)
+{
+    return {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->hinv64, &p->hinv32, &p->nrm, &p->wgt,
+            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->tabf, &p->posf, &p->tabf64, &p->posf64,
+            &p->fact_flag, &p->d_power, &p->obs64, &p->obs32, &p->resE, &p->resB, &p->partial,
+            &p->d_t, &p->tw, &p->timeE, &p->timeB, &p->d_spec, &p->d_obs_in, &p->d_modes};
+}
+
+void sc::prob_free_on(sc_prob *p, hipStream_t st)
+{
+    for (DevBuf *b : prob_buffers(p))
+        if (b->p && b->stream) b->stream = st;
+}
+
 extern "C" sc_status sc_prob_device_bytes(const sc_prob *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(SC_E_INVAL, "sc_prob_device_bytes: NULL argument");
-    const DevBuf *bufs[] = {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->hinv64, &p->hinv32, &p->nrm, &p->wgt,
-                            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->tabf, &p->posf, &p->tabf64, &p->posf64,
-                            &p->fact_flag, &p->d_power, &p->obs64, &p->obs32, &p->resE, &p->resB, &p->partial,
-                            &p->d_t, &p->tw, &p->timeE, &p->timeB, &p->d_spec, &p->d_obs_in, &p->d_modes};
     size_t s = 0;
-    for (const DevBuf *b : bufs) s += b->bytes;
+    for (const DevBuf *b : prob_buffers(const_cast<sc_prob *>(p))) s += b->bytes;
     *bytes = s;
     return SC_OK;
 }

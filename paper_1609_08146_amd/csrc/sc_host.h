@@ -174,6 +174,11 @@ struct sc_prob {
     sc::DevBuf d_spec, d_obs_in, d_modes;
     hipEvent_t stage_ev = nullptr;
     bool stage_pending = false;
+    // an optional pinned host area for the uploads (the serving loop's request block): pageable
+    // sources make a copy wait for the earlier work on the stream, pinned ones do not.  Bump
+    // allocated, never reused while the problem lives.
+    char *stage_ext = nullptr;
+    size_t stage_ext_cap = 0, stage_ext_off = 0;
     // launch override
     bool has_launch = false;
     sc_launch launch{};
@@ -199,6 +204,9 @@ size_t real_size(sc_precision prec);
 // Completes a deferred factoring test: with `block`, waits for its flag; without, *ready tells whether
 // the flag had arrived (and the test is complete).  A no-op when no test is pending.
 sc_status resolve_factoring(sc_prob *p, bool block, bool *ready);
+// Have a problem's stream-ordered buffers freed on `st` when it is destroyed (for a caller that
+// knows no queued work still uses them, so that the frees need not wait behind that stream's work).
+void prob_free_on(sc_prob *p, hipStream_t st);
 // Tables of the precision, partial and result buffers; fills `job` (tile0 = 0, offset 0, all tiles).
 sc_status prepare(sc_prob *p, sc_precision prec, const sc_launch &l, QuadJob &job);
 // Upload `jobs` (tile0 assigned here) and run one persistent quadrature launch on ctx's stream.

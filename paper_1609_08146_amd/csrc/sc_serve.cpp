@@ -154,6 +154,9 @@ struct sc_server {
     std::vector<sc_prob *> to_release;   // finished problems, released by the preparation thread
     int preparing = 0;
     hipStream_t copy_stream = nullptr;   // device-to-host copies of results
+    hipStream_t release_stream = nullptr;   // frees of finished problems (nothing else queued on it)
+    hipMemPool_t pool = nullptr;             // the device's default (stream-ordered) memory pool
+    uint64_t pool_threshold_saved = 0;       // its release threshold before the server
     PinnedPool pinned;
     uint64_t next_ticket = 1;
     std::deque<Req *> queue;
@@ -230,10 +233,14 @@ static sc_status setup_begin(sc_server *s, Req *r)
     const size_t rs = real_size(r->prec);
     r->res_bytes = rs * 6 * (size_t)n_k * r->n_obs;
     r->time_bytes = rs * 6 * (size_t)r->n_t * r->n_obs;
-    {   // one pinned block: E, B, then Et, Bt (each 256-byte aligned), then the factoring flag
+    {   // one pinned block: E, B, then Et, Bt (each 256-byte aligned), the factoring flag, and the
+        // staging area of the set-up's uploads (rule, frequencies, spectrum, points, times)
         const size_t re = (r->res_bytes + 255) & ~size_t(255), te = (r->time_bytes + 255) & ~size_t(255);
         const size_t tb = r->n_t > 0 ? 2 * te : 0;
-        HIP_TRY(s->pinned.get(2 * re + tb + 256, &r->host_block, &r->host_block_bytes));
+        auto up = [](size_t n) { return (sizeof(double) * n + 63) & ~size_t(63); };
+        const size_t stage = up(2 * (size_t)r->n_r + 1 + 2 * (size_t)r->n_phi) + up(r->k.size()) +
+                             up(2 * r->k.size()) + up(3 * (size_t)r->n_obs) + up((size_t)r->n_t);
+        HIP_TRY(s->pinned.get(2 * re + tb + 256 + stage, &r->host_block, &r->host_block_bytes));
         char *b = (char *)r->host_block;
         r->hE = b;
         r->hB = b + re;
@@ -242,6 +249,9 @@ static sc_status setup_begin(sc_server *s, Req *r)
             r->hBt = b + 2 * re + te;
         }
         p->fact_flag_host = (unsigned int *)(b + 2 * re + tb);
+        p->stage_ext = b + 2 * re + tb + 256;
+        p->stage_ext_cap = stage;
+        p->stage_ext_off = 0;
     }
     SC_TRY(sc_set_mirror(p, r->f, r->a, r->n_r, r->n_phi));
     SC_TRY(sc_set_frequencies(p, r->k.data(), n_k));
@@ -253,8 +263,14 @@ static sc_status setup_begin(sc_server *s, Req *r)
         SC_TRY(p->tw.reserve(sizeof(double) * 2 * (size_t)r->n_t * n_k, p->alloc_stream));
         SC_TRY(p->timeE.reserve(rs * 6 * (size_t)r->n_t * r->n_obs, p->alloc_stream));
         SC_TRY(p->timeB.reserve(rs * 6 * (size_t)r->n_t * r->n_obs, p->alloc_stream));
-        HIP_TRY(hipMemcpyAsync(p->d_t.p, r->t.data(), sizeof(double) * r->n_t, hipMemcpyHostToDevice,
-                               s->prep->stream));
+        const size_t tbytes = sizeof(double) * r->n_t;
+        const void *src = r->t.data();
+        if (p->stage_ext_off + tbytes <= p->stage_ext_cap) {   // the times from the pinned area
+            std::memcpy(p->stage_ext + p->stage_ext_off, r->t.data(), tbytes);
+            src = p->stage_ext + p->stage_ext_off;
+            p->stage_ext_off += (tbytes + 63) & ~size_t(63);
+        }
+        HIP_TRY(hipMemcpyAsync(p->d_t.p, src, tbytes, hipMemcpyHostToDevice, s->prep->stream));
     }
     HIP_TRY(hipEventCreateWithFlags(&r->ready_ev, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&r->fin_ev, hipEventDisableTiming));
@@ -433,7 +449,15 @@ static void prep_main(sc_server *s)
             std::vector<sc_prob *> rel;
             rel.swap(s->to_release);
             lk.unlock();
-            for (sc_prob *p : rel) (void)sc_prob_destroy(p);
+            for (sc_prob *p : rel) {
+                // no queued work uses a finished request's buffers: free them on a stream of their own,
+                // not behind the next requests' set-up on the preparation stream
+                prob_free_on(p, s->release_stream);
+                (void)sc_prob_destroy(p);
+            }
+            // the frees run at once on that stream; synchronising it lets the pool return what it holds
+            // beyond its release threshold
+            (void)hipStreamSynchronize(s->release_stream);
             lk.lock();
             continue;
         }
@@ -592,7 +616,28 @@ extern "C" sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_ru
         return st;
     }
     s->prep->tune = ctx->tune;
+    // Let the default memory pool keep some freed memory for reuse (a fresh mapping of a request's
+    // buffers costs host time on every set-up): up to half of what the budget leaves of the device,
+    // at most 32 GiB, so that the runtime keeps room of its own.
+    if (hipDeviceGetDefaultMemPool(&s->pool, ctx->device) == hipSuccess) {
+        size_t free_b = 0, total_b = 0;
+        (void)hipMemGetInfo(&free_b, &total_b);
+        const uint64_t keep = total_b > hbm_budget ? std::min<uint64_t>(uint64_t(32) << 30, (total_b - hbm_budget) / 2) : 0;
+        if (hipMemPoolGetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &s->pool_threshold_saved) != hipSuccess ||
+            hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, (void *)&keep) != hipSuccess)
+            s->pool = nullptr;
+        (void)hipGetLastError();
+    } else {
+        s->pool = nullptr;
+        (void)hipGetLastError();
+    }
     if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)sc_ctx_destroy(s->prep);
+        delete s;
+        return fail(SC_E_DEVICE, "sc_server_create: hipStreamCreateWithFlags failed");
+    }
+    if (hipStreamCreateWithFlags(&s->release_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(s->copy_stream);
         (void)sc_ctx_destroy(s->prep);
         delete s;
         return fail(SC_E_DEVICE, "sc_server_create: hipStreamCreateWithFlags failed");
@@ -604,6 +649,7 @@ extern "C" sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_ru
                 if (s->slot_start[j]) (void)hipEventDestroy(s->slot_start[j]);
             }
             (void)hipStreamDestroy(s->copy_stream);
+            (void)hipStreamDestroy(s->release_stream);
             (void)sc_ctx_destroy(s->prep);
             delete s;
             return fail(SC_E_DEVICE, "sc_server_create: hipEventCreate failed");
@@ -788,6 +834,12 @@ extern "C" sc_status sc_server_destroy(sc_server *s)
     }
     s->all.clear();
     s->pinned.clear();
+    (void)hipStreamSynchronize(s->release_stream);
+    (void)hipStreamDestroy(s->release_stream);
+    if (s->pool) {   // the pool as it was, and what the server left in it returned
+        (void)hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &s->pool_threshold_saved);
+        (void)hipMemPoolTrimTo(s->pool, 0);
+    }
     (void)hipStreamDestroy(s->copy_stream);
     for (int i = 0; i < sc_server::RING; ++i) {
         if (s->slot_ev[i]) (void)hipEventDestroy(s->slot_ev[i]);
