@@ -155,8 +155,7 @@ struct sc_server {
     int preparing = 0;
     hipStream_t copy_stream = nullptr;   // device-to-host copies of results
     hipStream_t release_stream = nullptr;   // frees of finished problems (nothing else queued on it)
-    hipMemPool_t pool = nullptr;             // the device's default (stream-ordered) memory pool
-    uint64_t pool_threshold_saved = 0;       // its release threshold before the server
+    hipMemPool_t pool = nullptr;             // the device's default pool, if this server set its threshold
     PinnedPool pinned;
     uint64_t next_ticket = 1;
     std::deque<Req *> queue;
@@ -595,6 +594,48 @@ static void worker_main(sc_server *s)
 
 // ======================================================================= ABI
 
+// While servers run on a device, its default memory pool keeps some freed memory for reuse (a fresh
+// mapping of a request's buffers costs host time on every set-up): up to half of what the budget
+// leaves of the device, at most 32 GiB, so that the runtime keeps room of its own.  The first server
+// on a device sets the threshold and the last one restores it and trims the pool.
+static std::mutex pool_mu;
+static std::map<int, std::pair<int, uint64_t>> pool_users;   // device -> (servers, saved threshold)
+
+static void pool_cache_acquire(sc_server *s, size_t budget)
+{
+    std::lock_guard<std::mutex> lk(pool_mu);
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, s->ctx->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    auto &u = pool_users[s->ctx->device];
+    if (u.first == 0) {
+        size_t free_b = 0, total_b = 0;
+        (void)hipMemGetInfo(&free_b, &total_b);
+        uint64_t keep = total_b > budget ? std::min<uint64_t>(uint64_t(32) << 30, (total_b - budget) / 2) : 0;
+        if (hipMemPoolGetAttribute(pool, hipMemPoolAttrReleaseThreshold, &u.second) != hipSuccess ||
+            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+    }
+    u.first++;
+    s->pool = pool;
+}
+
+static void pool_cache_release(sc_server *s)
+{
+    if (!s->pool) return;
+    std::lock_guard<std::mutex> lk(pool_mu);
+    auto &u = pool_users[s->ctx->device];
+    if (--u.first == 0) {   // the pool as it was, and what the servers left in it returned
+        (void)hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &u.second);
+        (void)hipMemPoolTrimTo(s->pool, 0);
+    }
+    s->pool = nullptr;
+}
+
 extern "C" sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_running, double quantum_ms,
                                       sc_server **out)
 {
@@ -616,21 +657,6 @@ extern "C" sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_ru
         return st;
     }
     s->prep->tune = ctx->tune;
-    // Let the default memory pool keep some freed memory for reuse (a fresh mapping of a request's
-    // buffers costs host time on every set-up): up to half of what the budget leaves of the device,
-    // at most 32 GiB, so that the runtime keeps room of its own.
-    if (hipDeviceGetDefaultMemPool(&s->pool, ctx->device) == hipSuccess) {
-        size_t free_b = 0, total_b = 0;
-        (void)hipMemGetInfo(&free_b, &total_b);
-        const uint64_t keep = total_b > hbm_budget ? std::min<uint64_t>(uint64_t(32) << 30, (total_b - hbm_budget) / 2) : 0;
-        if (hipMemPoolGetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &s->pool_threshold_saved) != hipSuccess ||
-            hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, (void *)&keep) != hipSuccess)
-            s->pool = nullptr;
-        (void)hipGetLastError();
-    } else {
-        s->pool = nullptr;
-        (void)hipGetLastError();
-    }
     if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess) {
         (void)sc_ctx_destroy(s->prep);
         delete s;
@@ -654,6 +680,7 @@ extern "C" sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_ru
             delete s;
             return fail(SC_E_DEVICE, "sc_server_create: hipEventCreate failed");
         }
+    pool_cache_acquire(s, hbm_budget);
     ctx->n_probs++;   // the context must outlive the server
     s->worker = std::thread(worker_main, s);
     s->preparer = std::thread(prep_main, s);
@@ -836,10 +863,7 @@ extern "C" sc_status sc_server_destroy(sc_server *s)
     s->pinned.clear();
     (void)hipStreamSynchronize(s->release_stream);
     (void)hipStreamDestroy(s->release_stream);
-    if (s->pool) {   // the pool as it was, and what the server left in it returned
-        (void)hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &s->pool_threshold_saved);
-        (void)hipMemPoolTrimTo(s->pool, 0);
-    }
+    pool_cache_release(s);
     (void)hipStreamDestroy(s->copy_stream);
     for (int i = 0; i < sc_server::RING; ++i) {
         if (s->slot_ev[i]) (void)hipEventDestroy(s->slot_ev[i]);

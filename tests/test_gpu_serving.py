@@ -135,6 +135,26 @@ def test_close_while_requests_are_being_prepared(ctx):
     assert time.perf_counter() - t0 < 120.0
 
 
+def test_two_servers_on_one_device(ctx):
+    """Two servers at once (each on a context of its own), closed in the order they were created:
+    both serve their requests with the alone results, and the device's memory-pool settings that the
+    servers share are restored by the last one."""
+    from paper_1609_08146_amd import Context, Server
+    ws = small_requests(4, seed=23)
+    ref = [alone(ctx, w, "fp32_split") for w in ws]
+    ctx2 = Context(0)
+    s1 = Server(ctx, hbm_budget=int(8e9), max_running=4, quantum_ms=2.0)
+    s2 = Server(ctx2, hbm_budget=int(8e9), max_running=4, quantum_ms=2.0)
+    t1 = [s1.submit(w, "fp32_split") for w in ws[:2]]
+    t2 = [s2.submit(w, "fp32_split") for w in ws[2:]]
+    got = [s1.wait(t)[:2] for t in t1] + [s2.wait(t)[:2] for t in t2]
+    s1.close()
+    s2.close()
+    ctx2.close()
+    for (E, B), (Er, Br, _, _) in zip(got, ref):
+        assert np.array_equal(E, Er) and np.array_equal(B, Br)
+
+
 def test_rejection_cancel_timeout_and_bad_request(ctx):
     from paper_1609_08146_amd import ScError, Server
     from paper_1609_08146_amd._abi import SC_E_CANCELLED, SC_E_INVAL, SC_E_REJECTED, SC_E_TIMEOUT
