@@ -497,7 +497,9 @@ typedef struct {
     double run_ms;            /* admitted -> result ready on host             */
     double total_ms;          /* submit -> result ready                       */
     int64_t evals;            /* obs x freq x surface nodes                   */
-    size_t device_bytes;      /* HBM footprint charged at admission           */
+    size_t device_bytes;      /* HBM charged against the budget: the set-up's
+                                 peak at admission, what the prepared request
+                                 holds once its tables are built              */
 } sc_request_stats;
 
 typedef struct {
@@ -511,6 +513,10 @@ typedef struct {
                                  tables ready (includes waiting for the device) */
     double prep_host_ms;      /* host time of the preparation thread's set-up
                                  calls (no waiting)                           */
+    size_t host_in_use, host_budget;   /* pinned host bytes of admitted requests
+                                 whose results are not yet collected, and
+                                 their limit (a quarter of the host memory, at
+                                 most 64 GiB): admission waits for collection */
 } sc_server_stats;
 
 /* Start a serving loop on `ctx`: requests are admitted while their HBM

@@ -60,7 +60,8 @@ class sc_server_stats(ctypes.Structure):
                 ("rejected", ctypes.c_int64), ("cancelled", ctypes.c_int64), ("queued", ctypes.c_int64),
                 ("running", ctypes.c_int64), ("hbm_in_use", ctypes.c_size_t), ("hbm_budget", ctypes.c_size_t),
                 ("launches", ctypes.c_int64), ("evals_done", ctypes.c_int64), ("evals_launched", ctypes.c_int64),
-                ("quad_ms", ctypes.c_double), ("prep_ms", ctypes.c_double), ("prep_host_ms", ctypes.c_double)]
+                ("quad_ms", ctypes.c_double), ("prep_ms", ctypes.c_double), ("prep_host_ms", ctypes.c_double),
+                ("host_in_use", ctypes.c_size_t), ("host_budget", ctypes.c_size_t)]
 
 
 V, I, D, P = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p

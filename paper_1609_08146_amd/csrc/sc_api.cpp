@@ -228,7 +228,7 @@ static void invalidate_tables(sc_prob *p)
 {
     p->has_tab = p->tab32_ok = p->tab32n_ok = p->has_tab64 = p->has_power = false;
     p->fact_checked = p->fact_ok = p->fact64_ok = p->fact32_built = p->fact64_built = false;
-    p->fact_pending = false;   // a flag still on its way belongs to the old tables
+    p->fact_pending = p->cast_pending = false;   // a flag still on its way belongs to the old tables
     p->res_prec = -1;
 }
 
@@ -259,6 +259,8 @@ static void apply_factoring_flag(sc_prob *p, unsigned int bad, bool need32, bool
     }
 }
 
+static sc_status drop_fp64_tables(sc_prob *p, bool cast);
+
 sc_status sc::resolve_factoring(sc_prob *p, bool block, bool *ready)
 {
     if (ready) *ready = true;
@@ -276,6 +278,13 @@ sc_status sc::resolve_factoring(sc_prob *p, bool block, bool *ready)
     }
     p->fact_pending = false;
     apply_factoring_flag(p, *p->fact_flag_host, p->fact_req32, p->fact_req64);
+    if (p->cast_pending) {
+        p->cast_pending = false;
+        const bool cast = !(p->allow_fact && p->fact_ok);
+        // without a cast the factoring kernel, finished now, was the FP64 tables' last user
+        if (!cast && p->free_stream && p->tab64.stream) p->tab64.stream = p->free_stream;
+        SC_TRY(drop_fp64_tables(p, cast));
+    }
     return SC_OK;
 }
 
@@ -350,11 +359,24 @@ static sc_status finish_tables(sc_prob *p)
     // tables
     SC_TRY(ensure_factored(p, p->eager_prec == SC_FP32_SPLIT, p->eager_prec == SC_FP64 && p->keep_fp64));
     if (p->keep_fp64) return SC_OK;
-    const size_t nrec = p->k.size() * (size_t)p->n_tot;
-    SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
-    HIP_TRY(launch_tables_cast(p->ctx->stream, (int)p->k.size(), p->n_tot, p->d_k.as<double>(), p->pos64.as<double>(),
-                               p->tab64.as<double>(), nullptr, p->tab32.as<float>(), 0));
-    p->tab32_ok = true;
+    if (p->fact_pending) {   // the general FP32 tables only if the current does not factor
+        p->cast_pending = true;
+        return SC_OK;
+    }
+    return drop_fp64_tables(p, true);
+}
+
+// FP32-only storage: the general FP32 tables cast from the FP64 ones (when `cast`), then the FP64
+// tables and their factored copy released.
+static sc_status drop_fp64_tables(sc_prob *p, bool cast)
+{
+    if (cast) {
+        const size_t nrec = p->k.size() * (size_t)p->n_tot;
+        SC_TRY(p->tab32.reserve(sizeof(float) * 8 * nrec, p->alloc_stream));
+        HIP_TRY(launch_tables_cast(p->ctx->stream, (int)p->k.size(), p->n_tot, p->d_k.as<double>(),
+                                   p->pos64.as<double>(), p->tab64.as<double>(), nullptr, p->tab32.as<float>(), 0));
+        p->tab32_ok = true;
+    }
     // a stream-ordered free runs after the cast; a plain hipFree needs the cast to have finished
     if (!p->tab64.stream) HIP_TRY(hipStreamSynchronize(p->ctx->stream));
     p->tab64.release();
@@ -965,7 +987,8 @@ static sc_status select_tables(sc_prob *p, sc_precision prec, bool build, const 
         return fail(SC_E_STATE, "evaluate: mirror, frequencies, incident field and observation points are required");
     if (prec == SC_FP64 && !p->has_tab64)
         return fail(SC_E_STATE, "evaluate: FP64 tables were not kept (sc_set_table_storage(p, 0))");
-    if (prec != SC_FP64 && !p->tab32_ok && !p->has_tab64)
+    if (prec != SC_FP64 && !p->tab32_ok && !p->has_tab64 &&
+        !(prec == SC_FP32_SPLIT && p->allow_fact && p->fact32_built))
         return fail(SC_E_STATE, "evaluate: no tables to build the FP32 tables from");
     static const char *not_built = "evaluate without allocation: the tables of this precision are not built yet "
                                    "(evaluate the problem once with sc_evaluate first)";

@@ -150,6 +150,12 @@ struct sc_prob {
     unsigned int *fact_flag_host = nullptr;
     hipEvent_t fact_ev = nullptr;
     bool fact_pending = false, fact_req32 = false, fact_req64 = false;
+    // FP32-only storage with a test pending: the FP64 tables are dropped when the test completes,
+    // after a cast to the general FP32 tables only if the current did not factor
+    bool cast_pending = false;
+    // a stream with nothing else queued (the serving loop's release stream): buffers whose last user
+    // is known to have finished are freed there, not behind the work queued on the problem's stream
+    hipStream_t free_stream = nullptr;
     // the factored tables built with the test when the incident field is set: FP32 split by
     // default; a caller that knows its one precision (the serving loop) picks that one's
     sc_precision eager_prec = SC_FP32_SPLIT;

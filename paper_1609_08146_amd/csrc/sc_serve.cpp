@@ -38,6 +38,8 @@
 #include <thread>
 #include <vector>
 
+#include <unistd.h>
+
 #include "sc_host.h"
 
 using namespace sc;
@@ -53,7 +55,9 @@ struct Req {
     int n_r = 0, n_phi = 0, consistent = 0, n_t = 0, n_obs = 0, beam = 0;
     sc_precision prec = SC_FP32_SPLIT;
     std::vector<double> k, spec, obs, t;
-    size_t bytes = 0;
+    size_t bytes = 0;        // device bytes charged against the budget
+    size_t held_bytes = 0;   // device bytes held once prepared
+    size_t host_bytes = 0;   // pinned host bytes of its block (results, flag, upload staging)
     ReqState state = R_QUEUED;
     sc_status status = SC_OK;
     std::string err;
@@ -156,6 +160,7 @@ struct sc_server {
     hipStream_t copy_stream = nullptr;   // device-to-host copies of results
     hipStream_t release_stream = nullptr;   // frees of finished problems (nothing else queued on it)
     hipMemPool_t pool = nullptr;             // the device's default pool, if this server set its threshold
+    size_t host_budget = 0, host_in_use = 0; // pinned host bytes of admitted, not yet collected requests
     PinnedPool pinned;
     uint64_t next_ticket = 1;
     std::deque<Req *> queue;
@@ -221,6 +226,25 @@ static int server_fpb(sc_precision prec) { return prec == SC_FP64 ? 2 : 4; }
 // preparation thread never waits for the device: setup_begin enqueues the tables and the factoring
 // test, whose flag arrives in the request's pinned block; setup_finish, once it has, sizes the
 // partials and results for the table layout the test chose and fills the request's job.
+// Layout of a request's pinned block: E, B, then Et, Bt (each 256-byte aligned), the factoring flag
+// (256 bytes), and the staging area of the set-up's uploads (rule, frequencies, spectrum, points,
+// times), each upload 64-byte aligned.
+struct BlockLayout {
+    size_t re, te, tb, stage, total;
+};
+static BlockLayout block_layout(const Req *r)
+{
+    BlockLayout b;
+    b.re = (r->res_bytes + 255) & ~size_t(255);
+    b.te = (r->time_bytes + 255) & ~size_t(255);
+    b.tb = r->n_t > 0 ? 2 * b.te : 0;
+    auto up = [](size_t n) { return (sizeof(double) * n + 63) & ~size_t(63); };
+    b.stage = up(2 * (size_t)r->n_r + 1 + 2 * (size_t)r->n_phi) + up(r->k.size()) + up(2 * r->k.size()) +
+              up(3 * (size_t)r->n_obs) + up((size_t)r->n_t);
+    b.total = 2 * b.re + b.tb + 256 + b.stage;
+    return b;
+}
+
 static sc_status setup_begin(sc_server *s, Req *r)
 {
     SC_TRY(sc_prob_create(s->prep, &r->prob));
@@ -228,28 +252,22 @@ static sc_status setup_begin(sc_server *s, Req *r)
     p->alloc_stream = s->prep->stream;
     p->keep_fp64 = r->prec == SC_FP64;   // FP32 requests keep only their FP32 tables
     p->eager_prec = r->prec;             // and the factored tables of their own precision only
+    p->free_stream = s->release_stream;
     const int n_k = (int)r->k.size();
     const size_t rs = real_size(r->prec);
-    r->res_bytes = rs * 6 * (size_t)n_k * r->n_obs;
-    r->time_bytes = rs * 6 * (size_t)r->n_t * r->n_obs;
-    {   // one pinned block: E, B, then Et, Bt (each 256-byte aligned), the factoring flag, and the
-        // staging area of the set-up's uploads (rule, frequencies, spectrum, points, times)
-        const size_t re = (r->res_bytes + 255) & ~size_t(255), te = (r->time_bytes + 255) & ~size_t(255);
-        const size_t tb = r->n_t > 0 ? 2 * te : 0;
-        auto up = [](size_t n) { return (sizeof(double) * n + 63) & ~size_t(63); };
-        const size_t stage = up(2 * (size_t)r->n_r + 1 + 2 * (size_t)r->n_phi) + up(r->k.size()) +
-                             up(2 * r->k.size()) + up(3 * (size_t)r->n_obs) + up((size_t)r->n_t);
-        HIP_TRY(s->pinned.get(2 * re + tb + 256 + stage, &r->host_block, &r->host_block_bytes));
+    {   // one pinned block (block_layout)
+        const BlockLayout bl = block_layout(r);
+        HIP_TRY(s->pinned.get(bl.total, &r->host_block, &r->host_block_bytes));
         char *b = (char *)r->host_block;
         r->hE = b;
-        r->hB = b + re;
+        r->hB = b + bl.re;
         if (r->n_t > 0) {
-            r->hEt = b + 2 * re;
-            r->hBt = b + 2 * re + te;
+            r->hEt = b + 2 * bl.re;
+            r->hBt = b + 2 * bl.re + bl.te;
         }
-        p->fact_flag_host = (unsigned int *)(b + 2 * re + tb);
-        p->stage_ext = b + 2 * re + tb + 256;
-        p->stage_ext_cap = stage;
+        p->fact_flag_host = (unsigned int *)(b + 2 * bl.re + bl.tb);
+        p->stage_ext = b + 2 * bl.re + bl.tb + 256;
+        p->stage_ext_cap = bl.stage;
         p->stage_ext_off = 0;
     }
     SC_TRY(sc_set_mirror(p, r->f, r->a, r->n_r, r->n_phi));
@@ -288,6 +306,9 @@ static sc_status setup_finish(sc_server *s, Req *r, bool *ready)
     l.freq_per_lane = server_fpb(r->prec);
     SC_TRY(prepare(p, r->prec, l, r->job));
     HIP_TRY(hipEventRecord(r->ready_ev, s->prep->stream));
+    // what the request holds from now on (the admission charged the set-up's peak: FP64 tables,
+    // general FP32 tables and factored ones at once)
+    SC_TRY(sc_prob_device_bytes(p, &r->held_bytes));
     // the time samples are copied from r->t, which lives as long as the request
     r->evals = (int64_t)r->n_obs * (int64_t)r->k.size() * p->n_surf;
     return SC_OK;
@@ -479,8 +500,15 @@ static void prep_main(sc_server *s)
             s->stats.prep_ms += ms_between(started.front().second, Clock::now());
             started.pop_front();
             s->preparing--;
-            if (st == SC_OK) s->active.push_back(r);
-            else complete_request(s, r, R_FAILED, st, err);
+            if (st == SC_OK) {
+                if (r->held_bytes < r->bytes) {   // give back what the set-up no longer holds
+                    s->stats.hbm_in_use -= std::min(s->stats.hbm_in_use, r->bytes - r->held_bytes);
+                    r->bytes = r->held_bytes;
+                }
+                s->active.push_back(r);
+            } else {
+                complete_request(s, r, R_FAILED, st, err);
+            }
             s->cv_work.notify_one();
         }
         if (s->to_prepare.empty() || (int)started.size() >= MAX_STARTED) continue;
@@ -518,7 +546,11 @@ static void worker_main(sc_server *s)
                (int)(s->active.size() + s->to_prepare.size()) + s->preparing < s->max_running) {
             Req *r = s->queue.front();
             if (s->stats.hbm_in_use + r->bytes > s->budget) break;
+            // results wait in pinned host memory until collected: admit only while they fit
+            if (s->host_in_use > 0 && s->host_in_use + r->host_bytes > s->host_budget) break;
             s->queue.pop_front();
+            s->host_in_use += r->host_bytes;
+            s->stats.host_in_use = s->host_in_use;
             r->state = R_RUNNING;
             r->t_admit = Clock::now();
             s->stats.hbm_in_use += r->bytes;
@@ -651,6 +683,12 @@ extern "C" sc_status sc_server_create(sc_ctx *ctx, size_t hbm_budget, int max_ru
     s->max_running = max_running;
     s->quantum_ms = quantum_ms;
     s->stats.hbm_budget = hbm_budget;
+    {   // pinned host memory for results not yet collected: a quarter of the host memory, at most 64 GiB
+        const long pages = sysconf(_SC_PHYS_PAGES), page = sysconf(_SC_PAGE_SIZE);
+        const uint64_t phys = pages > 0 && page > 0 ? (uint64_t)pages * (uint64_t)page : (uint64_t(16) << 30);
+        s->host_budget = (size_t)std::min<uint64_t>(uint64_t(64) << 30, phys / 4);
+        s->stats.host_budget = s->host_budget;
+    }
     sc_status st = sc_ctx_create(ctx->device, nullptr, &s->prep);
     if (st != SC_OK) {
         delete s;
@@ -743,6 +781,9 @@ extern "C" sc_status sc_server_submit(sc_server *s, const sc_request *q, uint64_
         const sc_launch l = resolve_launch(&probe, q->prec);
         r->bytes = footprint_bytes(q->n_r, q->n_phi, q->n_k, q->n_obs, q->n_t, q->prec, l.chunk);
     }
+    r->res_bytes = real_size(q->prec) * 6 * (size_t)q->n_k * q->n_obs;
+    r->time_bytes = real_size(q->prec) * 6 * (size_t)q->n_t * q->n_obs;
+    r->host_bytes = PinnedPool::bucket(block_layout(r).total);
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {
@@ -799,6 +840,12 @@ extern "C" sc_status sc_server_wait(sc_server *s, uint64_t ticket, double timeou
         st = fail(r->status, "request failed: %s", r->err.c_str());
     }
     free_req_host(s, r);
+    if (r->state != R_CANCELLED && r->host_bytes) {   // admitted: its host bytes go back to the budget
+        std::lock_guard<std::mutex> lk2(s->mu);
+        s->host_in_use -= std::min(s->host_in_use, r->host_bytes);
+        s->stats.host_in_use = s->host_in_use;
+        s->cv_work.notify_one();
+    }
     delete r;
     return st;
 }
