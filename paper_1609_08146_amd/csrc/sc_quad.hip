@@ -209,41 +209,41 @@ struct GeomD {
     double dx, dy, dz, rinv, delta;
 };
 
-// sin and cos of 2 pi t in FP64.  The fractional turn r = t - rint(t) is
-// exact, so is y = r - q/4 with the quadrant q = rint(4 r), |y| <= 1/8; with
-// x = 2 pi y (|x| <= pi/4) and u = x^2, sin x = x + x^3 S(u) and
-// cos x = 1 - u/2 + u^2 C(u), where S and C are degree-5 Chebyshev fits of
-// (sin x - x)/x^3 and (cos x - 1 + x^2/2)/x^4 on u in [0, (pi/4)^2] (fit errors
-// 2e-17 and 1.3e-18; sincos_f64_fit.py beside this file derives them).  In
-// FP64 arithmetic the results stay within 1e-16 of sin and cos (the Taylor
-// series through x^17 and x^18 that they replace did the same with four more
-// FMAs); the quadrant turns the pair by q pi/2.
-__device__ __forceinline__ void sincos_turns_f64(double t, double &s, double &c)
+// sin and cos of 2 pi j / 256, j = -128 ... 128, as (cos, sin) pairs in LDS: filled by the
+// workgroup at the start of an FP64 launch (sincospi of the exact argument j / 128).
+constexpr int TURN_STEPS = 256;
+__device__ __forceinline__ const double2 *turn_table_lds()
+{
+    __shared__ double2 tab[TURN_STEPS + 1];
+    for (int i = threadIdx.x; i <= TURN_STEPS; i += blockDim.x) {
+        double sv, cv;
+        sincospi((double)(i - TURN_STEPS / 2) / (double)(TURN_STEPS / 2), &sv, &cv);
+        tab[i] = make_double2(cv, sv);
+    }
+    __syncthreads();
+    return tab;
+}
+
+// sin and cos of 2 pi t in FP64.  The fractional turn r = t - rint(t) is exact, and so is
+// z = r - j / 256 with j = rint(256 r) (|z| <= 1/512 turn): then 2 pi t = 2 pi j / 256 + x,
+// x = 2 pi z, |x| <= pi / 256, and the angle sum combines the tabulated (cos, sin) of 2 pi j / 256
+// with sin x = x - x^3/6 + x^5/120 and cos x = 1 - x^2/2 + x^4/24 - x^6/720 (the first omitted
+// terms are below 1e-17 and 2e-20).
+__device__ __forceinline__ void sincos_turns_f64(double t, const double2 *tab, double &s, double &c)
 {
     const double r = t - rint(t);
-    const double q = rint(4.0 * r);
-    const double y = __fma_rn(-0.25, q, r);
-    const double x = y * TWO_PI_1;
+    const double j = rint((double)TURN_STEPS * r);
+    const double z = __fma_rn(-1.0 / TURN_STEPS, j, r);
+    const double x = z * TWO_PI_1;
     const double u = x * x;
-    double ps = 1.5918129294866608e-10;
-    ps = __fma_rn(ps, u, -2.5051131845003624e-08);
-    ps = __fma_rn(ps, u, 2.755731610255244e-06);
-    ps = __fma_rn(ps, u, -0.00019841269836758574);
-    ps = __fma_rn(ps, u, 0.008333333333330948);
-    ps = __fma_rn(ps, u, -0.16666666666666666);
-    const double s0 = __fma_rn(x * u, ps, x);
-    double pc = -1.1382632425521717e-11;
-    pc = __fma_rn(pc, u, 2.08761462684032e-09);
-    pc = __fma_rn(pc, u, -2.7557317271729793e-07);
-    pc = __fma_rn(pc, u, 2.480158729876569e-05);
-    pc = __fma_rn(pc, u, -0.0013888888888887398);
-    pc = __fma_rn(pc, u, 0.041666666666666664);
-    pc = __fma_rn(pc, u, -0.5);
-    const double c0 = __fma_rn(u, pc, 1.0);
-    const int qi = (int)q & 3;   // q in {-2, ..., 2}
-    const double sa = (qi & 1) ? c0 : s0, ca = (qi & 1) ? s0 : c0;
-    s = (qi >= 2) ? -sa : sa;                 // quadrants 2, 3: sin < 0 side
-    c = (qi == 1 || qi == 2) ? -ca : ca;      // quadrants 1, 2
+    const double ps = __fma_rn(u, 1.0 / 120.0, -1.0 / 6.0);
+    const double sx = __fma_rn(x * u, ps, x);
+    double pc = __fma_rn(u, -1.0 / 720.0, 1.0 / 24.0);
+    pc = __fma_rn(u, pc, -0.5);
+    const double cx = __fma_rn(u, pc, 1.0);
+    const double2 w = tab[(int)j + TURN_STEPS / 2];
+    s = __fma_rn(w.y, cx, w.x * sx);
+    c = __fma_rn(w.x, cx, -(w.y * sx));
 }
 
 // The FP64 geometry by series near the focus (see geom_series): with
@@ -295,10 +295,11 @@ __device__ __forceinline__ GeomD geom_f64(const double *p, const double4 o)
     return g;
 }
 
-__device__ __forceinline__ void freq_f64(const GeomD &g, const double *t, double k, double kt, double *acc)
+__device__ __forceinline__ void freq_f64(const GeomD &g, const double *t, double k, double kt, const double2 *ttab,
+                                         double *acc)
 {
     double s, c;
-    sincos_turns_f64(kt * g.delta, s, c);
+    sincos_turns_f64(kt * g.delta, ttab, s, c);
     const double dx = g.dx, dy = g.dy, dz = g.dz, rinv = g.rinv;
     const double gr = c * rinv, gi = s * rinv;
     const double a = -(rinv * rinv), b = k * rinv;
@@ -334,10 +335,10 @@ __device__ __forceinline__ void freq_f64(const GeomD &g, const double *t, double
 // t = (s, rho_t) as (re, im) pairs.
 __device__ __forceinline__ void freq_f64_factored(double rinv, double delta, const double *v, const double *e,
                                                   const double *w, const double *t, double k, double kt,
-                                                  double *acc)
+                                                  const double2 *ttab, double *acc)
 {
     double sn, c;
-    sincos_turns_f64(kt * delta, sn, c);
+    sincos_turns_f64(kt * delta, ttab, sn, c);
     const double ar = __fma_rn(t[0], c, -(t[1] * sn)), ai = __fma_rn(t[0], sn, t[1] * c);
     const double cr = __fma_rn(t[2], c, -(t[3] * sn)), ci = __fma_rn(t[2], sn, t[3] * c);
     const double amr = __fma_rn(-rinv, ar, -(k * ai)), ami = __fma_rn(-rinv, ai, k * ar);
@@ -358,7 +359,7 @@ __device__ __forceinline__ void freq_f64_factored(double rinv, double delta, con
 // records (s, rho_t), 8 and 4 doubles.  Plain FP64 sums.
 template <int OPL, int FPB, bool FACT, bool SER = false>
 __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
-                                         const double *k64, int n_valid)
+                                         const double *k64, int n_valid, const double2 *ttab)
 {
     constexpr int PS = FACT ? 8 : 4;   // doubles per node record
     constexpr int TS = FACT ? 4 : 8;   // doubles per table record
@@ -408,10 +409,10 @@ __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0,
                                      __fma_rn(pn[4], e[1], -(pn[5] * e[0]))};
 #pragma unroll
                 for (int f = 0; f < FPB; ++f)
-                    freq_f64_factored(g.rinv, g.delta, v, e, w, tn[f], k64[f], kt64[f], acc[s][f]);
+                    freq_f64_factored(g.rinv, g.delta, v, e, w, tn[f], k64[f], kt64[f], ttab, acc[s][f]);
             } else {
 #pragma unroll
-                for (int f = 0; f < FPB; ++f) freq_f64(g, tn[f], k64[f], kt64[f], acc[s][f]);
+                for (int f = 0; f < FPB; ++f) freq_f64(g, tn[f], k64[f], kt64[f], ttab, acc[s][f]);
             }
         }
     }
@@ -580,6 +581,8 @@ k_quad(const QuadJob *__restrict__ jobs_, int n_jobs, int64_t n_tiles,
 {
     cjob *jobs = (cjob *)jobs_;
     const int lane = threadIdx.x & 63;
+    const double2 *ttab = nullptr;   // the FP64 form's (cos, sin) table
+    if constexpr (MODE == MODE_FP64) ttab = turn_table_lds();
     // The tile list is cut into QUAD_SEGMENTS contiguous segments with a counter
     // each.  Workgroups are dispatched to the 8 XCDs round robin, so block b
     // starts on segment b % 8: the tiles that share a (frequency block, node
@@ -624,13 +627,13 @@ k_quad(const QuadJob *__restrict__ jobs_, int n_jobs, int64_t n_tiles,
         if constexpr (MODE == MODE_FP64) {
             const bool ser = jobs[j].series_delta != 0;
             if (jobs[j].factored && ser)
-                tile_f64<OPL, FPB, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                tile_f64<OPL, FPB, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid, ttab);
             else if (jobs[j].factored)
-                tile_f64<OPL, FPB, true, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                tile_f64<OPL, FPB, true, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid, ttab);
             else if (ser)
-                tile_f64<OPL, FPB, false, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                tile_f64<OPL, FPB, false, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid, ttab);
             else
-                tile_f64<OPL, FPB, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);
+                tile_f64<OPL, FPB, false, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid, ttab);
         } else if constexpr (MODE == MODE_SPLIT) {
             // per job (not per tile), so the bits of a point do not depend on the launch shape
             const bool raw = jobs[j].raw_phase != 0;
