@@ -45,20 +45,24 @@ import workloads  # noqa: E402
 #   per (node, point, frequency): phase 2, A = s Z 6, C = rho_t Z 6,
 #                                 A m, C m (m = ik - 1/R) 12, E += v A 12,
 #                                 E += (C m) e 12, B += (A m) w 12         62
+# The same with the charge tied to the current (rho_t = -i beta s / k):
+#   per (node, point):            the factored 34, e' = beta e 3           37
+#   per (node, point, frequency): phase 2, A = s Z 6, q = 1/(kR) 1,
+#                                 M = A (i - q) 4, E += v A 12,
+#                                 E += e' (-i M) 12, B += M w 12           49
 # The kernel shares the per-(node, point) work among the frequencies of a
 # lane (freq_per_lane of the launch, read back from the library for every
 # figure below).  Where the observation points lie within 4e-4 |r_s|
 # of the focus, the kernel forms delta and 1/|R| by short series instead of a
 # reciprocal and a square root (5 more flops per (node, point), not counted:
 # the constant stays the formula's).
-FLOPS_GEOM, FLOPS_FREQ = 18, 96
-FLOPS_GEOM_FACTORED, FLOPS_FREQ_FACTORED = 34, 62
+FLOPS = {"general": (18, 96), "factored": (34, 62), "tied": (37, 49)}   # (per node and point, per frequency)
 
 
-def flops_per_eval(factored: bool, freq_per_lane: int) -> float:
-    if factored:
-        return FLOPS_FREQ_FACTORED + FLOPS_GEOM_FACTORED / freq_per_lane
-    return FLOPS_FREQ + FLOPS_GEOM / freq_per_lane
+def flops_per_eval(layout: str, freq_per_lane: int) -> float:
+    """Algorithmic flops per evaluation of a table layout ("general", "factored", "tied")."""
+    geom, freq = FLOPS[layout]
+    return freq + geom / freq_per_lane
 
 
 # MI355X vector peaks: 256 CU x 4 SIMD x 2.4 GHz x (32 FP32 | 16 FP64) lanes x 2 (FMA)
@@ -115,6 +119,8 @@ def parse():
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--general-tables", action="store_true",
                     help="step, batch: never use the factored current (time the general-table layout)")
+    ap.add_argument("--no-tie", action="store_true",
+                    help="step, batch: the factored current without the tied charge (time that layout)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mode", default="step",
                     choices=["step", "batch", "serve", "copy", "table1", "valu", "convergence", "refine"],
@@ -216,7 +222,8 @@ def cpu_baseline(w, target_s):
                                     f"one thread, {dt1:.1f} s"}
 
 
-def batch_run(n_instances: int = 256, general: bool = False, tune: bool = True, tune_budget_ms: float = 20000.0):
+def batch_run(n_instances: int = 256, general: bool = False, tune: bool = True, tune_budget_ms: float = 20000.0,
+              tie: bool = True):
     """All instances of the seeded sweep in ONE persistent launch (FP32 split, FP32-only tables),
     timed with the library's batch launch and, when `tune`, again after sc_autotune_batch has tuned
     the launch on every 16th instance.  Returns a dict of both runs."""
@@ -230,8 +237,7 @@ def batch_run(n_instances: int = 256, general: bool = False, tune: bool = True, 
     for w in ws:
         p = Problem(ctx)
         p.set_table_storage(False)
-        if general:
-            p.set_factoring(False)
+        p.set_factoring(not general, tie_charge=tie)
         p.set_mirror(w.f, w.a, w.n_r, w.n_phi)
         p.set_frequencies(w.k)
         p.set_incident_gaussian(w.w0, w.pol, w.spectrum, False)
@@ -240,7 +246,8 @@ def batch_run(n_instances: int = 256, general: bool = False, tune: bool = True, 
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     evals = sum(w.evals for w in ws)
-    fact_evals = sum(w.evals for w, p in zip(ws, probs) if p.factored)
+    layouts = [p.layout_for("fp32_split") for p in probs]
+    layout_evals = {lay: sum(w.evals for w, l in zip(ws, layouts) if l == lay) for lay in FLOPS}
 
     def partial_bytes():
         # split-K partials: 12 reals per (chunk, frequency, padded point), at the chunk each problem used
@@ -256,7 +263,7 @@ def batch_run(n_instances: int = 256, general: bool = False, tune: bool = True, 
         dt = time.perf_counter() - t0
         quad_ms = probs[0].timing()["quad_ms"]
         fpl = launch["freq_per_lane"]
-        flops = flops_per_eval(True, fpl) * fact_evals + flops_per_eval(False, fpl) * (evals - fact_evals)
+        flops = sum(flops_per_eval(lay, fpl) * n for lay, n in layout_evals.items())
         return {"label": label, "value": evals / dt, "seconds": dt, "quad_ms": quad_ms,
                 "quad_evals_per_s": evals / (quad_ms * 1e-3), "launch": launch,
                 "tflops": flops / (quad_ms * 1e-3) / 1e12,
@@ -279,8 +286,9 @@ def batch_run(n_instances: int = 256, general: bool = False, tune: bool = True, 
         runs.append(r)
         ctx.set_batch_launch("fp32_split", reset=True)
     out = {"instances": len(ws), "evals": evals, "setup_s": setup,
-           "factored_instances": sum(1 for p in probs if p.factored), "precision": "fp32_split",
-           "tables": "general" if general else "factored where the current allows", "runs": runs}
+           "instances_by_layout": {lay: layouts.count(lay) for lay in FLOPS}, "precision": "fp32_split",
+           "tables": "general" if general else ("factored where the current allows, the charge tied where it is"
+                                                if tie else "factored where the current allows"), "runs": runs}
     for p in probs:
         p.close()
     ctx.close()
@@ -289,7 +297,7 @@ def batch_run(n_instances: int = 256, general: bool = False, tune: bool = True, 
 
 def bench_batch(args):
     """--mode batch: the 256-instance sweep in one persistent launch, library and tuned launch."""
-    out = batch_run(args.instances, args.general_tables)
+    out = batch_run(args.instances, args.general_tables, tie=not args.no_tie)
     best = max(out["runs"], key=lambda r: r["value"])
     print(json.dumps({"metric": "integrand evals/s, seeded sweep of uneven instances in one persistent launch",
                       "value": best["value"], "unit": "integrand evals/s", "n_gpus": 1, **out}), flush=True)
@@ -678,7 +686,7 @@ def main():
     ctx.set_profiling(True)
 
     p = Problem(ctx)
-    p.set_factoring(not args.general_tables)
+    p.set_factoring(not args.general_tables, tie_charge=not args.no_tie)
     for _ in range(args.warmup):
         run_step(p, w, args.precision)
     torch.cuda.synchronize()
@@ -697,7 +705,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     progress(f"{args.steps} timed steps, {elapsed * 1e3 / args.steps:.2f} ms per step")
-    factored = p.factored_for(args.precision)
+    layout = p.layout_for(args.precision)
+    factored = layout != "general"
     launch = p.launch(args.precision)
     # the same step with its results handed back in host memory: spectral E, B and the time
     # samples copied to (pageable) numpy arrays through the C ABI's host-output path
@@ -717,7 +726,7 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = evals * args.steps / elapsed
     quad_avg = float(np.mean(quad_ms))
-    fpe = flops_per_eval(factored, launch["freq_per_lane"])
+    fpe = flops_per_eval(layout, launch["freq_per_lane"])
     achieved = fpe * evals / (quad_avg * 1e-3) / 1e12
     peak = PEAK_FP64 if args.precision == "fp64" else PEAK_FP32
     # the counters were taken on the full FP32-split workload with the default launch
@@ -741,15 +750,18 @@ def main():
                         f"256 time samples; {shard_desc}",
             "precision": args.precision, "launch": (f"obs_per_lane={launch['obs_per_lane']}, freq_per_lane={launch['freq_per_lane']}, "
                                                  f"{launch['waves_per_block']} waves/block, chunk {launch['chunk']}"),
-            "current": "factored (Jt = u s: the current n x B keeps one real direction per node)" if factored
-                       else "general tables",
+            "current": {"tied": "factored with the tied charge (Jt = u s, rho_t = -i beta s / k: n x B keeps "
+                                 "one real direction per node and n.E carries its amplitude)",
+                        "factored": "factored (Jt = u s: the current n x B keeps one real direction per node)",
+                        "general": "general tables"}[layout],
             "n_obs": w.n_obs, "n_freq": w.n_k, "n_nodes": w.n_nodes, "n_time": len(w.t),
             "evals_per_step": evals,
         },
         "roofline": {
             "bound": "alu",
             "kernel": ("k_quad (split-form surface quadrature" + (" in FP64" if args.precision == "fp64" else "")
-                       + (", factored current)" if factored else ")")),
+                       + {"tied": ", factored current, tied charge)", "factored": ", factored current)",
+                          "general": ")"}[layout]),
             "achieved": achieved,
             "peak": peak,
             "unit": "TFLOP/s",
@@ -782,7 +794,8 @@ def main():
         p.evaluate("fp64", keep_on_device=True)
         torch.cuda.synchronize()
         q64 = p.timing()["quad_ms"]
-        fact64 = p.factored_for("fp64")
+        layout64 = p.layout_for("fp64")
+        fact64 = layout64 != "general"
         fpl64 = p.launch("fp64")["freq_per_lane"]
         # error of every output component of the chosen form against the FP64 form (itself held to the
         # oracle at 1e-12 by the tests) over the whole grid: max |F_c - F_c,64| / max |F_c,64| (the
@@ -800,16 +813,48 @@ def main():
         progress(f"FP64 form {q64:.1f} ms")
         r64 = w64.evals / (q64 * 1e-3)
         rq = evals / (quad_avg * 1e-3)
-        fpg = flops_per_eval(False, launch["freq_per_lane"])
-        fpg64 = flops_per_eval(False, fpl64)
-        f64 = flops_per_eval(fact64, fpl64)
+        fpg64 = flops_per_eval("general", fpl64)
+        f64 = flops_per_eval(layout64, fpl64)
         out["forms"] = {
             "fp64": {"quad_evals_per_s": r64, "quad_ms": q64, "n_freq": w64.n_k,
-                     "current": "factored" if fact64 else "general tables", "flops_per_eval": f64,
+                     "current": layout64, "flops_per_eval": f64,
                      "tflops": f64 * r64 / 1e12, "frac_fp64_peak": f64 * r64 / 1e12 / PEAK_FP64},
             args.precision: {"quad_evals_per_s": rq, "per_component_vs_fp64": per_comp},
             "speedup_vs_fp64": rq / r64,
         }
+        if layout == "tied":
+            # the factored current without the tied charge (a beam with a longitudinal E, such as the
+            # curl-consistent radial one, takes this layout): its quadrature on the same workload
+            qu = []
+            p = Problem(ctx)
+            p.set_factoring(True, tie_charge=False)
+            for _ in range(4):
+                run_step(p, w, args.precision)
+                torch.cuda.synchronize()
+                qu.append(p.timing()["quad_ms"])
+            fpu = flops_per_eval("factored", p.launch(args.precision)["freq_per_lane"])
+            p.close()
+            ru = evals / (min(qu[1:]) * 1e-3)
+            out["forms"]["fp32_split_factored_untied"] = {
+                "quad_evals_per_s": ru, "quad_ms": min(qu[1:]), "flops_per_eval": fpu, "tflops": fpu * ru / 1e12,
+                "frac_fp32_peak": fpu * ru / 1e12 / PEAK_FP32}
+        if layout64 == "tied":
+            # the FP64 form on the factored current without the tied charge
+            p = Problem(ctx)
+            p.set_factoring(True, tie_charge=False)
+            p.set_mirror(w64.f, w64.a, w64.n_r, w64.n_phi)
+            p.set_frequencies(w64.k)
+            p.set_incident_gaussian(w64.w0, 0.0, w64.spectrum, False)
+            p.set_observation(w64.obs)
+            p.evaluate("fp64", keep_on_device=True)
+            torch.cuda.synchronize()
+            qu64 = p.timing()["quad_ms"]
+            fpu64 = flops_per_eval("factored", p.launch("fp64")["freq_per_lane"])
+            p.close()
+            ru64 = w64.evals / (qu64 * 1e-3)
+            out["forms"]["fp64_factored_untied"] = {
+                "quad_evals_per_s": ru64, "quad_ms": qu64, "flops_per_eval": fpu64, "tflops": fpu64 * ru64 / 1e12,
+                "frac_fp64_peak": fpu64 * ru64 / 1e12 / PEAK_FP64}
         if factored:
             # the same split form on the general tables (what an arbitrary incident field costs): the
             # whole step, timed like the headline over a few steps, and its quadrature
@@ -824,7 +869,7 @@ def main():
                 torch.cuda.synchronize()
                 sg.append(time.perf_counter() - ts)
                 qg.append(p.timing()["quad_ms"])
-            fpg = flops_per_eval(False, p.launch(args.precision)["freq_per_lane"])
+            fpg = flops_per_eval("general", p.launch(args.precision)["freq_per_lane"])
             p.close()
             rg = evals / (min(qg) * 1e-3)
             out["value_general_tables"] = evals / float(np.mean(sg))

@@ -344,14 +344,32 @@ sc_status sc_set_table_storage(sc_prob *p, int keep_fp64);
  * are the same up to rounding (the same tolerances against the oracle
  * apply); results are reproducible and independent of the launch shape
  * either way, and a batch may mix factored and general problems.
+ *
+ * Tied charge.  When moreover rho~[k][q] = -i beta_q s[k][q] / k with a real
+ * beta_q per node (a factoring beam with no longitudinal field, B = -z x E:
+ * the literal linear, radial and azimuthal Gaussians, Laguerre-Gauss sets
+ * whose current factors; rho~ = (2W/4pi)(n.E) P and J~ = ik (2W/4pi)(n x B) P
+ * then carry the same amplitude; not the curl-consistent radial beam, whose
+ * E_z turns n.E by 90 degrees), the charge term needs no product of its
+ * own: with A = s e^{ik delta} and m = ik - 1/R,
+ *   rho~ (m e^{ik delta} / R^2) R = beta (R / R^2) (-i A m / k),
+ * and the B term (A m) (u x R / R^2) keeps A m / k with the factor k applied
+ * after the sum, so a (point, frequency, node) term takes about a quarter
+ * fewer operations than with the factored current alone.  The same test
+ * decides it (residual |rho~ + i beta s / k| against the node's largest
+ * (|rho~|^2 + |J~ / k|^2)^1/2, same tolerances); rim nodes, which carry a
+ * charge only, take u = 0, beta = 1 and s = i k rho~.  The tables are the
+ * factored ones plus beta per node (4 B in FP32, 8 B in FP64).
  * enable = 1 (default) uses the factored tables whenever the test passes,
- * 0 never.  The test needs the FP64 tables: with keep_fp64 = 0 it runs when
- * the incident field is set, so enabling afterwards has no effect until the
- * field is set again.                                                      */
+ * with the tied charge where it holds; 2 the factored current without the
+ * tied charge; 0 neither.  The test needs the FP64 tables: with keep_fp64 = 0
+ * it runs when the incident field is set, so enabling afterwards has no
+ * effect until the field is set again.  SC_E_INVAL for another value.      */
 sc_status sc_set_factoring(sc_prob *p, int enable);
-/* *active = 1 if evaluation of p in precision prec uses the factored tables
- * (runs the test if it has not run yet; always 0 for SC_FP32).  SC_E_STATE
- * without an incident field, SC_E_INVAL for an unknown precision.         */
+/* *active = the table layout evaluation of p in precision prec uses: 0 the
+ * general tables, 1 the factored current, 2 the factored current with the
+ * tied charge (runs the test if it has not run yet; always 0 for SC_FP32).
+ * SC_E_STATE without an incident field, SC_E_INVAL for an unknown precision. */
 sc_status sc_get_factoring_for(sc_prob *p, sc_precision prec, int *active);
 /* sc_get_factoring_for(p, SC_FP32_SPLIT, active).                          */
 sc_status sc_get_factoring(sc_prob *p, int *active);

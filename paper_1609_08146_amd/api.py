@@ -298,10 +298,11 @@ class Problem:
     def set_table_storage(self, keep_fp64: bool):
         call("sc_set_table_storage", self.h, int(bool(keep_fp64)))
 
-    def set_factoring(self, enable: bool):
-        """Use the factored current J~ = u s for "fp32_split" and "fp64" when the tables allow it
-        (sc_set_factoring)."""
-        call("sc_set_factoring", self.h, int(bool(enable)))
+    def set_factoring(self, enable: bool, tie_charge: bool = True):
+        """Use the factored current J~ = u s for "fp32_split" and "fp64" when the tables allow it,
+        and with `tie_charge` the charge tied to it, rho~ = -i beta s / k, where it is
+        (sc_set_factoring with 1; 2 without the tied charge, 0 neither)."""
+        call("sc_set_factoring", self.h, 0 if not enable else (1 if tie_charge else 2))
 
     @property
     def factored(self) -> bool:
@@ -312,9 +313,14 @@ class Problem:
 
     def factored_for(self, precision="fp32_split") -> bool:
         """True if evaluation in `precision` uses the factored tables (sc_get_factoring_for)."""
+        return self.layout_for(precision) != "general"
+
+    def layout_for(self, precision="fp32_split") -> str:
+        """Table layout of evaluation in `precision`: "general", "factored" (the current J~ = u s)
+        or "tied" (the factored current and the charge tied to it), from sc_get_factoring_for."""
         v = ctypes.c_int(0)
         call("sc_get_factoring_for", self.h, _prec(precision), ctypes.byref(v))
-        return bool(v.value)
+        return ("general", "factored", "tied")[v.value]
 
     def set_observation(self, xyz):
         dev = _is_device(xyz)

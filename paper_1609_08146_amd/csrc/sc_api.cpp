@@ -227,7 +227,8 @@ static void gauss_rule_cached(sc_ctx *c, int n, const std::vector<double> *out[2
 static void invalidate_tables(sc_prob *p)
 {
     p->has_tab = p->tab32_ok = p->tab32n_ok = p->has_tab64 = p->has_power = false;
-    p->fact_checked = p->fact_ok = p->fact64_ok = p->fact32_built = p->fact64_built = false;
+    p->fact_checked = p->fact_ok = p->fact64_ok = p->tie_ok = p->tie64_ok = false;
+    p->fact32_built = p->fact64_built = false;
     p->fact_pending = p->cast_pending = false;   // a flag still on its way belongs to the old tables
     p->res_prec = -1;
 }
@@ -236,26 +237,33 @@ static void invalidate_tables(sc_prob *p)
 // node's largest |Jt|): the built-in beams whose current keeps one real direction factor to rounding
 // (~1e-16); the longitudinal magnetic term of the curl-consistent linear beam turns the current by
 // O(1/(k w0)) and is rejected.  FP64 evaluation, accurate to ~1e-13, takes the factored tables only
-// when the residual is below 1e-14.
+// when the residual is below 1e-14.  The same tolerances, against the node's largest |rho_t|,
+// decide whether the charge is tied to the current (rho_t = -i beta s / k): it is, to rounding, for
+// the beams whose E and B share one complex amplitude.
 constexpr double FACTOR_TOL = 1e-10;
 constexpr double FACTOR_TOL_FP64 = 1e-14;
 
 // The outcome of the factoring test (bit 0: the FP32 split tolerance failed, bit 1: the FP64
-// one): which factored tables exist now, and the ones that will not be used are released.
+// one; bits 2 and 3 the same for the tied charge): which factored tables exist now, and the ones
+// that will not be used are released.
 static void apply_factoring_flag(sc_prob *p, unsigned int bad, bool need32, bool need64)
 {
     p->fact_checked = true;
     p->fact_ok = (bad & 1u) == 0;
     p->fact64_ok = p->fact_ok && (bad & 2u) == 0;
+    p->tie_ok = p->fact_ok && (bad & 4u) == 0;
+    p->tie64_ok = p->fact64_ok && (bad & 8u) == 0;
     p->fact32_built = p->fact32_built || (need32 && p->fact_ok);
     p->fact64_built = p->fact64_built || (need64 && p->fact64_ok);
     if (!p->fact_ok) {
         p->tabf.release();
         p->posf.release();
+        p->betaf.release();
     }
     if (!p->fact64_ok) {
         p->tabf64.release();
         p->posf64.release();
+        p->betaf64.release();
     }
 }
 
@@ -310,18 +318,21 @@ static sc_status ensure_factored(sc_prob *p, bool need32, bool need64)
     if (need32) {
         SC_TRY(p->tabf.reserve(sizeof(float) * 4 * nrec, p->alloc_stream));
         SC_TRY(p->posf.reserve(sizeof(float) * 8 * (size_t)p->n_tot, p->alloc_stream));
+        SC_TRY(p->betaf.reserve(sizeof(float) * (size_t)p->n_tot, p->alloc_stream));
     }
     if (need64) {
         SC_TRY(p->tabf64.reserve(sizeof(double) * 4 * nrec, p->alloc_stream));
         SC_TRY(p->posf64.reserve(sizeof(double) * 8 * (size_t)p->n_tot, p->alloc_stream));
+        SC_TRY(p->betaf64.reserve(sizeof(double) * (size_t)p->n_tot, p->alloc_stream));
     }
     SC_TRY(p->fact_flag.reserve(sizeof(unsigned int), p->alloc_stream));
     HIP_TRY(launch_fill_u32(st, p->fact_flag.as<unsigned int>(), 0u, 1));
-    HIP_TRY(launch_tables_factor(st, n_k, p->n_tot, p->tab64.as<double>(), p->pos32.as<float>(),
-                                 p->pos64.as<double>(), FACTOR_TOL, FACTOR_TOL_FP64,
+    HIP_TRY(launch_tables_factor(st, n_k, p->n_tot, p->d_k.as<double>(), p->tab64.as<double>(),
+                                 p->pos32.as<float>(), p->pos64.as<double>(), FACTOR_TOL, FACTOR_TOL_FP64,
                                  need32 ? p->tabf.as<float>() : nullptr, need32 ? p->posf.as<float>() : nullptr,
-                                 need64 ? p->tabf64.as<double>() : nullptr,
-                                 need64 ? p->posf64.as<double>() : nullptr, p->fact_flag.as<unsigned int>()));
+                                 need32 ? p->betaf.as<float>() : nullptr, need64 ? p->tabf64.as<double>() : nullptr,
+                                 need64 ? p->posf64.as<double>() : nullptr,
+                                 need64 ? p->betaf64.as<double>() : nullptr, p->fact_flag.as<unsigned int>()));
     if (p->fact_checked) {
         p->fact32_built = p->fact32_built || need32;
         p->fact64_built = p->fact64_built || need64;
@@ -336,7 +347,7 @@ static sc_status ensure_factored(sc_prob *p, bool need32, bool need64)
         p->fact_req64 = need64;
         return SC_OK;
     }
-    unsigned int bad = 3;
+    unsigned int bad = 15;
     HIP_TRY(hipMemcpyAsync(&bad, p->fact_flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     apply_factoring_flag(p, bad, need32, need64);
@@ -384,6 +395,7 @@ static sc_status drop_fp64_tables(sc_prob *p, bool cast)
     // without the FP64 tables there is no FP64 evaluation, so its factored tables go too
     p->tabf64.release();
     p->posf64.release();
+    p->betaf64.release();
     p->fact64_built = false;
     return SC_OK;
 }
@@ -400,7 +412,9 @@ extern "C" sc_status sc_set_table_storage(sc_prob *p, int keep_fp64)
 extern "C" sc_status sc_set_factoring(sc_prob *p, int enable)
 {
     if (!p) return fail(SC_E_INVAL, "sc_set_factoring: prob is NULL");
+    if (enable < 0 || enable > 2) return fail(SC_E_INVAL, "sc_set_factoring: enable must be 0, 1 or 2");
     p->allow_fact = enable != 0;
+    p->allow_tie = enable == 1;
     return SC_OK;
 }
 
@@ -412,8 +426,9 @@ extern "C" sc_status sc_get_factoring_for(sc_prob *p, sc_precision prec, int *ac
     if (!p->has_tab) return fail(SC_E_STATE, "sc_get_factoring: no incident field set");
     DeviceGuard g(p->ctx->device);
     SC_TRY(ensure_factored(p, false, false));   // runs the test if it has not run yet
-    if (prec == SC_FP32_SPLIT) *active = p->allow_fact && p->fact_ok ? 1 : 0;
-    else if (prec == SC_FP64) *active = p->allow_fact && p->fact64_ok && p->has_tab64 ? 1 : 0;
+    if (prec == SC_FP32_SPLIT) *active = p->allow_fact && p->fact_ok ? (p->allow_tie && p->tie_ok ? 2 : 1) : 0;
+    else if (prec == SC_FP64)
+        *active = p->allow_fact && p->fact64_ok && p->has_tab64 ? (p->allow_tie && p->tie64_ok ? 2 : 1) : 0;
     else *active = 0;
     return SC_OK;
 }
@@ -766,7 +781,8 @@ static sc_status scale_tables(sc_prob *p, const std::vector<double> &fac)
     if (p->has_tab64) {
         HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, 4, dfac.as<double>(), p->tab64.as<double>(), nullptr));
         p->tab32_ok = false;   // rebuilt from the scaled FP64 tables when needed
-        p->fact_checked = p->fact_ok = p->fact64_ok = p->fact32_built = p->fact64_built = false;
+        p->fact_checked = p->fact_ok = p->fact64_ok = p->tie_ok = p->tie64_ok = false;
+        p->fact32_built = p->fact64_built = false;
         p->fact_pending = false;
     } else {
         if (p->tab32_ok)
@@ -892,6 +908,13 @@ static bool uses_factored(const sc_prob *p, sc_precision prec)
     return false;
 }
 
+// The same for the factored layout with the charge tied to the current.
+static bool uses_tied(const sc_prob *p, sc_precision prec)
+{
+    if (!uses_factored(p, prec) || !p->allow_tie) return false;
+    return prec == SC_FP64 ? p->tie64_ok : p->tie_ok;
+}
+
 // Frequencies per lane by table layout: with the factored current a frequency costs 37 vector
 // instructions against the 30 of the geometry it shares, so four per lane (at five waves per SIMD)
 // beat two; the general tables' longer per-frequency work does not pay for the registers.
@@ -899,8 +922,8 @@ static int auto_freq_per_lane(sc_precision prec, bool fact) { return prec != SC_
 
 static TuneKey tune_key(const sc_prob *p, sc_precision prec)
 {
-    return {(int)prec, uses_factored(p, prec) ? 1 : 0, log2_bucket(p->n_obs), log2_bucket((int64_t)p->k.size()),
-            log2_bucket(p->n_tot)};
+    return {(int)prec, uses_tied(p, prec) ? 2 : uses_factored(p, prec) ? 1 : 0, log2_bucket(p->n_obs),
+            log2_bucket((int64_t)p->k.size()), log2_bucket(p->n_tot)};
 }
 
 sc_status sc::check_launch(const sc_launch &l)
@@ -1043,6 +1066,8 @@ static void fill_job(const sc_prob *p, sc_precision prec, const sc_launch &l, co
     job.tab = tab;
     job.pos = prec == SC_FP64 ? (fact ? p->posf64.p : p->pos64.p) : (fact ? p->posf.p : p->pos32.p);
     job.factored = fact ? 1 : 0;
+    job.tied = fact && p->allow_tie && (prec == SC_FP64 ? p->tie64_ok : p->tie_ok) ? 1 : 0;
+    job.beta = job.tied ? (prec == SC_FP64 ? p->betaf64.p : p->betaf.p) : nullptr;
     // |delta| = ||R| - |r_s|| <= |r'|, so the split phase k delta stays below k_max |r'|_max; the
     // hardware sin / cos take up to 256 turns directly (kept below 250 for the FP32 rounding of k delta)
     {
@@ -1109,8 +1134,8 @@ size_t sc::footprint_bytes(int n_r, int n_phi, int n_k, int n_obs, int n_t, sc_p
     b += (size_t)n_k * n_tot * sizeof(double) * 8;
     if (prec != SC_FP64) b += (size_t)n_k * n_tot * sizeof(float) * 8;                      // FP32 tables
     if (prec == SC_FP32_SPLIT)                                                               // factored tables
-        b += (size_t)n_k * n_tot * sizeof(float) * 4 + n_tot * sizeof(float) * 8;
-    if (prec == SC_FP64) b += (size_t)n_k * n_tot * sizeof(double) * 4 + n_tot * sizeof(double) * 8;
+        b += (size_t)n_k * n_tot * sizeof(float) * 4 + n_tot * sizeof(float) * 9;
+    if (prec == SC_FP64) b += (size_t)n_k * n_tot * sizeof(double) * 4 + n_tot * sizeof(double) * 9;
     b += pad * (sizeof(double) + sizeof(float)) * 4;                                        // observation records
     b += sizeof(double) * (2 * (size_t)n_k + 3 * (size_t)n_obs);                             // upload staging
     b += rs * 12 * (size_t)n_k * n_obs;                                                      // results E, B
@@ -1183,7 +1208,7 @@ extern "C" sc_status sc_evaluate(sc_prob *p, sc_precision prec, void *E, void *B
     p->res_prec = -1;
     SC_TRY(run_quad(p->ctx, jobs, prec, l, p));
     HIP_TRY(launch_reduce(p->ctx->stream, mode_of(prec), p->partial.p, job.n_chunks, job.n_k, p->n_obs,
-                          p->n_obs_pad, p->d_k.as<double>(), p->resE.p, p->resB.p));
+                          p->n_obs_pad, p->d_k.as<double>(), job.tied, p->resE.p, p->resB.p));
     ev_record(p, EV_R1);
     p->ev_quad = p->ctx->profiling;
     p->res_prec = (int)prec;
@@ -1261,7 +1286,7 @@ extern "C" sc_status sc_evaluate_noalloc(sc_prob *p, sc_precision prec, void *E,
     HIP_TRY(launch_quad(st, mode_of(prec), l.obs_per_lane, l.freq_per_lane, l.waves_per_block,
                         quad_grid(p->ctx, prec, l, job.n_tiles), djob, 1, job.n_tiles, counter));
     HIP_TRY(launch_reduce(st, mode_of(prec), b + SCRATCH_PARTIAL, job.n_chunks, job.n_k, p->n_obs, p->n_obs_pad,
-                          p->d_k.as<double>(), E, B));
+                          p->d_k.as<double>(), job.tied, E, B));
     return SC_OK;
 }
 
@@ -1377,7 +1402,7 @@ extern "C" sc_status sc_evaluate_batch(sc_ctx *c, sc_prob *const *probs, int n, 
     for (int i = 0; i < n; ++i) {
         sc_prob *p = probs[i];
         HIP_TRY(launch_reduce(c->stream, mode_of(prec), p->partial.p, jobs[i].n_chunks, jobs[i].n_k, p->n_obs,
-                              p->n_obs_pad, p->d_k.as<double>(), p->resE.p, p->resB.p));
+                              p->n_obs_pad, p->d_k.as<double>(), jobs[i].tied, p->resE.p, p->resB.p));
         p->res_prec = (int)prec;
         p->last_evals = (int64_t)p->n_obs * jobs[i].n_k * p->n_surf;
         p->last_tiles = jobs[i].n_tiles;
@@ -1581,8 +1606,8 @@ extern "C" sc_status sc_get_timing(const sc_prob *p, sc_timing *out)
 static std::vector<DevBuf *> prob_buffers(sc_prob *p)
 {
     return {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->hinv64, &p->hinv32, &p->nrm, &p->wgt,
-            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->tabf, &p->posf, &p->tabf64, &p->posf64,
-            &p->fact_flag, &p->d_power, &p->obs64, &p->obs32, &p->resE, &p->resB, &p->partial,
+            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->tabf, &p->posf, &p->betaf, &p->tabf64,
+            &p->posf64, &p->betaf64, &p->fact_flag, &p->d_power, &p->obs64, &p->obs32, &p->resE, &p->resB, &p->partial,
             &p->d_t, &p->tw, &p->timeE, &p->timeB, &p->d_spec, &p->d_obs_in, &p->d_modes};
 }
 

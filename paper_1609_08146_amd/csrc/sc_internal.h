@@ -53,10 +53,13 @@ hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, int n_cplx, c
 // (x, y, z, |r_s|, u, 1 / (2|r_s|)) in FP32, tabf64 / posf64 the same in FP64 (each output may be
 // NULL);
 // *bad (zeroed by the caller) gets bit 0 when some node's current has no single real direction
-// within tol32 (relative to its largest |Jt| over k), bit 1 for tol64.
-hipError_t launch_tables_factor(hipStream_t st, int n_k, int n_tot, const double *tab64, const float *pos32,
-                                const double *pos64, double tol32, double tol64, float *tabf, float *posf,
-                                double *tabf64, double *posf64, unsigned int *bad);
+// within tol32 (relative to its largest |Jt| over k), bit 1 for tol64; bits 2 and 3 when some
+// node's charge is not tied to its current (rho_t = -i beta s / k, beta real) within tol32, tol64
+// (relative to its largest (|rho_t|^2 + |Jt / k|^2)^1/2).
+hipError_t launch_tables_factor(hipStream_t st, int n_k, int n_tot, const double *k, const double *tab64,
+                                const float *pos32, const double *pos64, double tol32, double tol64, float *tabf,
+                                float *posf, float *betaf, double *tabf64, double *posf64, double *betaf64,
+                                unsigned int *bad);
 // Maxwell-residual diagnostics (sc_diag.hip).  Stencil results [rows][13 n_pts][3] complex (double
 // if is_f64, else float); work holds diag_slots() doubles per (row, point), mx 4 per row, out 1 per
 // (row, point).  The time form reads [n_t * 5][13 n_pts][3] (times t_m + (j - 2) dt).
@@ -72,7 +75,7 @@ hipError_t launch_energy(hipStream_t st, int is_f64, int n_t, int n_obs, const v
 hipError_t launch_quad(hipStream_t st, int mode, int obs_per_lane, int freq_per_lane, int waves_per_block,
                        int grid, const QuadJob *jobs, int n_jobs, int64_t n_tiles, unsigned int *counter);
 hipError_t launch_reduce(hipStream_t st, int mode, const void *partial, int n_chunks, int n_k, int n_obs,
-                         int n_obs_pad, const double *k, void *E, void *B);
+                         int n_obs_pad, const double *k, int b_over_k, void *E, void *B);
 hipError_t launch_twiddles(hipStream_t st, int n_k, const double *k, int n_t, const double *t, double dk,
                            double *tw);
 hipError_t launch_time(hipStream_t st, int is_f64, int n_k, int n_t, int64_t n_x, const double *tw,

@@ -7,7 +7,8 @@
 //                        azimuthally polarised Gaussian (Sec. III-A, IV-A)
 //  k_tables_cast         FP64 tables -> FP32 (split: as is; naive: node phase removed)
 //  k_tables_factor       FP64 tables -> factored FP32 / FP64 tables J~ = u s, when the current
-//                        of every node keeps one real direction over the frequencies
+//                        of every node keeps one real direction over the frequencies, and
+//                        the real beta of the charge tied to it, rho_t = -i beta s / k
 //  k_power_*             incident power per frequency through the aperture (Sec. III-B)
 //  k_tables_scale        spectral amplitude / phase applied to the tables (Sec. III-B)
 //  k_reduce<MODE>        deterministic split-K reduction into E, B
@@ -506,20 +507,31 @@ __global__ void k_tables_cast(int n_k, int n_tot, const double *__restrict__ kv,
 // spectrum, or a radially or azimuthally polarised beam): then
 // Jt[k][q] = u_q s[k][q] and the quadrature can use u_q and s.  One thread per
 // node q: u_q is the unit vector along the longer of Re Jt, Im Jt at the
-// frequency where |Jt[k][q]| is largest (u_q = 0 if Jt vanishes), s = u_q . Jt.
-// Bit 0 of *bad is set if |Jt[k][q] - u_q s[k][q]| > tol32 max_k |Jt[k][q]|
-// for any node and k, bit 1 if it exceeds tol64; the tables of a precision
-// must not be used when its bit is set.  Outputs, each optional (NULL skips
-// it): FP32 tabf[k][q] = (s, rho_t) and posf[q] = (x, y, z, |r_s|, u_q, 1 / (2|r_s|));
-// FP64 tabf64[k][q] and posf64[q], the same records in double.
-__global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ tab64, const float *__restrict__ pos32,
-                                const double *__restrict__ pos64, double tol32, double tol64,
-                                float *__restrict__ tabf, float *__restrict__ posf, double *__restrict__ tabf64,
-                                double *__restrict__ posf64, unsigned int *__restrict__ bad)
+// frequency kb where |Jt[k][q]| is largest (u_q = 0 if Jt vanishes), s = u_q . Jt.
+// Often the charge is tied to that current as well: when E and B of the beam
+// share one complex amplitude, n . E and n x B carry the same s, and with
+// rho_t = (2W / 4 pi) (n . E) P against Jt = i k (2W / 4 pi) (n x B) P,
+//   rho_t[k][q] = -i beta_q s[k][q] / k   with beta_q real,
+// beta_q = k (Re rho_t Im s - Im rho_t Re s) / |s|^2 at kb.  A node without current
+// (the rim, whose line term is a charge only) takes u_q = 0, beta_q = 1 and
+// s = i k rho_t, which ties its charge exactly and leaves Jt = u s = 0.
+// Bit 0 of *bad is set if |Jt[k][q] - u_q s[k][q]| > tol32 max_k |Jt[k][q]| for any
+// node and k, bit 1 if it exceeds tol64; bits 2 and 3 the same for
+// |rho_t[k][q] + i beta_q s[k][q] / k| against max_k (|rho_t[k][q]|^2 + |Jt[k][q] / k|^2)^1/2,
+// the node's scale of the charge term (a charge that vanishes but for rounding, as
+// n . E of the azimuthally polarised beam does, is tied with beta = 0).  The tables of a
+// precision must not be used when its bit is set.  Outputs, each optional (NULL
+// skips it): FP32 tabf[k][q] = (s, rho_t), posf[q] = (x, y, z, |r_s|, u_q, 1 / (2|r_s|))
+// and betaf[q] = beta_q; FP64 tabf64, posf64 and betaf64, the same in double.
+__global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ kv, const double *__restrict__ tab64,
+                                const float *__restrict__ pos32, const double *__restrict__ pos64, double tol32,
+                                double tol64, float *__restrict__ tabf, float *__restrict__ posf,
+                                float *__restrict__ betaf, double *__restrict__ tabf64, double *__restrict__ posf64,
+                                double *__restrict__ betaf64, unsigned int *__restrict__ bad)
 {
     const int64_t gq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gq >= n_tot) return;
-    double best = 0.0;
+    double best = 0.0, bestr = 0.0;
     int kb = 0;
     for (int kk = 0; kk < n_k; ++kk) {
         const double *v = tab64 + ((int64_t)kk * n_tot + gq) * 8;
@@ -529,8 +541,11 @@ __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ t
             best = m;
             kb = kk;
         }
+        const double k = kv[kk];
+        bestr = fmax(bestr, v[6] * v[6] + v[7] * v[7] + m / (k * k));
     }
     double u[3] = {0.0, 0.0, 0.0};
+    double beta = 1.0;
     if (best > 0.0) {
         const double *v = tab64 + ((int64_t)kb * n_tot + gq) * 8;
         const double re2 = v[0] * v[0] + v[2] * v[2] + v[4] * v[4];
@@ -538,14 +553,26 @@ __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ t
         const int part = re2 >= im2 ? 0 : 1;
         const double inv = 1.0 / sqrt(part ? im2 : re2);
         for (int c = 0; c < 3; ++c) u[c] = v[2 * c + part] * inv;
+        const double sr = u[0] * v[0] + u[1] * v[2] + u[2] * v[4];
+        const double si = u[0] * v[1] + u[1] * v[3] + u[2] * v[5];
+        const double s2 = sr * sr + si * si;
+        beta = s2 > 0.0 ? kv[kb] * (v[6] * si - v[7] * sr) / s2 : 0.0;
     }
     const double lim32 = tol32 * tol32 * best, lim64 = tol64 * tol64 * best;
+    const double rlim32 = tol32 * tol32 * bestr, rlim64 = tol64 * tol64 * bestr;
     unsigned int flags = 0;
     for (int kk = 0; kk < n_k; ++kk) {
         const int64_t rec = (int64_t)kk * n_tot + gq;
         const double *v = tab64 + rec * 8;
-        const double sr = u[0] * v[0] + u[1] * v[2] + u[2] * v[4];
-        const double si = u[0] * v[1] + u[1] * v[3] + u[2] * v[5];
+        const double k = kv[kk];
+        double sr, si;
+        if (best > 0.0) {
+            sr = u[0] * v[0] + u[1] * v[2] + u[2] * v[4];
+            si = u[0] * v[1] + u[1] * v[3] + u[2] * v[5];
+        } else {   // s = i k rho_t
+            sr = -k * v[7];
+            si = k * v[6];
+        }
         double r2 = 0.0;
         for (int c = 0; c < 3; ++c) {
             const double dr = v[2 * c] - u[c] * sr, di = v[2 * c + 1] - u[c] * si;
@@ -553,6 +580,11 @@ __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ t
         }
         if (!(r2 <= lim32)) flags |= 1u;
         if (!(r2 <= lim64)) flags |= 2u;
+        // rho_t + i beta s / k
+        const double tr = v[6] - beta * si / k, ti = v[7] + beta * sr / k;
+        const double t2 = tr * tr + ti * ti;
+        if (!(t2 <= rlim32)) flags |= 4u;
+        if (!(t2 <= rlim64)) flags |= 8u;
         if (tabf) {
             float *t = tabf + rec * 4;
             t[0] = (float)sr;
@@ -573,20 +605,23 @@ __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ t
         for (int c = 0; c < 4; ++c) pr[c] = pos32[gq * 4 + c];
         for (int c = 0; c < 3; ++c) pr[4 + c] = (float)u[c];
         pr[7] = pos64[gq * 4 + 3] > 0.0 ? (float)(0.5 / pos64[gq * 4 + 3]) : 0.0f;   // 1 / (2 |r_s|)
+        betaf[gq] = (float)beta;
     }
     if (posf64) {
         double *pr = posf64 + gq * 8;
         for (int c = 0; c < 4; ++c) pr[c] = pos64[gq * 4 + c];
         for (int c = 0; c < 3; ++c) pr[4 + c] = u[c];
         pr[7] = pos64[gq * 4 + 3] > 0.0 ? 0.5 / pos64[gq * 4 + 3] : 0.0;   // 1 / (2 |r_s|)
+        betaf64[gq] = beta;
     }
     if (flags) atomicOr(bad, flags);
 }
 
-// Split-K reduction: E[k][o][c] = sum over chunks (in FP64, fixed order); B gets the 1/(ik) factor.
+// Split-K reduction: E[k][o][c] = sum over chunks (in FP64, fixed order); B gets the 1/(ik) factor,
+// or 1/i where the quadrature's B sums already carry 1/k (b_over_k).
 template <typename PT, typename OT>
 __global__ void k_reduce(const PT *__restrict__ partial, int n_chunks, int n_k, int n_obs, int n_obs_pad,
-                         const double *__restrict__ kv, OT *__restrict__ E, OT *__restrict__ B)
+                         const double *__restrict__ kv, int b_over_k, OT *__restrict__ E, OT *__restrict__ B)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n_k * n_obs) return;
@@ -599,7 +634,7 @@ __global__ void k_reduce(const PT *__restrict__ partial, int n_chunks, int n_k, 
         const PT *p = partial + ((size_t)ch * n_k + kk) * 12 * (size_t)n_obs_pad + (size_t)(o >> 6) * 768 + (o & 63);
         for (int c = 0; c < 12; ++c) acc[c] += (double)p[c * 64];
     }
-    const double ik_inv = 1.0 / kv[kk];   // 1/(ik) = -i/k
+    const double ik_inv = b_over_k ? 1.0 : 1.0 / kv[kk];   // 1/(ik) = -i/k
     OT *e = E + idx * 6, *b = B + idx * 6;
     for (int c = 0; c < 3; ++c) {
         e[2 * c] = (OT)acc[2 * c];
@@ -758,12 +793,13 @@ hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, int n_cplx, c
     return hipGetLastError();
 }
 
-hipError_t launch_tables_factor(hipStream_t st, int n_k, int n_tot, const double *tab64, const float *pos32,
-                                const double *pos64, double tol32, double tol64, float *tabf, float *posf,
-                                double *tabf64, double *posf64, unsigned int *bad)
+hipError_t launch_tables_factor(hipStream_t st, int n_k, int n_tot, const double *k, const double *tab64,
+                                const float *pos32, const double *pos64, double tol32, double tol64, float *tabf,
+                                float *posf, float *betaf, double *tabf64, double *posf64, double *betaf64,
+                                unsigned int *bad)
 {
-    hipLaunchKernelGGL(k_tables_factor, dim3(nblocks(n_tot, 256)), dim3(256), 0, st, n_k, n_tot, tab64, pos32, pos64,
-                       tol32, tol64, tabf, posf, tabf64, posf64, bad);
+    hipLaunchKernelGGL(k_tables_factor, dim3(nblocks(n_tot, 256)), dim3(256), 0, st, n_k, n_tot, k, tab64, pos32,
+                       pos64, tol32, tol64, tabf, posf, betaf, tabf64, posf64, betaf64, bad);
     return hipGetLastError();
 }
 
@@ -776,15 +812,15 @@ hipError_t launch_tables_cast(hipStream_t st, int n_k, int n_tot, const double *
 }
 
 hipError_t launch_reduce(hipStream_t st, int mode, const void *partial, int n_chunks, int n_k, int n_obs,
-                         int n_obs_pad, const double *k, void *E, void *B)
+                         int n_obs_pad, const double *k, int b_over_k, void *E, void *B)
 {
     const unsigned int nb = nblocks((int64_t)n_k * n_obs, 256);
     if (mode == MODE_FP64)
         hipLaunchKernelGGL((k_reduce<double, double>), dim3(nb), dim3(256), 0, st, (const double *)partial, n_chunks,
-                           n_k, n_obs, n_obs_pad, k, (double *)E, (double *)B);
+                           n_k, n_obs, n_obs_pad, k, b_over_k, (double *)E, (double *)B);
     else
         hipLaunchKernelGGL((k_reduce<float, float>), dim3(nb), dim3(256), 0, st, (const float *)partial, n_chunks,
-                           n_k, n_obs, n_obs_pad, k, (float *)E, (float *)B);
+                           n_k, n_obs, n_obs_pad, k, b_over_k, (float *)E, (float *)B);
     return hipGetLastError();
 }
 

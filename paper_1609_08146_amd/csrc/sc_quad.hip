@@ -5,7 +5,9 @@
 //   MODE_SPLIT  per-pair FP32 with the node phase folded into the tables;
 //               per job either general tables or the factored current
 //               J~ = u s (a real direction u per node, a complex s per
-//               frequency and node), which needs fewer operations per pair
+//               frequency and node), which needs fewer operations per pair,
+//               and fewer still when the charge is tied to it as
+//               rho_t = -i beta s / k (a real beta per node)
 //   MODE_FP64   the same split form in FP64, on either table layout
 //   MODE_NAIVE  the whole phase k|R| per pair in FP32 (the precision ablation)
 //
@@ -24,7 +26,9 @@ namespace sc {
 // Constant-address-space views: uniform loads through them become scalar
 // (SMEM) loads into SGPRs, so node data costs no VGPRs and no LDS traffic.
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(4))) const v4f cv4f;
+typedef __attribute__((address_space(4))) const v2f cv2f;
 typedef __attribute__((address_space(4))) const double cdouble;
 typedef __attribute__((address_space(4))) const float cfloat;
 typedef __attribute__((address_space(4))) const QuadJob cjob;
@@ -183,6 +187,42 @@ __device__ __forceinline__ void freq_factored(float rinv, float delta, float vx,
     acc[9] = __fmaf_rn(wy, ami, acc[9]);
     acc[10] = __fmaf_rn(wz, amr, acc[10]);
     acc[11] = __fmaf_rn(wz, ami, acc[11]);
+}
+
+// Factored current with the charge tied to it, one frequency.  When moreover
+// rho_t = -i beta s / k with a real beta per node (the charge of the beams
+// whose E and B share one complex amplitude: n . E and n x B then carry the
+// same s, and rho_t = (2W / 4 pi) n.E P against Jt = i k (2W / 4 pi) (n x B) P),
+// then with A = s Z and m = ik - 1/R,
+//   rho_t ht R = (rho_t Z m) e = beta e (-i A m / k),   (Jt ht) x R = k (A m / k) w,
+// and A m / k = A (i - q) with q = 1 / (k R): no product rho_t Z, no product
+// with m of its own, and the factor k of the B term is left to the reduction.
+// e carries beta (e = beta R / R^2, formed once per node and point); t = s as (re, im); kinv = 1/k.
+template <bool RAW>
+__device__ __forceinline__ void freq_tied(float rinv, float delta, float vx, float vy, float vz, float ex, float ey,
+                                          float ez, float wx, float wy, float wz, const v2f t, float kinv, float kt,
+                                          float *acc)
+{
+    float c, sn;
+    sincos_turns<RAW>(kt * delta, sn, c);
+    const float ar = __fmaf_rn(t.x, c, -(t.y * sn)), ai = __fmaf_rn(t.x, sn, t.y * c);
+    const float q = rinv * kinv;
+    // M = A m / k = (-q ar - ai) + i (ar - q ai);  -i M = M.im - i M.re
+    const float mr = __fmaf_rn(-q, ar, -ai), mi = __fmaf_rn(-q, ai, ar);
+    // E += v A + e (-i M)
+    acc[0] = __fmaf_rn(mi, ex, __fmaf_rn(vx, ar, acc[0]));
+    acc[1] = __fmaf_rn(-mr, ex, __fmaf_rn(vx, ai, acc[1]));
+    acc[2] = __fmaf_rn(mi, ey, __fmaf_rn(vy, ar, acc[2]));
+    acc[3] = __fmaf_rn(-mr, ey, __fmaf_rn(vy, ai, acc[3]));
+    acc[4] = __fmaf_rn(mi, ez, __fmaf_rn(vz, ar, acc[4]));
+    acc[5] = __fmaf_rn(-mr, ez, __fmaf_rn(vz, ai, acc[5]));
+    // B += M w   (B before 1/i)
+    acc[6] = __fmaf_rn(wx, mr, acc[6]);
+    acc[7] = __fmaf_rn(wx, mi, acc[7]);
+    acc[8] = __fmaf_rn(wy, mr, acc[8]);
+    acc[9] = __fmaf_rn(wy, mi, acc[9]);
+    acc[10] = __fmaf_rn(wz, mr, acc[10]);
+    acc[11] = __fmaf_rn(wz, mi, acc[11]);
 }
 
 // Naive FP32 form, one frequency: the whole phase k |R| in FP32 (the table carries no node phase).
@@ -352,25 +392,49 @@ __device__ __forceinline__ void freq_f64_factored(double rinv, double delta, con
     }
 }
 
+// The tied charge in FP64, one frequency: the algebra of freq_tied (M = A m / k = A (i - q),
+// q = 1 / (k R); E += v A + e (-i M) with e = beta R / R^2, B += M w).
+__device__ __forceinline__ void freq_f64_tied(double rinv, double delta, const double *v, const double *e,
+                                              const double *w, const double *t, double kinv, double kt,
+                                              const double2 *ttab, double *acc)
+{
+    double sn, c;
+    sincos_turns_f64(kt * delta, ttab, sn, c);
+    const double ar = __fma_rn(t[0], c, -(t[1] * sn)), ai = __fma_rn(t[0], sn, t[1] * c);
+    const double q = rinv * kinv;
+    const double mr = __fma_rn(-q, ar, -ai), mi = __fma_rn(-q, ai, ar);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        acc[2 * d] = __fma_rn(mi, e[d], __fma_rn(v[d], ar, acc[2 * d]));
+        acc[2 * d + 1] = __fma_rn(-mr, e[d], __fma_rn(v[d], ai, acc[2 * d + 1]));
+        acc[6 + 2 * d] = __fma_rn(w[d], mr, acc[6 + 2 * d]);
+        acc[7 + 2 * d] = __fma_rn(w[d], mi, acc[7 + 2 * d]);
+    }
+}
+
 // One tile of the FP64 form: nodes [n0, n1) of a chunk, 64*OPL points, FPB
 // frequencies.  General layout: node records (x, y, z, |r_s|) and table
 // records (Jt.x, Jt.y, Jt.z, rho_t) as (re, im) pairs, 4 and 8 doubles;
 // factored (FACT): node records (x, y, z, |r_s|, u, 1 / (2|r_s|)) and table
-// records (s, rho_t), 8 and 4 doubles.  Plain FP64 sums.
-template <int OPL, int FPB, bool FACT, bool SER = false>
+// records (s, rho_t), 8 and 4 doubles; with the tied charge (TIE) only s of a
+// table record is read, and beta from the job's per-node array.  Plain FP64 sums.
+template <int OPL, int FPB, bool FACT, bool SER = false, bool TIE = false>
 __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
                                          const double *k64, int n_valid, const double2 *ttab)
 {
+    static_assert(!TIE || FACT, "the tied charge needs the factored layout");
+    constexpr int TL = TIE ? 2 : (FACT ? 4 : 8);   // doubles of a table record that are read
     constexpr int PS = FACT ? 8 : 4;   // doubles per node record
     constexpr int TS = FACT ? 4 : 8;   // doubles per table record
     const int n_tot = job->n_tot, n_k = job->n_k, n_obs_pad = job->n_obs_pad;
     cdouble *pos = (cdouble *)job->pos;
     cdouble *tab[FPB];
-    double kt64[FPB];   // wavenumbers in turns per unit length
+    double kt64[FPB], kinv64[FPB];   // wavenumbers in turns per unit length, 1 / k
 #pragma unroll
     for (int f = 0; f < FPB; ++f) {
         tab[f] = (cdouble *)job->tab + (size_t)kidx[f] * n_tot * TS;
         kt64[f] = k64[f] * INV_TWO_PI;
+        kinv64[f] = 1.0 / k64[f];
     }
     const double4 *obs = (const double4 *)job->obs;
     double4 o[OPL];
@@ -384,9 +448,11 @@ __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0,
             for (int c = 0; c < 12; ++c) acc[s][f][c] = 0.0;
     }
     for (int n = n0; n < n1; ++n) {
-        double pn[PS], tn[FPB][TS];
+        double pn[PS], tn[FPB][TL];
 #pragma unroll
         for (int c = 0; c < PS; ++c) pn[c] = pos[PS * (size_t)n + c];
+        double bn = 0.0;
+        if constexpr (TIE) bn = ((cdouble *)job->beta)[n];
         // h = 1 / (2|r_s|): last entry of the factored node record, else the per-node array
         double hn = 0.0;
         if constexpr (SER && FACT) hn = pn[PS - 1];
@@ -394,7 +460,7 @@ __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0,
 #pragma unroll
         for (int f = 0; f < FPB; ++f)
 #pragma unroll
-            for (int c = 0; c < TS; ++c) tn[f][c] = tab[f][TS * (size_t)n + c];
+            for (int c = 0; c < TL; ++c) tn[f][c] = tab[f][TS * (size_t)n + c];
 #pragma unroll
         for (int s = 0; s < OPL; ++s) {
             GeomD g;
@@ -407,9 +473,16 @@ __device__ __forceinline__ void tile_f64(cjob *job, int lane, int chunk, int n0,
                 const double e[3] = {g.dx * r2, g.dy * r2, g.dz * r2};
                 const double w[3] = {__fma_rn(pn[5], e[2], -(pn[6] * e[1])), __fma_rn(pn[6], e[0], -(pn[4] * e[2])),
                                      __fma_rn(pn[4], e[1], -(pn[5] * e[0]))};
+                if constexpr (TIE) {
+                    const double eb[3] = {e[0] * bn, e[1] * bn, e[2] * bn};
 #pragma unroll
-                for (int f = 0; f < FPB; ++f)
-                    freq_f64_factored(g.rinv, g.delta, v, e, w, tn[f], k64[f], kt64[f], ttab, acc[s][f]);
+                    for (int f = 0; f < FPB; ++f)
+                        freq_f64_tied(g.rinv, g.delta, v, eb, w, tn[f], kinv64[f], kt64[f], ttab, acc[s][f]);
+                } else {
+#pragma unroll
+                    for (int f = 0; f < FPB; ++f)
+                        freq_f64_factored(g.rinv, g.delta, v, e, w, tn[f], k64[f], kt64[f], ttab, acc[s][f]);
+                }
             } else {
 #pragma unroll
                 for (int f = 0; f < FPB; ++f) freq_f64(g, tn[f], k64[f], kt64[f], ttab, acc[s][f]);
@@ -452,6 +525,8 @@ constexpr int SUM_BLOCK = 512;
 // frequencies.  FACT selects the factored layout: node records of two v4f
 // (x, y, z, |r_s|), (u, 1 / (2|r_s|)) and one v4f (s, rho_t) per table record, instead of
 // one v4f node record and two v4f (Jt.x, Jt.y), (Jt.z, rho_t) per table record.
+// TIE (factored only) takes the charge tied to the current (freq_tied): of
+// each table record only s is read, and beta from the job's per-node array.
 // RAW passes the split phase k delta / 2 pi to the hardware sin / cos without
 // taking its fractional part (the job guarantees it stays below 250 turns).
 // SER forms delta by its series (geom_series) from h = 1 / (2|r_s|), in the
@@ -466,16 +541,17 @@ constexpr int SUM_BLOCK = 512;
 // frequencies at five waves per SIMD.  The slices in use (12 KB per wave at
 // four frequencies) outgrow an XCD's L2, so the load-add-store goes to memory:
 // traffic, but no time, since the tile is bound by its VALU issue.
-template <int MODE, int OPL, int FPB, bool FACT, bool RAW, bool SER = false>
+template <int MODE, int OPL, int FPB, bool FACT, bool RAW, bool SER = false, bool TIE = false>
 __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
                                          const double *k64, int n_valid)
 {
+    static_assert(!TIE || FACT, "the tied charge needs the factored layout");
     constexpr int PS = FACT ? 2 : 1;   // v4f per node record
     constexpr int TS = FACT ? 1 : 2;   // v4f per table record
     const int n_tot = job->n_tot, n_k = job->n_k, n_obs_pad = job->n_obs_pad;
     cv4f *pos = (cv4f *)job->pos;
     cv4f *tab[FPB];
-    float k[FPB], kt[FPB];
+    float k[FPB], kt[FPB], kinv[FPB];
     float *part[FPB];
     const int ob64 = (obase - lane) >> 6;   // the tile's first block of 64 points
 #pragma unroll
@@ -483,6 +559,7 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
         tab[f] = (cv4f *)job->tab + (size_t)kidx[f] * n_tot * TS;
         k[f] = (float)k64[f];
         kt[f] = (float)(k64[f] * INV_TWO_PI);
+        kinv[f] = (float)(1.0 / k64[f]);
         // partials [chunk][k][point / 64][12][64]: the tile's [12][64 * OPL] slice is contiguous
         part[f] = (float *)job->partial + ((size_t)chunk * n_k + kidx[f]) * 12 * (size_t)n_obs_pad +
                   (size_t)ob64 * 768;
@@ -493,6 +570,7 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
     for (int s = 0; s < OPL; ++s) o[s] = obs[obase + 64 * s];
     constexpr bool HV = SER && !FACT;   // h from the per-node array
     cfloat *hv = (cfloat *)job->hinv;
+    cfloat *bv = (cfloat *)job->beta;
     for (int b0 = n0; b0 < n1; b0 += SUM_BLOCK) {
         const int b1 = min(b0 + SUM_BLOCK, n1);
         float blk[OPL][FPB][12];
@@ -506,12 +584,15 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
             const v4f pn = pos[PS * n];
             v4f un = {0.0f, 0.0f, 0.0f, 0.0f};
             if constexpr (FACT) un = pos[PS * n + 1];
-            float hn = 0.0f;
+            float hn = 0.0f, bn = 0.0f;
             if constexpr (HV) hn = hv[n];
+            if constexpr (TIE) bn = bv[n];
             v4f t0[FPB], t1[FPB];
+            v2f ts[FPB];
 #pragma unroll
             for (int f = 0; f < FPB; ++f) {
-                t0[f] = tab[f][TS * n];
+                if constexpr (TIE) ts[f] = ((cv2f *)tab[f])[2 * n];
+                else t0[f] = tab[f][TS * n];
                 if constexpr (!FACT) t1[f] = tab[f][TS * n + 1];
             }
 #pragma unroll
@@ -525,10 +606,18 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
                     const float wx = __fmaf_rn(un.y, ez, -(un.z * ey));
                     const float wy = __fmaf_rn(un.z, ex, -(un.x * ez));
                     const float wz = __fmaf_rn(un.x, ey, -(un.y * ex));
+                    if constexpr (TIE) {
+                        const float bx = ex * bn, by = ey * bn, bz = ez * bn;
 #pragma unroll
-                    for (int f = 0; f < FPB; ++f)
-                        freq_factored<RAW>(g.rinv, g.delta, vx, vy, vz, ex, ey, ez, wx, wy, wz, t0[f], k[f], kt[f],
+                        for (int f = 0; f < FPB; ++f)
+                            freq_tied<RAW>(g.rinv, g.delta, vx, vy, vz, bx, by, bz, wx, wy, wz, ts[f], kinv[f], kt[f],
                                            blk[s][f]);
+                    } else {
+#pragma unroll
+                        for (int f = 0; f < FPB; ++f)
+                            freq_factored<RAW>(g.rinv, g.delta, vx, vy, vz, ex, ey, ez, wx, wy, wz, t0[f], k[f],
+                                               kt[f], blk[s][f]);
+                    }
                 } else if constexpr (MODE == MODE_SPLIT) {
                     const GeomF g = SER ? geom_series(pn, o[s], hn) : geom_split(pn, o[s]);
 #pragma unroll
@@ -626,7 +715,11 @@ k_quad(const QuadJob *__restrict__ jobs_, int n_jobs, int64_t n_tiles,
 
         if constexpr (MODE == MODE_FP64) {
             const bool ser = jobs[j].series_delta != 0;
-            if (jobs[j].factored && ser)
+            if (jobs[j].tied && ser)
+                tile_f64<OPL, FPB, true, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid, ttab);
+            else if (jobs[j].tied)
+                tile_f64<OPL, FPB, true, false, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid, ttab);
+            else if (jobs[j].factored && ser)
                 tile_f64<OPL, FPB, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid, ttab);
             else if (jobs[j].factored)
                 tile_f64<OPL, FPB, true, false>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid, ttab);
@@ -637,7 +730,21 @@ k_quad(const QuadJob *__restrict__ jobs_, int n_jobs, int64_t n_tiles,
         } else if constexpr (MODE == MODE_SPLIT) {
             // per job (not per tile), so the bits of a point do not depend on the launch shape
             const bool raw = jobs[j].raw_phase != 0;
-            if (jobs[j].factored) {
+            if (jobs[j].tied) {
+                const bool ser = jobs[j].series_delta != 0;
+                if (raw && ser)
+                    tile_f32<MODE, OPL, FPB, true, true, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64,
+                                                                     n_valid);
+                else if (raw)
+                    tile_f32<MODE, OPL, FPB, true, true, false, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64,
+                                                                      n_valid);
+                else if (ser)
+                    tile_f32<MODE, OPL, FPB, true, false, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64,
+                                                                      n_valid);
+                else
+                    tile_f32<MODE, OPL, FPB, true, false, false, true>(jobs + j, lane, chunk, n0, n1, obase, kidx,
+                                                                       k64, n_valid);
+            } else if (jobs[j].factored) {
                 const bool ser = jobs[j].series_delta != 0;
                 if (raw && ser)
                     tile_f32<MODE, OPL, FPB, true, true, true>(jobs + j, lane, chunk, n0, n1, obase, kidx, k64, n_valid);

@@ -15,6 +15,7 @@ struct QuadJob {
     const void *pos;      // [n_tot][4] real; factored: [n_tot][8] real
     const void *obs;      // [n_obs_pad][4] real
     const void *hinv;     // [n_tot] 1 / (2|r_s|) real (general layout, series_delta)
+    const void *beta;     // [n_tot] real (factored layout with the tied charge): rho_t = -i beta s / k
     const double *k;      // [n_k]
     void *partial;        // [n_chunks][n_k][n_obs_pad / 64][12][64] real
     int n_tot;            // surface + rim nodes
@@ -24,6 +25,8 @@ struct QuadJob {
     int n_chunks;
     int obs_blocks;       // n_obs_pad / (64 * obs_per_lane)
     int factored;         // split form (FP32 or FP64) with the current factored as J~ = u s (u real, per node)
+    int tied;             // factored, and the charge tied to the current: rho_t = -i beta s / k (beta real,
+                          // per node); the B sums then carry 1/k, so the reduction drops its own 1/k
     int raw_phase;        // FP32 split form: |k delta| / 2 pi < 250 turns for every pair of the job
     int series_delta;     // split forms: |r'| <= 4e-4 |r_s| for every pair (delta and 1/|R| by series)
     int64_t tile0;        // first global tile of this job in the launch

@@ -321,7 +321,7 @@ static sc_status finish_request(sc_server *s, Req *r)
     sc_prob *p = r->prob;
     const int n_k = (int)r->k.size();
     HIP_TRY(launch_reduce(st, mode_of(r->prec), p->partial.p, r->job.n_chunks, n_k, r->n_obs, p->n_obs_pad,
-                          p->d_k.as<double>(), p->resE.p, p->resB.p));
+                          p->d_k.as<double>(), r->job.tied, p->resE.p, p->resB.p));
     if (r->n_t > 0) {
         const int f64 = r->prec == SC_FP64;
         const int64_t n_x = (int64_t)r->n_obs * 3;

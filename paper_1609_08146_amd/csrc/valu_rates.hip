@@ -18,7 +18,7 @@ namespace {
 constexpr int CH = 16;          // independent chains per lane
 constexpr int BLOCKS = 4096;    // 256-thread blocks: 16 waves per SIMD on 256 CUs (two rounds of 8)
 
-enum Op { FMAC_V, FMAC_S, MUL_V, ADD_V, SIN_V, RSQ_V, FMA_F64, FMAC_UNIFORM, FMAC_SV };
+enum Op { FMAC_V, FMAC_S, MUL_V, ADD_V, SIN_V, RSQ_V, FMA_F64, FMAC_UNIFORM, FMAC_SV, MUL_F64, ADD_F64 };
 
 template <int OP>
 __global__ void __launch_bounds__(256) k_rate(float *out, int iters, float s_y)
@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(256) k_rate(float *out, int iters, float s_y)
     out[blockIdx.x * 256 + threadIdx.x] = s;
 }
 
+template <int OP>
 __global__ void __launch_bounds__(256) k_rate_f64(double *out, int iters)
 {
     const double y = 0.999 + threadIdx.x * 1e-12;
@@ -64,7 +65,11 @@ __global__ void __launch_bounds__(256) k_rate_f64(double *out, int iters)
     }
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
-        for (int c = 0; c < CH; ++c) acc[c] = __builtin_fma(x[c], y, acc[c]);
+        for (int c = 0; c < CH; ++c) {
+            if (OP == FMA_F64) acc[c] = __builtin_fma(x[c], y, acc[c]);
+            if (OP == MUL_F64) acc[c] = acc[c] * y;
+            if (OP == ADD_F64) acc[c] = acc[c] + x[c];
+        }
     }
     double s = 0.0;
 #pragma unroll
@@ -75,7 +80,8 @@ __global__ void __launch_bounds__(256) k_rate_f64(double *out, int iters)
 template <int OP>
 void launch(float *o, double *od, int iters)
 {
-    if (OP == FMA_F64) hipLaunchKernelGGL(k_rate_f64, dim3(BLOCKS), dim3(256), 0, 0, od, iters);
+    if (OP == FMA_F64 || OP == MUL_F64 || OP == ADD_F64)
+        hipLaunchKernelGGL((k_rate_f64<OP>), dim3(BLOCKS), dim3(256), 0, 0, od, iters);
     else hipLaunchKernelGGL((k_rate<OP>), dim3(BLOCKS), dim3(256), 0, 0, o, iters, 0.999f);
 }
 
@@ -117,12 +123,14 @@ int main()
     printf("{\"unit\": \"SIMD cycles per wave64 instruction at 2.4 GHz\", "
            "\"v_fmac_f32 (VGPR operands)\": %.3f, \"v_fmac_f32 (SGPR operand)\": %.3f, \"v_mul_f32\": %.3f, "
            "\"v_add_f32\": %.3f, \"v_sin_f32\": %.3f, \"v_rsq_f32 + v_add_f32\": %.3f, \"v_fma_f64\": %.3f, "
-           "\"v_fmac_f32 (lane-uniform data)\": %.3f, \"v_fmac_f32 (SGPR and VGPR operands alternating)\": %.3f}\n",
+           "\"v_fmac_f32 (lane-uniform data)\": %.3f, \"v_fmac_f32 (SGPR and VGPR operands alternating)\": %.3f, "
+           "\"v_mul_f64\": %.3f, \"v_add_f64\": %.3f}\n",
            cycles_per_instruction<FMAC_V>(o, od, it), cycles_per_instruction<FMAC_S>(o, od, it),
            cycles_per_instruction<MUL_V>(o, od, it), cycles_per_instruction<ADD_V>(o, od, it),
            cycles_per_instruction<SIN_V>(o, od, it / 4), cycles_per_instruction<RSQ_V>(o, od, it / 4),
            cycles_per_instruction<FMA_F64>(o, od, it), cycles_per_instruction<FMAC_UNIFORM>(o, od, it),
-           cycles_per_instruction<FMAC_SV>(o, od, it));
+           cycles_per_instruction<FMAC_SV>(o, od, it), cycles_per_instruction<MUL_F64>(o, od, it),
+           cycles_per_instruction<ADD_F64>(o, od, it));
     (void)hipFree(o);
     (void)hipFree(od);
     return 0;

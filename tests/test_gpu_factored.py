@@ -15,6 +15,15 @@ n x B = (1 + c/2f) (-y, x, 0) g, azimuthal whatever the longitudinal c.
 The curl-consistent linear beam does not: its B_z = -2iy/(k w0^2) psi adds
 (-y c/2f, x c/2f, 0) to n x (0, -1, 0) psi = (1, 0, x/2f) psi, a direction
 that changes with k.  Random tables have no structure either.
+
+The charge is tied to the factored current (rho_t = -i beta s / k, beta real per
+node) when n.E carries the amplitude of n x B: for every factoring beam with no
+longitudinal E.  The radially polarised curl-consistent beam has E_z = i c g,
+which turns n.E by 90 degrees against n x B, so it keeps the factored layout
+without the tie; the azimuthally polarised ones have n.E = 0 on the paraboloid
+(E = (-y, x, 0) g against n = (-x/2f, -y/2f, 1)), tied with beta = 0.  The tied
+layout computes the charge term from s, so it is held to the oracle and to the
+other two layouts at the same tolerances.
 """
 from dataclasses import replace
 
@@ -30,6 +39,14 @@ def rel_l2(a, b):
     return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
 
 
+# table layout -> sc_set_factoring arguments (enable, tie_charge)
+LAYOUTS = {"tied": (True, True), "factored": (True, False), "general": (False, True)}
+
+
+def set_layout(p, name):
+    p.set_factoring(*LAYOUTS[name])
+
+
 @pytest.fixture(scope="module")
 def ctx():
     import torch
@@ -41,10 +58,10 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("beam,consistent,w0,expect", [
-    (0, 0, 0.05, True), (0, 0, np.inf, True), (0, 1, 0.05, False),
-    (1, 0, 0.05, True), (1, 1, 0.05, True), (2, 0, 0.05, True), (2, 1, 0.05, True)])
-def test_which_fields_factor(ctx, beam, consistent, w0, expect):
+@pytest.mark.parametrize("beam,consistent,w0,layout", [
+    (0, 0, 0.05, "tied"), (0, 0, np.inf, "tied"), (0, 1, 0.05, "general"),
+    (1, 0, 0.05, "tied"), (1, 1, 0.05, "factored"), (2, 0, 0.05, "tied"), (2, 1, 0.05, "tied")])
+def test_which_fields_factor(ctx, beam, consistent, w0, layout):
     from paper_1609_08146_amd import Problem
     rng = np.random.default_rng(11)
     k = 7.854e6 * np.array([0.8, 1.0, 1.25])
@@ -54,13 +71,17 @@ def test_which_fields_factor(ctx, beam, consistent, w0, expect):
     p.set_frequencies(k)
     p.set_incident_beam(beam, w0, 0.3 if beam == 0 else 0.0, spec, bool(consistent))
     p.set_observation(np.zeros((1, 3)))
-    assert p.factored is expect
+    expect = layout != "general"
+    assert p.factored is expect and p.layout_for("fp32_split") == layout
     # the beams that factor at all do so to rounding, below the FP64 form's tolerance too
     assert p.factored_for("fp64") is expect and p.factored_for("fp32") is False
+    assert p.layout_for("fp64") == layout and p.layout_for("fp32") == "general"
     p.set_factoring(False)
     assert p.factored is False and p.factored_for("fp64") is False
+    p.set_factoring(True, tie_charge=False)
+    assert p.layout_for("fp32_split") == ("factored" if expect else "general")
     p.set_factoring(True)
-    assert p.factored is expect
+    assert p.factored is expect and p.layout_for("fp64") == layout
     p.close()
 
 
@@ -86,16 +107,17 @@ def test_factored_and_general_match_the_oracle(ctx, orc, name):
         sub = w.subset(obs_idx=np.arange(0, w.n_obs, 1023), k_idx=[0, 31, 63])
     Eo, Bo = orc.solve(sub)
     p = problem_from_workload(ctx, sub)
-    assert p.factored
-    Ef, Bf = p.evaluate("fp32_split")
-    p.set_factoring(False)
-    assert not p.factored
-    Eg, Bg = p.evaluate("fp32_split")
-    errs = dict(factored=max(rel_l2(Ef, Eo), rel_l2(Bf, Bo)), general=max(rel_l2(Eg, Eo), rel_l2(Bg, Bo)),
-                between=max(rel_l2(Ef, Eg), rel_l2(Bf, Bg)))
+    res = {}
+    for layout in LAYOUTS:
+        set_layout(p, layout)
+        assert p.layout_for("fp32_split") == layout
+        res[layout] = p.evaluate("fp32_split")
+    errs = {k: max(rel_l2(E, Eo), rel_l2(B, Bo)) for k, (E, B) in res.items()}
+    for a, b in [("tied", "general"), ("factored", "general"), ("tied", "factored")]:
+        errs[f"{a}-{b}"] = max(rel_l2(res[a][0], res[b][0]), rel_l2(res[a][1], res[b][1]))
     print(name, {k: f"{v:.2e}" for k, v in errs.items()})
-    assert errs["factored"] < 1e-5 and errs["general"] < 1e-5
-    assert errs["between"] < 2e-6
+    assert errs["tied"] < 1e-5 and errs["factored"] < 1e-5 and errs["general"] < 1e-5
+    assert errs["tied-general"] < 2e-6 and errs["factored-general"] < 2e-6 and errs["tied-factored"] < 2e-6
     p.close()
 
 
@@ -110,11 +132,13 @@ def test_factored_cylindrical_beams_match_the_oracle(ctx, orc, beam, consistent)
     Ei, Bi = orc.incident_tables(m, w.k, kind, w.w0, 0.0, w.spectrum)
     Eo, Bo = orc.reflected_field(m, w.k, Ei, Bi, w.obs)
     p = problem_from_workload(ctx, w)
-    assert p.factored
-    E, B = p.evaluate("fp32_split")
-    err = max(rel_l2(E, Eo), rel_l2(B, Bo))
-    print(f"beam {beam} consistent {consistent} factored: {err:.2e}")
-    assert err < 1e-5
+    assert p.layout_for("fp32_split") == ("factored" if (beam, consistent) == (1, 1) else "tied")
+    for layout in ("tied", "factored"):
+        set_layout(p, layout)
+        E, B = p.evaluate("fp32_split")
+        err = max(rel_l2(E, Eo), rel_l2(B, Bo))
+        print(f"beam {beam} consistent {consistent} {p.layout_for('fp32_split')}: {err:.2e}")
+        assert err < 1e-5
     p.close()
 
 
@@ -128,9 +152,9 @@ def test_factored_launch_shapes_and_batch_bitwise(ctx):
     far = np.concatenate([w.obs, [[0.0, 0.0, 400 * workloads.LAMBDA0]]])
     for obs in (w.obs, far):
         p.set_observation(obs)
-        for fact in (True, False):
-            p.set_factoring(fact)
-            assert p.factored is fact
+        for layout in LAYOUTS:
+            set_layout(p, layout)
+            assert p.layout_for("fp32_split") == layout
             ref = None
             for opl, fpb in [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4)]:
                 for wpb in (1, 4):
@@ -140,14 +164,16 @@ def test_factored_launch_shapes_and_batch_bitwise(ctx):
                         ref = (E, B)
                     else:
                         assert np.array_equal(E, ref[0]) and np.array_equal(B, ref[1]), \
-                            (len(obs), fact, opl, fpb, wpb)
+                            (len(obs), layout, opl, fpb, wpb)
     p.close()
     ws = workloads.sweep(6)
     ws = [w.with_nodes(min(w.n_r, 80), min(w.n_phi, 48)).subset(k_idx=np.arange(min(w.n_k, 3))) for w in ws]
     ws[1] = replace(ws[1], consistent=1)          # does not factor
     probs = [problem_from_workload(ctx, w) for w in ws]
     probs[2].set_factoring(False)                 # factors, but forced onto the general tables
-    assert [q.factored for q in probs] == [True, False, False, True, True, True]
+    set_layout(probs[3], "factored")              # ties, but forced onto the factored layout alone
+    assert [q.layout_for("fp32_split") for q in probs] == ["tied", "general", "general", "factored", "tied",
+                                                           "tied"]
     alone = [q.evaluate("fp32_split") for q in probs]
     ctx.evaluate_batch(probs, "fp32_split")
     for q, (E, B) in zip(probs, alone):
@@ -191,16 +217,17 @@ def test_fp64_factored_and_general_match_the_oracle(ctx, orc, name):
         sub = w.subset(obs_idx=np.arange(0, w.n_obs, 1023), k_idx=[0, 31, 63])
     Eo, Bo = orc.solve(sub)
     p = problem_from_workload(ctx, sub)
-    assert p.factored_for("fp64")
-    Ef, Bf = p.evaluate("fp64")
-    p.set_factoring(False)
-    assert not p.factored_for("fp64")
-    Eg, Bg = p.evaluate("fp64")
-    errs = dict(factored=max(rel_l2(Ef, Eo), rel_l2(Bf, Bo)), general=max(rel_l2(Eg, Eo), rel_l2(Bg, Bo)),
-                between=max(rel_l2(Ef, Eg), rel_l2(Bf, Bg)))
+    res = {}
+    for layout in LAYOUTS:
+        set_layout(p, layout)
+        assert p.layout_for("fp64") == layout
+        res[layout] = p.evaluate("fp64")
+    errs = {k: max(rel_l2(E, Eo), rel_l2(B, Bo)) for k, (E, B) in res.items()}
+    for a, b in [("tied", "general"), ("factored", "general"), ("tied", "factored")]:
+        errs[f"{a}-{b}"] = max(rel_l2(res[a][0], res[b][0]), rel_l2(res[a][1], res[b][1]))
     print(name, {k: f"{v:.2e}" for k, v in errs.items()})
-    assert errs["factored"] < 1e-12 and errs["general"] < 1e-12
-    assert errs["between"] < 1e-13
+    assert errs["tied"] < 1e-12 and errs["factored"] < 1e-12 and errs["general"] < 1e-12
+    assert errs["tied-general"] < 1e-13 and errs["factored-general"] < 1e-13 and errs["tied-factored"] < 1e-13
     p.close()
 
 
@@ -212,9 +239,9 @@ def test_fp64_factored_launch_shapes_batch_and_rescaling(ctx, orc):
     from paper_1609_08146_amd import problem_from_workload
     w = workloads.broadband(n_k=5, n_nodes=64)
     p = problem_from_workload(ctx, w)
-    for fact in (True, False):                    # both layouts take the near-focus series here
-        p.set_factoring(fact)
-        assert p.factored_for("fp64") is fact
+    for layout in LAYOUTS:                        # every layout takes the near-focus series here
+        set_layout(p, layout)
+        assert p.layout_for("fp64") == layout
         ref = None
         for opl, fpb in [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4)]:
             p.set_launch(obs_per_lane=opl, freq_per_lane=fpb, waves_per_block=2, chunk=1024)
@@ -222,14 +249,15 @@ def test_fp64_factored_launch_shapes_batch_and_rescaling(ctx, orc):
             if ref is None:
                 ref = (E, B)
             else:
-                assert np.array_equal(E, ref[0]) and np.array_equal(B, ref[1]), (fact, opl, fpb)
+                assert np.array_equal(E, ref[0]) and np.array_equal(B, ref[1]), (layout, opl, fpb)
     p.close()
 
     ws = workloads.sweep(4)
     ws = [w.with_nodes(min(w.n_r, 60), min(w.n_phi, 40)).subset(k_idx=np.arange(min(w.n_k, 2))) for w in ws]
     ws[1] = replace(ws[1], consistent=1)          # does not factor
     probs = [problem_from_workload(ctx, w) for w in ws]
-    assert [q.factored_for("fp64") for q in probs] == [True, False, True, True]
+    set_layout(probs[2], "factored")
+    assert [q.layout_for("fp64") for q in probs] == ["tied", "general", "factored", "tied"]
     alone = [q.evaluate("fp64") for q in probs]
     ctx.evaluate_batch(probs, "fp64")
     for q, (E, B) in zip(probs, alone):
@@ -305,8 +333,8 @@ def test_current_that_factors_only_at_the_split_tolerance(ctx, orc):
     p.close()
 
 
-@pytest.mark.parametrize("factored", [True, False])
-def test_delta_by_series_and_by_division(ctx, orc, factored):
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+def test_delta_by_series_and_by_division(ctx, orc, layout):
     """delta = |r_s - r'| - |r_s| comes from its series when every point lies within 4e-4 |r_s|
     (here f = 0.1 m, points within 4 wavelengths), else from the division.  One point 100
     wavelengths out switches the series off while the phase still skips the fractional turn
@@ -319,23 +347,23 @@ def test_delta_by_series_and_by_division(ctx, orc, factored):
     sub = replace(w, obs=near)
     Eo, Bo = orc.solve(sub)
     p = problem_from_workload(ctx, sub)
-    p.set_factoring(factored)
-    assert p.factored is factored
+    set_layout(p, layout)
+    assert p.layout_for("fp32_split") == layout
     Es, Bs = p.evaluate("fp32_split")
     p.set_observation(np.concatenate([near, far]))
     Ed, Bd = p.evaluate("fp32_split")
     Ed, Bd = Ed[:, : len(near)], Bd[:, : len(near)]
     errs = dict(series=max(rel_l2(Es, Eo), rel_l2(Bs, Bo)), division=max(rel_l2(Ed, Eo), rel_l2(Bd, Bo)),
                 between=max(rel_l2(Es, Ed), rel_l2(Bs, Bd)))
-    print("factored" if factored else "general", {k: f"{v:.2e}" for k, v in errs.items()})
+    print(layout, {k: f"{v:.2e}" for k, v in errs.items()})
     assert errs["series"] < 1e-5 and errs["division"] < 1e-5
     assert errs["between"] < 2e-6
     assert not np.array_equal(Es, Ed)          # the two paths really differ in rounding
     p.close()
 
 
-@pytest.mark.parametrize("factored", [True, False])
-def test_fp64_delta_by_series_and_by_division(ctx, orc, factored):
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+def test_fp64_delta_by_series_and_by_division(ctx, orc, layout):
     """The FP64 form near the focus: delta and 1/|R| by their series (host points within 4e-4 |r_s|)
     against the division and the square root (the same points handed over in device memory take
     the general forms), on either table layout.  Both within 1e-12 of the oracle and within 1e-13 of
@@ -347,14 +375,14 @@ def test_fp64_delta_by_series_and_by_division(ctx, orc, factored):
     sub = replace(w, obs=near)
     Eo, Bo = orc.solve(sub)
     p = problem_from_workload(ctx, sub)
-    p.set_factoring(factored)
-    assert p.factored_for("fp64") is factored
+    set_layout(p, layout)
+    assert p.layout_for("fp64") == layout
     Es, Bs = p.evaluate("fp64")
     p.set_observation(torch.tensor(near, dtype=torch.float64, device="cuda"))
     Ed, Bd = p.evaluate("fp64")
     errs = dict(series=max(rel_l2(Es, Eo), rel_l2(Bs, Bo)), division=max(rel_l2(Ed, Eo), rel_l2(Bd, Bo)),
                 between=max(rel_l2(Es, Ed), rel_l2(Bs, Bd)))
-    print("factored" if factored else "general", {k: f"{v:.2e}" for k, v in errs.items()})
+    print(layout, {k: f"{v:.2e}" for k, v in errs.items()})
     assert errs["series"] < 1e-12 and errs["division"] < 1e-12
     assert errs["between"] < 1e-13
     assert not np.array_equal(Es, Ed)          # the two paths really differ in rounding
