@@ -272,7 +272,7 @@ def batch_run(n_instances: int = 256, general: bool = False, tune: bool = True, 
                 "partial_bytes": partial_bytes()}
 
     # the library's batch launch: the shape of the layout carrying most evaluations, each problem's chunk
-    fact_major = 2 * fact_evals > evals
+    fact_major = 2 * (layout_evals["factored"] + layout_evals["tied"]) > evals
     lib = {"obs_per_lane": 1, "freq_per_lane": 4 if fact_major else 2, "waves_per_block": 4, "chunk": 0,
            "blocks_per_cu": 0}
     runs = [timed("library launch", lib)]

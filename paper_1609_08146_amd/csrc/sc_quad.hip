@@ -656,11 +656,17 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
 // Resident waves per SIMD the register allocation plans for.  One point x four frequencies per
 // lane in FP32 holds 48 accumulators; unconstrained, the compiler interleaves the four
 // frequencies' chains with up to ~116 VGPRs (4 waves); at 5 waves (<= 102 VGPRs) it keeps most of
-// that overlap without spilling, which measured fastest.  Other shapes: no constraint.
+// that overlap without spilling, which measured fastest.  The FP64 form at one point x two
+// frequencies takes 131 VGPRs unconstrained (3 waves) and 127 at 4 waves, without spilling: the
+// fourth wave hides more of the scalar-load latency of each node step (at 5 waves it spills).
+// Other shapes (and the naive ablation, whose library sine and cosine spill at 5 waves): no
+// constraint.
 template <int MODE, int OPL, int FPB>
 constexpr int quad_waves_per_eu()
 {
-    return MODE != MODE_FP64 && OPL == 1 && FPB == 4 ? 5 : 1;
+    if (OPL != 1) return 1;
+    if (MODE == MODE_FP64) return FPB == 2 ? 4 : 1;
+    return MODE == MODE_SPLIT && FPB == 4 ? 5 : 1;
 }
 
 template <int MODE, int OPL, int FPB>

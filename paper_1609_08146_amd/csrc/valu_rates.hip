@@ -8,7 +8,10 @@
 // Operands differ from lane to lane (as in the quadrature) except in the
 // lane-uniform variant, which shows how much of the FMA cost depends on the
 // data; the interleaved variant alternates FMAs with and without an SGPR
-// operand, as the quadrature's instruction stream does.
+// operand, as the quadrature's instruction stream does.  The first wave of
+// every block also reads the core-cycle counter and the constant-rate wall
+// clock around its loop, which gives the clock the SIMDs actually ran at, and
+// with it the cycles per instruction at that clock.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -20,8 +23,22 @@ constexpr int BLOCKS = 4096;    // 256-thread blocks: 16 waves per SIMD on 256 C
 
 enum Op { FMAC_V, FMAC_S, MUL_V, ADD_V, SIN_V, RSQ_V, FMA_F64, FMAC_UNIFORM, FMAC_SV, MUL_F64, ADD_F64 };
 
+// clk[2 b], clk[2 b + 1]: core cycles and wall-clock ticks of block b's loop (thread 0)
+__device__ __forceinline__ void clock_mark(unsigned long long *clk, bool end)
+{
+    if (threadIdx.x != 0) return;
+    const unsigned long long c = (unsigned long long)clock64(), w = (unsigned long long)wall_clock64();
+    if (!end) {
+        clk[2 * blockIdx.x] = c;
+        clk[2 * blockIdx.x + 1] = w;
+    } else {
+        clk[2 * blockIdx.x] = c - clk[2 * blockIdx.x];
+        clk[2 * blockIdx.x + 1] = w - clk[2 * blockIdx.x + 1];
+    }
+}
+
 template <int OP>
-__global__ void __launch_bounds__(256) k_rate(float *out, int iters, float s_y)
+__global__ void __launch_bounds__(256) k_rate(float *out, unsigned long long *clk, int iters, float s_y)
 {
     float lane_term = (float)threadIdx.x;
     if (OP == FMAC_UNIFORM) {   // zero in every lane, but opaque: the operands stay in VGPRs
@@ -35,6 +52,7 @@ __global__ void __launch_bounds__(256) k_rate(float *out, int iters, float s_y)
         acc[c] = (lane_term + c) * 1e-3f;
         x[c] = 1e-4f * (c + 1) + lane_term * 1e-10f;
     }
+    clock_mark(clk, false);
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
@@ -47,6 +65,7 @@ __global__ void __launch_bounds__(256) k_rate(float *out, int iters, float s_y)
             if (OP == RSQ_V) acc[c] = __builtin_amdgcn_rsqf(acc[c] + 1.0f);
         }
     }
+    clock_mark(clk, true);
     float s = 0.f;
 #pragma unroll
     for (int c = 0; c < CH; ++c) s += acc[c] + x[c];
@@ -54,7 +73,7 @@ __global__ void __launch_bounds__(256) k_rate(float *out, int iters, float s_y)
 }
 
 template <int OP>
-__global__ void __launch_bounds__(256) k_rate_f64(double *out, int iters)
+__global__ void __launch_bounds__(256) k_rate_f64(double *out, unsigned long long *clk, int iters)
 {
     const double y = 0.999 + threadIdx.x * 1e-12;
     double acc[CH], x[CH];
@@ -63,6 +82,7 @@ __global__ void __launch_bounds__(256) k_rate_f64(double *out, int iters)
         acc[c] = (double)(threadIdx.x + c) * 1e-3;
         x[c] = 1e-4 * (c + 1) + threadIdx.x * 1e-13;   // per-lane: a VGPR operand
     }
+    clock_mark(clk, false);
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
@@ -71,67 +91,99 @@ __global__ void __launch_bounds__(256) k_rate_f64(double *out, int iters)
             if (OP == ADD_F64) acc[c] = acc[c] + x[c];
         }
     }
+    clock_mark(clk, true);
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < CH; ++c) s += acc[c];
     out[blockIdx.x * 256 + threadIdx.x] = s;
 }
 
-template <int OP>
-void launch(float *o, double *od, int iters)
-{
-    if (OP == FMA_F64 || OP == MUL_F64 || OP == ADD_F64)
-        hipLaunchKernelGGL((k_rate_f64<OP>), dim3(BLOCKS), dim3(256), 0, 0, od, iters);
-    else hipLaunchKernelGGL((k_rate<OP>), dim3(BLOCKS), dim3(256), 0, 0, o, iters, 0.999f);
-}
+struct Buffers {
+    float *o;
+    double *od;
+    unsigned long long *clk;   // [2 * BLOCKS]
+    double wall_hz;            // wall_clock64 rate
+};
 
 template <int OP>
-double cycles_per_instruction(float *o, double *od, int iters)
+void launch(const Buffers &b, int iters)
+{
+    if (OP == FMA_F64 || OP == MUL_F64 || OP == ADD_F64)
+        hipLaunchKernelGGL((k_rate_f64<OP>), dim3(BLOCKS), dim3(256), 0, 0, b.od, b.clk, iters);
+    else hipLaunchKernelGGL((k_rate<OP>), dim3(BLOCKS), dim3(256), 0, 0, b.o, b.clk, iters, 0.999f);
+}
+
+struct Rate {
+    double cycles;   // SIMD cycles per wave instruction at 2.4 GHz
+    double ghz;      // the core clock of the timed launch, from the first wave of each block
+};
+
+template <int OP>
+Rate measure(const Buffers &b, int iters)
 {
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return {-1.0, -1.0};
     float best = 1e30f;
+    double ghz = 0.0;
+    static unsigned long long h[2 * BLOCKS];
     for (int rep = 0; rep < 4; ++rep) {
         (void)hipEventRecord(e0);
-        launch<OP>(o, od, iters);
+        launch<OP>(b, iters);
         (void)hipEventRecord(e1);
-        if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
+        if (hipEventSynchronize(e1) != hipSuccess) return {-1.0, -1.0};
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0 && ms < best) best = ms;
+        if (rep > 0 && ms < best) {
+            best = ms;
+            if (hipMemcpy(h, b.clk, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return {-1.0, -1.0};
+            double cyc = 0.0, wall = 0.0;
+            for (int i = 0; i < BLOCKS; ++i) {
+                cyc += (double)h[2 * i];
+                wall += (double)h[2 * i + 1];
+            }
+            ghz = wall > 0.0 ? cyc / wall * b.wall_hz * 1e-9 : -1.0;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     const double wave_instr = (double)BLOCKS * 4 * iters * CH;
-    return best * 1e-3 * 2.4e9 * 1024.0 / wave_instr;   // SIMD cycles per wave instruction
+    return {best * 1e-3 * 2.4e9 * 1024.0 / wave_instr, ghz};   // SIMD cycles per wave instruction
 }
 
 }  // namespace
 
 int main()
 {
-    float *o = nullptr;
-    double *od = nullptr;
-    if (hipMalloc(&o, sizeof(float) * BLOCKS * 256) != hipSuccess ||
-        hipMalloc(&od, sizeof(double) * BLOCKS * 256) != hipSuccess) {
-        fprintf(stderr, "valu_rates: allocation failed\n");
+    Buffers b{};
+    int wall_khz = 0;
+    if (hipMalloc(&b.o, sizeof(float) * BLOCKS * 256) != hipSuccess ||
+        hipMalloc(&b.od, sizeof(double) * BLOCKS * 256) != hipSuccess ||
+        hipMalloc(&b.clk, sizeof(unsigned long long) * 2 * BLOCKS) != hipSuccess ||
+        hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, 0) != hipSuccess || wall_khz <= 0) {
+        fprintf(stderr, "valu_rates: set-up failed\n");
         return 1;
     }
-    for (int w = 0; w < 40; ++w) launch<FMAC_V>(o, od, 8192);   // ~0.5 s: clocks up
+    b.wall_hz = 1e3 * wall_khz;
+    for (int w = 0; w < 40; ++w) launch<FMAC_V>(b, 8192);   // ~0.5 s: clocks up
     if (hipDeviceSynchronize() != hipSuccess) return 2;
     const int it = 8192;
-    printf("{\"unit\": \"SIMD cycles per wave64 instruction at 2.4 GHz\", "
-           "\"v_fmac_f32 (VGPR operands)\": %.3f, \"v_fmac_f32 (SGPR operand)\": %.3f, \"v_mul_f32\": %.3f, "
-           "\"v_add_f32\": %.3f, \"v_sin_f32\": %.3f, \"v_rsq_f32 + v_add_f32\": %.3f, \"v_fma_f64\": %.3f, "
-           "\"v_fmac_f32 (lane-uniform data)\": %.3f, \"v_fmac_f32 (SGPR and VGPR operands alternating)\": %.3f, "
-           "\"v_mul_f64\": %.3f, \"v_add_f64\": %.3f}\n",
-           cycles_per_instruction<FMAC_V>(o, od, it), cycles_per_instruction<FMAC_S>(o, od, it),
-           cycles_per_instruction<MUL_V>(o, od, it), cycles_per_instruction<ADD_V>(o, od, it),
-           cycles_per_instruction<SIN_V>(o, od, it / 4), cycles_per_instruction<RSQ_V>(o, od, it / 4),
-           cycles_per_instruction<FMA_F64>(o, od, it), cycles_per_instruction<FMAC_UNIFORM>(o, od, it),
-           cycles_per_instruction<FMAC_SV>(o, od, it), cycles_per_instruction<MUL_F64>(o, od, it),
-           cycles_per_instruction<ADD_F64>(o, od, it));
-    (void)hipFree(o);
-    (void)hipFree(od);
+    const char *names[] = {"v_fmac_f32 (VGPR operands)", "v_fmac_f32 (SGPR operand)", "v_mul_f32", "v_add_f32",
+                           "v_sin_f32", "v_rsq_f32 + v_add_f32", "v_fma_f64", "v_fmac_f32 (lane-uniform data)",
+                           "v_fmac_f32 (SGPR and VGPR operands alternating)", "v_mul_f64", "v_add_f64"};
+    const Rate r[] = {measure<FMAC_V>(b, it), measure<FMAC_S>(b, it), measure<MUL_V>(b, it),
+                      measure<ADD_V>(b, it), measure<SIN_V>(b, it / 4), measure<RSQ_V>(b, it / 4),
+                      measure<FMA_F64>(b, it), measure<FMAC_UNIFORM>(b, it), measure<FMAC_SV>(b, it),
+                      measure<MUL_F64>(b, it), measure<ADD_F64>(b, it)};
+    const int n = (int)(sizeof(r) / sizeof(r[0]));
+    printf("{\"unit\": \"SIMD cycles per wave64 instruction at 2.4 GHz\"");
+    for (int i = 0; i < n; ++i) printf(", \"%s\": %.3f", names[i], r[i].cycles);
+    printf(", \"clock_ghz\": {");
+    for (int i = 0; i < n; ++i) printf("%s\"%s\": %.3f", i ? ", " : "", names[i], r[i].ghz);
+    printf("}, \"cycles_at_measured_clock\": {");
+    for (int i = 0; i < n; ++i) printf("%s\"%s\": %.3f", i ? ", " : "", names[i], r[i].cycles * r[i].ghz / 2.4);
+    printf("}}\n");
+    (void)hipFree(b.o);
+    (void)hipFree(b.od);
+    (void)hipFree(b.clk);
     return 0;
 }

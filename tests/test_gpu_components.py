@@ -56,9 +56,10 @@ def test_per_component_errors_on_the_precision_workload(ctx, orc):
     Eo, Bo = orc.solve(sub)
     p = problem_from_workload(ctx, sub)
     forms = {}
-    for name, prec, fact in (("fp64", "fp64", True), ("fp32_split factored", "fp32_split", True),
-                             ("fp32_split general", "fp32_split", False), ("fp32 naive", "fp32", True)):
-        p.set_factoring(fact)
+    for name, prec, fact, tie in (("fp64", "fp64", True, True), ("fp32_split tied", "fp32_split", True, True),
+                                  ("fp32_split factored", "fp32_split", True, False),
+                                  ("fp32_split general", "fp32_split", False, True), ("fp32 naive", "fp32", True, True)):
+        p.set_factoring(fact, tie_charge=tie)
         E, B = p.evaluate(prec)
         forms[name] = component_errors(E, B, Eo, Bo)
     p.close()
@@ -68,6 +69,7 @@ def test_per_component_errors_on_the_precision_workload(ctx, orc):
     for name, (own, field) in forms.items():
         print(f"{name:22s}" + "".join(f"{o:>10.2e} [{f:8.2e}]" for o, f in zip(own, field)))
     assert forms["fp64"][1].max() < 1e-12
+    assert forms["fp32_split tied"][1].max() < 1e-5
     assert forms["fp32_split factored"][1].max() < 1e-5
     assert forms["fp32_split general"][1].max() < 1e-5
     assert forms["fp32 naive"][1].max() > 100 * forms["fp32_split factored"][1].max()

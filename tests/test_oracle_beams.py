@@ -87,3 +87,48 @@ def test_reflected_cylindrical_fields_are_tm_and_te(orc):
         assert np.abs(G[0, 3:, :2]).max() < 1e-11 * s            # transverse part of the other on the axis
         assert np.abs(F[0, 3:, :]).max() < 1e-11 * s             # the azimuthal field vanishes on the axis
         assert np.abs(G[0, 3, 2]) > 1e-2 * s                     # a strong longitudinal field at the focus
+
+
+def _tie(m, Ei, Bi):
+    """Per surface node: J = n x B and rho = n . E over the frequencies; returns the residual of J
+    off one real direction u, and of rho off gamma * (u . J) with one real gamma for all frequencies,
+    each relative to the node's largest |J| and |J| + |rho|."""
+    ns = m.n_surf
+    n = m.nrm[:ns]
+    J = np.cross(n[None], Bi[:, :ns])                        # [k, q, 3]
+    rho = np.einsum("qc,kqc->kq", n, Ei[:, :ns])
+    kb = np.argmax(np.linalg.norm(J, axis=-1), axis=0)        # per node, the k of the largest |J|
+    Jb = J[kb, np.arange(ns)]
+    part = np.where(np.linalg.norm(Jb.real, axis=-1) >= np.linalg.norm(Jb.imag, axis=-1), 0, 1)
+    u = np.where(part[:, None] == 0, Jb.real, Jb.imag)
+    u /= np.linalg.norm(u, axis=-1, keepdims=True)
+    c = np.einsum("qc,kqc->kq", u, J)
+    scale = np.linalg.norm(J, axis=-1).max(axis=0)
+    res_J = (np.linalg.norm(J - u[None] * c[..., None], axis=-1).max(axis=0) / scale).max()
+    cb = c[kb, np.arange(ns)]
+    gamma = (rho[kb, np.arange(ns)] / cb).real
+    scale_r = (np.abs(rho) + np.abs(c)).max(axis=0)
+    res_rho = (np.abs(rho - gamma[None] * c).max(axis=0) / scale_r).max()
+    return res_J, res_rho
+
+
+@pytest.mark.parametrize("kind_name,tied", [("GAUSSIAN", True), ("PLANE", True), ("RADIAL", True),
+                                            ("AZIMUTHAL", True), ("AZIMUTHAL_CONSISTENT", True),
+                                            ("RADIAL_CONSISTENT", False)])
+def test_charge_tied_to_the_current(orc, kind_name, tied):
+    """The tied-charge layout of the split kernels rests on a property of the incident fields: where
+    the current n x B keeps one real direction u with amplitude c at every frequency, n . E = gamma c
+    with gamma real and the same for all frequencies, for every beam without a longitudinal E
+    (B = -z x E: both carry one complex amplitude; on the paraboloid n . E of the azimuthal beams
+    vanishes, gamma = 0).  The curl-consistent radial beam's E_z = i c' g turns n . E against n x B by
+    an amount that changes with k, so its current factors and its charge does not tie."""
+    kind = getattr(orc, kind_name)
+    m = orc.mirror(20.0, 25.0, 30, 24)
+    spec = np.array([1.0, 0.3 - 0.8j, -0.6 + 0.2j])
+    Ei, Bi = orc.incident_tables(m, [K, 1.3 * K, 1.7 * K], kind, 12.0, 0.4, spec)
+    res_J, res_rho = _tie(m, Ei, Bi)
+    assert res_J < 1e-13
+    if tied:
+        assert res_rho < 1e-13
+    else:
+        assert res_rho > 1e-4
