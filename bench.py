@@ -45,23 +45,26 @@ import workloads  # noqa: E402
 #   per (node, point, frequency): phase 2, A = s Z 6, C = rho_t Z 6,
 #                                 A m, C m (m = ik - 1/R) 12, E += v A 12,
 #                                 E += (C m) e 12, B += (A m) w 12         62
-# The same with the charge tied to the current (rho_t = -i beta s / k):
+# The same with the charge tied to the current (rho_t = -i beta s / k) and s
+# in polar form (|s|, arg s / 2 pi), its phase added to the sine's argument:
 #   per (node, point):            the factored 34, e' = beta e 3           37
-#   per (node, point, frequency): phase 2, A = s Z 6, q = 1/(kR) 1,
-#                                 M = A (i - q) 4, E += v A 12,
-#                                 E += e' (-i M) 12, B += M w 12           49
+#   per (node, point, frequency): phase 2, A = |s| (cos, sin) 2,
+#                                 q = 1/(kR) 1, M = A (i - q) 4, E += v A 12,
+#                                 E += e' (-i M) 12, B += M w 12           45
+#   (the FP64 form keeps s as a complex number: A = s Z 6,                 49)
 # The kernel shares the per-(node, point) work among the frequencies of a
 # lane (freq_per_lane of the launch, read back from the library for every
 # figure below).  Where the observation points lie within 4e-4 |r_s|
 # of the focus, the kernel forms delta and 1/|R| by short series instead of a
 # reciprocal and a square root (5 more flops per (node, point), not counted:
 # the constant stays the formula's).
-FLOPS = {"general": (18, 96), "factored": (34, 62), "tied": (37, 49)}   # (per node and point, per frequency)
+FLOPS = {"general": (18, 96), "factored": (34, 62), "tied": (37, 45)}   # (per node and point, per frequency)
+FLOPS_FP64 = {**FLOPS, "tied": (37, 49)}
 
 
-def flops_per_eval(layout: str, freq_per_lane: int) -> float:
+def flops_per_eval(layout: str, freq_per_lane: int, fp64: bool = False) -> float:
     """Algorithmic flops per evaluation of a table layout ("general", "factored", "tied")."""
-    geom, freq = FLOPS[layout]
+    geom, freq = (FLOPS_FP64 if fp64 else FLOPS)[layout]
     return freq + geom / freq_per_lane
 
 
@@ -726,7 +729,7 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = evals * args.steps / elapsed
     quad_avg = float(np.mean(quad_ms))
-    fpe = flops_per_eval(layout, launch["freq_per_lane"])
+    fpe = flops_per_eval(layout, launch["freq_per_lane"], args.precision == "fp64")
     achieved = fpe * evals / (quad_avg * 1e-3) / 1e12
     peak = PEAK_FP64 if args.precision == "fp64" else PEAK_FP32
     # the counters were taken on the full FP32-split workload with the default launch
@@ -813,8 +816,8 @@ def main():
         progress(f"FP64 form {q64:.1f} ms")
         r64 = w64.evals / (q64 * 1e-3)
         rq = evals / (quad_avg * 1e-3)
-        fpg64 = flops_per_eval("general", fpl64)
-        f64 = flops_per_eval(layout64, fpl64)
+        fpg64 = flops_per_eval("general", fpl64, True)
+        f64 = flops_per_eval(layout64, fpl64, True)
         out["forms"] = {
             "fp64": {"quad_evals_per_s": r64, "quad_ms": q64, "n_freq": w64.n_k,
                      "current": layout64, "flops_per_eval": f64,
@@ -849,7 +852,7 @@ def main():
             p.evaluate("fp64", keep_on_device=True)
             torch.cuda.synchronize()
             qu64 = p.timing()["quad_ms"]
-            fpu64 = flops_per_eval("factored", p.launch("fp64")["freq_per_lane"])
+            fpu64 = flops_per_eval("factored", p.launch("fp64")["freq_per_lane"], True)
             p.close()
             ru64 = w64.evals / (qu64 * 1e-3)
             out["forms"]["fp64_factored_untied"] = {

@@ -259,6 +259,7 @@ static void apply_factoring_flag(sc_prob *p, unsigned int bad, bool need32, bool
         p->tabf.release();
         p->posf.release();
         p->betaf.release();
+        p->tabp.release();
     }
     if (!p->fact64_ok) {
         p->tabf64.release();
@@ -319,6 +320,7 @@ static sc_status ensure_factored(sc_prob *p, bool need32, bool need64)
         SC_TRY(p->tabf.reserve(sizeof(float) * 4 * nrec, p->alloc_stream));
         SC_TRY(p->posf.reserve(sizeof(float) * 8 * (size_t)p->n_tot, p->alloc_stream));
         SC_TRY(p->betaf.reserve(sizeof(float) * (size_t)p->n_tot, p->alloc_stream));
+        SC_TRY(p->tabp.reserve(sizeof(float) * 2 * nrec, p->alloc_stream));
     }
     if (need64) {
         SC_TRY(p->tabf64.reserve(sizeof(double) * 4 * nrec, p->alloc_stream));
@@ -330,7 +332,8 @@ static sc_status ensure_factored(sc_prob *p, bool need32, bool need64)
     HIP_TRY(launch_tables_factor(st, n_k, p->n_tot, p->d_k.as<double>(), p->tab64.as<double>(),
                                  p->pos32.as<float>(), p->pos64.as<double>(), FACTOR_TOL, FACTOR_TOL_FP64,
                                  need32 ? p->tabf.as<float>() : nullptr, need32 ? p->posf.as<float>() : nullptr,
-                                 need32 ? p->betaf.as<float>() : nullptr, need64 ? p->tabf64.as<double>() : nullptr,
+                                 need32 ? p->betaf.as<float>() : nullptr, need32 ? p->tabp.as<float>() : nullptr,
+                                 need64 ? p->tabf64.as<double>() : nullptr,
                                  need64 ? p->posf64.as<double>() : nullptr,
                                  need64 ? p->betaf64.as<double>() : nullptr, p->fact_flag.as<unsigned int>()));
     if (p->fact_checked) {
@@ -787,8 +790,10 @@ static sc_status scale_tables(sc_prob *p, const std::vector<double> &fac)
     } else {
         if (p->tab32_ok)
             HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, 4, dfac.as<double>(), nullptr, p->tab32.as<float>()));
-        if (p->fact32_built)   // a factor per frequency keeps the direction: scale s and rho_t
+        if (p->fact32_built) {   // a factor per frequency keeps the direction: scale s and rho_t
             HIP_TRY(launch_tables_scale(st, n_k, p->n_tot, 2, dfac.as<double>(), nullptr, p->tabf.as<float>()));
+            HIP_TRY(launch_tables_polar(st, (int64_t)n_k * p->n_tot, p->tabf.as<float>(), p->tabp.as<float>()));
+        }
     }
     p->tab32n_ok = false;
     p->res_prec = -1;
@@ -1068,8 +1073,10 @@ static void fill_job(const sc_prob *p, sc_precision prec, const sc_launch &l, co
     job.factored = fact ? 1 : 0;
     job.tied = fact && p->allow_tie && (prec == SC_FP64 ? p->tie64_ok : p->tie_ok) ? 1 : 0;
     job.beta = job.tied ? (prec == SC_FP64 ? p->betaf64.p : p->betaf.p) : nullptr;
+    job.tabp = job.tied && prec != SC_FP64 ? p->tabp.p : nullptr;
     // |delta| = ||R| - |r_s|| <= |r'|, so the split phase k delta stays below k_max |r'|_max; the
-    // hardware sin / cos take up to 256 turns directly (kept below 250 for the FP32 rounding of k delta)
+    // hardware sin / cos take up to 256 turns directly (kept below 250 for the FP32 rounding of k delta;
+    // the tied charge adds the phase of s, at most half a turn)
     {
         const double kmax = *std::max_element(p->k.begin(), p->k.end());
         const double tmax = p->obs_r2max >= 0.0 ? kmax / (2.0 * M_PI) * std::sqrt(p->obs_r2max) : 1e300;
@@ -1134,7 +1141,7 @@ size_t sc::footprint_bytes(int n_r, int n_phi, int n_k, int n_obs, int n_t, sc_p
     b += (size_t)n_k * n_tot * sizeof(double) * 8;
     if (prec != SC_FP64) b += (size_t)n_k * n_tot * sizeof(float) * 8;                      // FP32 tables
     if (prec == SC_FP32_SPLIT)                                                               // factored tables
-        b += (size_t)n_k * n_tot * sizeof(float) * 4 + n_tot * sizeof(float) * 9;
+        b += (size_t)n_k * n_tot * sizeof(float) * 6 + n_tot * sizeof(float) * 9;
     if (prec == SC_FP64) b += (size_t)n_k * n_tot * sizeof(double) * 4 + n_tot * sizeof(double) * 9;
     b += pad * (sizeof(double) + sizeof(float)) * 4;                                        // observation records
     b += sizeof(double) * (2 * (size_t)n_k + 3 * (size_t)n_obs);                             // upload staging
@@ -1605,10 +1612,12 @@ extern "C" sc_status sc_get_timing(const sc_prob *p, sc_timing *out)
 // Every device buffer a problem owns.
 static std::vector<DevBuf *> prob_buffers(sc_prob *p)
 {
-    return {&p->d_r, &p->d_wr, &p->d_c, &p->d_s, &p->pos64, &p->pos32, &p->hinv64, &p->hinv32, &p->nrm, &p->wgt,
-            &p->tan, &p->d_k, &p->tab64, &p->tab32, &p->tab32n, &p->tabf, &p->posf, &p->betaf, &p->tabf64,
-            &p->posf64, &p->betaf64, &p->fact_flag, &p->d_power, &p->obs64, &p->obs32, &p->resE, &p->resB, &p->partial,
-            &p->d_t, &p->tw, &p->timeE, &p->timeB, &p->d_spec, &p->d_obs_in, &p->d_modes};
+    return {&p->d_r,    &p->d_wr,    &p->d_c,       &p->d_s,     &p->pos64,    &p->pos32,  &p->hinv64,
+            &p->hinv32, &p->nrm,     &p->wgt,       &p->tan,     &p->d_k,      &p->tab64,  &p->tab32,
+            &p->tab32n, &p->tabf,    &p->posf,      &p->betaf,   &p->tabp,     &p->tabf64, &p->posf64,
+            &p->betaf64, &p->fact_flag, &p->d_power, &p->obs64,  &p->obs32,    &p->resE,   &p->resB,
+            &p->partial, &p->d_t,    &p->tw,        &p->timeE,   &p->timeB,    &p->d_spec, &p->d_obs_in,
+            &p->d_modes};
 }
 
 void sc::prob_free_on(sc_prob *p, hipStream_t st)

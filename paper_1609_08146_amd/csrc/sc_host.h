@@ -141,12 +141,13 @@ struct sc_prob {
     sc::DevBuf tab64, tab32, tab32n;
     // factored tables (current Jt = u s with a real direction u per node), built from tab64: the
     // test runs once per table set (fact_ok: FP32 split tolerance, fact64_ok: FP64 tolerance), the
-    // FP32 (tabf, posf, betaf) and FP64 (tabf64, posf64, betaf64) tables are built when first
-    // needed; tie_ok, tie64_ok: the charge is tied to the current as well (rho_t = -i beta s / k)
+    // FP32 (tabf, posf, betaf, and tabp: s in polar form) and FP64 (tabf64, posf64, betaf64) tables
+    // are built when first needed; tie_ok, tie64_ok: the charge is tied to the current as well
+    // (rho_t = -i beta s / k)
     bool allow_fact = true, allow_tie = true, fact_checked = false, fact_ok = false, fact64_ok = false;
     bool tie_ok = false, tie64_ok = false;
     bool fact32_built = false, fact64_built = false;
-    sc::DevBuf tabf, posf, betaf, tabf64, posf64, betaf64, fact_flag;
+    sc::DevBuf tabf, posf, betaf, tabp, tabf64, posf64, betaf64, fact_flag;
     // deferred test (set by a caller that must not wait, the serving loop): the flag goes to the
     // pinned word fact_flag_host, fact_ev marks its arrival, and resolve_factoring completes the test
     unsigned int *fact_flag_host = nullptr;

@@ -58,8 +58,10 @@ hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, int n_cplx, c
 // (relative to its largest (|rho_t|^2 + |Jt / k|^2)^1/2).
 hipError_t launch_tables_factor(hipStream_t st, int n_k, int n_tot, const double *k, const double *tab64,
                                 const float *pos32, const double *pos64, double tol32, double tol64, float *tabf,
-                                float *posf, float *betaf, double *tabf64, double *posf64, double *betaf64,
-                                unsigned int *bad);
+                                float *posf, float *betaf, float *tabp, double *tabf64, double *posf64,
+                                double *betaf64, unsigned int *bad);
+// tabp[r] = (|s|, arg(s) / 2 pi) from the FP32 factored records tabf[r] = (s, rho_t), r < n_rec.
+hipError_t launch_tables_polar(hipStream_t st, int64_t n_rec, const float *tabf, float *tabp);
 // Maxwell-residual diagnostics (sc_diag.hip).  Stencil results [rows][13 n_pts][3] complex (double
 // if is_f64, else float); work holds diag_slots() doubles per (row, point), mx 4 per row, out 1 per
 // (row, point).  The time form reads [n_t * 5][13 n_pts][3] (times t_m + (j - 2) dt).

@@ -521,13 +521,15 @@ __global__ void k_tables_cast(int n_k, int n_tot, const double *__restrict__ kv,
 // the node's scale of the charge term (a charge that vanishes but for rounding, as
 // n . E of the azimuthally polarised beam does, is tied with beta = 0).  The tables of a
 // precision must not be used when its bit is set.  Outputs, each optional (NULL
-// skips it): FP32 tabf[k][q] = (s, rho_t), posf[q] = (x, y, z, |r_s|, u_q, 1 / (2|r_s|))
-// and betaf[q] = beta_q; FP64 tabf64, posf64 and betaf64, the same in double.
+// skips it): FP32 tabf[k][q] = (s, rho_t), posf[q] = (x, y, z, |r_s|, u_q, 1 / (2|r_s|)),
+// betaf[q] = beta_q and tabp[k][q] = (|s|, arg(s) / 2 pi), s in polar form for the tied
+// charge (the turn in (-1/2, 1/2]); FP64 tabf64, posf64 and betaf64, the same in double.
 __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ kv, const double *__restrict__ tab64,
                                 const float *__restrict__ pos32, const double *__restrict__ pos64, double tol32,
                                 double tol64, float *__restrict__ tabf, float *__restrict__ posf,
-                                float *__restrict__ betaf, double *__restrict__ tabf64, double *__restrict__ posf64,
-                                double *__restrict__ betaf64, unsigned int *__restrict__ bad)
+                                float *__restrict__ betaf, float *__restrict__ tabp, double *__restrict__ tabf64,
+                                double *__restrict__ posf64, double *__restrict__ betaf64,
+                                unsigned int *__restrict__ bad)
 {
     const int64_t gq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gq >= n_tot) return;
@@ -591,6 +593,8 @@ __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ k
             t[1] = (float)si;
             t[2] = (float)v[6];
             t[3] = (float)v[7];
+            tabp[rec * 2] = (float)sqrt(sr * sr + si * si);
+            tabp[rec * 2 + 1] = (float)(atan2(si, sr) * INV_TWO_PI);
         }
         if (tabf64) {
             double *t = tabf64 + rec * 4;
@@ -615,6 +619,17 @@ __global__ void k_tables_factor(int n_k, int n_tot, const double *__restrict__ k
         betaf64[gq] = beta;
     }
     if (flags) atomicOr(bad, flags);
+}
+
+// The polar records of the tied charge again from the FP32 factored records, after these were
+// scaled in place (a spectral factor on FP32-only tables): tabp[r] = (|s|, arg(s) / 2 pi).
+__global__ void k_tables_polar(int64_t n_rec, const float *__restrict__ tabf, float *__restrict__ tabp)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rec) return;
+    const double sr = tabf[r * 4], si = tabf[r * 4 + 1];
+    tabp[r * 2] = (float)sqrt(sr * sr + si * si);
+    tabp[r * 2 + 1] = (float)(atan2(si, sr) * INV_TWO_PI);
 }
 
 // Split-K reduction: E[k][o][c] = sum over chunks (in FP64, fixed order); B gets the 1/(ik) factor,
@@ -795,11 +810,17 @@ hipError_t launch_tables_scale(hipStream_t st, int n_k, int n_tot, int n_cplx, c
 
 hipError_t launch_tables_factor(hipStream_t st, int n_k, int n_tot, const double *k, const double *tab64,
                                 const float *pos32, const double *pos64, double tol32, double tol64, float *tabf,
-                                float *posf, float *betaf, double *tabf64, double *posf64, double *betaf64,
-                                unsigned int *bad)
+                                float *posf, float *betaf, float *tabp, double *tabf64, double *posf64,
+                                double *betaf64, unsigned int *bad)
 {
     hipLaunchKernelGGL(k_tables_factor, dim3(nblocks(n_tot, 256)), dim3(256), 0, st, n_k, n_tot, k, tab64, pos32,
-                       pos64, tol32, tol64, tabf, posf, betaf, tabf64, posf64, betaf64, bad);
+                       pos64, tol32, tol64, tabf, posf, betaf, tabp, tabf64, posf64, betaf64, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables_polar(hipStream_t st, int64_t n_rec, const float *tabf, float *tabp)
+{
+    hipLaunchKernelGGL(k_tables_polar, dim3(nblocks(n_rec, 256)), dim3(256), 0, st, n_rec, tabf, tabp);
     return hipGetLastError();
 }
 

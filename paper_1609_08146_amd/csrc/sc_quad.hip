@@ -197,15 +197,18 @@ __device__ __forceinline__ void freq_factored(float rinv, float delta, float vx,
 //   rho_t ht R = (rho_t Z m) e = beta e (-i A m / k),   (Jt ht) x R = k (A m / k) w,
 // and A m / k = A (i - q) with q = 1 / (k R): no product rho_t Z, no product
 // with m of its own, and the factor k of the B term is left to the reduction.
-// e carries beta (e = beta R / R^2, formed once per node and point); t = s as (re, im); kinv = 1/k.
+// s comes in polar form, t = (|s|, arg(s) / 2 pi): its phase joins the sine's
+// argument (one FMA) and A = |s| (cos, sin), two MULs instead of a complex
+// product.  e carries beta (e = beta R / R^2, formed once per node and point);
+// kinv = 1/k.
 template <bool RAW>
 __device__ __forceinline__ void freq_tied(float rinv, float delta, float vx, float vy, float vz, float ex, float ey,
                                           float ez, float wx, float wy, float wz, const v2f t, float kinv, float kt,
                                           float *acc)
 {
     float c, sn;
-    sincos_turns<RAW>(kt * delta, sn, c);
-    const float ar = __fmaf_rn(t.x, c, -(t.y * sn)), ai = __fmaf_rn(t.x, sn, t.y * c);
+    sincos_turns<RAW>(__fmaf_rn(kt, delta, t.y), sn, c);
+    const float ar = t.x * c, ai = t.x * sn;
     const float q = rinv * kinv;
     // M = A m / k = (-q ar - ai) + i (ar - q ai);  -i M = M.im - i M.re
     const float mr = __fmaf_rn(-q, ar, -ai), mi = __fmaf_rn(-q, ai, ar);
@@ -525,8 +528,8 @@ constexpr int SUM_BLOCK = 512;
 // frequencies.  FACT selects the factored layout: node records of two v4f
 // (x, y, z, |r_s|), (u, 1 / (2|r_s|)) and one v4f (s, rho_t) per table record, instead of
 // one v4f node record and two v4f (Jt.x, Jt.y), (Jt.z, rho_t) per table record.
-// TIE (factored only) takes the charge tied to the current (freq_tied): of
-// each table record only s is read, and beta from the job's per-node array.
+// TIE (factored only) takes the charge tied to the current (freq_tied): s in
+// polar form from the job's tabp records, beta from its per-node array.
 // RAW passes the split phase k delta / 2 pi to the hardware sin / cos without
 // taking its fractional part (the job guarantees it stays below 250 turns).
 // SER forms delta by its series (geom_series) from h = 1 / (2|r_s|), in the
@@ -571,6 +574,9 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
     constexpr bool HV = SER && !FACT;   // h from the per-node array
     cfloat *hv = (cfloat *)job->hinv;
     cfloat *bv = (cfloat *)job->beta;
+    cv2f *tabp[FPB];
+#pragma unroll
+    for (int f = 0; f < FPB; ++f) tabp[f] = TIE ? (cv2f *)job->tabp + (size_t)kidx[f] * n_tot : nullptr;
     for (int b0 = n0; b0 < n1; b0 += SUM_BLOCK) {
         const int b1 = min(b0 + SUM_BLOCK, n1);
         float blk[OPL][FPB][12];
@@ -591,7 +597,7 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
             v2f ts[FPB];
 #pragma unroll
             for (int f = 0; f < FPB; ++f) {
-                if constexpr (TIE) ts[f] = ((cv2f *)tab[f])[2 * n];
+                if constexpr (TIE) ts[f] = tabp[f][n];
                 else t0[f] = tab[f][TS * n];
                 if constexpr (!FACT) t1[f] = tab[f][TS * n + 1];
             }

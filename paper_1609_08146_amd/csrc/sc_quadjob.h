@@ -16,6 +16,7 @@ struct QuadJob {
     const void *obs;      // [n_obs_pad][4] real
     const void *hinv;     // [n_tot] 1 / (2|r_s|) real (general layout, series_delta)
     const void *beta;     // [n_tot] real (factored layout with the tied charge): rho_t = -i beta s / k
+    const void *tabp;     // [n_k][n_tot][2] float (FP32 split form, tied charge): (|s|, arg(s) / 2 pi)
     const double *k;      // [n_k]
     void *partial;        // [n_chunks][n_k][n_obs_pad / 64][12][64] real
     int n_tot;            // surface + rim nodes
