@@ -28,7 +28,7 @@ BUILD = os.path.join(HERE, "native", "_build")
 def test_abi_paths_under_address_sanitizer():
     exe = os.path.join(BUILD, "abi_address")
     if not os.path.exists(exe):
-        pytest.skip(f"{exe} is not built (run __graft_entry__.build())")
+        pytest.skip(f"{exe} is not built (the repository build step builds it)")
     env = dict(os.environ)
     env["ASAN_OPTIONS"] = "detect_leaks=1:halt_on_error=1"
     env["LSAN_OPTIONS"] = "suppressions=" + os.path.join(HERE, "native", "lsan_rocm.supp")
