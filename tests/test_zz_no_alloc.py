@@ -2,7 +2,7 @@
 memory (work counters, job record, split-K partials) is a static device array, so the call allocates
 nothing.  Through the C ABI it must give sc_evaluate's results bit for bit (same kernels, same node
 chunks), on two calls in a row with the second problem smaller than the first (the array keeps the
-first call's contents), in both split forms, and refuse cleanly when the problem's tables are not
+first call's contents), in both split forms and on each table layout, and refuse cleanly when the problem's tables are not
 built yet or its partials do not fit the array.
 """
 import numpy as np
@@ -11,6 +11,9 @@ import pytest
 import workloads
 
 pytestmark = pytest.mark.gpu
+
+# (enable factoring, tie the charge) per table layout
+LAYOUTS = {"tied": (True, True), "factored": (True, False), "general": (False, True)}
 
 
 @pytest.fixture(scope="module")
@@ -32,8 +35,9 @@ def _out(w, prec):
             torch.full(shape, complex("nan"), dtype=dt, device="cuda"))
 
 
+@pytest.mark.parametrize("layout", list(LAYOUTS))
 @pytest.mark.parametrize("prec", ["fp32_split", "fp64"])
-def test_noalloc_matches_evaluate_on_two_calls_in_a_row(ctx, prec):
+def test_noalloc_matches_evaluate_on_two_calls_in_a_row(ctx, prec, layout):
     from paper_1609_08146_amd import ScError, problem_from_workload
     from paper_1609_08146_amd._abi import SC_E_STATE
     big = workloads.broadband(n_k=8, n_nodes=96).subset(obs_idx=np.arange(0, 4160, 7))     # 595 points, 3 chunks
@@ -41,10 +45,13 @@ def test_noalloc_matches_evaluate_on_two_calls_in_a_row(ctx, prec):
     probs, refs = [], []
     for w in (big, small):
         p = problem_from_workload(ctx, w)
-        # the FP64 (and naive FP32) tables are built by the first evaluation in that precision: before
-        # it, refused with nothing enqueued (the FP32-split tables of these beams exist already)
+        p.set_factoring(*LAYOUTS[layout])
+        assert p.layout_for(prec) == layout, (w.name, prec)
+        # the factored FP64 (and naive FP32) tables are built by the first evaluation in that precision:
+        # before it, refused with nothing enqueued (the FP32-split tables of these beams exist already,
+        # and so do the general FP64 ones, which the general layout reads as they are)
         for unbuilt in ("fp64", "fp32"):
-            if unbuilt == prec:
+            if unbuilt == prec or (unbuilt == "fp64" and layout == "general"):
                 continue
             with pytest.raises(ScError) as e:
                 p.evaluate_noalloc(_out(w, unbuilt), unbuilt)
@@ -55,7 +62,7 @@ def test_noalloc_matches_evaluate_on_two_calls_in_a_row(ctx, prec):
         held = p.device_bytes()
         E, B = p.evaluate_noalloc(_out(w, prec), prec)
         ctx.synchronize()
-        assert np.array_equal(E.cpu().numpy(), E0) and np.array_equal(B.cpu().numpy(), B0), (w.name, prec)
+        assert np.array_equal(E.cpu().numpy(), E0) and np.array_equal(B.cpu().numpy(), B0), (w.name, prec, layout)
         assert p.device_bytes() == held            # the problem's own buffers did not grow
         Er, Br = p.result()                         # the stored result is still sc_evaluate's
         assert np.array_equal(Er, E0) and np.array_equal(Br, B0)
