@@ -537,13 +537,17 @@ constexpr int SUM_BLOCK = 512;
 // (the job guarantees |r'| <= 4e-4 |r_s|).
 // The sums: each block of SUM_BLOCK nodes (counted from the chunk start) is
 // summed plainly in registers, and the block sums are added in order into the
-// tile's own slice of the partials in device memory, which is the chunk's
-// running sum (the first block stores, the later ones load, add and store:
-// every address belongs to one lane of one tile).  No LDS, and no second set of
-// 12 accumulators per (point, frequency) in registers, so a lane can hold four
-// frequencies at five waves per SIMD.  The slices in use (12 KB per wave at
-// four frequencies) outgrow an XCD's L2, so the load-add-store goes to memory:
-// traffic, but no time, since the tile is bound by its VALU issue.
+// chunk's running sum (the first block stores, the later ones load, add and
+// store; every address belongs to one lane of one wave).  No second set of 12
+// accumulators per (point, frequency) in registers, so a lane can hold four
+// frequencies at five waves per SIMD.  The running sums of E sit in the wave's
+// slice of the dynamic LDS ([OPL][FPB][6][64] floats: 6 KB per wave at four
+// frequencies, 120 KB per CU at five waves per SIMD) and are stored into the
+// partials after the last block; those of B are kept in the tile's own slice
+// of the partials in device memory, whose slices in use outgrow an XCD's L2,
+// so that load-add-store goes to memory: traffic, but no time, since the tile
+// is bound by its VALU issue.  The order of the additions, and so every bit of
+// the result, does not depend on where a running sum is kept.
 template <int MODE, int OPL, int FPB, bool FACT, bool RAW, bool SER = false, bool TIE = false>
 __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0, int n1, int obase, const int *kidx,
                                          const double *k64, int n_valid)
@@ -577,6 +581,9 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
     cv2f *tabp[FPB];
 #pragma unroll
     for (int f = 0; f < FPB; ++f) tabp[f] = TIE ? (cv2f *)job->tabp + (size_t)kidx[f] * n_tot : nullptr;
+    // the wave's running sums of E in LDS: [OPL][FPB][6][64]
+    extern __shared__ float run_lds[];
+    float *run = run_lds + (size_t)(threadIdx.x >> 6) * (OPL * FPB * 6 * 64) + lane;
     for (int b0 = n0; b0 < n1; b0 += SUM_BLOCK) {
         const int b1 = min(b0 + SUM_BLOCK, n1);
         float blk[OPL][FPB][12];
@@ -643,13 +650,27 @@ __device__ __forceinline__ void tile_f32(cjob *job, int lane, int chunk, int n0,
         for (int f = 0; f < FPB; ++f) {
             if (f >= n_valid) break;
 #pragma unroll
-            for (int s = 0; s < OPL; ++s)
+            for (int s = 0; s < OPL; ++s) {
 #pragma unroll
-                for (int c = 0; c < 12; ++c) {
+                for (int c = 0; c < 6; ++c) {
+                    float *q = run + ((s * FPB + f) * 6 + c) * 64;
+                    *q = first ? blk[s][f][c] : *q + blk[s][f][c];
+                }
+#pragma unroll
+                for (int c = 6; c < 12; ++c) {
                     float *q = part[f] + s * 768 + c * 64 + lane;
                     *q = first ? blk[s][f][c] : *q + blk[s][f][c];
                 }
+            }
         }
+    }
+#pragma unroll
+    for (int f = 0; f < FPB; ++f) {
+        if (f >= n_valid) break;
+#pragma unroll
+        for (int s = 0; s < OPL; ++s)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) part[f][s * 768 + c * 64 + lane] = run[((s * FPB + f) * 6 + c) * 64];
     }
 }
 
@@ -806,11 +827,19 @@ static const void *quad_fn_dyn(int mode, int opl, int fpb)
     return nullptr;
 }
 
+// Dynamic LDS of a launch: the FP32 forms' running sums of E, 6 floats per (point, frequency) of a lane.
+static size_t quad_lds_bytes(int mode, int opl, int fpb, int waves_per_block)
+{
+    return mode == MODE_FP64 ? 0 : sizeof(float) * 6 * 64 * (size_t)(opl * fpb * waves_per_block);
+}
+
 int quad_max_blocks_per_cu(int mode, int opl, int fpb, int waves_per_block)
 {
     const void *fn = quad_fn_dyn(mode, opl, fpb);
     int nb = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * waves_per_block, 0) != hipSuccess)
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * waves_per_block,
+                                                            quad_lds_bytes(mode, opl, fpb, waves_per_block)) !=
+                   hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
@@ -822,7 +851,8 @@ hipError_t launch_quad(hipStream_t st, int mode, int opl, int fpb, int waves_per
     dim3 g(grid), b(64 * waves_per_block);
 #define SC_QUAD_LAUNCH(M, O, F)                                                                          \
     if (mode == M && opl == O && fpb == F) {                                                            \
-        hipLaunchKernelGGL((k_quad<M, O, F>), g, b, 0, st, jobs, n_jobs, n_tiles, counter);           \
+        hipLaunchKernelGGL((k_quad<M, O, F>), g, b, quad_lds_bytes(M, O, F, waves_per_block), st, jobs, n_jobs, \
+                           n_tiles, counter);                                                           \
         return hipGetLastError();                                                                       \
     }
     SC_QUAD_SHAPES(SC_QUAD_LAUNCH, MODE_FP64)
